@@ -1,0 +1,397 @@
+"""CPU oracle of the single-pass online randomized ID (test infrastructure only).
+
+Plain, slow, binary64 code that follows the paper step by step.  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg use it; the
+product path (the HIP library and its binding) never imports it, and this
+module imports nothing from the product path.
+
+What it computes (Li, Becker, Doostan, "Single-pass randomized ID"):
+
+* Alg. 3 (single-pass randomized ID): per snapshot a_j, the sketch
+  s_j = Omega a_j, SS^T += s_j s_j^T, ||A_obs||_F^2 += ||a_j||^2 and buffering
+  into D; when t columns are buffered, ridge leverage scores of the basis C and
+  the buffer D (eq. ``sketch_ridge_leverage_score``), the reservoir-style
+  prune/fill of the basis, then the coefficients and the error estimate.
+* Alg. 4 (eq. ``coeff_rID_fullsketch``): P = (Omega A_J)^+ (Omega A_obs).
+* Alg. 8 with eqs. ``NAhutchPP_expansion`` and ``NAhutchPP_2nd_term``:
+  the NA-Hutch++ estimate of ||A_obs - A_J P||_F^2.
+
+Readings taken where the paper is silent or garbled (each is listed, with its
+reason, in the design notes of the repository):
+
+* Omega has unit-variance entries (Alg. 3 step 2, Sec. 3.3); the ridge term
+  compares ||A_obs||_F^2 with ||S_k||_F^2 / l (the energy of the normalised
+  sketch Omega / sqrt(l)), i.e. tau = s^T (SS^T + l*lam I)^{-1} s with
+  lam = max((F - ||S_k||^2 / l) / k, rho F / k).
+* S holds every observed column (l x n_obs), not l x t.
+* The update fires right after the t-th buffered column (and its norm) has
+  been added; a partial buffer is flushed by ``finalize``.
+* Fill step: slot by slot, scan the buffer in arrival order, skip columns
+  already placed in this update, and the first successful draw fills the slot.
+* A draw "with probability p" succeeds iff U < p, U a 53-bit uniform.
+* Alg. 4 is solved over the occupied slots with an SVD pseudo-inverse; rows of
+  empty slots are zero.
+* NA-Hutch++ uses the contiguous row split [0,n1), [n1,n1+n2), [n1+n2,l) with
+  n1 = l//4, n2 = l//2 by default, and the formula of eq. NAhutchPP_2nd_term
+  as printed.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from .omega import omega_block, round_to_bf16
+from .philox import PRUNE_DRAW, decision_uniform
+
+
+@dataclass
+class Config:
+    m: int
+    ell: int
+    k: int
+    t: int
+    omega_seed: int = 1
+    select_seed: int = 2
+    delta: float = 0.05        # success probability 1 - delta (Sec. 4.1 channel flow)
+    eps: float = 0.5           # accuracy epsilon (Sec. 4.1 channel flow)
+    c_sample: float = 1.0      # the constant c of the fill probability
+    ridge_floor: float = 1e-8  # rho of the ridge floor
+    hutch_n1: int | None = None
+    hutch_n2: int | None = None
+    operand: str = "f64"       # operand rounding of the sketch: f64, f32 or bf16
+    row_chunk: int = 1 << 16   # rows of Omega regenerated at a time
+
+    @property
+    def n1(self):
+        return self.ell // 4 if self.hutch_n1 is None else self.hutch_n1
+
+    @property
+    def n2(self):
+        return self.ell // 2 if self.hutch_n2 is None else self.hutch_n2
+
+    @property
+    def n3(self):
+        return self.ell - self.n1 - self.n2
+
+
+def fill_factor(cfg):
+    """c (k ln k + k ln(1/delta)/eps) / t: the factor multiplying tau^D in the
+    fill probability (Alg. 3 fill step; the bound on t in Sec. 2.2.2)."""
+    k = cfg.k
+    return cfg.c_sample * (k * math.log(k) + k * math.log(1.0 / cfg.delta) / cfg.eps) / cfg.t
+
+
+# --------------------------------------------------------------------------
+# Sketch (eq. random_sketch; Alg. 3 steps 10-13)
+# --------------------------------------------------------------------------
+
+def _round_operand(x, operand):
+    if operand == "f64":
+        return np.asarray(x, dtype=np.float64)
+    if operand == "f32":
+        return np.asarray(x, dtype=np.float32).astype(np.float64)
+    if operand == "bf16":
+        return round_to_bf16(x)
+    raise ValueError(f"unknown operand rounding {operand!r}")
+
+
+def sketch_columns(cols, omega_seed, ell, operand="f64", row_chunk=1 << 16):
+    """S = Omega A for the columns of ``cols`` (m x b), and ||a_j||^2.
+
+    Omega is regenerated block by block from its counter.  ``operand`` names
+    the rounding applied to both operands before the (exact binary64) product:
+    the reduced-precision sketch forms multiply rounded operands.  Column norms
+    are always those of the unrounded data, accumulated in binary64."""
+    cols = np.asarray(cols)
+    m, b = cols.shape
+    S = np.zeros((ell, b), dtype=np.float64)
+    colsq = np.zeros(b, dtype=np.float64)
+    for i0 in range(0, m, row_chunk):
+        n = min(row_chunk, m - i0)
+        blk = cols[i0:i0 + n].astype(np.float64)
+        om = omega_block(omega_seed, ell, i0, n)
+        S += _round_operand(om, operand) @ _round_operand(blk, operand)
+        colsq += np.einsum("ij,ij->j", blk, blk)
+    return S, colsq
+
+
+# --------------------------------------------------------------------------
+# Ridge leverage scores (eq. sketch_ridge_leverage_score; Alg. 3 function)
+# --------------------------------------------------------------------------
+
+def ridge_lambda(SST, F, k, ell, floor):
+    """||S_k||_F^2 (sum of the top min(k, l) eigenvalues of SS^T) and the ridge
+    parameter lam = max((F - ||S_k||^2/l)/k, floor*F/k)."""
+    mu = np.linalg.eigvalsh(SST)[::-1]
+    sk2 = float(np.sum(mu[:min(k, ell)]))
+    lam = max((F - sk2 / ell) / k, floor * F / k)
+    return sk2, lam, mu
+
+
+def ridge_scores(SST, lam, ell, cols_S):
+    """tau_i = s_i^T (SS^T + l*lam*I)^{-1} s_i for the columns s_i of cols_S."""
+    M = SST + (ell * lam) * np.eye(SST.shape[0])
+    L = np.linalg.cholesky(M)
+    Y = sla.solve_triangular(L, cols_S, lower=True)
+    return np.sum(Y * Y, axis=0)
+
+
+# --------------------------------------------------------------------------
+# Prune / fill (Alg. 3 inner loop over slots)
+# --------------------------------------------------------------------------
+
+@dataclass
+class Decision:
+    kind: str      # "prune" or "fill"
+    slot: int
+    r: int
+    p: float
+    U: float
+    success: bool
+
+
+def select_slots(u, J, tau_old, tau_C, tau_D, d_idx, fill_mult, select_seed):
+    """One pass of the prune/fill loop.
+
+    J: slot -> snapshot index (-1 = empty); tau_C: current scores of the
+    occupied slots (already min'ed with tau_old); tau_D, d_idx: scores and
+    snapshot indices of the buffered columns in arrival order.
+    Returns the new J, tau_old, the mask of slots filled in this update and the
+    list of decisions taken."""
+    J = np.array(J, dtype=np.int64).copy()
+    tau_old = np.array(tau_old, dtype=np.float64).copy()
+    t = J.shape[0]
+    q = np.minimum(1.0, fill_mult * np.asarray(tau_D, dtype=np.float64))
+    used = np.zeros(len(d_idx), dtype=bool)
+    filled = np.zeros(t, dtype=bool)
+    decisions = []
+    for i in range(t):
+        if J[i] >= 0:
+            p = 1.0 - tau_C[i] / tau_old[i]
+            U = float(decision_uniform(select_seed, u, i, PRUNE_DRAW))
+            hit = U < p
+            decisions.append(Decision("prune", i, -1, p, U, hit))
+            if hit:
+                J[i] = -1
+                tau_old[i] = 1.0
+            else:
+                tau_old[i] = tau_C[i]
+        if J[i] < 0:
+            for r in range(len(d_idx)):
+                if used[r]:
+                    continue
+                U = float(decision_uniform(select_seed, u, i, r))
+                hit = U < q[r]
+                decisions.append(Decision("fill", i, r, float(q[r]), U, hit))
+                if hit:
+                    J[i] = d_idx[r]
+                    tau_old[i] = tau_D[r]
+                    used[r] = True
+                    filled[i] = True
+                    break
+    return J, tau_old, filled, decisions
+
+
+# --------------------------------------------------------------------------
+# Alg. 4 and Alg. 8
+# --------------------------------------------------------------------------
+
+def pinv(a):
+    """Moore-Penrose pseudo-inverse by SVD; singular values at or below
+    max(rows, cols) * eps * sigma_max are treated as zero."""
+    a = np.asarray(a, dtype=np.float64)
+    if a.size == 0:
+        return np.zeros((a.shape[1], a.shape[0]))
+    U, s, Vt = np.linalg.svd(a, full_matrices=False)
+    cut = max(a.shape) * np.finfo(np.float64).eps * (s[0] if s.size else 0.0)
+    inv = np.where(s > cut, 1.0 / np.where(s > cut, s, 1.0), 0.0)
+    return (Vt.T * inv) @ U.T
+
+
+def coeff_alg4(S, J):
+    """P = (S_J)^+ S over the occupied slots of J (eq. coeff_rID_fullsketch);
+    rows of empty slots are zero.  S is l x n_obs."""
+    t = len(J)
+    P = np.zeros((t, S.shape[1]))
+    occ = np.flatnonzero(np.asarray(J) >= 0)
+    if occ.size:
+        SJ = S[:, np.asarray(J)[occ]]
+        P[occ] = pinv(SJ) @ S
+    return P
+
+
+def nahutchpp(S, SJ, P, G, F, n1, n2):
+    """NA-Hutch++ estimate of ||A_obs - A_J P||_F^2 (Alg. 8).
+
+    S = Omega A_obs (l x n), SJ = Omega A_J (l x t), P (t x n), G = A_J^T A_J,
+    F = ||A_obs||_F^2.  Rows [0,n1), [n1,n1+n2), [n1+n2,l) of Omega play the
+    parts of Omega_1, Omega_2, Omega_3."""
+    ell = S.shape[0]
+    n3 = ell - n1 - n2
+    W = SJ @ P
+    S1, S2, S3 = S[:n1], S[n1:n1 + n2], S[n1 + n2:]
+    W2, W3 = W[n1:n1 + n2], W[n1 + n2:]
+    K = S1 @ W2.T
+    Kp = pinv(K)
+    Y1 = S1 @ P.T
+    Y2 = S2 @ P.T
+    term1 = float(np.trace(Kp @ Y1 @ G @ Y2.T)) if n1 and n2 else 0.0
+    h = float(np.sum(S3 * W3))
+    corr = float(np.trace(W3 @ S2.T @ Kp @ S1 @ W3.T)) if n1 and n2 else 0.0
+    tr_est = term1 + (h - corr) / n3
+    gpp = float(np.sum((G @ P) * P))
+    e2 = F - 2.0 * tr_est + gpp
+    return dict(E2=e2, tr_est=tr_est, gpp=gpp, term1=term1, h=h, corr=corr,
+                E=math.sqrt(max(e2, 0.0)), rel=(math.sqrt(max(e2, 0.0)) / math.sqrt(F)) if F > 0 else 0.0)
+
+
+# --------------------------------------------------------------------------
+# The streaming driver (Alg. 3)
+# --------------------------------------------------------------------------
+
+@dataclass
+class UpdateRecord:
+    u: int
+    n_obs: int
+    count: int
+    F: float
+    sk2: float = float("nan")
+    lam: float = float("nan")
+    skipped: bool = False
+    tau_C: np.ndarray | None = None
+    tau_D: np.ndarray | None = None
+    J: np.ndarray | None = None
+    filled: np.ndarray | None = None
+    n_pruned: int = 0
+    n_filled: int = 0
+    decisions: list = field(default_factory=list)
+    hutch: dict | None = None
+
+    def min_margin(self):
+        """Smallest |U - p| over the draws whose outcome was not forced."""
+        ms = [abs(d.U - d.p) for d in self.decisions if 0.0 < d.p < 1.0]
+        return min(ms) if ms else float("inf")
+
+
+class OnlineRID:
+    """Alg. 3 with Alg. 4 coefficients and the Alg. 8 error estimate."""
+
+    def __init__(self, cfg: Config, n_max: int | None = None):
+        self.cfg = cfg
+        self.fill_mult = fill_factor(cfg)
+        cap = n_max or 1024
+        self.S = np.zeros((cfg.ell, cap))
+        self.colsq = np.zeros(cap)
+        self.SST = np.zeros((cfg.ell, cfg.ell))
+        self.F = 0.0
+        self.n_obs = 0
+        self.D = []                       # buffered (snapshot index, column)
+        self.J = np.full(cfg.t, -1, dtype=np.int64)
+        self.J_prev = self.J.copy()
+        self.tau_old = np.ones(cfg.t)
+        self.C = None                     # m x t basis columns (data dtype)
+        self.G = np.zeros((cfg.t, cfg.t))
+        self.P = np.zeros((cfg.t, 0))
+        self.u = 0
+        self.records: list[UpdateRecord] = []
+
+    # -- ingest ------------------------------------------------------------
+    def _grow(self, need):
+        cap = self.S.shape[1]
+        if need <= cap:
+            return
+        new = max(need, 2 * cap)
+        S = np.zeros((self.cfg.ell, new)); S[:, :cap] = self.S; self.S = S
+        c = np.zeros(new); c[:cap] = self.colsq; self.colsq = c
+
+    def push(self, cols):
+        """Push snapshots given as the columns of an (m x b) array."""
+        cols = np.asarray(cols)
+        if cols.ndim == 1:
+            cols = cols[:, None]
+        cfg = self.cfg
+        if cols.shape[0] != cfg.m:
+            raise ValueError("snapshot length differs from m")
+        if not np.all(np.isfinite(cols)):
+            raise FloatingPointError("non-finite snapshot value")
+        if self.C is None:
+            self.C = np.zeros((cfg.m, cfg.t), dtype=cols.dtype)
+        Sb, sq = sketch_columns(cols, cfg.omega_seed, cfg.ell, cfg.operand, cfg.row_chunk)
+        self._grow(self.n_obs + cols.shape[1])
+        for jj in range(cols.shape[1]):
+            j = self.n_obs
+            s = Sb[:, jj]
+            self.S[:, j] = s
+            self.colsq[j] = sq[jj]
+            self.SST += np.outer(s, s)
+            self.F += sq[jj]
+            self.D.append((j, cols[:, jj]))
+            self.n_obs += 1
+            if len(self.D) == cfg.t:
+                self._update()
+
+    def finalize(self):
+        """Run the last update over a partially filled buffer."""
+        if self.D:
+            self._update()
+
+    # -- one update (Alg. 3 steps 16-32) -----------------------------------
+    def _update(self):
+        cfg = self.cfg
+        t = cfg.t
+        rec = UpdateRecord(u=self.u, n_obs=self.n_obs, count=len(self.D), F=self.F)
+        d_idx = [j for j, _ in self.D]
+        S = self.S[:, :self.n_obs]
+        filled = np.zeros(t, dtype=bool)
+        J_before = self.J.copy()
+        if self.F > 0.0:
+            sk2, lam, _ = ridge_lambda(self.SST, self.F, cfg.k, cfg.ell, cfg.ridge_floor)
+            rec.sk2, rec.lam = sk2, lam
+            occ = self.J >= 0
+            tau_C = np.full(t, np.nan)
+            if occ.any():
+                tau_C[occ] = np.minimum(self.tau_old[occ], ridge_scores(self.SST, lam, cfg.ell, S[:, self.J[occ]]))
+            tau_D = ridge_scores(self.SST, lam, cfg.ell, S[:, d_idx])
+            J, tau_old, filled, decisions = select_slots(
+                self.u, self.J, self.tau_old, tau_C, tau_D, d_idx, self.fill_mult, cfg.select_seed)
+            rec.tau_C, rec.tau_D, rec.decisions = tau_C, tau_D, decisions
+            rec.n_pruned = int(np.sum((J_before >= 0) & (J != J_before)))
+            self.J, self.tau_old = J, tau_old
+        else:
+            rec.skipped = True
+        rec.filled = filled
+        rec.n_filled = int(filled.sum())
+        # basis columns C (Alg. 3 fill step sets c_i = d_r; emptied slots are zero)
+        cols_by_idx = {j: col for j, col in self.D}
+        for i in range(t):
+            if filled[i]:
+                self.C[:, i] = cols_by_idx[self.J[i]]
+            elif self.J[i] < 0:
+                self.C[:, i] = 0
+        self.G = basis_gram(self.C, self.J)
+        self.P = coeff_alg4(S, self.J)
+        SJ = np.zeros((cfg.ell, t))
+        occ = self.J >= 0
+        SJ[:, occ] = S[:, self.J[occ]]
+        rec.hutch = nahutchpp(S, SJ, self.P, self.G, self.F, cfg.n1, cfg.n2)
+        rec.J = self.J.copy()
+        self.records.append(rec)
+        self.J_prev = self.J.copy()
+        self.D = []
+        self.u += 1
+
+
+def basis_gram(C, J, row_chunk=1 << 18):
+    """G = A_J^T A_J in binary64 (zero rows and columns for empty slots)."""
+    t = C.shape[1]
+    G = np.zeros((t, t))
+    occ = np.flatnonzero(np.asarray(J) >= 0)
+    if occ.size == 0:
+        return G
+    for i0 in range(0, C.shape[0], row_chunk):
+        blk = C[i0:i0 + row_chunk, occ].astype(np.float64)
+        G[np.ix_(occ, occ)] += blk.T @ blk
+    return G
