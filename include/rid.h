@@ -1,0 +1,273 @@
+/*
+ * rid.h - C ABI of the MI355X streaming randomized interpolative decomposition.
+ *
+ * The library computes, for a stream of snapshots a_1, a_2, ... (the columns of
+ * an m x n matrix A that arrive one time step at a time and are discarded after
+ * use, Sec. 1), the single-pass randomized ID A ~ A(:,J) P of Alg. 3:
+ *
+ *   per snapshot   s_j = Omega a_j, SS^T += s_j s_j^T, ||A_obs||_F^2 += ||a_j||^2
+ *                  (eq. random_sketch; Alg. 3 steps 10-13);
+ *   per t columns  sketched ridge leverage scores of the basis and of the new
+ *                  columns (eq. sketch_ridge_leverage_score), the prune/fill of
+ *                  the basis (Alg. 3 steps 16-27), the full-sketch coefficients
+ *                  of Alg. 4 (eq. coeff_rID_fullsketch) and the NA-Hutch++ error
+ *                  estimate of Alg. 8 (eqs. NAhutchPP_expansion and
+ *                  NAhutchPP_2nd_term).
+ *
+ * Conventions shared by every entry point:
+ *  - All matrices are column-major.  A batch of b snapshots is a device buffer
+ *    holding b columns of m elements each, element stride 1, column stride
+ *    ld >= m elements (a contiguous torch tensor of shape (b, m)).
+ *  - "device" pointers are HIP device memory on the stream's device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the library owns all stream state and never frees caller memory.
+ *  - Every call that launches work enqueues it on the stream given to
+ *    rid_init_stream (a hipStream_t passed as void*; NULL = the null stream).
+ *    Only the getters (rid_select, rid_coefficients, rid_error_estimate,
+ *    rid_get_info, rid_get_update, rid_debug_*) synchronise that stream.
+ *  - A handle is not thread safe; distinct handles are independent.
+ *  - Errors are reported by the return code, never by exceptions.  The first
+ *    device error or non-finite input latches the handle into the FAILED
+ *    state: afterwards only rid_get_info, rid_last_error and rid_destroy
+ *    succeed (others return RID_ESTATE).
+ *  - Snapshot indices are 0-based; an empty basis slot holds -1.
+ */
+#ifndef RID_H
+#define RID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rid_status {
+  RID_OK = 0,
+  RID_EINVAL = 1,     /* invalid argument (null pointer, bad size or range) */
+  RID_ENOMEM = 2,     /* device or host allocation failed */
+  RID_EDEVICE = 3,    /* a HIP call or kernel launch failed */
+  RID_ESTATE = 4,     /* call not valid in the handle's current state */
+  RID_ECAPACITY = 5,  /* the push would exceed n_max observed columns */
+  RID_ENUMERIC = 6,   /* non-finite input or numerical breakdown */
+  RID_ENOTSUP = 7     /* configuration not supported by this build */
+} rid_status;
+
+/* Element type of the snapshots. */
+typedef enum rid_dtype { RID_F32 = 0, RID_F64 = 1 } rid_dtype;
+
+/* Arithmetic of the sketch contraction Omega * a_j.  Every form accumulates in
+ * binary32 inside a row slab and in binary64 across slabs, except RID_SKETCH_F64
+ * which is binary64 throughout.  RID_SKETCH_F64 needs RID_F64 data; the other
+ * forms need RID_F32 data. */
+typedef enum rid_sketch_prec {
+  RID_SKETCH_F64 = 0,   /* binary64 test matrix and products */
+  RID_SKETCH_F32 = 1,   /* binary32 test matrix and data, matrix cores */
+  RID_SKETCH_BF16 = 2   /* bfloat16-rounded test matrix and data, matrix cores */
+} rid_sketch_prec;
+
+/* Push flags. */
+#define RID_COPY   0u  /* copy the columns into the library's ring; the buffer
+                          may be reused once prior work on the stream is done */
+#define RID_BORROW 1u  /* keep pointers only; the buffer must stay valid and
+                          unmodified until rid_get_info reports a
+                          release_watermark past its last column */
+
+/* Where rid_coefficients writes P. */
+#define RID_HOST   0u
+#define RID_DEVICE 1u
+
+/* Stream configuration.  Fill it with rid_config_default, then set the sizes.
+ * Parameters follow Alg. 3: l = k + p sketch rows, target rank k, basis size t
+ * (the paper sets k = t), accuracy eps and failure probability delta of the
+ * fill probability c (k ln k + k ln(1/delta)/eps) tau^D / t. */
+typedef struct rid_config {
+  int64_t m;              /* rows per snapshot, >= 1 */
+  int32_t ell;            /* sketch rows l, 4 <= l <= 512 */
+  int32_t k;              /* target rank, 1 <= k <= l */
+  int32_t t;              /* basis size, 1 <= t <= min(l, 256) */
+  int32_t data_dtype;     /* rid_dtype */
+  int32_t sketch_prec;    /* rid_sketch_prec */
+  uint64_t omega_seed;    /* seed of the Philox stream that defines Omega */
+  uint64_t select_seed;   /* seed of the Philox stream of the prune/fill draws */
+  double delta;           /* 0 < delta < 1 (default 0.05) */
+  double eps;             /* eps > 0 (default 0.5) */
+  double c_sample;        /* c > 0 (default 1) */
+  double ridge_floor;     /* rho >= 0: lam >= rho F / k (default 1e-8) */
+  int32_t hutch_n1;       /* rows of Omega_1 (0 = l/4) */
+  int32_t hutch_n2;       /* rows of Omega_2 (0 = l/2); n1 + n2 < l */
+  int32_t lookahead;      /* columns buffered before a sketch launch; 0 = auto */
+  int32_t reserved0;
+  int64_t n_max;          /* capacity: maximum number of pushed columns */
+} rid_config;
+
+/* Error estimate of the last completed update (Alg. 8). */
+typedef struct rid_error {
+  double E2;        /* estimate of ||A_obs - A_J P||_F^2 (may be negative) */
+  double E_abs;     /* sqrt(max(E2, 0)) */
+  double rel;       /* E_abs / sqrt(F) (0 when F = 0) */
+  double F;         /* ||A_obs||_F^2 */
+  int64_t n_obs;    /* columns covered by P */
+  int64_t update;   /* index of the update the estimate belongs to */
+} rid_error;
+
+/* Per-update record (all values as computed on the device). */
+typedef struct rid_update {
+  int64_t update;       /* 0-based update index u */
+  int64_t n_obs;        /* observed columns when the update ran */
+  int64_t count;        /* buffered columns the update scanned */
+  double F;             /* ||A_obs||_F^2 */
+  double sk2;           /* ||S_k||_F^2: sum of the top min(k,l) eigenvalues of SS^T */
+  double lam;           /* ridge parameter lam (tau uses SS^T + l*lam*I) */
+  double E2, tr_est, gpp, term1, h, corr;  /* NA-Hutch++ terms (Alg. 8) */
+  int32_t n_pruned;     /* slots emptied by the prune draws */
+  int32_t n_filled;     /* slots filled from the buffer */
+  int32_t n_occupied;   /* occupied slots after the update */
+  int32_t flags;        /* RID_UPD_* bits */
+} rid_update;
+
+#define RID_UPD_SKIPPED       1  /* F = 0: selection skipped */
+#define RID_UPD_RANK_DEFICIENT 2 /* Omega A_J numerically rank deficient */
+#define RID_UPD_PINV_TRUNCATED 4 /* NA-Hutch++ K truncated to its numerical rank */
+
+typedef struct rid_info {
+  int64_t n_pushed;           /* columns pushed so far */
+  int64_t n_sketched;         /* columns whose sketch has been enqueued */
+  int64_t n_updates;          /* updates enqueued */
+  int64_t release_watermark;  /* columns < this are no longer read (BORROW) */
+  int32_t failed;             /* 1 when the handle is latched FAILED */
+  int32_t finalized;          /* 1 after rid_finalize */
+  int32_t last_status;        /* status that latched FAILED (RID_OK otherwise) */
+  int32_t reserved0;
+  int64_t device_bytes;       /* device memory held by the handle */
+} rid_info;
+
+typedef struct rid_stream rid_stream;
+
+/* Fills *cfg with the defaults listed above (sizes zero).  Never fails on a
+ * non-null pointer; returns RID_EINVAL for NULL. */
+rid_status rid_config_default(rid_config* cfg);
+
+/* Validates *cfg, allocates the stream state on the current HIP device and
+ * returns the handle in *out.  stream: hipStream_t passed as void* (NULL = the
+ * null stream).  Errors: RID_EINVAL (bad sizes, t > l, k > l, l < 4, m < 1,
+ * dtype/precision mismatch), RID_ENOMEM, RID_EDEVICE. */
+rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out);
+
+/* Pushes b snapshots: d_cols is a device buffer of b columns of m elements
+ * (the data dtype), column stride ld >= m elements.  flags: RID_COPY or
+ * RID_BORROW.  Asynchronous; may enqueue sketches and zero or more updates.
+ * Alg. 3 steps 9-13 (and steps 14-32 whenever t columns are buffered).
+ * Errors: RID_EINVAL, RID_ECAPACITY (n_pushed + b > n_max), RID_ESTATE
+ * (finalized or failed), RID_EDEVICE. */
+rid_status rid_push_snapshots(rid_stream* h, const void* d_cols, int64_t ld, int32_t b,
+                              uint32_t flags);
+
+/* Enqueues the sketch of every pushed column and every update whose t columns
+ * are all pushed.  Asynchronous.  Errors: RID_ESTATE, RID_EDEVICE. */
+rid_status rid_flush(rid_stream* h);
+
+/* Ends the stream: flushes, then runs one last update over the partially filled
+ * buffer when it is not empty, so that P covers every pushed column.
+ * Asynchronous.  Errors: RID_ESTATE (already finalized or failed). */
+rid_status rid_finalize(rid_stream* h);
+
+/* Restarts the stream (no columns observed, empty basis) keeping its
+ * allocations.  Asynchronous.  Errors: RID_ESTATE (failed). */
+rid_status rid_reset(rid_stream* h);
+
+/* Copies the current index set J (slot order, -1 = empty) into the host array
+ * J[0..cap), cap >= t, and stores t in *t_out.  Flushes and synchronises.
+ * Errors: RID_EINVAL, RID_ESTATE (no update yet, or failed), RID_ENUMERIC. */
+rid_status rid_select(rid_stream* h, int64_t* J, int32_t cap, int32_t* t_out);
+
+/* Copies P (t x n_cols, binary64, column-major, rows in slot order, rows of
+ * empty slots zero) of the last update into P with leading dimension ldp >= t
+ * and at most cap_cols columns; *n_cols receives the number of columns P
+ * covers.  where: RID_HOST (host pointer) or RID_DEVICE (device pointer).
+ * Flushes and synchronises.  Alg. 4.  Errors: RID_EINVAL (ldp < t or
+ * cap_cols < n_cols), RID_ESTATE, RID_ENUMERIC. */
+rid_status rid_coefficients(rid_stream* h, double* P, int64_t ldp, int64_t cap_cols,
+                            int64_t* n_cols, uint32_t where);
+
+/* The NA-Hutch++ estimate of the last update (Alg. 8).  Flushes and
+ * synchronises.  Errors: RID_EINVAL, RID_ESTATE, RID_ENUMERIC. */
+rid_status rid_error_estimate(rid_stream* h, rid_error* e);
+
+/* Writes d_out(:, 0:c) = A_J P(:, j0:j0+c) (m x c, data dtype, column stride
+ * ld >= m, device memory).  Eq. eqn:id.  Asynchronous; the columns must be
+ * covered by the last update.  Errors: RID_EINVAL (range outside the covered
+ * columns, ld < m), RID_ESTATE. */
+rid_status rid_reconstruct(rid_stream* h, int64_t j0, int32_t c, void* d_out, int64_t ld);
+
+/* Counters and state of the handle.  Synchronises.  Never fails on a valid
+ * handle (RID_EINVAL for NULL arguments). */
+rid_status rid_get_info(rid_stream* h, rid_info* info);
+
+/* Record of update u (0 <= u < n_updates) and, when non-null, the index set
+ * after it (J_out[0..t)) and the scores it used (tau_C[0..t): scores of the
+ * slots occupied before the update, NaN for empty slots; tau_D[0..count):
+ * scores of the buffered columns).  Flushes and synchronises.  Errors:
+ * RID_EINVAL (u out of range), RID_ESTATE. */
+rid_status rid_get_update(rid_stream* h, int64_t u, rid_update* rec, int64_t* J_out,
+                          double* tau_C, double* tau_D);
+
+/* Frees every resource of the handle; valid in any state, synchronises. */
+rid_status rid_destroy(rid_stream* h);
+
+/* Static text for a status code. */
+const char* rid_status_string(rid_status s);
+
+/* Copies the last error message of the handle (or of the library when h is
+ * NULL) into buf[0..n), NUL-terminated. */
+rid_status rid_last_error(rid_stream* h, char* buf, size_t n);
+
+/* ---- live timing --------------------------------------------------------- */
+
+/* Device time of the work the handle enqueued since profiling was enabled,
+ * measured with HIP events recorded on the handle's stream around each launch
+ * group. */
+typedef struct rid_profile {
+  double sketch_ms;         /* sketch contraction kernels (eq. random_sketch) */
+  int64_t sketch_launches;  /* number of sketch contraction launches */
+  double sketch_bytes;      /* snapshot bytes those launches read (columns x m x size) */
+  double reduce_ms;         /* slab reductions of the sketch */
+  double update_ms;         /* per-update phases (Alg. 3 steps 16-32, Alg. 4, Alg. 8) */
+  int64_t updates;          /* updates timed */
+  double gram_ms;           /* basis copy + Gram kernels inside the updates */
+  double gram_bytes;        /* bytes the basis copy + Gram kernels must move */
+} rid_profile;
+
+/* on != 0 starts recording (and clears earlier records); on == 0 stops.
+ * Errors: RID_EINVAL, RID_EDEVICE. */
+rid_status rid_profile_enable(rid_stream* h, int32_t on);
+
+/* Synchronises the stream and sums the recorded intervals into *p.
+ * Errors: RID_EINVAL, RID_EDEVICE. */
+rid_status rid_profile_read(rid_stream* h, rid_profile* p);
+
+/* ---- inspection entry points used by the parity tests ------------------ */
+
+/* Sketch state: S (l x n_sketched, binary64) into the host array S with
+ * leading dimension lds >= l and at most cap_cols columns, ||a_j||^2 into
+ * colsq[0..n_sketched) (may be NULL) and the basis Gram G = A_J^T A_J (t x t)
+ * into G (may be NULL).  Flushes and synchronises.  Errors: RID_EINVAL,
+ * RID_ESTATE. */
+rid_status rid_debug_state(rid_stream* h, double* S, int64_t lds, int64_t cap_cols,
+                           int64_t* n_cols, double* colsq, double* G);
+
+/* Writes Omega(0:ell, i0:i0+count) of the given seed into the device buffer
+ * d_out (ell x count, column-major, column stride ld >= ell), evaluated the way
+ * the sketch form `prec` evaluates it (binary32 for RID_SKETCH_F32 and
+ * RID_SKETCH_BF16, binary64 for RID_SKETCH_F64; the element type of d_out is
+ * float for the former and double for the latter, and RID_SKETCH_BF16 values
+ * are rounded to bfloat16 before being widened).  Alg. 3 step 2.
+ * Asynchronous on `stream`.  Errors: RID_EINVAL, RID_EDEVICE. */
+rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64_t i0,
+                           int64_t count, void* d_out, int64_t ld, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RID_H */

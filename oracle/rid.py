@@ -269,6 +269,8 @@ class UpdateRecord:
     n_filled: int = 0
     decisions: list = field(default_factory=list)
     hutch: dict | None = None
+    kappa: float = float("nan")     # cond(SS^T + l lam I): diagnostic for tolerances
+    cond_SJ: float = float("nan")   # cond(Omega A_J) over occupied slots: diagnostic
 
     def min_margin(self):
         """Smallest |U - p| over the draws whose outcome was not forced."""
@@ -348,8 +350,9 @@ class OnlineRID:
         filled = np.zeros(t, dtype=bool)
         J_before = self.J.copy()
         if self.F > 0.0:
-            sk2, lam, _ = ridge_lambda(self.SST, self.F, cfg.k, cfg.ell, cfg.ridge_floor)
+            sk2, lam, mu = ridge_lambda(self.SST, self.F, cfg.k, cfg.ell, cfg.ridge_floor)
             rec.sk2, rec.lam = sk2, lam
+            rec.kappa = float((mu[0] + cfg.ell * lam) / (max(mu[-1], 0.0) + cfg.ell * lam))
             occ = self.J >= 0
             tau_C = np.full(t, np.nan)
             if occ.any():
@@ -376,6 +379,9 @@ class OnlineRID:
         SJ = np.zeros((cfg.ell, t))
         occ = self.J >= 0
         SJ[:, occ] = S[:, self.J[occ]]
+        if occ.any():
+            sv = np.linalg.svd(SJ[:, occ], compute_uv=False)
+            rec.cond_SJ = float(sv[0] / sv[-1]) if sv[-1] > 0 else float("inf")
         rec.hutch = nahutchpp(S, SJ, self.P, self.G, self.F, cfg.n1, cfg.n2)
         rec.J = self.J.copy()
         self.records.append(rec)

@@ -1,0 +1,797 @@
+// Host runtime and C ABI of the streaming randomized ID (include/rid.h).
+//
+// A handle owns the device state of one stream.  Pushed columns are recorded
+// in a column-pointer table (BORROW: the caller's addresses; COPY: slots of a
+// device ring the columns are copied into).  Sketches are launched over up to
+// `lookahead` buffered columns at a time (the sketch of a column does not
+// depend on its batch), and the update of Alg. 3 is enqueued for every group
+// of t consecutive sketched columns.  No device-to-host traffic happens except
+// in the getters.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "rid_internal.h"
+
+namespace rid {
+
+// ---------------------------------------------------------------------------
+// reconstruct: out(:, jj) = sum over occupied slots i of C(:, i) P(i, j0 + jj)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void reconstruct_kernel(const T* __restrict__ C, int64_t ldc,
+                                                          const double* __restrict__ P, int t,
+                                                          const int64_t* __restrict__ J, int64_t m,
+                                                          int64_t j0, int c, T* out, int64_t ld) {
+  constexpr int CB = 16;
+  __shared__ double pt[kMaxT][CB];
+  __shared__ int occ[kMaxT];
+  __shared__ int nocc;
+  const int tid = threadIdx.x;
+  const int cb0 = blockIdx.y * CB;
+  if (tid == 0) {
+    int no = 0;
+    for (int i = 0; i < t; ++i)
+      if (J[i] >= 0) occ[no++] = i;
+    nocc = no;
+  }
+  for (int idx = tid; idx < t * CB; idx += blockDim.x) {
+    const int i = idx / CB, jj = idx % CB;
+    pt[i][jj] = (cb0 + jj < c) ? P[(j0 + cb0 + jj) * t + i] : 0.0;
+  }
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + tid;
+  if (row >= m) return;
+  double acc[CB];
+#pragma unroll
+  for (int jj = 0; jj < CB; ++jj) acc[jj] = 0.0;
+  for (int q = 0; q < nocc; ++q) {
+    const int i = occ[q];
+    const double x = (double)C[(int64_t)i * ldc + row];
+#pragma unroll
+    for (int jj = 0; jj < CB; ++jj) acc[jj] = fma(x, pt[i][jj], acc[jj]);
+  }
+#pragma unroll
+  for (int jj = 0; jj < CB; ++jj)
+    if (cb0 + jj < c) out[(int64_t)(cb0 + jj) * ld + row] = (T)acc[jj];
+}
+
+__global__ void init_state_kernel(int64_t* J, double* tau_old, int t, DevScalars* sc) {
+  const int i = threadIdx.x;
+  if (i < t) {
+    J[i] = -1;
+    tau_old[i] = 1.0;
+  }
+  if (i == 0) {
+    sc->F = 0.0;
+    sc->lam = 0.0;
+    sc->shift = 0.0;
+    sc->skip = 0;
+    sc->nonfinite = 0;
+    sc->n_new = 0;
+    sc->n_occ = 0;
+    sc->rank = 0;
+  }
+}
+
+}  // namespace rid
+
+using namespace rid;
+
+struct rid_stream {
+  rid_config cfg;
+  hipStream_t s = nullptr;
+  int dev = 0;
+  int ell = 0, k = 0, t = 0, n1 = 0, n2 = 0, prec = 0, esize = 4, data_f64 = 0;
+  int64_t m = 0, n_max = 0;
+  double fill_mult = 0.0;
+  // sketch geometry
+  int ell_pad = 0, n_mt = 0, cols_per_wg = 0, b_max = 0, n_slabs = 0;
+  int64_t slab_rows = 0;
+  int gslabs = 0;
+  int64_t gslab_rows = 0;
+  int64_t ldc = 0;
+  // device memory
+  std::vector<void*> allocs;
+  size_t dev_bytes = 0;
+  double *S = nullptr, *colsq = nullptr, *SST = nullptr, *W = nullptr, *hv = nullptr;
+  double *tauC = nullptr, *tauD = nullptr, *tau_old = nullptr, *tauC_hist = nullptr,
+         *tauD_hist = nullptr;
+  double *G = nullptr, *gpart = nullptr, *QR = nullptr, *qr_tau = nullptr, *P = nullptr;
+  double *Y = nullptr, *PPt = nullptr, *hw = nullptr;
+  int64_t *J = nullptr, *J_hist = nullptr;
+  uint64_t* colptr_dev = nullptr;
+  uint64_t* colptr_host = nullptr;  // pinned
+  void* cpool = nullptr;
+  void* ring = nullptr;
+  int64_t ring_cap = 0, ring_ld = 0;
+  void* part = nullptr;
+  double* normpart = nullptr;
+  DevScalars* sc = nullptr;
+  rid_update* recs = nullptr;
+  int64_t max_updates = 0;
+  // host counters
+  int64_t n_pushed = 0, n_sketched = 0, n_uploaded = 0, n_updates = 0, last_nobs = 0;
+  bool finalized = false, failed = false;
+  rid_status last_status = RID_OK;
+  std::string last_err;
+  // live timing: event pairs recorded on the stream around launch groups
+  struct Mark {
+    hipEvent_t a, b;
+    int kind;        // 0 sketch, 1 reduce, 2 update, 3 gram
+    double bytes;
+  };
+  bool profiling = false;
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
+};
+
+static thread_local std::string g_last_err;
+
+static rid_status fail(rid_stream* h, rid_status st, const std::string& msg) {
+  if (h) {
+    h->last_err = msg;
+    if (st == RID_EDEVICE || st == RID_ENUMERIC) {
+      h->failed = true;
+      h->last_status = st;
+    }
+  } else {
+    g_last_err = msg;
+  }
+  return st;
+}
+
+#define RID_HIP(h, expr)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((h), RID_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static rid_status dalloc(rid_stream* h, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(h, RID_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  h->allocs.push_back(*p);
+  h->dev_bytes += bytes;
+  return RID_OK;
+}
+
+template <typename T>
+static rid_status dalloc_t(rid_stream* h, T** p, size_t count) {
+  void* v = nullptr;
+  rid_status st = dalloc(h, &v, count * sizeof(T));
+  *p = reinterpret_cast<T*>(v);
+  return st;
+}
+
+static void free_all(rid_stream* h) {
+  for (auto& mk : h->marks) {
+    (void)hipEventDestroy(mk.a);
+    (void)hipEventDestroy(mk.b);
+  }
+  h->marks.clear();
+  for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+  h->event_pool.clear();
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  if (h->colptr_host) (void)hipHostFree(h->colptr_host);
+  h->colptr_host = nullptr;
+}
+
+static int auto_lookahead(const rid_config* c) {
+  int la = c->lookahead > 0 ? c->lookahead : 1024;
+  la = std::max(la, 2 * c->t);
+  return (int)std::min<int64_t>(la, std::max<int64_t>(c->n_max, 1));
+}
+
+extern "C" {
+
+rid_status rid_config_default(rid_config* cfg) {
+  if (!cfg) return RID_EINVAL;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->data_dtype = RID_F32;
+  cfg->sketch_prec = RID_SKETCH_F32;
+  cfg->omega_seed = 1;
+  cfg->select_seed = 2;
+  cfg->delta = 0.05;
+  cfg->eps = 0.5;
+  cfg->c_sample = 1.0;
+  cfg->ridge_floor = 1e-8;
+  return RID_OK;
+}
+
+const char* rid_status_string(rid_status s) {
+  switch (s) {
+    case RID_OK: return "RID_OK";
+    case RID_EINVAL: return "RID_EINVAL: invalid argument";
+    case RID_ENOMEM: return "RID_ENOMEM: allocation failed";
+    case RID_EDEVICE: return "RID_EDEVICE: HIP error";
+    case RID_ESTATE: return "RID_ESTATE: call not valid in this state";
+    case RID_ECAPACITY: return "RID_ECAPACITY: more than n_max columns";
+    case RID_ENUMERIC: return "RID_ENUMERIC: non-finite input or numerical breakdown";
+    case RID_ENOTSUP: return "RID_ENOTSUP: configuration not supported";
+  }
+  return "unknown rid_status";
+}
+
+rid_status rid_last_error(rid_stream* h, char* buf, size_t n) {
+  if (!buf || n == 0) return RID_EINVAL;
+  const std::string& m = h ? h->last_err : g_last_err;
+  snprintf(buf, n, "%s", m.c_str());
+  return RID_OK;
+}
+
+static rid_status validate(const rid_config* c) {
+  if (c->m < 1) return fail(nullptr, RID_EINVAL, "m must be >= 1");
+  if (c->ell < 4 || c->ell > kMaxEll) return fail(nullptr, RID_EINVAL, "ell must be in [4, 512]");
+  if (c->k < 1 || c->k > c->ell) return fail(nullptr, RID_EINVAL, "k must be in [1, ell]");
+  if (c->t < 1 || c->t > c->ell || c->t > kMaxT)
+    return fail(nullptr, RID_EINVAL, "t must be in [1, min(ell, 256)]");
+  if (c->n_max < 1) return fail(nullptr, RID_EINVAL, "n_max must be >= 1");
+  if (c->data_dtype != RID_F32 && c->data_dtype != RID_F64)
+    return fail(nullptr, RID_EINVAL, "unknown data dtype");
+  if (c->sketch_prec < RID_SKETCH_F64 || c->sketch_prec > RID_SKETCH_BF16)
+    return fail(nullptr, RID_EINVAL, "unknown sketch precision");
+  if ((c->sketch_prec == RID_SKETCH_F64) != (c->data_dtype == RID_F64))
+    return fail(nullptr, RID_EINVAL, "the f64 sketch needs f64 data and the others f32 data");
+  if (!(c->delta > 0.0 && c->delta < 1.0) || !(c->eps > 0.0) || !(c->c_sample > 0.0) ||
+      !(c->ridge_floor >= 0.0))
+    return fail(nullptr, RID_EINVAL, "delta, eps, c_sample or ridge_floor out of range");
+  const int n1 = c->hutch_n1 > 0 ? c->hutch_n1 : c->ell / 4;
+  const int n2 = c->hutch_n2 > 0 ? c->hutch_n2 : c->ell / 2;
+  if (n1 < 1 || n2 <= n1 || n1 + n2 >= c->ell)
+    return fail(nullptr, RID_EINVAL, "need 1 <= n1 < n2 and n1 + n2 < ell");
+  if (n1 > kMaxEll / 4) return fail(nullptr, RID_ENOTSUP, "n1 above 128 is not supported");
+  if (c->lookahead < 0) return fail(nullptr, RID_EINVAL, "lookahead must be >= 0");
+  return RID_OK;
+}
+
+rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out) {
+  if (!cfg || !out) return fail(nullptr, RID_EINVAL, "null argument");
+  *out = nullptr;
+  rid_status st = validate(cfg);
+  if (st != RID_OK) return st;
+  rid_stream* h = new rid_stream();
+  h->cfg = *cfg;
+  h->s = reinterpret_cast<hipStream_t>(stream);
+  if (hipGetDevice(&h->dev) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    return fail(nullptr, RID_EDEVICE, "no HIP device");
+  }
+  h->m = cfg->m;
+  h->ell = cfg->ell;
+  h->k = cfg->k;
+  h->t = cfg->t;
+  h->n1 = cfg->hutch_n1 > 0 ? cfg->hutch_n1 : cfg->ell / 4;
+  h->n2 = cfg->hutch_n2 > 0 ? cfg->hutch_n2 : cfg->ell / 2;
+  h->prec = cfg->sketch_prec;
+  h->data_f64 = cfg->data_dtype == RID_F64;
+  h->esize = h->data_f64 ? 8 : 4;
+  h->n_max = cfg->n_max;
+  {
+    const double k = cfg->k;
+    h->fill_mult = cfg->c_sample * (k * log(k) + k * log(1.0 / cfg->delta) / cfg->eps) / cfg->t;
+  }
+  // sketch geometry
+  h->ell_pad = (h->ell + kMTile - 1) / kMTile * kMTile;
+  h->n_mt = h->ell_pad / kMTile;
+  h->cols_per_wg = sketch_cols_per_wg(h->prec);
+  h->b_max = auto_lookahead(cfg);
+  {
+    const int n_nt = (h->b_max + h->cols_per_wg - 1) / h->cols_per_wg;
+    const int64_t cap = (h->prec == RID_SKETCH_BF16) ? 65536 : (h->prec == RID_SKETCH_F32 ? 32768 : 16384);
+    const int64_t target = std::max<int64_t>(1, 2048 / (h->n_mt * n_nt));
+    int64_t rows = (h->m + target - 1) / target;
+    rows = (rows + 255) / 256 * 256;
+    rows = std::min(std::max<int64_t>(rows, 256), cap);
+    h->slab_rows = rows;
+    h->n_slabs = (int)((h->m + rows - 1) / rows);
+  }
+  {
+    const int tt = (h->t + 63) / 64;
+    const int64_t target = std::max<int64_t>(1, 2048 / (tt * tt));
+    int64_t rows = (h->m + target - 1) / target;
+    rows = (rows + 255) / 256 * 256;
+    rows = std::max<int64_t>(rows, 1024);
+    h->gslab_rows = rows;
+    h->gslabs = (int)((h->m + rows - 1) / rows);
+  }
+  h->ldc = (h->m + 63) / 64 * 64;
+  h->max_updates = (h->n_max + h->t - 1) / h->t + 1;
+  const size_t ell = h->ell, t = h->t;
+  const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
+#define ALLOC(ptr, n) \
+  if ((st = dalloc_t(h, &(ptr), (n))) != RID_OK) goto fail_alloc;
+  {
+    ALLOC(h->S, ell * h->n_max);
+    ALLOC(h->colsq, h->n_max);
+    ALLOC(h->SST, ell * ell);
+    ALLOC(h->W, ell * ell);
+    ALLOC(h->hv, 6 * ell);
+    ALLOC(h->tauC, (size_t)kMaxT);
+    ALLOC(h->tauD, (size_t)kMaxT);
+    ALLOC(h->tau_old, (size_t)kMaxT);
+    ALLOC(h->tauC_hist, t * h->max_updates);
+    ALLOC(h->tauD_hist, t * h->max_updates);
+    ALLOC(h->J, (size_t)kMaxT);
+    ALLOC(h->J_hist, t * h->max_updates);
+    ALLOC(h->G, t * t);
+    ALLOC(h->gpart, (size_t)h->gslabs * t * t);
+    ALLOC(h->QR, ell * t);
+    ALLOC(h->qr_tau, (size_t)kMaxT);
+    ALLOC(h->P, t * h->n_max);
+    ALLOC(h->Y, ell * t);
+    ALLOC(h->PPt, t * t);
+    ALLOC(h->hw, hutch_work_doubles());
+    ALLOC(h->colptr_dev, (size_t)h->n_max);
+    ALLOC(h->normpart, (size_t)h->n_slabs * h->b_max);
+    ALLOC(h->sc, (size_t)1);
+    ALLOC(h->recs, (size_t)h->max_updates);
+    if ((st = dalloc(h, &h->part, (size_t)h->n_slabs * h->b_max * h->ell_pad * psize)) != RID_OK)
+      goto fail_alloc;
+    if ((st = dalloc(h, &h->cpool, (size_t)h->ldc * t * h->esize)) != RID_OK) goto fail_alloc;
+  }
+#undef ALLOC
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->colptr_host), sizeof(uint64_t) * h->n_max,
+                    hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    st = fail(nullptr, RID_ENOMEM, "pinned host allocation failed");
+    goto fail_alloc;
+  }
+  if (hipMemsetAsync(h->cpool, 0, (size_t)h->ldc * t * h->esize, h->s) != hipSuccess ||
+      hipMemsetAsync(h->SST, 0, ell * ell * 8, h->s) != hipSuccess ||
+      hipMemsetAsync(h->G, 0, t * t * 8, h->s) != hipSuccess ||
+      hipMemsetAsync(h->recs, 0, sizeof(rid_update) * h->max_updates, h->s) != hipSuccess) {
+    st = fail(nullptr, RID_EDEVICE, "hipMemsetAsync failed");
+    goto fail_alloc;
+  }
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc);
+  if (hipGetLastError() != hipSuccess) {
+    st = fail(nullptr, RID_EDEVICE, "init kernel launch failed");
+    goto fail_alloc;
+  }
+  *out = h;
+  return RID_OK;
+fail_alloc:
+  g_last_err = h->last_err.empty() ? g_last_err : h->last_err;
+  free_all(h);
+  delete h;
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// internal stream operations
+// ---------------------------------------------------------------------------
+static hipEvent_t take_event(rid_stream* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Starts a timed interval on the handle's stream (no-op unless profiling).
+static int mark_begin(rid_stream* h, int kind, double bytes) {
+  if (!h->profiling) return -1;
+  rid_stream::Mark mk{take_event(h), take_event(h), kind, bytes};
+  if (!mk.a || !mk.b || hipEventRecord(mk.a, h->s) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  h->marks.push_back(mk);
+  return (int)h->marks.size() - 1;
+}
+
+static void mark_end(rid_stream* h, int idx) {
+  if (idx < 0) return;
+  if (hipEventRecord(h->marks[idx].b, h->s) != hipSuccess) (void)hipGetLastError();
+}
+static rid_status upload_colptrs(rid_stream* h) {
+  if (h->n_uploaded < h->n_pushed) {
+    const int64_t n = h->n_pushed - h->n_uploaded;
+    RID_HIP(h, hipMemcpyAsync(h->colptr_dev + h->n_uploaded, h->colptr_host + h->n_uploaded,
+                              n * sizeof(uint64_t), hipMemcpyHostToDevice, h->s));
+    h->n_uploaded = h->n_pushed;
+  }
+  return RID_OK;
+}
+
+static rid_status sketch_range(rid_stream* h, int64_t c0, int b) {
+  SketchArgs a;
+  a.colptr = h->colptr_dev;
+  a.c0 = c0;
+  a.b = b;
+  a.b_max = h->b_max;
+  a.m = h->m;
+  a.slab_rows = h->slab_rows;
+  a.n_slabs = h->n_slabs;
+  a.n_mt = h->n_mt;
+  a.n_nt = (b + h->cols_per_wg - 1) / h->cols_per_wg;
+  a.ell_pad = h->ell_pad;
+  a.seed = h->cfg.omega_seed;
+  a.part = h->part;
+  a.normpart = h->normpart;
+  int mk = mark_begin(h, 0, (double)b * (double)h->m * h->esize);
+  RID_HIP(h, launch_sketch(h->prec, a, h->s));
+  mark_end(h, mk);
+  mk = mark_begin(h, 1, 0.0);
+  RID_HIP(h, launch_sketch_reduce(h->prec, a, h->ell, h->S, h->colsq, &h->sc->nonfinite, h->s));
+  mark_end(h, mk);
+  return RID_OK;
+}
+
+static rid_status run_update(rid_stream* h, int cnt) {
+  UpdArgs a;
+  a.ell = h->ell;
+  a.k = h->k;
+  a.t = h->t;
+  a.n1 = h->n1;
+  a.n2 = h->n2;
+  a.u = h->n_updates;
+  a.c0 = h->n_updates * h->t;
+  a.cnt = cnt;
+  a.n_obs = a.c0 + cnt;
+  a.fill_mult = h->fill_mult;
+  a.ridge_floor = h->cfg.ridge_floor;
+  a.select_seed = h->cfg.select_seed;
+  a.m = h->m;
+  a.ldc = h->ldc;
+  a.data_f64 = h->data_f64;
+  a.S = h->S;
+  a.colsq = h->colsq;
+  a.SST = h->SST;
+  a.W = h->W;
+  a.hv = h->hv;
+  a.J = h->J;
+  a.tau_old = h->tau_old;
+  a.tauC = h->tauC;
+  a.tauD = h->tauD;
+  a.J_hist = h->J_hist;
+  a.tauC_hist = h->tauC_hist;
+  a.tauD_hist = h->tauD_hist;
+  a.colptr = h->colptr_dev;
+  a.cpool = h->cpool;
+  a.G = h->G;
+  a.gpart = h->gpart;
+  a.gslabs = h->gslabs;
+  a.gslab_rows = h->gslab_rows;
+  a.QR = h->QR;
+  a.qr_tau = h->qr_tau;
+  a.P = h->P;
+  a.Y = h->Y;
+  a.PPt = h->PPt;
+  a.hw = h->hw;
+  a.sc = h->sc;
+  a.recs = h->recs;
+  int mk = mark_begin(h, 2, (double)a.u);
+  RID_HIP(h, launch_update_select(a, h->s));
+  mark_end(h, mk);
+  mk = mark_begin(h, 3, (double)a.u);
+  RID_HIP(h, launch_update_gram(a, h->s));
+  mark_end(h, mk);
+  mk = mark_begin(h, 2, (double)a.u);
+  RID_HIP(h, launch_update_coeff(a, h->s));
+  mark_end(h, mk);
+  h->n_updates += 1;
+  h->last_nobs = a.n_obs;
+  return RID_OK;
+}
+
+// Sketch every pushed column (in batches of at most b_max) and enqueue every
+// update whose t columns are sketched.
+static rid_status flush_all(rid_stream* h) {
+  rid_status st = upload_colptrs(h);
+  if (st != RID_OK) return st;
+  while (h->n_sketched < h->n_pushed) {
+    const int b = (int)std::min<int64_t>(h->b_max, h->n_pushed - h->n_sketched);
+    if ((st = sketch_range(h, h->n_sketched, b)) != RID_OK) return st;
+    h->n_sketched += b;
+    while ((h->n_updates + 1) * h->t <= h->n_sketched)
+      if ((st = run_update(h, h->t)) != RID_OK) return st;
+  }
+  return RID_OK;
+}
+
+// Sketch only full batches (the lookahead); used after pushes.
+static rid_status flush_full(rid_stream* h) {
+  rid_status st = RID_OK;
+  if (h->n_pushed - h->n_sketched < h->b_max) return RID_OK;
+  if ((st = upload_colptrs(h)) != RID_OK) return st;
+  while (h->n_pushed - h->n_sketched >= h->b_max) {
+    if ((st = sketch_range(h, h->n_sketched, h->b_max)) != RID_OK) return st;
+    h->n_sketched += h->b_max;
+    while ((h->n_updates + 1) * h->t <= h->n_sketched)
+      if ((st = run_update(h, h->t)) != RID_OK) return st;
+  }
+  return RID_OK;
+}
+
+static rid_status sync_check(rid_stream* h) {
+  RID_HIP(h, hipStreamSynchronize(h->s));
+  int32_t nf = 0;
+  RID_HIP(h, hipMemcpy(&nf, &h->sc->nonfinite, sizeof(nf), hipMemcpyDeviceToHost));
+  if (nf) return fail(h, RID_ENUMERIC, "non-finite snapshot value");
+  return RID_OK;
+}
+
+extern "C" {
+
+rid_status rid_push_snapshots(rid_stream* h, const void* d_cols, int64_t ld, int32_t b, uint32_t flags) {
+  if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  if (h->failed || h->finalized) return fail(h, RID_ESTATE, "stream finalized or failed");
+  if (b < 0 || ld < h->m || (b > 0 && !d_cols) || (flags != RID_COPY && flags != RID_BORROW))
+    return fail(h, RID_EINVAL, "bad push arguments");
+  if (b == 0) return RID_OK;
+  if (h->n_pushed + b > h->n_max) return fail(h, RID_ECAPACITY, "push exceeds n_max");
+  const uintptr_t base = reinterpret_cast<uintptr_t>(d_cols);
+  const int64_t es = h->esize;
+  rid_status st;
+  if (flags == RID_BORROW) {
+    if (base % 16 != 0 || (ld * es) % 16 != 0)
+      return fail(h, RID_EINVAL, "BORROW needs 16-byte aligned columns (pointer and ld * size)");
+    for (int j = 0; j < b; ++j) h->colptr_host[h->n_pushed + j] = base + (uint64_t)j * ld * es;
+    h->n_pushed += b;
+    return flush_full(h);
+  }
+  // COPY: stage the columns in the ring, never overwriting a column that an
+  // enqueued update has not consumed yet.
+  if (!h->ring) {
+    h->ring_cap = std::max<int64_t>(h->b_max, 2 * (int64_t)h->t);
+    h->ring_cap = (h->ring_cap + h->t - 1) / h->t * h->t;
+    h->ring_ld = h->ldc;
+    if ((st = dalloc(h, &h->ring, (size_t)h->ring_cap * h->ring_ld * es)) != RID_OK) return st;
+  }
+  int done = 0;
+  while (done < b) {
+    const int64_t consumed = h->n_updates * h->t;
+    int64_t space = h->ring_cap - (h->n_pushed - consumed);
+    if (space <= 0) {
+      if ((st = flush_all(h)) != RID_OK) return st;
+      continue;
+    }
+    const int64_t slot = h->n_pushed % h->ring_cap;
+    int64_t chunk = std::min<int64_t>({(int64_t)(b - done), space, h->ring_cap - slot});
+    char* dst = reinterpret_cast<char*>(h->ring) + slot * h->ring_ld * es;
+    const char* src = reinterpret_cast<const char*>(d_cols) + (int64_t)done * ld * es;
+    RID_HIP(h, hipMemcpy2DAsync(dst, h->ring_ld * es, src, ld * es, h->m * es, chunk,
+                                hipMemcpyDeviceToDevice, h->s));
+    for (int64_t j = 0; j < chunk; ++j)
+      h->colptr_host[h->n_pushed + j] = reinterpret_cast<uint64_t>(dst) + (uint64_t)j * h->ring_ld * es;
+    h->n_pushed += chunk;
+    done += (int)chunk;
+    if (h->n_pushed - h->n_sketched >= h->b_max || h->n_pushed - consumed >= h->ring_cap)
+      if ((st = flush_all(h)) != RID_OK) return st;
+  }
+  return RID_OK;
+}
+
+rid_status rid_flush(rid_stream* h) {
+  if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  if (h->failed) return fail(h, RID_ESTATE, "stream failed");
+  return flush_all(h);
+}
+
+rid_status rid_finalize(rid_stream* h) {
+  if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  if (h->failed || h->finalized) return fail(h, RID_ESTATE, "stream finalized or failed");
+  rid_status st = flush_all(h);
+  if (st != RID_OK) return st;
+  const int64_t rem = h->n_pushed - h->n_updates * h->t;
+  if (rem > 0 && (st = run_update(h, (int)rem)) != RID_OK) return st;
+  h->finalized = true;
+  return RID_OK;
+}
+
+rid_status rid_reset(rid_stream* h) {
+  if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  if (h->failed) return fail(h, RID_ESTATE, "stream failed");
+  RID_HIP(h, hipStreamSynchronize(h->s));
+  const size_t ell = h->ell, t = h->t;
+  RID_HIP(h, hipMemsetAsync(h->SST, 0, ell * ell * 8, h->s));
+  RID_HIP(h, hipMemsetAsync(h->G, 0, t * t * 8, h->s));
+  RID_HIP(h, hipMemsetAsync(h->recs, 0, sizeof(rid_update) * h->max_updates, h->s));
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc);
+  RID_HIP(h, hipGetLastError());
+  h->n_pushed = h->n_sketched = h->n_uploaded = h->n_updates = h->last_nobs = 0;
+  h->finalized = false;
+  return RID_OK;
+}
+
+static rid_status getter_prologue(rid_stream* h) {
+  if (h->failed) return fail(h, RID_ESTATE, "stream failed");
+  rid_status st = flush_all(h);
+  if (st != RID_OK) return st;
+  return sync_check(h);
+}
+
+rid_status rid_select(rid_stream* h, int64_t* J, int32_t cap, int32_t* t_out) {
+  if (!h || !J || !t_out) return fail(h, RID_EINVAL, "null argument");
+  if (cap < h->t) return fail(h, RID_EINVAL, "cap < t");
+  rid_status st = getter_prologue(h);
+  if (st != RID_OK) return st;
+  if (h->n_updates == 0) return fail(h, RID_ESTATE, "no update has run yet");
+  RID_HIP(h, hipMemcpy(J, h->J, sizeof(int64_t) * h->t, hipMemcpyDeviceToHost));
+  *t_out = h->t;
+  return RID_OK;
+}
+
+rid_status rid_coefficients(rid_stream* h, double* P, int64_t ldp, int64_t cap_cols, int64_t* n_cols,
+                            uint32_t where) {
+  if (!h || !P || !n_cols) return fail(h, RID_EINVAL, "null argument");
+  if (ldp < h->t || (where != RID_HOST && where != RID_DEVICE)) return fail(h, RID_EINVAL, "bad ldp or where");
+  rid_status st = getter_prologue(h);
+  if (st != RID_OK) return st;
+  if (h->n_updates == 0) return fail(h, RID_ESTATE, "no update has run yet");
+  if (cap_cols < h->last_nobs) return fail(h, RID_EINVAL, "cap_cols smaller than the covered columns");
+  *n_cols = h->last_nobs;
+  RID_HIP(h, hipMemcpy2D(P, ldp * 8, h->P, (size_t)h->t * 8, (size_t)h->t * 8, h->last_nobs,
+                         where == RID_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice));
+  return RID_OK;
+}
+
+rid_status rid_error_estimate(rid_stream* h, rid_error* e) {
+  if (!h || !e) return fail(h, RID_EINVAL, "null argument");
+  rid_status st = getter_prologue(h);
+  if (st != RID_OK) return st;
+  if (h->n_updates == 0) return fail(h, RID_ESTATE, "no update has run yet");
+  rid_update r;
+  RID_HIP(h, hipMemcpy(&r, h->recs + (h->n_updates - 1), sizeof(r), hipMemcpyDeviceToHost));
+  e->E2 = r.E2;
+  e->E_abs = sqrt(r.E2 > 0.0 ? r.E2 : 0.0);
+  e->rel = r.F > 0.0 ? e->E_abs / sqrt(r.F) : 0.0;
+  e->F = r.F;
+  e->n_obs = r.n_obs;
+  e->update = r.update;
+  return RID_OK;
+}
+
+rid_status rid_reconstruct(rid_stream* h, int64_t j0, int32_t c, void* d_out, int64_t ld) {
+  if (!h || (!d_out && c > 0)) return fail(h, RID_EINVAL, "null argument");
+  if (h->failed) return fail(h, RID_ESTATE, "stream failed");
+  if (h->n_updates == 0) return fail(h, RID_ESTATE, "no update has run yet");
+  if (j0 < 0 || c < 0 || j0 + c > h->last_nobs || ld < h->m)
+    return fail(h, RID_EINVAL, "columns outside the covered range or ld < m");
+  if (c == 0) return RID_OK;
+  dim3 grid((unsigned)((h->m + 255) / 256), (unsigned)((c + 15) / 16));
+  if (h->data_f64)
+    hipLaunchKernelGGL(reconstruct_kernel<double>, grid, dim3(256), 0, h->s,
+                       reinterpret_cast<const double*>(h->cpool), h->ldc, h->P, h->t, h->J, h->m, j0, c,
+                       reinterpret_cast<double*>(d_out), ld);
+  else
+    hipLaunchKernelGGL(reconstruct_kernel<float>, grid, dim3(256), 0, h->s,
+                       reinterpret_cast<const float*>(h->cpool), h->ldc, h->P, h->t, h->J, h->m, j0, c,
+                       reinterpret_cast<float*>(d_out), ld);
+  RID_HIP(h, hipGetLastError());
+  return RID_OK;
+}
+
+rid_status rid_get_info(rid_stream* h, rid_info* info) {
+  if (!h || !info) return fail(h, RID_EINVAL, "null argument");
+  if (!h->failed) {
+    hipError_t e = hipStreamSynchronize(h->s);
+    if (e != hipSuccess) fail(h, RID_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  }
+  info->n_pushed = h->n_pushed;
+  info->n_sketched = h->n_sketched;
+  info->n_updates = h->n_updates;
+  info->release_watermark = h->failed ? 0 : std::min(h->n_updates * h->t, h->n_sketched);
+  if (h->finalized && !h->failed) info->release_watermark = h->n_pushed;
+  info->failed = h->failed ? 1 : 0;
+  info->finalized = h->finalized ? 1 : 0;
+  info->last_status = h->last_status;
+  info->reserved0 = 0;
+  info->device_bytes = (int64_t)h->dev_bytes;
+  return RID_OK;
+}
+
+rid_status rid_get_update(rid_stream* h, int64_t u, rid_update* rec, int64_t* J_out, double* tau_C,
+                          double* tau_D) {
+  if (!h || !rec) return fail(h, RID_EINVAL, "null argument");
+  rid_status st = getter_prologue(h);
+  if (st != RID_OK) return st;
+  if (u < 0 || u >= h->n_updates) return fail(h, RID_EINVAL, "update index out of range");
+  RID_HIP(h, hipMemcpy(rec, h->recs + u, sizeof(*rec), hipMemcpyDeviceToHost));
+  if (J_out) RID_HIP(h, hipMemcpy(J_out, h->J_hist + u * h->t, sizeof(int64_t) * h->t, hipMemcpyDeviceToHost));
+  if (tau_C) RID_HIP(h, hipMemcpy(tau_C, h->tauC_hist + u * h->t, sizeof(double) * h->t, hipMemcpyDeviceToHost));
+  if (tau_D) RID_HIP(h, hipMemcpy(tau_D, h->tauD_hist + u * h->t, sizeof(double) * rec->count, hipMemcpyDeviceToHost));
+  return RID_OK;
+}
+
+rid_status rid_debug_state(rid_stream* h, double* S, int64_t lds, int64_t cap_cols, int64_t* n_cols,
+                           double* colsq, double* G) {
+  if (!h || !n_cols) return fail(h, RID_EINVAL, "null argument");
+  rid_status st = getter_prologue(h);
+  if (st != RID_OK) return st;
+  *n_cols = h->n_sketched;
+  if (S) {
+    if (lds < h->ell || cap_cols < h->n_sketched) return fail(h, RID_EINVAL, "S too small");
+    if (h->n_sketched > 0)
+      RID_HIP(h, hipMemcpy2D(S, lds * 8, h->S, (size_t)h->ell * 8, (size_t)h->ell * 8, h->n_sketched,
+                             hipMemcpyDeviceToHost));
+  }
+  if (colsq && h->n_sketched > 0)
+    RID_HIP(h, hipMemcpy(colsq, h->colsq, sizeof(double) * h->n_sketched, hipMemcpyDeviceToHost));
+  if (G) RID_HIP(h, hipMemcpy(G, h->G, sizeof(double) * h->t * h->t, hipMemcpyDeviceToHost));
+  return RID_OK;
+}
+
+rid_status rid_profile_enable(rid_stream* h, int32_t on) {
+  if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  RID_HIP(h, hipStreamSynchronize(h->s));
+  for (auto& mk : h->marks) {
+    h->event_pool.push_back(mk.a);
+    h->event_pool.push_back(mk.b);
+  }
+  h->marks.clear();
+  h->profiling = on != 0;
+  return RID_OK;
+}
+
+rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
+  if (!h || !p) return fail(h, RID_EINVAL, "null argument");
+  RID_HIP(h, hipStreamSynchronize(h->s));
+  memset(p, 0, sizeof(*p));
+  for (auto& mk : h->marks) {
+    float ms = 0.0f;
+    RID_HIP(h, hipEventElapsedTime(&ms, mk.a, mk.b));
+    switch (mk.kind) {
+      case 0: p->sketch_ms += ms; p->sketch_launches += 1; p->sketch_bytes += mk.bytes; break;
+      case 1: p->reduce_ms += ms; break;
+      case 2: p->update_ms += ms; break;
+      default: {
+        // the Gram phase reads every occupied basis column once and copies
+        // the new ones in (one read of the buffered column, one write)
+        rid_update r;
+        RID_HIP(h, hipMemcpy(&r, h->recs + (int64_t)mk.bytes, sizeof(r), hipMemcpyDeviceToHost));
+        p->update_ms += ms;
+        p->updates += 1;
+        p->gram_ms += ms;
+        if (r.n_filled > 0)
+          p->gram_bytes += (double)(r.n_occupied + 2 * r.n_filled) * (double)h->m * h->esize;
+        break;
+      }
+    }
+  }
+  return RID_OK;
+}
+
+rid_status rid_destroy(rid_stream* h) {
+  if (!h) return RID_EINVAL;
+  (void)hipStreamSynchronize(h->s);
+  (void)hipGetLastError();
+  free_all(h);
+  delete h;
+  return RID_OK;
+}
+
+rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64_t i0, int64_t count,
+                           void* d_out, int64_t ld, void* stream) {
+  if (prec < RID_SKETCH_F64 || prec > RID_SKETCH_BF16 || ell < 1 || ell > kMaxEll || i0 < 0 ||
+      count < 0 || (count > 0 && !d_out) || ld < ell)
+    return fail(nullptr, RID_EINVAL, "bad omega block arguments");
+  if (count == 0) return RID_OK;
+  hipError_t e = launch_omega_block(prec, omega_seed, ell, i0, count, d_out, ld,
+                                    reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(nullptr, RID_EDEVICE, hipGetErrorString(e));
+  return RID_OK;
+}
+
+}  // extern "C"

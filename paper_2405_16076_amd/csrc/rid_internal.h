@@ -1,0 +1,230 @@
+// Internal declarations of the streaming randomized-ID library (gfx950).
+//
+// Everything here is private to the library; the public interface is
+// include/rid.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rid.h"
+
+namespace rid {
+
+constexpr int kMaxEll = 512;     // sketch rows supported
+constexpr int kMaxT = 256;       // basis slots supported
+constexpr int kMTile = 64;       // test-matrix rows per sketch workgroup
+constexpr int kOmegaRowsPerCall = 8;
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit multiplies and xors, with a Weyl key schedule.
+// ---------------------------------------------------------------------------
+struct Words4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n3 = (uint32_t)p0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+// Counter word 3 of each random stream.
+constexpr uint32_t kDomainOmega = 0;
+constexpr uint32_t kDomainDecision = 1;
+constexpr uint32_t kPruneDraw = 0xFFFFFFFFu;
+
+// Uniform on [0,1) with 53 bits: ((x0 >> 5) 2^26 + (x1 >> 6)) 2^-53, exact.
+__device__ __forceinline__ double uniform53(uint32_t x0, uint32_t x1) {
+  return ((double)(x0 >> 5) * 67108864.0 + (double)(x1 >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+// The decision uniform of draw (u, slot, r) of the prune/fill step.
+__device__ __forceinline__ double decision_uniform(uint64_t seed, uint32_t u, uint32_t slot,
+                                                   uint32_t r) {
+  Words4 w = philox4x32_10(u, slot, r, kDomainDecision, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return uniform53(w.x, w.y);
+}
+
+// ---------------------------------------------------------------------------
+// The test matrix Omega.  Entry (r, i): the Philox call with counter
+// (i mod 2^32, i / 2^32, r / 8, 0) yields four words; word p gives a Box-Muller
+// pair from the 16-bit uniforms u1 = (lo16 + 1) / 2^16 in (0,1] and
+// u2 = hi16 / 2^16 in [0,1): z_{2p} = R cos(2 pi u2), z_{2p+1} = R sin(2 pi u2),
+// R = sqrt(-2 ln u1); Omega(r, i) = z_{r mod 8}.
+// ---------------------------------------------------------------------------
+
+// Binary32 evaluation with the hardware transcendentals: v_log_f32 is log2,
+// v_sin_f32 / v_cos_f32 take their argument in turns.  u1 and u2 are exact
+// in binary32.
+__device__ __forceinline__ void box_muller16_f32(uint32_t w, float& z0, float& z1) {
+  const float u1 = (float)((w & 0xFFFFu) + 1u) * (1.0f / 65536.0f);
+  const float u2 = (float)(w >> 16) * (1.0f / 65536.0f);
+  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  z0 = rad * __builtin_amdgcn_cosf(u2);
+  z1 = rad * __builtin_amdgcn_sinf(u2);
+}
+
+// Binary32 evaluation with the correctly rounded square root and the
+// accurate device-library log and sincospi (used by the binary32 form, whose
+// sketch error is otherwise dominated by the hardware approximations).
+__device__ __forceinline__ void box_muller16_f32_accurate(uint32_t w, float& z0, float& z1) {
+  const float u1 = (float)((w & 0xFFFFu) + 1u) * (1.0f / 65536.0f);
+  const float u2 = (float)(w >> 16) * (1.0f / 65536.0f);
+  const float rad = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
+__device__ __forceinline__ void box_muller16_f64(uint32_t w, double& z0, double& z1) {
+  const double u1 = (double)((w & 0xFFFFu) + 1u) * (1.0 / 65536.0);
+  const double u2 = (double)(w >> 16) * (1.0 / 65536.0);
+  const double rad = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
+// Eight consecutive test-matrix rows 8g..8g+7 at data row i.
+__device__ __forceinline__ void omega8_f32(uint64_t seed, uint64_t i, uint32_t g, float z[8]) {
+  Words4 w = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), g, kDomainOmega, (uint32_t)seed,
+                           (uint32_t)(seed >> 32));
+  box_muller16_f32(w.x, z[0], z[1]);
+  box_muller16_f32(w.y, z[2], z[3]);
+  box_muller16_f32(w.z, z[4], z[5]);
+  box_muller16_f32(w.w, z[6], z[7]);
+}
+
+__device__ __forceinline__ void omega8_f32_accurate(uint64_t seed, uint64_t i, uint32_t g,
+                                                    float z[8]) {
+  Words4 w = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), g, kDomainOmega, (uint32_t)seed,
+                           (uint32_t)(seed >> 32));
+  box_muller16_f32_accurate(w.x, z[0], z[1]);
+  box_muller16_f32_accurate(w.y, z[2], z[3]);
+  box_muller16_f32_accurate(w.z, z[4], z[5]);
+  box_muller16_f32_accurate(w.w, z[6], z[7]);
+}
+
+__device__ __forceinline__ void omega8_f64(uint64_t seed, uint64_t i, uint32_t g, double z[8]) {
+  Words4 w = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), g, kDomainOmega, (uint32_t)seed,
+                           (uint32_t)(seed >> 32));
+  box_muller16_f64(w.x, z[0], z[1]);
+  box_muller16_f64(w.y, z[2], z[3]);
+  box_muller16_f64(w.z, z[4], z[5]);
+  box_muller16_f64(w.w, z[6], z[7]);
+}
+
+// Round-to-nearest-even binary32 -> bfloat16 bits (finite inputs).
+__device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Device-resident state of one stream (one allocation, read and written by the
+// update kernels; the host never reads it between updates).
+// ---------------------------------------------------------------------------
+struct DevScalars {
+  double F;            // ||A_obs||_F^2 of the observed columns
+  double lam;          // ridge parameter of the running update
+  double shift;        // l * lam
+  int32_t skip;        // 1 when the running update skips selection (F == 0)
+  int32_t nonfinite;   // 1 once a non-finite snapshot value was seen
+  int32_t n_new;       // slots filled by the running update
+  int32_t n_occ;       // occupied slots after the running update
+  int32_t rank;        // numerical rank of Omega A_J in the running update
+  int32_t pad0;
+  int32_t new_slot[kMaxT];   // slots filled by the running update
+  int32_t new_src[kMaxT];    // their position in the buffer
+  int32_t occ_slot[kMaxT];   // occupied slots in slot order
+};
+
+struct SketchArgs {
+  const uint64_t* colptr;  // device address of every pushed column, by global index
+  int64_t c0;              // first global column of the batch
+  int32_t b;               // columns in the batch
+  int32_t b_max;           // column stride of a partial block
+  int64_t m;               // rows per snapshot
+  int64_t slab_rows;       // rows per slab (multiple of 32)
+  int32_t n_slabs, n_mt, n_nt, ell_pad;
+  uint64_t seed;
+  void* part;              // [n_slabs][b_max][ell_pad] float (double for F64)
+  double* normpart;        // [n_slabs][b_max]
+};
+
+struct UpdArgs {
+  int ell, k, t, n1, n2;
+  int64_t u;           // update index
+  int64_t c0;          // first column of the buffer
+  int cnt;             // buffered columns
+  int64_t n_obs;       // observed columns after the buffer
+  double fill_mult;    // c (k ln k + k ln(1/delta)/eps) / t
+  double ridge_floor;
+  uint64_t select_seed;
+  int64_t m, ldc;      // rows and column-pool stride
+  int data_f64;
+  // state
+  double* S;           // l x n_max
+  double* colsq;
+  double* SST;         // l x l
+  double* W;           // l x l tridiagonalisation work (reflectors below the subdiagonal)
+  double* hv;          // per-reflector tau (l), diag d (l), offdiag e (l), Dinv (l), L (l)
+  int64_t* J;          // t
+  double* tau_old;     // t
+  double* tauC;        // t (running update)
+  double* tauD;        // kMaxT (running update)
+  int64_t* J_hist;     // [update][t]
+  double* tauC_hist;   // [update][t]
+  double* tauD_hist;   // [update][t]
+  const uint64_t* colptr;
+  void* cpool;         // m x t columns, stride ldc
+  double* G;           // t x t
+  double* gpart;       // gram partials
+  int gslabs;
+  int64_t gslab_rows;
+  double* QR;          // l x t
+  double* qr_tau;      // t
+  double* P;           // t x n_max
+  double* Y;           // l x t  (S P^T)
+  double* PPt;         // t x t
+  double* hw;          // NA-Hutch++ work
+  DevScalars* sc;
+  rid_update* recs;
+};
+
+// launchers (sketch.hip, update.hip)
+int sketch_cols_per_wg(int prec);
+hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s);
+hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, int ell, double* S, double* colsq,
+                                int32_t* nonfinite, hipStream_t s);
+hipError_t launch_omega_block(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,
+                              void* out, int64_t ld, hipStream_t s);
+hipError_t launch_update_select(const UpdArgs& a, hipStream_t s);
+hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
+hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s);
+size_t hutch_work_doubles();
+
+}  // namespace rid

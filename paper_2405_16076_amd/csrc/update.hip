@@ -1,0 +1,827 @@
+// The per-update phase of Alg. 3 (every t buffered columns), in binary64:
+//   sst_update     SS^T += S_u S_u^T, F += sum ||a_j||^2     (Alg. 3 steps 11, 13)
+//   tridiag        Householder tridiagonalisation of SS^T, the top min(k, l)
+//                  eigenvalues by Sturm bisection -> ||S_k||^2, the ridge lam,
+//                  and the LDL^T factors of T + l*lam*I      (eq. sketch_ridge_leverage_score)
+//   scores         tau = s^T (SS^T + l*lam I)^{-1} s for the basis slots and the
+//                  buffered columns (Alg. 3 function, steps 17-18)
+//   select         prune / fill draws (Alg. 3 steps 19-27)
+//   copy_new/gram  new basis columns into the column pool and their Gram entries
+//                  G = A_J^T A_J (Alg. 5 step 1, reused by Alg. 8 step 1)
+//   alg4_qr/apply  P = (Omega A_J)^+ (Omega A_obs) by Householder QR (Alg. 4)
+//   hutch_*        NA-Hutch++ estimate of ||A_obs - A_J P||_F^2 (Alg. 8)
+#include "rid_internal.h"
+
+namespace rid {
+
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Block-wide sum; every thread gets the total.  red must hold blockDim/64 doubles.
+__device__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double tot = 0.0;
+  for (int i = 0; i < nw; ++i) tot += red[i];  // fixed order
+  return tot;
+}
+
+// ---------------------------------------------------------------------------
+// SS^T += S_u S_u^T, F and the start of the update record.
+// ---------------------------------------------------------------------------
+__global__ void sst_update_kernel(UpdArgs a) {
+  const int r1 = blockIdx.x * 16 + threadIdx.x;
+  const int r2 = blockIdx.y * 16 + threadIdx.y;
+  if (r1 < a.ell && r2 < a.ell) {
+    double s = a.SST[(int64_t)r2 * a.ell + r1];
+    for (int c = 0; c < a.cnt; ++c) {
+      const double* col = a.S + (a.c0 + c) * a.ell;
+      s = fma(col[r1], col[r2], s);
+    }
+    a.SST[(int64_t)r2 * a.ell + r1] = s;
+  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    double F = a.sc->F;
+    for (int c = 0; c < a.cnt; ++c) F += a.colsq[a.c0 + c];
+    a.sc->F = F;
+    a.sc->skip = (F > 0.0) ? 0 : 1;
+    rid_update* rec = a.recs + a.u;
+    rec->update = a.u;
+    rec->n_obs = a.n_obs;
+    rec->count = a.cnt;
+    rec->F = F;
+    rec->flags = (F > 0.0) ? 0 : RID_UPD_SKIPPED;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tridiagonalisation + bisection + LDL^T.  One workgroup of 1024 threads.
+// hv layout: [0,l) reflector tau, [l,2l) d, [2l,3l) e, [3l,4l) Dinv, [4l,5l) L,
+// [5l,6l) top eigenvalues (descending).
+// ---------------------------------------------------------------------------
+__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(1024) void tridiag_kernel(UpdArgs a) {
+  __shared__ double v[kMaxEll];
+  __shared__ double p[kMaxEll];
+  __shared__ double red[16];
+  __shared__ double e2s[kMaxEll];
+  __shared__ double ds[kMaxEll];
+  const int n = a.ell, tid = threadIdx.x, nth = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
+  double* W = a.W;
+  double* htau = a.hv;
+  double* d = a.hv + n;
+  double* e = a.hv + 2 * n;
+  double* Dinv = a.hv + 3 * n;
+  double* L = a.hv + 4 * n;
+  double* mu = a.hv + 5 * n;
+  if (a.sc->skip) {
+    if (tid == 0) {
+      a.sc->lam = 0.0;
+      a.sc->shift = 0.0;
+      a.recs[a.u].sk2 = 0.0;
+      a.recs[a.u].lam = 0.0;
+    }
+    return;
+  }
+  for (int64_t i = tid; i < (int64_t)n * n; i += nth) W[i] = a.SST[i];
+  __syncthreads();
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;           // order of the trailing block
+    double* x = W + (int64_t)j * n + j + 1;   // column j, rows j+1..n-1
+    double part = 0.0;
+    for (int i = 1 + tid; i < m; i += nth) part += x[i] * x[i];
+    const double xn2 = block_sum(part, red);
+    const double alpha = x[0];
+    double tau = 0.0, beta = alpha;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      const double scal = 1.0 / (alpha - beta);
+      for (int i = tid; i < m; i += nth) v[i] = (i == 0) ? 1.0 : x[i] * scal;
+    } else {
+      for (int i = tid; i < m; i += nth) v[i] = (i == 0) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      htau[j] = tau;
+      e[j] = beta;
+      d[j] = W[(int64_t)j * n + j];
+    }
+    for (int i = 1 + tid; i < m; i += nth) x[i] = v[i];  // store the reflector
+    if (tau != 0.0) {
+      // p = tau * A22 v (A22 symmetric: its row i is its column i, contiguous)
+      double* A22 = W + (int64_t)(j + 1) * n + (j + 1);
+      for (int i = wv; i < m; i += nw) {
+        const double* col = A22 + (int64_t)i * n;
+        double s = 0.0;
+        for (int kk = lane; kk < m; kk += 64) s = fma(col[kk], v[kk], s);
+        s = wave_sum(s);
+        if (lane == 0) p[i] = tau * s;
+      }
+      __syncthreads();
+      double pv = 0.0;
+      for (int i = tid; i < m; i += nth) pv += p[i] * v[i];
+      const double K = 0.5 * tau * block_sum(pv, red);
+      for (int i = tid; i < m; i += nth) p[i] = p[i] - K * v[i];  // p -> w
+      __syncthreads();
+      // A22 -= v w^T + w v^T
+      for (int64_t idx = tid; idx < (int64_t)m * m; idx += nth) {
+        const int col = (int)(idx / m), row = (int)(idx % m);
+        A22[(int64_t)col * n + row] -= v[row] * p[col] + p[row] * v[col];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      d[n - 2] = W[(int64_t)(n - 2) * n + n - 2];
+      e[n - 2] = W[(int64_t)(n - 2) * n + n - 1];
+      htau[n - 2] = 0.0;
+    }
+    d[n - 1] = W[(int64_t)(n - 1) * n + n - 1];
+    e[n - 1] = 0.0;
+    htau[n - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nth) {
+    ds[i] = d[i];
+    e2s[i] = (i + 1 < n) ? e[i] * e[i] : 0.0;
+  }
+  __syncthreads();
+  // Gershgorin interval and pivot threshold
+  double lo = 0.0, hi = 0.0, emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < n) ? fabs(e[i]) : 0.0);
+    lo = (i == 0) ? ds[i] - r : fmin(lo, ds[i] - r);
+    hi = (i == 0) ? ds[i] + r : fmax(hi, ds[i] + r);
+    emax2 = fmax(emax2, e2s[i]);
+  }
+  const double bnd = fmax(fabs(lo), fabs(hi));
+  lo -= 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
+  hi += 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  const int kk = min(a.k, n);
+  for (int idx = tid; idx < kk; idx += nth) {
+    const int target = n - 1 - idx;  // ascending index of the idx-th largest
+    double aa = lo, bb = hi;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (aa + bb);
+      if (mid <= aa || mid >= bb) break;
+      if (bb - aa <= 2.220446049250313e-16 * fmax(fabs(aa), fabs(bb))) break;
+      if (sturm_count(ds, e2s, n, mid, pivmin) <= target)
+        aa = mid;
+      else
+        bb = mid;
+    }
+    mu[idx] = 0.5 * (aa + bb);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sk2 = 0.0;
+    for (int i = 0; i < kk; ++i) sk2 += mu[i];
+    const double F = a.sc->F;
+    const double lam = fmax((F - sk2 / n) / a.k, a.ridge_floor * F / a.k);
+    const double shift = n * lam;
+    a.sc->lam = lam;
+    a.sc->shift = shift;
+    a.recs[a.u].sk2 = sk2;
+    a.recs[a.u].lam = lam;
+    // T + shift I = L D L^T (T symmetric positive definite for shift > 0)
+    double Di = ds[0] + shift;
+    Dinv[0] = 1.0 / Di;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double li = e[i] / Di;
+      L[i] = li;
+      Di = ds[i + 1] + shift - li * e[i];
+      Dinv[i + 1] = 1.0 / Di;
+    }
+    L[n - 1] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Scores.  One wave per scored column: y = Q^T s (reflectors in order), then
+// tau = sum_i z_i^2 / D_i with L z = y.
+// Items [0, t): basis slots; items [t, t + cnt): buffered columns.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void scores_kernel(UpdArgs a) {
+  __shared__ double y[kMaxEll];
+  const int item = blockIdx.x, lane = threadIdx.x, n = a.ell;
+  if (a.sc->skip) return;
+  int64_t col;
+  if (item < a.t) {
+    col = a.J[item];
+    if (col < 0) {
+      if (lane == 0) {
+        a.tauC[item] = __longlong_as_double(0x7FF8000000000000LL);
+        a.tauC_hist[a.u * a.t + item] = __longlong_as_double(0x7FF8000000000000LL);
+      }
+      return;
+    }
+  } else {
+    col = a.c0 + (item - a.t);
+  }
+  const double* s = a.S + col * n;
+  for (int i = lane; i < n; i += 64) y[i] = s[i];
+  __syncthreads();
+  const double* htau = a.hv;
+  for (int j = 0; j + 2 < n; ++j) {
+    const double tj = htau[j];
+    if (tj == 0.0) continue;
+    const double* vcol = a.W + (int64_t)j * n;  // v = [1, W[j+2.., j]] on rows j+1..
+    double part = 0.0;
+    for (int i = j + 1 + lane; i < n; i += 64) part = fma((i == j + 1) ? 1.0 : vcol[i], y[i], part);
+    const double g = tj * wave_sum(part);
+    __syncthreads();
+    for (int i = j + 1 + lane; i < n; i += 64) y[i] -= g * ((i == j + 1) ? 1.0 : vcol[i]);
+    __syncthreads();
+  }
+  if (lane == 0) {
+    const double* Dinv = a.hv + 3 * n;
+    const double* L = a.hv + 4 * n;
+    double z = y[0];
+    double tau = z * z * Dinv[0];
+    for (int i = 1; i < n; ++i) {
+      z = y[i] - L[i - 1] * z;
+      tau = fma(z * z, Dinv[i], tau);
+    }
+    if (item < a.t) {
+      const double tc = fmin(a.tau_old[item], tau);
+      a.tauC[item] = tc;
+      a.tauC_hist[a.u * a.t + item] = tc;
+    } else {
+      a.tauD[item - a.t] = tau;
+      a.tauD_hist[a.u * a.t + (item - a.t)] = tau;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prune / fill.  One wave; slots in order; the fill scan evaluates 64
+// candidate draws at once and takes the first success.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void select_kernel(UpdArgs a) {
+  __shared__ int used[kMaxT];
+  const int lane = threadIdx.x;
+  DevScalars* sc = a.sc;
+  for (int r = lane; r < kMaxT; r += 64) used[r] = 0;
+  __syncthreads();
+  int n_new = 0, n_pruned = 0;
+  if (!sc->skip) {
+    for (int i = 0; i < a.t; ++i) {
+      int64_t Ji = a.J[i];
+      if (Ji >= 0) {
+        const double p = 1.0 - a.tauC[i] / a.tau_old[i];
+        const double U = decision_uniform(a.select_seed, (uint32_t)a.u, (uint32_t)i, kPruneDraw);
+        if (U < p) {
+          Ji = -1;
+          ++n_pruned;
+          if (lane == 0) {
+            a.J[i] = -1;
+            a.tau_old[i] = 1.0;
+          }
+        } else if (lane == 0) {
+          a.tau_old[i] = a.tauC[i];
+        }
+      }
+      if (Ji < 0) {
+        for (int base = 0; base < a.cnt; base += 64) {
+          const int r = base + lane;
+          bool hit = false;
+          if (r < a.cnt && !used[r]) {
+            const double q = fmin(1.0, a.fill_mult * a.tauD[r]);
+            hit = decision_uniform(a.select_seed, (uint32_t)a.u, (uint32_t)i, (uint32_t)r) < q;
+          }
+          const uint64_t ball = __ballot(hit);
+          if (ball) {
+            const int rs = base + __ffsll((unsigned long long)ball) - 1;
+            if (lane == 0) {
+              a.J[i] = a.c0 + rs;
+              a.tau_old[i] = a.tauD[rs];
+              used[rs] = 1;
+              sc->new_slot[n_new] = i;
+              sc->new_src[n_new] = rs;
+            }
+            __syncthreads();
+            ++n_new;
+            break;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (lane == 0) {
+    int n_occ = 0;
+    for (int i = 0; i < a.t; ++i) {
+      const int64_t Ji = a.J[i];
+      a.J_hist[a.u * a.t + i] = Ji;
+      if (Ji >= 0) sc->occ_slot[n_occ++] = i;
+    }
+    sc->n_new = n_new;
+    sc->n_occ = n_occ;
+    rid_update* rec = a.recs + a.u;
+    rec->n_pruned = n_pruned;
+    rec->n_filled = n_new;
+    rec->n_occupied = n_occ;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Copy the new basis columns into the column pool.
+// grid.y = new-slot index; blocks beyond n_new return.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void copy_new_kernel(UpdArgs a) {
+  const int q = blockIdx.y;
+  if (q >= a.sc->n_new) return;
+  const T* src = reinterpret_cast<const T*>(a.colptr[a.c0 + a.sc->new_src[q]]);
+  T* dst = reinterpret_cast<T*>(a.cpool) + (int64_t)a.sc->new_slot[q] * a.ldc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Gram partials: gpart[gslab][q][jj] = sum over the slab rows of
+// C(:, new_slot[q]) * C(:, occ_slot[jj]).  64 x 64 (q, jj) tile per workgroup,
+// 32-row chunks staged in LDS, binary64 accumulation of exact products.
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_kernel(UpdArgs a) {
+  constexpr int RC = 32;
+  __shared__ double tq[RC][65];
+  __shared__ double tj[RC][65];
+  const DevScalars* sc = a.sc;
+  const int n_new = sc->n_new, n_occ = sc->n_occ;
+  const int qt = blockIdx.y, jt = blockIdx.z, slab = blockIdx.x;
+  if (qt * 64 >= n_new || jt * 64 >= n_occ) return;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const T* C = reinterpret_cast<const T*>(a.cpool);
+  const int64_t r0 = (int64_t)slab * a.gslab_rows;
+  const int64_t r1 = min(a.m, r0 + a.gslab_rows);
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  // loader: thread -> tile column lc = tid / 4 (0..63), rows 8 (tid % 4) .. +8
+  const int lc = tid >> 2, lr = (tid & 3) * 8;
+  const int qg = qt * 64 + lc, jg = jt * 64 + lc;
+  const T* cq = (qg < n_new) ? C + (int64_t)sc->new_slot[qg] * a.ldc : nullptr;
+  const T* cj = (jg < n_occ) ? C + (int64_t)sc->occ_slot[jg] * a.ldc : nullptr;
+  for (int64_t k0 = r0; k0 < r1; k0 += RC) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t row = k0 + lr + j;
+      tq[lr + j][lc] = (cq && row < r1) ? (double)cq[row] : 0.0;
+      tj[lr + j][lc] = (cj && row < r1) ? (double)cj[row] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < RC; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = tq[kk][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = tj[kk][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* out = a.gpart + (int64_t)slab * a.t * a.t;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int q = qt * 64 + ty * 4 + i;
+    if (q >= n_new) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int jj = jt * 64 + tx * 4 + j;
+      if (jj < n_occ) out[(int64_t)q * a.t + jj] = acc[i][j];
+    }
+  }
+}
+
+// Zero the Gram rows/columns of empty slots, then write the new entries
+// (fixed-order sum over slabs), symmetrically.
+__global__ void gram_zero_kernel(UpdArgs a) {
+  const int i = blockIdx.x, j = threadIdx.x;
+  if (i >= a.t || j >= a.t) return;
+  if (a.J[i] < 0 || a.J[j] < 0) a.G[(int64_t)j * a.t + i] = 0.0;
+}
+
+__global__ void gram_reduce_kernel(UpdArgs a) {
+  const DevScalars* sc = a.sc;
+  const int q = blockIdx.x, jj = threadIdx.x + blockIdx.y * blockDim.x;
+  if (q >= sc->n_new || jj >= sc->n_occ) return;
+  double s = 0.0;
+  for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
+  const int si = sc->new_slot[q], sj = sc->occ_slot[jj];
+  a.G[(int64_t)sj * a.t + si] = s;
+  a.G[(int64_t)si * a.t + sj] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 4: Householder QR of Omega A_J (occupied slots in slot order), then
+// P = R^{-1} Q^T S column by column.  Columns whose pivot |R_ii| falls to
+// max(l, n) eps max|R| are dropped from the solve (flag RID_UPD_RANK_DEFICIENT).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void alg4_qr_kernel(UpdArgs a) {
+  __shared__ double red[16];
+  __shared__ double v[kMaxEll];
+  const int n = a.ell, tid = threadIdx.x, nth = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
+  DevScalars* sc = a.sc;
+  const int no = sc->n_occ;
+  double* A = a.QR;
+  for (int64_t idx = tid; idx < (int64_t)n * no; idx += nth) {
+    const int jj = (int)(idx / n), r = (int)(idx % n);
+    A[(int64_t)jj * n + r] = a.S[a.J[sc->occ_slot[jj]] * n + r];
+  }
+  __syncthreads();
+  for (int jj = 0; jj < no && jj < n; ++jj) {
+    double* x = A + (int64_t)jj * n + jj;
+    const int len = n - jj;
+    double part = 0.0;
+    for (int i = 1 + tid; i < len; i += nth) part += x[i] * x[i];
+    const double xn2 = block_sum(part, red);
+    const double alpha = x[0];
+    double tau = 0.0, beta = alpha;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      const double scal = 1.0 / (alpha - beta);
+      for (int i = tid; i < len; i += nth) v[i] = (i == 0) ? 1.0 : x[i] * scal;
+    } else {
+      for (int i = tid; i < len; i += nth) v[i] = (i == 0) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int i = 1 + tid; i < len; i += nth) x[i] = v[i];
+    if (tid == 0) {
+      x[0] = beta;
+      a.qr_tau[jj] = tau;
+    }
+    if (tau != 0.0) {
+      for (int c = jj + 1 + wv; c < no; c += nw) {
+        double* y = A + (int64_t)c * n + jj;
+        double s = 0.0;
+        for (int i = lane; i < len; i += 64) s = fma(v[i], y[i], s);
+        const double g = tau * wave_sum(s);
+        for (int i = lane; i < len; i += 64) y[i] -= g * v[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double rmax = 0.0;
+    const int nd = min(no, n);
+    for (int i = 0; i < nd; ++i) rmax = fmax(rmax, fabs(A[(int64_t)i * n + i]));
+    const double tol = (double)max(n, no) * 2.220446049250313e-16 * rmax;
+    int rank = 0;
+    for (int i = 0; i < nd; ++i) rank += (fabs(A[(int64_t)i * n + i]) > tol);
+    sc->rank = rank;
+    if (rank < no) a.recs[a.u].flags |= RID_UPD_RANK_DEFICIENT;
+  }
+}
+
+// One wave per observed column c: z = Q^T S(:, c), back substitution, scatter.
+__global__ __launch_bounds__(64) void alg4_apply_kernel(UpdArgs a) {
+  __shared__ double y[kMaxEll];
+  const int64_t c = blockIdx.x;
+  const int lane = threadIdx.x, n = a.ell;
+  const DevScalars* sc = a.sc;
+  const int no = min(sc->n_occ, n);
+  double* Pc = a.P + c * a.t;
+  for (int i = lane; i < a.t; i += 64) Pc[i] = 0.0;
+  if (no == 0) return;
+  const double* A = a.QR;
+  const double* s = a.S + c * n;
+  for (int i = lane; i < n; i += 64) y[i] = s[i];
+  __syncthreads();
+  for (int jj = 0; jj < no; ++jj) {
+    const double tj = a.qr_tau[jj];
+    if (tj == 0.0) continue;
+    const double* vc = A + (int64_t)jj * n;
+    double part = 0.0;
+    for (int i = jj + lane; i < n; i += 64) part = fma((i == jj) ? 1.0 : vc[i], y[i], part);
+    const double g = tj * wave_sum(part);
+    __syncthreads();
+    for (int i = jj + lane; i < n; i += 64) y[i] -= g * ((i == jj) ? 1.0 : vc[i]);
+    __syncthreads();
+  }
+  // R x = y(0:no), dropping columns with negligible pivots
+  double rmax = 0.0;
+  for (int i = 0; i < no; ++i) rmax = fmax(rmax, fabs(A[(int64_t)i * n + i]));
+  const double tol = (double)max(n, sc->n_occ) * 2.220446049250313e-16 * rmax;
+  for (int i = no - 1; i >= 0; --i) {
+    const double rii = A[(int64_t)i * n + i];
+    const double xi = (fabs(rii) > tol) ? y[i] / rii : 0.0;
+    __syncthreads();
+    for (int r = lane; r < i; r += 64) y[r] -= xi * A[(int64_t)i * n + r];
+    if (lane == 0) Pc[sc->occ_slot[i]] = xi;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// NA-Hutch++ (Alg. 8).  Large products first: Y = S P^T (l x t) and
+// PPt = P P^T (t x t), one thread per entry.
+// ---------------------------------------------------------------------------
+__global__ void hutch_prod_kernel(UpdArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = a.ell, t = a.t;
+  const int64_t nY = (int64_t)n * t, nPP = (int64_t)t * t;
+  if (idx < nY) {
+    const int r = (int)(idx % n), j = (int)(idx / n);
+    double s = 0.0;
+    for (int64_t c = 0; c < a.n_obs; ++c) s = fma(a.S[c * n + r], a.P[c * t + j], s);
+    a.Y[(int64_t)j * n + r] = s;
+  } else if (idx < nY + nPP) {
+    const int64_t q = idx - nY;
+    const int i = (int)(q % t), j = (int)(q / t);
+    double s = 0.0;
+    for (int64_t c = 0; c < a.n_obs; ++c) s = fma(a.P[c * t + i], a.P[c * t + j], s);
+    a.PPt[(int64_t)j * t + i] = s;
+  }
+}
+
+// The small part of Alg. 8 in one workgroup.  With the row blocks
+// [0,n1), [n1,n1+n2), [n1+n2,l) of S, of S_J = Omega A_J and of Y:
+//   K = Y1 SJ2^T, X = Y1 G Y2^T, A1 = Y1 SJ3^T, A2 = SJ3 Y2^T,
+//   term1 = tr(K^+ X), corr = tr(K^+ A1 A2), h = <Y3, SJ3>, gpp = <G, P P^T>.
+// K^+ is applied through a column-pivoted Householder QR of K^T truncated to
+// its numerical rank (max(n1, n2) eps |R_00|): K^- = Q_r R11^{-T} [I 0] Pi^T,
+// the pseudo-inverse when K has full row rank.
+__global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
+  __shared__ double red[16];
+  __shared__ double v[kMaxEll];
+  __shared__ double cn[kMaxEll];
+  __shared__ int perm[kMaxEll];
+  const int n = a.ell, t = a.t, n1 = a.n1, n2 = a.n2, n3 = a.ell - a.n1 - a.n2;
+  const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
+  const DevScalars* sc = a.sc;
+  rid_update* rec = a.recs + a.u;
+  const double F = sc->F;
+  // work layout
+  double* KT = a.hw;                                   // n2 x n1 (ld n2)
+  double* X = KT + (int64_t)kMaxEll * kMaxEll / 4;      // n1 x n2 (ld n1)
+  double* AA = X + (int64_t)kMaxEll * kMaxEll / 4;      // n1 x n2 (ld n1)
+  double* YG = AA + (int64_t)kMaxEll * kMaxEll / 4;     // n1 x t  (ld n1)
+  double* A1 = YG + (int64_t)kMaxEll * kMaxT;           // n1 x n3 (ld n1)
+  double* A2 = A1 + (int64_t)kMaxEll * kMaxEll / 4;     // n3 x n2 (ld n3)
+  double* SJ = A2 + (int64_t)kMaxEll * kMaxEll / 4;     // l x t   (ld l)
+  const double* Y = a.Y;
+  const double* G = a.G;
+  // gather S_J (zero columns for empty slots)
+  for (int64_t idx = tid; idx < (int64_t)n * t; idx += nth) {
+    const int j = (int)(idx / n), r = (int)(idx % n);
+    const int64_t Jj = a.J[j];
+    SJ[idx] = (Jj >= 0) ? a.S[Jj * n + r] : 0.0;
+  }
+  __syncthreads();
+  // h and gpp
+  double hp = 0.0, gp = 0.0;
+  for (int64_t idx = tid; idx < (int64_t)n3 * t; idx += nth) {
+    const int c = (int)(idx % n3), j = (int)(idx / n3);
+    hp = fma(Y[(int64_t)j * n + n1 + n2 + c], SJ[(int64_t)j * n + n1 + n2 + c], hp);
+  }
+  for (int64_t idx = tid; idx < (int64_t)t * t; idx += nth) gp = fma(G[idx], a.PPt[idx], gp);
+  const double h = block_sum(hp, red);
+  const double gpp = block_sum(gp, red);
+  double term1 = 0.0, corr = 0.0;
+  int trunc = 0;
+  if (n1 > 0 && n2 > 0) {
+    // KT(b, a) = K(a, b) = sum_j Y1(a, j) SJ2(b, j)
+    for (int64_t idx = tid; idx < (int64_t)n1 * n2; idx += nth) {
+      const int b = (int)(idx % n2), aa = (int)(idx / n2);
+      double s = 0.0;
+      for (int j = 0; j < t; ++j) s = fma(Y[(int64_t)j * n + aa], SJ[(int64_t)j * n + n1 + b], s);
+      KT[(int64_t)aa * n2 + b] = s;
+    }
+    // YG = Y1 G
+    for (int64_t idx = tid; idx < (int64_t)n1 * t; idx += nth) {
+      const int aa = (int)(idx % n1), j = (int)(idx / n1);
+      double s = 0.0;
+      for (int i = 0; i < t; ++i) s = fma(Y[(int64_t)i * n + aa], G[(int64_t)j * t + i], s);
+      YG[(int64_t)j * n1 + aa] = s;
+    }
+    // A1 = Y1 SJ3^T (n1 x n3), A2 = SJ3 Y2^T (n3 x n2)
+    for (int64_t idx = tid; idx < (int64_t)n1 * n3; idx += nth) {
+      const int aa = (int)(idx % n1), c = (int)(idx / n1);
+      double s = 0.0;
+      for (int j = 0; j < t; ++j) s = fma(Y[(int64_t)j * n + aa], SJ[(int64_t)j * n + n1 + n2 + c], s);
+      A1[(int64_t)c * n1 + aa] = s;
+    }
+    for (int64_t idx = tid; idx < (int64_t)n3 * n2; idx += nth) {
+      const int c = (int)(idx % n3), b = (int)(idx / n3);
+      double s = 0.0;
+      for (int j = 0; j < t; ++j) s = fma(SJ[(int64_t)j * n + n1 + n2 + c], Y[(int64_t)j * n + n1 + b], s);
+      A2[(int64_t)b * n3 + c] = s;
+    }
+    __syncthreads();
+    // X = YG Y2^T and AA = A1 A2 (n1 x n2)
+    for (int64_t idx = tid; idx < (int64_t)n1 * n2; idx += nth) {
+      const int aa = (int)(idx % n1), b = (int)(idx / n1);
+      double s = 0.0;
+      for (int j = 0; j < t; ++j) s = fma(YG[(int64_t)j * n1 + aa], Y[(int64_t)j * n + n1 + b], s);
+      X[(int64_t)b * n1 + aa] = s;
+      double s2 = 0.0;
+      for (int c = 0; c < n3; ++c) s2 = fma(A1[(int64_t)c * n1 + aa], A2[(int64_t)b * n3 + c], s2);
+      AA[(int64_t)b * n1 + aa] = s2;
+    }
+    for (int i = tid; i < n1; i += nth) perm[i] = i;
+    __syncthreads();
+    // column-pivoted Householder QR of KT (n2 x n1)
+    int rank = 0;
+    double r00 = 0.0;
+    const int nsteps = min(n1, n2);
+    for (int jj = 0; jj < nsteps; ++jj) {
+      // squared norms of the remaining columns, rows jj..n2-1 (recomputed)
+      for (int c = jj + wv; c < n1; c += nw) {
+        const double* col = KT + (int64_t)c * n2;
+        double s = 0.0;
+        for (int i = jj + lane; i < n2; i += 64) s = fma(col[i], col[i], s);
+        s = wave_sum(s);
+        if (lane == 0) cn[c] = s;
+      }
+      __syncthreads();
+      int piv = jj;
+      double best = cn[jj];
+      for (int c = jj + 1; c < n1; ++c)
+        if (cn[c] > best) {
+          best = cn[c];
+          piv = c;
+        }
+      if (jj == 0) r00 = sqrt(best);
+      if (!(sqrt(best) > (double)max(n1, n2) * 2.220446049250313e-16 * r00) || best == 0.0) break;
+      if (piv != jj) {
+        for (int i = tid; i < n2; i += nth) {
+          const double tmp = KT[(int64_t)jj * n2 + i];
+          KT[(int64_t)jj * n2 + i] = KT[(int64_t)piv * n2 + i];
+          KT[(int64_t)piv * n2 + i] = tmp;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          const int tp = perm[jj];
+          perm[jj] = perm[piv];
+          perm[piv] = tp;
+        }
+      }
+      double* x = KT + (int64_t)jj * n2 + jj;
+      const int len = n2 - jj;
+      double part = 0.0;
+      for (int i = 1 + tid; i < len; i += nth) part += x[i] * x[i];
+      const double xn2 = block_sum(part, red);
+      const double alpha = x[0];
+      double tau = 0.0, beta = alpha;
+      if (xn2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        const double scal = 1.0 / (alpha - beta);
+        for (int i = tid; i < len; i += nth) v[i] = (i == 0) ? 1.0 : x[i] * scal;
+      } else {
+        for (int i = tid; i < len; i += nth) v[i] = (i == 0) ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      for (int i = 1 + tid; i < len; i += nth) x[i] = v[i];
+      if (tid == 0) {
+        x[0] = beta;
+      }
+      if (tau != 0.0) {
+        for (int c = jj + 1 + wv; c < n1; c += nw) {
+          double* y = KT + (int64_t)c * n2 + jj;
+          double s = 0.0;
+          for (int i = lane; i < len; i += 64) s = fma(v[i], y[i], s);
+          const double g = tau * wave_sum(s);
+          for (int i = lane; i < len; i += 64) y[i] -= g * v[i];
+        }
+        // rows of X and AA: x^T <- x^T H  (apply H to the row vectors)
+        for (int rr = wv; rr < 2 * n1; rr += nw) {
+          double* row = (rr < n1) ? X + rr : AA + (rr - n1);
+          double s = 0.0;
+          for (int i = lane; i < len; i += 64) s = fma(v[i], row[(int64_t)(jj + i) * n1], s);
+          const double g = tau * wave_sum(s);
+          for (int i = lane; i < len; i += 64) row[(int64_t)(jj + i) * n1] -= g * v[i];
+        }
+      }
+      __syncthreads();
+      ++rank;
+    }
+    trunc = (rank < n1);
+    // Z = rows perm[0..rank) of (X Q)(:, 0:rank); W = R11^{-T} Z; trace(W)
+    // One thread per right-hand side b (column of Z) and matrix (X or AA).
+    double tr_x = 0.0, tr_a = 0.0;
+    for (int job = tid; job < 2 * rank; job += nth) {
+      const int b = job % rank;
+      const double* M = (job < rank) ? X : AA;
+      // forward substitution on R11^T w = Z(:, b), only w_b is needed, but
+      // w_b depends on w_0..w_{b-1}
+      double wv_local[kMaxEll / 4];
+      double wb = 0.0;
+      for (int i = 0; i <= b; ++i) {
+        double s = M[(int64_t)b * n1 + perm[i]];
+        for (int kq = 0; kq < i; ++kq) s -= KT[(int64_t)i * n2 + kq] * wv_local[kq];
+        const double wi = s / KT[(int64_t)i * n2 + i];
+        wv_local[i] = wi;
+        wb = wi;
+      }
+      if (job < rank)
+        tr_x += wb;
+      else
+        tr_a += wb;
+    }
+    term1 = block_sum(tr_x, red);
+    corr = block_sum(tr_a, red);
+  }
+  if (tid == 0) {
+    const double tr_est = term1 + (h - corr) / n3;
+    const double E2 = F - 2.0 * tr_est + gpp;
+    rec->E2 = E2;
+    rec->tr_est = tr_est;
+    rec->gpp = gpp;
+    rec->term1 = term1;
+    rec->h = h;
+    rec->corr = corr;
+    if (trunc) rec->flags |= RID_UPD_PINV_TRUNCATED;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+// scores and selection (Alg. 3 steps 11-27)
+hipError_t launch_update_select(const UpdArgs& a, hipStream_t s) {
+  {
+    dim3 grid((a.ell + 15) / 16, (a.ell + 15) / 16);
+    hipLaunchKernelGGL(sst_update_kernel, grid, dim3(16, 16), 0, s, a);
+  }
+  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(scores_kernel, dim3(a.t + a.cnt), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// new basis columns into the column pool and their Gram entries
+hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
+  {
+    const int nb = (int)std::min<int64_t>(1024, (a.m + 1023) / 1024);
+    if (a.data_f64)
+      hipLaunchKernelGGL(copy_new_kernel<double>, dim3(nb, a.t), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(copy_new_kernel<float>, dim3(nb, a.t), dim3(256), 0, s, a);
+  }
+  {
+    const int tt = (a.t + 63) / 64;
+    dim3 grid(a.gslabs, tt, tt);
+    if (a.data_f64)
+      hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(256), 0, s, a);
+  }
+  hipLaunchKernelGGL(gram_zero_kernel, dim3(a.t), dim3(kMaxT), 0, s, a);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(a.t, 1), dim3(kMaxT), 0, s, a);
+  return hipGetLastError();
+}
+
+// Alg. 4 and Alg. 8
+hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(alg4_qr_kernel, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(alg4_apply_kernel, dim3((unsigned)a.n_obs), dim3(64), 0, s, a);
+  {
+    const int64_t tot = (int64_t)(a.ell + a.t) * a.t;
+    hipLaunchKernelGGL(hutch_prod_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+  }
+  hipLaunchKernelGGL(hutch_small_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+size_t hutch_work_doubles() {
+  return (size_t)kMaxEll * kMaxEll / 4 * 5 + (size_t)kMaxEll * kMaxT * 2;
+}
+
+}  // namespace rid

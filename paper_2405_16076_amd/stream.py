@@ -1,0 +1,188 @@
+"""Python binding of the streaming randomized ID (include/rid.h).
+
+Argument marshalling only: every step runs in the HIP library.  Snapshot
+batches are CUDA tensors of shape (b, m) (each row one contiguous snapshot,
+i.e. b columns of A); results come back as numpy arrays or CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DTYPE = {torch.float32: L.RID_F32, torch.float64: L.RID_F64}
+PREC = {"f64": L.RID_SKETCH_F64, "f32": L.RID_SKETCH_F32, "bf16": L.RID_SKETCH_BF16}
+
+
+@dataclass
+class StreamConfig:
+    m: int
+    ell: int
+    k: int
+    t: int
+    n_max: int
+    dtype: torch.dtype = torch.float32
+    sketch: str = "f32"
+    omega_seed: int = 1
+    select_seed: int = 2
+    delta: float = 0.05
+    eps: float = 0.5
+    c_sample: float = 1.0
+    ridge_floor: float = 1e-8
+    hutch_n1: int = 0
+    hutch_n2: int = 0
+    lookahead: int = 0
+
+    def to_c(self):
+        c = L.rid_config()
+        L.check(L.lib().rid_config_default(C.byref(c)))
+        c.m, c.ell, c.k, c.t, c.n_max = self.m, self.ell, self.k, self.t, self.n_max
+        c.data_dtype = _DTYPE[self.dtype]
+        c.sketch_prec = PREC[self.sketch]
+        c.omega_seed, c.select_seed = self.omega_seed, self.select_seed
+        c.delta, c.eps, c.c_sample, c.ridge_floor = self.delta, self.eps, self.c_sample, self.ridge_floor
+        c.hutch_n1, c.hutch_n2, c.lookahead = self.hutch_n1, self.hutch_n2, self.lookahead
+        return c
+
+
+def _stream_handle(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class OnlineRID:
+    """One streaming randomized ID on one GPU (Alg. 3 with Alg. 4 and Alg. 8)."""
+
+    def __init__(self, cfg: StreamConfig, device="cuda:0"):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self._h = C.c_void_p()
+        ccfg = cfg.to_c()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rid_init_stream(C.byref(ccfg), _stream_handle(self.device), C.byref(self._h)))
+        self._keep = []  # borrowed batches kept alive until release
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if self._h:
+            L.lib().rid_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        L.check(st, self._h)
+
+    # -- ingest --------------------------------------------------------------
+    def push(self, cols: torch.Tensor, borrow: bool = False):
+        """Push a (b, m) CUDA tensor of snapshots (row j = snapshot j)."""
+        if cols.dim() == 1:
+            cols = cols.unsqueeze(0)
+        if cols.device != self.device or cols.dtype != self.cfg.dtype or cols.shape[1] != self.cfg.m:
+            raise ValueError("snapshots must be a (b, m) tensor of the stream's dtype on its device")
+        if cols.stride(1) != 1:
+            raise ValueError("each snapshot must be contiguous")
+        flags = L.RID_BORROW if borrow else L.RID_COPY
+        self._check(L.lib().rid_push_snapshots(self._h, C.c_void_p(cols.data_ptr()), cols.stride(0),
+                                                cols.shape[0], flags))
+        if borrow:
+            self._keep.append(cols)
+
+    def flush(self):
+        self._check(L.lib().rid_flush(self._h))
+
+    def finalize(self):
+        self._check(L.lib().rid_finalize(self._h))
+
+    def reset(self):
+        self._check(L.lib().rid_reset(self._h))
+        self._keep = []
+
+    # -- results -------------------------------------------------------------
+    def select(self):
+        J = np.empty(self.cfg.t, dtype=np.int64)
+        t = C.c_int32()
+        self._check(L.lib().rid_select(self._h, J.ctypes.data_as(C.POINTER(C.c_int64)), self.cfg.t, C.byref(t)))
+        return J
+
+    def coefficients(self, device=False):
+        info = self.info()
+        cap = max(int(info.n_pushed), 1)
+        n = C.c_int64()
+        if device:
+            P = torch.empty((cap, self.cfg.t), dtype=torch.float64, device=self.device)
+            self._check(L.lib().rid_coefficients(self._h, C.c_void_p(P.data_ptr()), self.cfg.t, cap,
+                                                 C.byref(n), L.RID_DEVICE))
+            return P[:n.value].T
+        P = np.zeros((cap, self.cfg.t), dtype=np.float64)
+        self._check(L.lib().rid_coefficients(self._h, P.ctypes.data_as(C.c_void_p), self.cfg.t, cap,
+                                             C.byref(n), L.RID_HOST))
+        return np.ascontiguousarray(P[:n.value].T)
+
+    def error_estimate(self):
+        e = L.rid_error()
+        self._check(L.lib().rid_error_estimate(self._h, C.byref(e)))
+        return dict(E2=e.E2, E=e.E_abs, rel=e.rel, F=e.F, n_obs=e.n_obs, update=e.update)
+
+    def reconstruct(self, j0, c):
+        out = torch.empty((c, self.cfg.m), dtype=self.cfg.dtype, device=self.device)
+        self._check(L.lib().rid_reconstruct(self._h, j0, c, C.c_void_p(out.data_ptr()), self.cfg.m))
+        return out
+
+    def info(self):
+        i = L.rid_info()
+        self._check(L.lib().rid_get_info(self._h, C.byref(i)))
+        return i
+
+    def update(self, u):
+        rec = L.rid_update()
+        t = self.cfg.t
+        J = np.empty(t, dtype=np.int64)
+        tc = np.empty(t, dtype=np.float64)
+        td = np.empty(t, dtype=np.float64)
+        self._check(L.lib().rid_get_update(self._h, u, C.byref(rec), J.ctypes.data_as(C.c_void_p),
+                                           tc.ctypes.data_as(C.c_void_p), td.ctypes.data_as(C.c_void_p)))
+        d = {f: getattr(rec, f) for f, _ in L.rid_update._fields_}
+        d["J"] = J
+        d["tau_C"] = tc
+        d["tau_D"] = td[:rec.count].copy()
+        return d
+
+    def profile_enable(self, on=True):
+        self._check(L.lib().rid_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        p = L.rid_profile()
+        self._check(L.lib().rid_profile_read(self._h, C.byref(p)))
+        return {f: getattr(p, f) for f, _ in L.rid_profile._fields_}
+
+    def debug_state(self):
+        info = self.info()
+        n = int(info.n_pushed)
+        S = np.zeros((max(n, 1), self.cfg.ell), dtype=np.float64)
+        q = np.zeros(max(n, 1), dtype=np.float64)
+        G = np.zeros((self.cfg.t, self.cfg.t), dtype=np.float64)
+        nc = C.c_int64()
+        self._check(L.lib().rid_debug_state(self._h, S.ctypes.data_as(C.c_void_p), self.cfg.ell, max(n, 1),
+                                            C.byref(nc), q.ctypes.data_as(C.c_void_p),
+                                            G.ctypes.data_as(C.c_void_p)))
+        k = nc.value
+        return np.ascontiguousarray(S[:k].T), q[:k].copy(), G.T.copy()
+
+
+def omega_block(prec, seed, ell, i0, count, device="cuda:0"):
+    """Omega(0:ell, i0:i0+count) as the sketch form `prec` evaluates it."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    out = torch.empty((count, ell), dtype=dt, device=device)
+    with torch.cuda.device(torch.device(device)):
+        L.check(L.lib().rid_omega_block(PREC[prec], seed, ell, i0, count, C.c_void_p(out.data_ptr()), ell,
+                                        _stream_handle(torch.device(device))))
+    return out.T

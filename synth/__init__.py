@@ -157,3 +157,44 @@ def blobs(h, w, n, seed, n_blobs=6, rel_noise=0.01, dtype=np.float32):
         fr += rel_noise * rms * rng.standard_normal((h, w))
         out[t] = fr.reshape(-1)
     return out
+
+
+def channel_torch(nx, ny, nz, n, seed, fields=4, n_modes=300, device="cuda:0", rows_per_chunk=1 << 20,
+                  ld=None):
+    """The channel stream generated on a device with torch (same mode table and
+    recipe as ``channel``; evaluated in binary64, stored as binary32).  Returns
+    an (n, ld) tensor whose [:, :m] view holds the snapshots; ld defaults to m
+    rounded up to 64 elements."""
+    import torch
+    modes = channel_modes(seed, n_modes=n_modes, fields=fields)
+    npts = nx * ny * nz
+    m = fields * npts
+    ld = ld or (m + 63) // 64 * 64
+    dev = torch.device(device)
+    T = torch.tensor(channel_temporal(modes, n), dtype=torch.float64, device=dev).to(torch.float32)
+    x, y, z = channel_grid(nx, ny, nz)
+    xt = torch.tensor(x, dtype=torch.float64, device=dev)
+    yt = torch.tensor(y, dtype=torch.float64, device=dev)
+    zt = torch.tensor(z, dtype=torch.float64, device=dev)
+    kx = torch.tensor(modes["kx"], dtype=torch.float64, device=dev)
+    kz = torch.tensor(modes["kz"], dtype=torch.float64, device=dev)
+    beta = torch.tensor(modes["beta"], dtype=torch.float64, device=dev)
+    out = torch.empty((n, ld), dtype=torch.float32, device=dev)
+    for f in range(fields):
+        w0 = torch.tensor(modes["amp"] * modes["r"][f] * modes["fscale"][f], dtype=torch.float64, device=dev)
+        ph = torch.tensor(modes["phase"][f], dtype=torch.float64, device=dev)
+        for r0 in range(0, npts, rows_per_chunk):
+            r1 = min(npts, r0 + rows_per_chunk)
+            rows = torch.arange(r0, r1, device=dev)
+            ix = rows % nx
+            iz = (rows // nx) % nz
+            iy = rows // (nx * nz)
+            th = 2.0 * math.pi * (torch.outer(xt[ix], kx) + torch.outer(zt[iz], kz)) + ph[None, :]
+            ay = 1.0 - torch.abs(yt[iy])
+            w = w0[None, :] * torch.tanh(torch.outer(ay, beta))
+            mean = torch.tanh(8.0 * ay) if f == 0 else torch.zeros_like(ay)
+            B = torch.cat([w * torch.sin(th), -w * torch.cos(th), mean[:, None]], dim=1).to(torch.float32)
+            del th, w
+            out[:, f * npts + r0:f * npts + r1] = (B @ T).T
+            del B
+    return out

@@ -1,0 +1,182 @@
+"""Shared helpers of the GPU parity tests: run the HIP path and the oracle on
+the same seeded bytes and compare."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from oracle.rid import Config, OnlineRID as OracleRID
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(A_cols, ell, k, t, sketch, omega_seed, select_seed, batch=None, borrow=True, lookahead=0,
+            finalize=True, n1=0, n2=0):
+    """A_cols: numpy (n, m) (row j = snapshot j).  Returns the stream after
+    pushing every snapshot (and finalizing)."""
+    from paper_2405_16076_amd import OnlineRID, StreamConfig
+    n, m = A_cols.shape
+    dt = torch.float64 if A_cols.dtype == np.float64 else torch.float32
+    cfg = StreamConfig(m=m, ell=ell, k=k, t=t, n_max=n, dtype=dt, sketch=sketch, omega_seed=omega_seed,
+                       select_seed=select_seed, lookahead=lookahead, hutch_n1=n1, hutch_n2=n2)
+    s = OnlineRID(cfg)
+    # padded device copy: every column starts on a 64-byte boundary
+    ld = (m + 15) // 16 * 16
+    Xp = torch.zeros((n, ld), dtype=dt, device="cuda:0")
+    Xp[:, :m] = torch.from_numpy(A_cols).to("cuda:0")
+    X = Xp[:, :m]
+    batch = batch or n
+    for j0 in range(0, n, batch):
+        s.push(X[j0:j0 + batch], borrow=borrow)
+    if finalize:
+        s.finalize()
+    torch.cuda.synchronize()
+    s._data = X
+    return s
+
+
+def run_oracle(A_cols, ell, k, t, sketch, omega_seed, select_seed, finalize=True, n1=None, n2=None):
+    n, m = A_cols.shape
+    operand = {"f64": "f64", "f32": "f32", "bf16": "bf16"}[sketch]
+    cfg = Config(m=m, ell=ell, k=k, t=t, omega_seed=omega_seed, select_seed=select_seed, operand=operand,
+                 hutch_n1=n1, hutch_n2=n2)
+    o = OracleRID(cfg, n_max=n)
+    o.push(A_cols.T)
+    if finalize:
+        o.finalize()
+    return o
+
+
+def rel_fro(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
+
+
+def compare_updates(s, o, tol, log_prefix=""):
+    """J of every update must match exactly; tau within the per-update
+    tolerance.  Returns the worst tau ratio (diff / tolerance) and the smallest
+    decision margin."""
+    worst = 0.0
+    min_margin = math.inf
+    for u, rec in enumerate(o.records):
+        g = s.update(u)
+        mm = rec.min_margin()
+        min_margin = min(min_margin, mm)
+        if rec.tau_D is not None:
+            d = float(np.max(np.abs(g["tau_D"] - rec.tau_D) / np.maximum(np.abs(rec.tau_D), 1e-300)))
+            occ = ~np.isnan(rec.tau_C)
+            if occ.any():
+                d = max(d, float(np.max(np.abs(g["tau_C"][occ] - rec.tau_C[occ]) / np.abs(rec.tau_C[occ]))))
+            worst = max(worst, d / tol["tau"][u])
+            assert d <= tol["tau"][u], (u, d, tol["tau"][u])
+        if not np.array_equal(g["J"], rec.J):
+            raise AssertionError(f"{log_prefix} J differs at update {u}: min margin {mm:.3e}\n"
+                                 f" gpu {g['J']}\n orc {rec.J}")
+        assert g["n_filled"] == rec.n_filled and g["n_pruned"] == rec.n_pruned, (u, g, rec.n_filled, rec.n_pruned)
+    return worst, min_margin
+
+
+# Relative accuracy of the sketch S of each form against the oracle's S of the
+# same operands: binary64 sums in another order (~sqrt(m) 2^-53); binary32
+# accumulation within a slab plus binary32 transcendentals (~1e-6); bfloat16
+# operands: binary32 accumulation and rare one-ulp differences of the rounded
+# test matrix (~1e-5).
+SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-5}
+
+
+def hutch_regrouped(S, SJ, P, G, F, n1, n2):
+    """The NA-Hutch++ terms of the oracle's formula with the same products
+    grouped another way (through Y = S P^T and P P^T).  Mathematically equal;
+    the spread between the two groupings measures how much rounding inside the
+    formula itself can move the result."""
+    from oracle.rid import pinv
+    ell = S.shape[0]
+    n3 = ell - n1 - n2
+    Y = S @ P.T
+    Y1, Y2, Y3 = Y[:n1], Y[n1:n1 + n2], Y[n1 + n2:]
+    SJ2, SJ3 = SJ[n1:n1 + n2], SJ[n1 + n2:]
+    Kp = pinv(Y1 @ SJ2.T)
+    term1 = float(np.trace(Kp @ (Y1 @ G @ Y2.T)))
+    corr = float(np.trace(Kp @ ((Y1 @ SJ3.T) @ (SJ3 @ Y2.T))))
+    h = float(np.sum(Y3 * SJ3))
+    tr_est = term1 + (h - corr) / n3
+    gpp = float(np.sum(G * (P @ P.T)))
+    return dict(tr_est=tr_est, gpp=gpp, E2=F - 2.0 * tr_est + gpp)
+
+
+def perturbation_tolerances(o, A_cols, sketch, draws=3, factor=10.0, seed=0):
+    """Forward-error tolerances derived from the conditioning of each step.
+
+    The oracle's own S is perturbed column by column at the sketch accuracy of
+    the form; tau, P, the NA-Hutch++ terms and the reconstruction are
+    recomputed with the oracle's functions; for the NA-Hutch++ terms the spread
+    between two groupings of the same products is included as well.  The
+    tolerance is `factor` times the largest change seen (plus a floor at the
+    binary64 rounding level).  No GPU value enters."""
+    from oracle.rid import coeff_alg4, nahutchpp, ridge_lambda, ridge_scores
+    rng = np.random.default_rng(seed)
+    cfg = o.cfg
+    u_S = SKETCH_ACCURACY[sketch]
+    A64 = A_cols.T.astype(np.float64)
+    tol = {"tau": [], "tr_est": [], "gpp": [], "E2": []}
+    S_full = o.S[:, :o.n_obs]
+    norms = np.linalg.norm(S_full, axis=0) / np.sqrt(cfg.ell)
+    perturbed = [S_full + u_S * norms * rng.standard_normal(S_full.shape) for _ in range(draws)]
+    for rec in o.records:
+        n = rec.n_obs
+        S = S_full[:, :n]
+        J = rec.J
+        occ = np.flatnonzero(J >= 0)
+        G = np.zeros((cfg.t, cfg.t))
+        if occ.size:
+            G[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
+        P0 = coeff_alg4(S, J)
+        SJ0 = np.zeros((cfg.ell, cfg.t)); SJ0[:, occ] = S[:, J[occ]]
+        h0 = nahutchpp(S, SJ0, P0, G, rec.F, cfg.n1, cfg.n2)
+        hr = hutch_regrouped(S, SJ0, P0, G, rec.F, cfg.n1, cfg.n2)
+        dtr = abs(hr["tr_est"] - h0["tr_est"])
+        dgpp = abs(hr["gpp"] - h0["gpp"])
+        dE2 = abs(hr["E2"] - h0["E2"])
+        dtau = 0.0
+        for Sp_full in perturbed:
+            Sp = Sp_full[:, :n]
+            if rec.tau_D is not None:
+                SST = Sp @ Sp.T
+                _, lam, _ = ridge_lambda(SST, rec.F, cfg.k, cfg.ell, cfg.ridge_floor)
+                cols = list(range(n - rec.count, n))
+                tD = ridge_scores(SST, lam, cfg.ell, Sp[:, cols])
+                dtau = max(dtau, float(np.max(np.abs(tD - rec.tau_D) / rec.tau_D)))
+            Pp = coeff_alg4(Sp, J)
+            SJp = np.zeros((cfg.ell, cfg.t)); SJp[:, occ] = Sp[:, J[occ]]
+            hp = nahutchpp(Sp, SJp, Pp, G, rec.F, cfg.n1, cfg.n2)
+            dtr = max(dtr, abs(hp["tr_est"] - h0["tr_est"]))
+            dgpp = max(dgpp, abs(hp["gpp"] - h0["gpp"]))
+            dE2 = max(dE2, abs(hp["E2"] - h0["E2"]))
+        floor = 1e-11 * max(rec.F, 1e-300)
+        tol["tau"].append(factor * dtau + 1e-12)
+        tol["tr_est"].append(factor * dtr + floor)
+        tol["gpp"].append(factor * dgpp + floor)
+        tol["E2"].append(factor * dE2 + 2 * floor)
+    # final coefficients and reconstruction
+    Pn = o.P
+    dP = dR = 0.0
+    J = o.J
+    occ = np.flatnonzero(J >= 0)
+    R0 = A64[:, J[occ]] @ Pn[occ]
+    for Sp_full in perturbed:
+        Pp = coeff_alg4(Sp_full, J)
+        dP = max(dP, float(np.linalg.norm(Pp - Pn) / max(np.linalg.norm(Pn), 1e-300)))
+        Rp = A64[:, J[occ]] @ Pp[occ]
+        dR = max(dR, float(np.linalg.norm(Rp - R0) / max(np.linalg.norm(R0), 1e-300)))
+    tol["P"] = factor * dP + 1e-12
+    tol["recon"] = factor * dR + 1e-7 if sketch != "f64" else factor * dR + 1e-12
+    return tol

@@ -1,0 +1,221 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances:
+* Omega: binary64 evaluation differs from the oracle's by a few ulp (4e-15
+  absolute); the binary32 form uses the accurate device-library log/sincospi
+  on binary32-exact uniforms (error a few ulp of |z| <= 4.71); the bfloat16
+  form rounds hardware-transcendental binary32 values, so a small fraction of
+  entries may land one bfloat16 ulp away from the oracle's rounding.
+* Sketch S: binary64 sums in another order (1e-12 relative Frobenius);
+  binary32 accumulation within a row slab (2e-5); bfloat16 against the
+  oracle's product of bfloat16-rounded operands (1e-4).
+* Everything downstream of S (scores, coefficients, NA-Hutch++ terms,
+  reconstruction) is compared with a forward-error tolerance computed by the
+  oracle itself: its own S is perturbed at the sketch accuracy of the form and
+  the step is recomputed; the tolerance is 10x the largest change seen
+  (gpu_common.perturbation_tolerances).  The index sets J must match exactly
+  (the smallest decision margin |U - p| is logged).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import compare_updates, log, perturbation_tolerances, rel_fro, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_16076_amd import _lib
+    _lib.lib()
+
+
+# ---------------------------------------------------------------------------
+# Omega
+# ---------------------------------------------------------------------------
+def test_omega_f64_matches_oracle():
+    from paper_2405_16076_amd import omega_block
+    for seed, ell, i0, cnt in [(1001, 40, 0, 5000), (7, 301, (1 << 32) - 100, 300)]:
+        log("omega f64", seed, ell, i0, cnt)
+        g = omega_block("f64", seed, ell, i0, cnt).cpu().numpy()
+        o = oracle.omega_block(seed, ell, i0, cnt)
+        assert np.max(np.abs(g - o)) <= 4e-15 * (1 + np.max(np.abs(o)))
+
+
+def test_omega_f32_and_bf16_match_oracle():
+    from paper_2405_16076_amd import omega_block
+    seed, ell, cnt = 2024, 320, 20000
+    o = oracle.omega_block(seed, ell, 0, cnt)
+    g = omega_block("f32", seed, ell, 0, cnt).cpu().numpy().astype(np.float64)
+    err = np.abs(g - o)
+    log("omega f32 max abs err", err.max(), "rms", math.sqrt(np.mean(err ** 2)))
+    # binary32 transcendentals on exact binary32 uniforms: a few ulp of |z| <= 4.71
+    assert err.max() <= 2e-5
+    assert math.sqrt(np.mean(err ** 2)) <= 2e-6
+    gb = omega_block("bf16", seed, ell, 0, cnt).cpu().numpy().astype(np.float64)
+    ob = oracle.round_to_bf16(o.astype(np.float32))
+    mism = np.mean(gb != ob)
+    log("omega bf16 mismatch fraction", mism)
+    assert mism <= 1e-3
+    assert np.max(np.abs(gb - ob)) <= 2.0 ** -7 * (1 + np.abs(ob).max())
+
+
+# ---------------------------------------------------------------------------
+# sketch S = Omega A and ||a_j||^2
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sketch,m,n,ell,tol", [
+    ("f64", 4096, 64, 40, 1e-12),
+    ("f64", 3001, 33, 71, 1e-12),
+    ("f32", 100_003, 300, 40, 2e-5),
+    ("f32", 70_000, 70, 300, 2e-5),
+    ("bf16", 100_003, 300, 40, 1e-4),
+    ("bf16", 65_536, 600, 300, 1e-4),
+])
+def test_sketch_matches_oracle(sketch, m, n, ell, tol):
+    log("sketch", sketch, m, n, ell)
+    rng = np.random.default_rng(m + n)
+    dt = np.float64 if sketch == "f64" else np.float32
+    A = rng.standard_normal((n, m)).astype(dt)
+    s = run_gpu(A, ell, k=4, t=4, sketch=sketch, omega_seed=77, select_seed=78, finalize=False, lookahead=256)
+    S, q, _ = s.debug_state()
+    So, qo = oracle.sketch_columns(A.T, 77, ell, operand=sketch)
+    e = rel_fro(S, So)
+    log("  rel fro", e, "colsq max rel", np.max(np.abs(q - qo) / qo))
+    assert e <= tol
+    assert np.max(np.abs(q - qo) / qo) <= 1e-13
+
+
+def test_sketch_is_independent_of_batching():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((200, 50_001)).astype(np.float32)
+    ref = run_gpu(A, 64, 8, 8, "f32", 3, 4, finalize=False, lookahead=256).debug_state()
+    for batch, la in [(1, 0), (7, 100), (64, 64)]:
+        got = run_gpu(A, 64, 8, 8, "f32", 3, 4, batch=batch, finalize=False, lookahead=la).debug_state()
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+# ---------------------------------------------------------------------------
+# whole stream: J, tau, P, E^2, reconstruction
+# ---------------------------------------------------------------------------
+def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True):
+    s = run_gpu(A, ell, k, t, sketch, oseed, sseed, batch=batch, borrow=borrow)
+    o = run_oracle(A, ell, k, t, sketch, oseed, sseed)
+    tol = perturbation_tolerances(o, A, sketch)
+    worst_tau, margin = compare_updates(s, o, tol)
+    log(f"  updates {len(o.records)} tau diff/tol {worst_tau:.2e} min margin {margin:.2e} "
+        f"max kappa {max(r.kappa for r in o.records if r.tau_D is not None):.2e}")
+    J = s.select()
+    assert np.array_equal(J, o.J)
+    P = s.coefficients()
+    e = rel_fro(P, o.P)
+    log(f"  P rel fro {e:.2e} (tol {tol['P']:.2e}, cond S_J {o.records[-1].cond_SJ:.2e})")
+    assert e <= tol["P"]
+    occ = J >= 0
+    assert np.allclose(P[occ][:, J[occ]], np.eye(int(occ.sum())), atol=1e-9 if sketch == "f64" else 1e-5)
+    # NA-Hutch++ terms of every update
+    worst = {}
+    for u, rec in enumerate(o.records):
+        g = s.update(u)
+        h = rec.hutch
+        assert abs(g["F"] - rec.F) <= 1e-12 * max(rec.F, 1e-300)
+        for key in ("tr_est", "gpp", "E2"):
+            d = abs(g[key] - h[key])
+            worst[key] = max(worst.get(key, 0.0), d / tol[key][u])
+            assert d <= tol[key][u], (u, key, g[key], h[key], tol[key][u])
+    log("  NA-Hutch++ diff/tol " + " ".join(f"{k} {v:.2e}" for k, v in worst.items()))
+    _, _, G = s.debug_state()
+    assert rel_fro(G, o.G) <= 1e-12
+    # reconstruction of a column range
+    n = A.shape[0]
+    c0, c = max(0, n // 2 - 5), min(17, n)
+    R = s.reconstruct(c0, c).cpu().numpy().astype(np.float64)
+    occi = np.flatnonzero(occ)
+    Ro = (A.T[:, J[occi]].astype(np.float64) @ o.P[occi][:, c0:c0 + c]).T
+    er = rel_fro(R, Ro)
+    log(f"  reconstruct rel fro {er:.2e} (tol {tol['recon']:.2e})")
+    assert er <= tol["recon"]
+    return s, o
+
+
+def test_pipeline_f64_sines():
+    log("pipeline f64 sines 4096 x 512, l=40, t=20")
+    A = synth.sines(4096, 512, seed=synth.data_seed(1))
+    _pipeline(A, 40, 20, 20, "f64", 1001, 2001)
+
+
+def test_pipeline_f64_ragged_small_batches_copy():
+    log("pipeline f64 ragged, copy pushes of 7")
+    A = synth.sines(1000, 97, seed=3)
+    _pipeline(A, 24, 8, 8, "f64", 5, 6, batch=7, borrow=False)
+
+
+def test_pipeline_f32_lowrank():
+    log("pipeline f32 lowrank 65536 x 400, l=40, t=20")
+    A = synth.lowrank(65536, 400, seed=synth.data_seed(2), rank=60)
+    _pipeline(A, 40, 20, 20, "f32", 1002, 2002, batch=32)
+
+
+def test_pipeline_f32_channel():
+    log("pipeline f32 channel 24x17x24x4, l=60, t=30")
+    A = synth.channel(24, 17, 24, 300, seed=synth.data_seed(3), n_modes=120)
+    _pipeline(A, 60, 30, 30, "f32", 1003, 2003)
+
+
+def test_pipeline_bf16_channel_operand_rounding():
+    log("pipeline bf16 channel vs oracle with bf16-rounded operands")
+    A = synth.channel(24, 17, 24, 300, seed=synth.data_seed(3), n_modes=120)
+    _pipeline(A, 60, 30, 30, "bf16", 1003, 2003)
+
+
+def test_fewer_columns_than_slots_gives_zero_error():
+    log("n < t: one partial update keeps every column")
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((6, 5000))
+    s = run_gpu(A, 32, 8, 8, "f64", 3, 4)
+    J = s.select()
+    assert sorted(J[J >= 0]) == list(range(6))
+    R = s.reconstruct(0, 6).cpu().numpy()
+    assert rel_fro(R, A) <= 1e-12
+    assert abs(s.error_estimate()["E2"]) <= 1e-9 * float(np.sum(A * A))
+
+
+def test_zero_stream_skips_selection():
+    A = np.zeros((10, 777))
+    s = run_gpu(A, 16, 4, 4, "f64", 1, 2)
+    rec = s.update(0)
+    from paper_2405_16076_amd import _lib
+    assert rec["flags"] & _lib.RID_UPD_SKIPPED
+    assert np.all(s.select() == -1)
+    assert s.error_estimate()["E2"] == 0.0
+
+
+def test_non_finite_input_latches_enumeric():
+    from paper_2405_16076_amd import RIDError
+    A = np.ones((8, 1000), dtype=np.float32)
+    A[3, 17] = np.nan
+    s = run_gpu(A, 16, 4, 4, "f32", 1, 2, finalize=False)
+    with pytest.raises(RIDError) as ei:
+        s.select()
+    assert ei.value.status == 6
+    info = s.info()
+    assert info.failed == 1
+
+
+def test_reset_and_rerun_are_bitwise_identical():
+    A = synth.lowrank(20000, 120, seed=11, rank=30)
+    s = run_gpu(A, 32, 10, 10, "f32", 8, 9, batch=40)
+    J1, P1 = s.select(), s.coefficients()
+    s.reset()
+    X = s._data
+    for j0 in range(0, 120, 25):
+        s.push(X[j0:j0 + 25], borrow=False)
+    s.finalize()
+    assert np.array_equal(s.select(), J1)
+    assert np.array_equal(s.coefficients(), P1)
