@@ -67,10 +67,6 @@ __global__ void init_state_kernel(int64_t* J, double* tau_old, int t, DevScalars
     tau_old[i] = 1.0;
   }
   if (i == 0) {
-    sc->F = 0.0;
-    sc->lam = 0.0;
-    sc->shift = 0.0;
-    sc->skip = 0;
     sc->nonfinite = 0;
     sc->n_new = 0;
     sc->n_occ = 0;
@@ -90,7 +86,7 @@ struct rid_stream {
   int64_t m = 0, n_max = 0;
   double fill_mult = 0.0;
   // sketch geometry
-  int ell_pad = 0, n_mt = 0, cols_per_wg = 0, b_max = 0, n_slabs = 0;
+  int ell_pad = 0, n_mt = 0, rbw = 0, cols_per_wg = 0, b_max = 0, n_slabs = 0;
   int64_t slab_rows = 0;
   int gslabs = 0;
   int64_t gslab_rows = 0;
@@ -98,7 +94,12 @@ struct rid_stream {
   // device memory
   std::vector<void*> allocs;
   size_t dev_bytes = 0;
-  double *S = nullptr, *colsq = nullptr, *SST = nullptr, *W = nullptr, *hv = nullptr;
+  double *S = nullptr, *colsq = nullptr, *W = nullptr, *hv = nullptr;
+  double* SST[2] = {nullptr, nullptr};  // SS^T after the last enqueued update (ping-pong)
+  int sst_cur = 0;
+  int nzmax = 0;                        // updates per batch (slots of W and hv)
+  double* Fu = nullptr;
+  int32_t* skipu = nullptr;
   double *tauC = nullptr, *tauD = nullptr, *tau_old = nullptr, *tauC_hist = nullptr,
          *tauD_hist = nullptr;
   double *G = nullptr, *gpart = nullptr, *QR = nullptr, *qr_tau = nullptr, *P = nullptr;
@@ -283,8 +284,17 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     h->fill_mult = cfg->c_sample * (k * log(k) + k * log(1.0 / cfg->delta) / cfg->eps) / cfg->t;
   }
   // sketch geometry
-  h->ell_pad = (h->ell + kMTile - 1) / kMTile * kMTile;
-  h->n_mt = h->ell_pad / kMTile;
+  if (h->prec == RID_SKETCH_BF16) {
+    // all test-matrix rows in one workgroup up to 320 rows, else split
+    const int rows = (h->ell + 63) / 64 * 64;
+    h->n_mt = (rows + 319) / 320;
+    h->rbw = (rows + 64 * h->n_mt - 1) / (64 * h->n_mt);
+    h->ell_pad = h->n_mt * 64 * h->rbw;
+  } else {
+    h->ell_pad = (h->ell + kMTile - 1) / kMTile * kMTile;
+    h->n_mt = h->ell_pad / kMTile;
+    h->rbw = 0;
+  }
   h->cols_per_wg = sketch_cols_per_wg(h->prec);
   h->b_max = auto_lookahead(cfg);
   {
@@ -298,8 +308,9 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     h->n_slabs = (int)((h->m + rows - 1) / rows);
   }
   {
-    const int tt = (h->t + 63) / 64;
-    const int64_t target = std::max<int64_t>(1, 2048 / (tt * tt));
+    // Gram slabs: about two 1024-thread workgroups per compute unit
+    const int tt = (h->t + 159) / 160;
+    const int64_t target = std::max<int64_t>(1, 512 / (tt * tt));
     int64_t rows = (h->m + target - 1) / target;
     rows = (rows + 255) / 256 * 256;
     rows = std::max<int64_t>(rows, 1024);
@@ -308,6 +319,7 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
   }
   h->ldc = (h->m + 63) / 64 * 64;
   h->max_updates = (h->n_max + h->t - 1) / h->t + 1;
+  h->nzmax = h->b_max / h->t + 2;
   const size_t ell = h->ell, t = h->t;
   const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
 #define ALLOC(ptr, n) \
@@ -315,9 +327,12 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
   {
     ALLOC(h->S, ell * h->n_max);
     ALLOC(h->colsq, h->n_max);
-    ALLOC(h->SST, ell * ell);
-    ALLOC(h->W, ell * ell);
-    ALLOC(h->hv, 6 * ell);
+    ALLOC(h->SST[0], ell * ell);
+    ALLOC(h->SST[1], ell * ell);
+    ALLOC(h->W, ell * ell * h->nzmax);
+    ALLOC(h->hv, 6 * ell * h->nzmax);
+    ALLOC(h->Fu, (size_t)h->max_updates);
+    ALLOC(h->skipu, (size_t)h->max_updates);
     ALLOC(h->tauC, (size_t)kMaxT);
     ALLOC(h->tauD, (size_t)kMaxT);
     ALLOC(h->tau_old, (size_t)kMaxT);
@@ -349,7 +364,7 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     goto fail_alloc;
   }
   if (hipMemsetAsync(h->cpool, 0, (size_t)h->ldc * t * h->esize, h->s) != hipSuccess ||
-      hipMemsetAsync(h->SST, 0, ell * ell * 8, h->s) != hipSuccess ||
+      hipMemsetAsync(h->SST[0], 0, ell * ell * 8, h->s) != hipSuccess ||
       hipMemsetAsync(h->G, 0, t * t * 8, h->s) != hipSuccess ||
       hipMemsetAsync(h->recs, 0, sizeof(rid_update) * h->max_updates, h->s) != hipSuccess) {
     st = fail(nullptr, RID_EDEVICE, "hipMemsetAsync failed");
@@ -426,6 +441,8 @@ static rid_status sketch_range(rid_stream* h, int64_t c0, int b) {
   a.n_mt = h->n_mt;
   a.n_nt = (b + h->cols_per_wg - 1) / h->cols_per_wg;
   a.ell_pad = h->ell_pad;
+  a.ell = h->ell;
+  a.rbw = h->rbw;
   a.seed = h->cfg.omega_seed;
   a.part = h->part;
   a.normpart = h->normpart;
@@ -438,60 +455,90 @@ static rid_status sketch_range(rid_stream* h, int64_t c0, int b) {
   return RID_OK;
 }
 
-static rid_status run_update(rid_stream* h, int cnt) {
-  UpdArgs a;
-  a.ell = h->ell;
-  a.k = h->k;
-  a.t = h->t;
-  a.n1 = h->n1;
-  a.n2 = h->n2;
-  a.u = h->n_updates;
-  a.c0 = h->n_updates * h->t;
-  a.cnt = cnt;
-  a.n_obs = a.c0 + cnt;
-  a.fill_mult = h->fill_mult;
-  a.ridge_floor = h->cfg.ridge_floor;
-  a.select_seed = h->cfg.select_seed;
-  a.m = h->m;
-  a.ldc = h->ldc;
-  a.data_f64 = h->data_f64;
-  a.S = h->S;
-  a.colsq = h->colsq;
-  a.SST = h->SST;
-  a.W = h->W;
-  a.hv = h->hv;
-  a.J = h->J;
-  a.tau_old = h->tau_old;
-  a.tauC = h->tauC;
-  a.tauD = h->tauD;
-  a.J_hist = h->J_hist;
-  a.tauC_hist = h->tauC_hist;
-  a.tauD_hist = h->tauD_hist;
-  a.colptr = h->colptr_dev;
-  a.cpool = h->cpool;
-  a.G = h->G;
-  a.gpart = h->gpart;
-  a.gslabs = h->gslabs;
-  a.gslab_rows = h->gslab_rows;
-  a.QR = h->QR;
-  a.qr_tau = h->qr_tau;
-  a.P = h->P;
-  a.Y = h->Y;
-  a.PPt = h->PPt;
-  a.hw = h->hw;
-  a.sc = h->sc;
-  a.recs = h->recs;
-  int mk = mark_begin(h, 2, (double)a.u);
-  RID_HIP(h, launch_update_select(a, h->s));
+// Enqueues updates n_updates .. n_updates + nz - 1: n_full of t columns and,
+// when last > 0, one more of `last` columns.
+static rid_status run_updates(rid_stream* h, int n_full, int last) {
+  const int nz = n_full + (last > 0 ? 1 : 0);
+  if (nz == 0) return RID_OK;
+  if (nz > h->nzmax) return fail(h, RID_EDEVICE, "internal: update batch larger than its slots");
+  BatchArgs b;
+  b.ell = h->ell;
+  b.k = h->k;
+  b.t = h->t;
+  b.nz = nz;
+  b.u0 = h->n_updates;
+  b.c0 = h->n_updates * h->t;
+  b.total = (int64_t)n_full * h->t + last;
+  b.ridge_floor = h->cfg.ridge_floor;
+  b.S = h->S;
+  b.colsq = h->colsq;
+  b.sst_in = h->SST[h->sst_cur];
+  b.sst_out = h->SST[h->sst_cur ^ 1];
+  b.W = h->W;
+  b.hv = h->hv;
+  b.Fu = h->Fu;
+  b.skipu = h->skipu;
+  b.recs = h->recs;
+  int mk = mark_begin(h, 2, 0.0);
+  RID_HIP(h, launch_update_batch(b, h->s));
   mark_end(h, mk);
-  mk = mark_begin(h, 3, (double)a.u);
-  RID_HIP(h, launch_update_gram(a, h->s));
-  mark_end(h, mk);
-  mk = mark_begin(h, 2, (double)a.u);
-  RID_HIP(h, launch_update_coeff(a, h->s));
-  mark_end(h, mk);
-  h->n_updates += 1;
-  h->last_nobs = a.n_obs;
+  h->sst_cur ^= 1;
+  for (int z = 0; z < nz; ++z) {
+    UpdArgs a;
+    a.ell = h->ell;
+    a.k = h->k;
+    a.t = h->t;
+    a.n1 = h->n1;
+    a.n2 = h->n2;
+    a.u = h->n_updates;
+    a.c0 = h->n_updates * h->t;
+    a.cnt = (z < n_full) ? h->t : last;
+    a.n_obs = a.c0 + a.cnt;
+    a.fill_mult = h->fill_mult;
+    a.ridge_floor = h->cfg.ridge_floor;
+    a.select_seed = h->cfg.select_seed;
+    a.m = h->m;
+    a.ldc = h->ldc;
+    a.data_f64 = h->data_f64;
+    a.S = h->S;
+    a.colsq = h->colsq;
+    a.W = h->W + (size_t)z * h->ell * h->ell;
+    a.hv = h->hv + (size_t)z * 6 * h->ell;
+    a.Fu = h->Fu;
+    a.skipu = h->skipu;
+    a.J = h->J;
+    a.tau_old = h->tau_old;
+    a.tauC = h->tauC;
+    a.tauD = h->tauD;
+    a.J_hist = h->J_hist;
+    a.tauC_hist = h->tauC_hist;
+    a.tauD_hist = h->tauD_hist;
+    a.colptr = h->colptr_dev;
+    a.cpool = h->cpool;
+    a.G = h->G;
+    a.gpart = h->gpart;
+    a.gslabs = h->gslabs;
+    a.gslab_rows = h->gslab_rows;
+    a.QR = h->QR;
+    a.qr_tau = h->qr_tau;
+    a.P = h->P;
+    a.Y = h->Y;
+    a.PPt = h->PPt;
+    a.hw = h->hw;
+    a.sc = h->sc;
+    a.recs = h->recs;
+    mk = mark_begin(h, 2, (double)a.u);
+    RID_HIP(h, launch_update_select(a, h->s));
+    mark_end(h, mk);
+    mk = mark_begin(h, 3, (double)a.u);
+    RID_HIP(h, launch_update_gram(a, h->s));
+    mark_end(h, mk);
+    mk = mark_begin(h, 2, (double)a.u);
+    RID_HIP(h, launch_update_coeff(a, h->s));
+    mark_end(h, mk);
+    h->n_updates += 1;
+    h->last_nobs = a.n_obs;
+  }
   return RID_OK;
 }
 
@@ -504,8 +551,8 @@ static rid_status flush_all(rid_stream* h) {
     const int b = (int)std::min<int64_t>(h->b_max, h->n_pushed - h->n_sketched);
     if ((st = sketch_range(h, h->n_sketched, b)) != RID_OK) return st;
     h->n_sketched += b;
-    while ((h->n_updates + 1) * h->t <= h->n_sketched)
-      if ((st = run_update(h, h->t)) != RID_OK) return st;
+    const int full = (int)(h->n_sketched / h->t - h->n_updates);
+    if ((st = run_updates(h, full, 0)) != RID_OK) return st;
   }
   return RID_OK;
 }
@@ -518,8 +565,8 @@ static rid_status flush_full(rid_stream* h) {
   while (h->n_pushed - h->n_sketched >= h->b_max) {
     if ((st = sketch_range(h, h->n_sketched, h->b_max)) != RID_OK) return st;
     h->n_sketched += h->b_max;
-    while ((h->n_updates + 1) * h->t <= h->n_sketched)
-      if ((st = run_update(h, h->t)) != RID_OK) return st;
+    const int full = (int)(h->n_sketched / h->t - h->n_updates);
+    if ((st = run_updates(h, full, 0)) != RID_OK) return st;
   }
   return RID_OK;
 }
@@ -595,7 +642,7 @@ rid_status rid_finalize(rid_stream* h) {
   rid_status st = flush_all(h);
   if (st != RID_OK) return st;
   const int64_t rem = h->n_pushed - h->n_updates * h->t;
-  if (rem > 0 && (st = run_update(h, (int)rem)) != RID_OK) return st;
+  if (rem > 0 && (st = run_updates(h, 0, (int)rem)) != RID_OK) return st;
   h->finalized = true;
   return RID_OK;
 }
@@ -605,7 +652,8 @@ rid_status rid_reset(rid_stream* h) {
   if (h->failed) return fail(h, RID_ESTATE, "stream failed");
   RID_HIP(h, hipStreamSynchronize(h->s));
   const size_t ell = h->ell, t = h->t;
-  RID_HIP(h, hipMemsetAsync(h->SST, 0, ell * ell * 8, h->s));
+  h->sst_cur = 0;
+  RID_HIP(h, hipMemsetAsync(h->SST[0], 0, ell * ell * 8, h->s));
   RID_HIP(h, hipMemsetAsync(h->G, 0, t * t * 8, h->s));
   RID_HIP(h, hipMemsetAsync(h->recs, 0, sizeof(rid_update) * h->max_updates, h->s));
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc);

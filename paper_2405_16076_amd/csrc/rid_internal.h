@@ -136,6 +136,42 @@ __device__ __forceinline__ void omega8_f64(uint64_t seed, uint64_t i, uint32_t g
   box_muller16_f64(w.w, z[6], z[7]);
 }
 
+// Column addresses come from a table in device memory, so the compiler cannot
+// infer their address space and would emit FLAT accesses; FLAT loads also
+// count against the LDS wait counter, which would make every LDS wait also
+// wait for in-flight prefetches.  These casts make them global accesses.
+template <typename T>
+using gmem_t = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ const gmem_t<T>* gload_ptr(const T* p) {
+  return (const gmem_t<T>*)p;
+}
+
+template <typename T>
+__device__ __forceinline__ gmem_t<T>* gstore_ptr(T* p) {
+  return (gmem_t<T>*)p;
+}
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+// 16-byte global loads and stores (the address must be 16-byte aligned)
+__device__ __forceinline__ float4 gload_f4(const gmem_t<float>* p) {
+  const vf4 v = *reinterpret_cast<const gmem_t<vf4>*>(p);
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void gstore_f4(gmem_t<float>* p, float4 x) {
+  *reinterpret_cast<gmem_t<vf4>*>(p) = vf4{x.x, x.y, x.z, x.w};
+}
+__device__ __forceinline__ double2 gload_d2(const gmem_t<double>* p) {
+  const vd2 v = *reinterpret_cast<const gmem_t<vd2>*>(p);
+  return make_double2(v[0], v[1]);
+}
+__device__ __forceinline__ void gstore_d2(gmem_t<double>* p, double2 x) {
+  *reinterpret_cast<gmem_t<vd2>*>(p) = vd2{x.x, x.y};
+}
+
 // Round-to-nearest-even binary32 -> bfloat16 bits (finite inputs).
 __device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
   uint32_t b = __float_as_uint(f);
@@ -148,10 +184,6 @@ __device__ __forceinline__ uint16_t bf16_bits_rne(float f) {
 // update kernels; the host never reads it between updates).
 // ---------------------------------------------------------------------------
 struct DevScalars {
-  double F;            // ||A_obs||_F^2 of the observed columns
-  double lam;          // ridge parameter of the running update
-  double shift;        // l * lam
-  int32_t skip;        // 1 when the running update skips selection (F == 0)
   int32_t nonfinite;   // 1 once a non-finite snapshot value was seen
   int32_t n_new;       // slots filled by the running update
   int32_t n_occ;       // occupied slots after the running update
@@ -160,6 +192,7 @@ struct DevScalars {
   int32_t new_slot[kMaxT];   // slots filled by the running update
   int32_t new_src[kMaxT];    // their position in the buffer
   int32_t occ_slot[kMaxT];   // occupied slots in slot order
+  int32_t slot_src[kMaxT];   // buffer position of a slot filled by the running update, else -1
 };
 
 struct SketchArgs {
@@ -170,9 +203,31 @@ struct SketchArgs {
   int64_t m;               // rows per snapshot
   int64_t slab_rows;       // rows per slab (multiple of 32)
   int32_t n_slabs, n_mt, n_nt, ell_pad;
+  int32_t ell;             // test-matrix rows l
+  int32_t rbw;             // bfloat16 form: 32-row blocks per wave (rows per workgroup / 64)
   uint64_t seed;
   void* part;              // [n_slabs][b_max][ell_pad] float (double for F64)
   double* normpart;        // [n_slabs][b_max]
+};
+
+// The updates enqueued by one flush share one launch of the SS^T kernel and
+// of the tridiagonalisation (one workgroup per update): SS^T and F of update
+// u depend only on the sketch, not on the selection.
+struct BatchArgs {
+  int ell, k, t, nz;
+  int64_t u0;             // first update of the batch
+  int64_t c0;             // first buffered column of update u0
+  int64_t total;          // columns covered by the batch's updates
+  double ridge_floor;
+  const double* S;
+  const double* colsq;
+  const double* sst_in;   // SS^T after update u0 - 1
+  double* sst_out;        // SS^T after the batch's last update
+  double* W;              // nz slots of l x l
+  double* hv;             // nz slots of 6 l
+  double* Fu;             // ||A_obs||^2 per update
+  int32_t* skipu;         // 1 when the update skips selection (F == 0)
+  rid_update* recs;
 };
 
 struct UpdArgs {
@@ -189,9 +244,10 @@ struct UpdArgs {
   // state
   double* S;           // l x n_max
   double* colsq;
-  double* SST;         // l x l
-  double* W;           // l x l tridiagonalisation work (reflectors below the subdiagonal)
-  double* hv;          // per-reflector tau (l), diag d (l), offdiag e (l), Dinv (l), L (l)
+  double* W;           // this update's l x l slot: reflectors below the subdiagonal
+  double* hv;          // this update's slot: tau (l), d (l), e (l), Dinv (l), L (l), top eigenvalues (l)
+  double* Fu;          // ||A_obs||^2 per update
+  int32_t* skipu;      // 1 when the update skips selection (F == 0)
   int64_t* J;          // t
   double* tau_old;     // t
   double* tauC;        // t (running update)
@@ -222,6 +278,7 @@ hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, int ell, double* 
                                 int32_t* nonfinite, hipStream_t s);
 hipError_t launch_omega_block(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,
                               void* out, int64_t ld, hipStream_t s);
+hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s);
 hipError_t launch_update_select(const UpdArgs& a, hipStream_t s);
 hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s);

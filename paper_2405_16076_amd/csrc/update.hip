@@ -6,7 +6,7 @@
 //   scores         tau = s^T (SS^T + l*lam I)^{-1} s for the basis slots and the
 //                  buffered columns (Alg. 3 function, steps 17-18)
 //   select         prune / fill draws (Alg. 3 steps 19-27)
-//   copy_new/gram  new basis columns into the column pool and their Gram entries
+//   gram           new basis columns into the column pool and their Gram entries
 //                  G = A_J^T A_J (Alg. 5 step 1, reused by Alg. 8 step 1)
 //   alg4_qr/apply  P = (Omega A_J)^+ (Omega A_obs) by Householder QR (Alg. 4)
 //   hutch_*        NA-Hutch++ estimate of ||A_obs - A_J P||_F^2 (Alg. 8)
@@ -37,28 +37,37 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
-// SS^T += S_u S_u^T, F and the start of the update record.
+// SS^T and F of every update of a batch: slot z receives
+//   SS^T_{u0-1} + sum of s_c s_c^T over the batch columns up to update u0+z,
+// and slot nz (sst_out) the state after the last update.  Also starts each
+// update's record.
 // ---------------------------------------------------------------------------
-__global__ void sst_update_kernel(UpdArgs a) {
+__global__ void sst_batch_kernel(BatchArgs b) {
   const int r1 = blockIdx.x * 16 + threadIdx.x;
   const int r2 = blockIdx.y * 16 + threadIdx.y;
-  if (r1 < a.ell && r2 < a.ell) {
-    double s = a.SST[(int64_t)r2 * a.ell + r1];
-    for (int c = 0; c < a.cnt; ++c) {
-      const double* col = a.S + (a.c0 + c) * a.ell;
+  const int z = blockIdx.z;
+  const int zz = min(z, b.nz - 1);
+  const int64_t cend = b.c0 + min((int64_t)(zz + 1) * b.t, b.total);
+  if (r1 < b.ell && r2 < b.ell) {
+    double s = b.sst_in[(int64_t)r2 * b.ell + r1];
+    for (int64_t c = b.c0; c < cend; ++c) {
+      const double* col = b.S + c * b.ell;
       s = fma(col[r1], col[r2], s);
     }
-    a.SST[(int64_t)r2 * a.ell + r1] = s;
+    double* dst = (z < b.nz) ? b.W + (int64_t)z * b.ell * b.ell : b.sst_out;
+    dst[(int64_t)r2 * b.ell + r1] = s;
   }
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-    double F = a.sc->F;
-    for (int c = 0; c < a.cnt; ++c) F += a.colsq[a.c0 + c];
-    a.sc->F = F;
-    a.sc->skip = (F > 0.0) ? 0 : 1;
-    rid_update* rec = a.recs + a.u;
-    rec->update = a.u;
-    rec->n_obs = a.n_obs;
-    rec->count = a.cnt;
+  if (z < b.nz && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    const int64_t u = b.u0 + z;
+    // F of update u0 - 1 was written by an earlier launch
+    double F = (b.u0 > 0) ? b.Fu[b.u0 - 1] : 0.0;
+    for (int64_t c = b.c0; c < cend; ++c) F += b.colsq[c];
+    b.Fu[u] = F;
+    b.skipu[u] = (F > 0.0) ? 0 : 1;
+    rid_update* rec = b.recs + u;
+    rec->update = u;
+    rec->n_obs = cend;
+    rec->count = cend - (b.c0 + (int64_t)zz * b.t);
     rec->F = F;
     rec->flags = (F > 0.0) ? 0 : RID_UPD_SKIPPED;
   }
@@ -82,32 +91,31 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
   return cnt;
 }
 
-__global__ __launch_bounds__(1024) void tridiag_kernel(UpdArgs a) {
+__global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) {
   __shared__ double v[kMaxEll];
   __shared__ double p[kMaxEll];
   __shared__ double red[16];
   __shared__ double e2s[kMaxEll];
   __shared__ double ds[kMaxEll];
-  const int n = a.ell, tid = threadIdx.x, nth = blockDim.x;
+  const int z = blockIdx.x;
+  const int64_t u = b.u0 + z;
+  const int n = b.ell, tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
-  double* W = a.W;
-  double* htau = a.hv;
-  double* d = a.hv + n;
-  double* e = a.hv + 2 * n;
-  double* Dinv = a.hv + 3 * n;
-  double* L = a.hv + 4 * n;
-  double* mu = a.hv + 5 * n;
-  if (a.sc->skip) {
+  double* W = b.W + (int64_t)z * n * n;   // holds SS^T of update u on entry
+  double* hv = b.hv + (int64_t)z * 6 * n;
+  double* htau = hv;
+  double* d = hv + n;
+  double* e = hv + 2 * n;
+  double* Dinv = hv + 3 * n;
+  double* L = hv + 4 * n;
+  double* mu = hv + 5 * n;
+  if (b.skipu[u]) {
     if (tid == 0) {
-      a.sc->lam = 0.0;
-      a.sc->shift = 0.0;
-      a.recs[a.u].sk2 = 0.0;
-      a.recs[a.u].lam = 0.0;
+      b.recs[u].sk2 = 0.0;
+      b.recs[u].lam = 0.0;
     }
     return;
   }
-  for (int64_t i = tid; i < (int64_t)n * n; i += nth) W[i] = a.SST[i];
-  __syncthreads();
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;           // order of the trailing block
     double* x = W + (int64_t)j * n + j + 1;   // column j, rows j+1..n-1
@@ -147,10 +155,11 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(UpdArgs a) {
       const double K = 0.5 * tau * block_sum(pv, red);
       for (int i = tid; i < m; i += nth) p[i] = p[i] - K * v[i];  // p -> w
       __syncthreads();
-      // A22 -= v w^T + w v^T
-      for (int64_t idx = tid; idx < (int64_t)m * m; idx += nth) {
-        const int col = (int)(idx / m), row = (int)(idx % m);
-        A22[(int64_t)col * n + row] -= v[row] * p[col] + p[row] * v[col];
+      // A22 -= v w^T + w v^T (one wave per column)
+      for (int col = wv; col < m; col += nw) {
+        double* cp = A22 + (int64_t)col * n;
+        const double vc = v[col], pc = p[col];
+        for (int row = lane; row < m; row += 64) cp[row] -= v[row] * pc + p[row] * vc;
       }
     }
     __syncthreads();
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(UpdArgs a) {
   lo -= 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   hi += 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-  const int kk = min(a.k, n);
+  const int kk = min(b.k, n);
   for (int idx = tid; idx < kk; idx += nth) {
     const int target = n - 1 - idx;  // ascending index of the idx-th largest
     double aa = lo, bb = hi;
@@ -202,13 +211,11 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(UpdArgs a) {
   if (tid == 0) {
     double sk2 = 0.0;
     for (int i = 0; i < kk; ++i) sk2 += mu[i];
-    const double F = a.sc->F;
-    const double lam = fmax((F - sk2 / n) / a.k, a.ridge_floor * F / a.k);
+    const double F = b.Fu[u];
+    const double lam = fmax((F - sk2 / n) / b.k, b.ridge_floor * F / b.k);
     const double shift = n * lam;
-    a.sc->lam = lam;
-    a.sc->shift = shift;
-    a.recs[a.u].sk2 = sk2;
-    a.recs[a.u].lam = lam;
+    b.recs[u].sk2 = sk2;
+    b.recs[u].lam = lam;
     // T + shift I = L D L^T (T symmetric positive definite for shift > 0)
     double Di = ds[0] + shift;
     Dinv[0] = 1.0 / Di;
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(UpdArgs a) {
 __global__ __launch_bounds__(64) void scores_kernel(UpdArgs a) {
   __shared__ double y[kMaxEll];
   const int item = blockIdx.x, lane = threadIdx.x, n = a.ell;
-  if (a.sc->skip) return;
+  if (a.skipu[a.u]) return;
   int64_t col;
   if (item < a.t) {
     col = a.J[item];
@@ -290,7 +297,7 @@ __global__ __launch_bounds__(64) void select_kernel(UpdArgs a) {
   for (int r = lane; r < kMaxT; r += 64) used[r] = 0;
   __syncthreads();
   int n_new = 0, n_pruned = 0;
-  if (!sc->skip) {
+  if (!a.skipu[a.u]) {
     for (int i = 0; i < a.t; ++i) {
       int64_t Ji = a.J[i];
       if (Ji >= 0) {
@@ -337,6 +344,8 @@ __global__ __launch_bounds__(64) void select_kernel(UpdArgs a) {
   __syncthreads();
   if (lane == 0) {
     int n_occ = 0;
+    for (int i = 0; i < a.t; ++i) sc->slot_src[i] = -1;
+    for (int q = 0; q < n_new; ++q) sc->slot_src[sc->new_slot[q]] = sc->new_src[q];
     for (int i = 0; i < a.t; ++i) {
       const int64_t Ji = a.J[i];
       a.J_hist[a.u * a.t + i] = Ji;
@@ -352,77 +361,127 @@ __global__ __launch_bounds__(64) void select_kernel(UpdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Copy the new basis columns into the column pool.
-// grid.y = new-slot index; blocks beyond n_new return.
+// Gram entries of the new basis columns, fused with their copy into the pool.
+// One workgroup of 16 waves per (row slab, tile of up to 160 new slots, tile
+// of up to 160 occupied slots), so each basis column is read once per slab.
+// Per 32-row chunk the q columns (new slots, read from the buffered snapshot)
+// and the j columns (occupied slots: the snapshot for new ones, the pool for
+// kept ones) are staged in LDS in 128-byte runs; 16 x 16 blocks of the tile
+// are spread over the waves and accumulated with v_mfma_f64_16x16x4_f64
+// (A lane l: row l%16, k = l/16; B lane l: column l%16, k = l/16; D lane l,
+// element v: column l%16, row l/16 + 4v).  Products of binary32 data are exact
+// in binary64 and all sums are binary64.  When every occupied slot is new the
+// two lists coincide and only blocks on or above the diagonal are computed.
+// Workgroups of j tile 0 also write the new columns into the pool.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void copy_new_kernel(UpdArgs a) {
-  const int q = blockIdx.y;
-  if (q >= a.sc->n_new) return;
-  const T* src = reinterpret_cast<const T*>(a.colptr[a.c0 + a.sc->new_src[q]]);
-  T* dst = reinterpret_cast<T*>(a.cpool) + (int64_t)a.sc->new_slot[q] * a.ldc;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.m;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
+typedef double f64x4_g __attribute__((ext_vector_type(4)));
+constexpr int kGramTile = 160;
+constexpr int kGramMaxBlocks = 7;   // ceil(10 * 10 / 16)
 
-// Gram partials: gpart[gslab][q][jj] = sum over the slab rows of
-// C(:, new_slot[q]) * C(:, occ_slot[jj]).  64 x 64 (q, jj) tile per workgroup,
-// 32-row chunks staged in LDS, binary64 accumulation of exact products.
 template <typename T>
-__global__ __launch_bounds__(256) void gram_partial_kernel(UpdArgs a) {
-  constexpr int RC = 32;
-  __shared__ double tq[RC][65];
-  __shared__ double tj[RC][65];
+__global__ __launch_bounds__(1024) void gram_kernel(UpdArgs a) {
+  constexpr int KC = (sizeof(T) == 4) ? 32 : 16;  // rows per chunk
+  constexpr int LDC = KC + 1;
+  __shared__ T sq[kGramTile * LDC];
+  __shared__ T sj[kGramTile * LDC];
+  __shared__ int blk[kGramMaxBlocks * 16];
+  __shared__ int nblk;
   const DevScalars* sc = a.sc;
   const int n_new = sc->n_new, n_occ = sc->n_occ;
   const int qt = blockIdx.y, jt = blockIdx.z, slab = blockIdx.x;
-  if (qt * 64 >= n_new || jt * 64 >= n_occ) return;
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  const T* C = reinterpret_cast<const T*>(a.cpool);
+  if (qt * kGramTile >= n_new || jt * kGramTile >= n_occ) return;
+  const int nq = min(kGramTile, n_new - qt * kGramTile);
+  const int nj = min(kGramTile, n_occ - jt * kGramTile);
+  const bool sym = (n_new == n_occ) && (qt == jt);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
   const int64_t r0 = (int64_t)slab * a.gslab_rows;
   const int64_t r1 = min(a.m, r0 + a.gslab_rows);
-  double acc[4][4];
+  const int QB = (nq + 15) / 16, JB = (nj + 15) / 16;
+  if (tid == 0) {
+    int n = 0;
+    for (int bq = 0; bq < QB; ++bq)
+      for (int bj = sym ? bq : 0; bj < JB; ++bj) blk[n++] = bq * 16 + bj;
+    nblk = n;
+  }
+  // staging: thread -> one (column, 4-row group) pair per round
+  constexpr int RG = KC / 4;                   // 4-row groups per column
+  const int ncol_stage = sym ? nq : nq + nj;   // columns staged per chunk
+  __syncthreads();
+  f64x4_g acc[kGramMaxBlocks];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int b = 0; b < kGramMaxBlocks; ++b) acc[b] = f64x4_g{0.0, 0.0, 0.0, 0.0};
+  const T* cpool = reinterpret_cast<const T*>(a.cpool);
+  for (int64_t k0 = r0; k0 < r1; k0 += KC) {
+    for (int it = tid; it < ncol_stage * RG; it += 1024) {
+      const int col = it / RG, rgp = it % RG;
+      const int64_t row = k0 + 4 * rgp;
+      const gmem_t<T>* src;
+      gmem_t<T>* cdst = nullptr;
+      T* lds;
+      if (col < nq) {
+        const int q = qt * kGramTile + col;
+        src = gload_ptr(reinterpret_cast<const T*>(a.colptr[a.c0 + sc->new_src[q]]));
+        if (jt == 0) cdst = gstore_ptr(reinterpret_cast<T*>(a.cpool) + (int64_t)sc->new_slot[q] * a.ldc);
+        lds = sq + col * LDC + 4 * rgp;
+      } else {
+        const int jj = jt * kGramTile + (col - nq);
+        const int slot = sc->occ_slot[jj];
+        const int s = sc->slot_src[slot];
+        src = gload_ptr((s >= 0) ? reinterpret_cast<const T*>(a.colptr[a.c0 + s]) : cpool + (int64_t)slot * a.ldc);
+        lds = sj + (col - nq) * LDC + 4 * rgp;
+      }
+      T v[4];
+      if (row + 4 <= r1) {
+        // 16-byte aligned: columns start on 64-element boundaries, rows on 4
+        if constexpr (sizeof(T) == 4) {
+          const float4 x = gload_f4(src + row);
+          v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+          if (cdst) gstore_f4(cdst + row, x);
+        } else {
+          const double2 x0 = gload_d2(src + row);
+          const double2 x1 = gload_d2(src + row + 2);
+          v[0] = x0.x; v[1] = x0.y; v[2] = x1.x; v[3] = x1.y;
+          if (cdst) {
+            gstore_d2(cdst + row, x0);
+            gstore_d2(cdst + row + 2, x1);
+          }
+        }
+      } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  // loader: thread -> tile column lc = tid / 4 (0..63), rows 8 (tid % 4) .. +8
-  const int lc = tid >> 2, lr = (tid & 3) * 8;
-  const int qg = qt * 64 + lc, jg = jt * 64 + lc;
-  const T* cq = (qg < n_new) ? C + (int64_t)sc->new_slot[qg] * a.ldc : nullptr;
-  const T* cj = (jg < n_occ) ? C + (int64_t)sc->occ_slot[jg] * a.ldc : nullptr;
-  for (int64_t k0 = r0; k0 < r1; k0 += RC) {
+        for (int j = 0; j < 4; ++j) {
+          v[j] = (row + j < r1) ? src[row + j] : (T)0;
+          if (cdst && row + j < r1) cdst[row + j] = v[j];
+        }
+      }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t row = k0 + lr + j;
-      tq[lr + j][lc] = (cq && row < r1) ? (double)cq[row] : 0.0;
-      tj[lr + j][lc] = (cj && row < r1) ? (double)cj[row] : 0.0;
+      for (int j = 0; j < 4; ++j) lds[j] = v[j];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < RC; ++kk) {
-      double av[4], bv[4];
+    const T* SJ = sym ? sq : sj;
+    for (int b = 0; b < kGramMaxBlocks; ++b) {
+      const int bi = wave + 16 * b;
+      if (bi >= nblk) break;
+      const int bq = blk[bi] >> 4, bj = blk[bi] & 15;
+      const T* pa = sq + (bq * 16 + i16) * LDC + k4;
+      const T* pb = SJ + (bj * 16 + i16) * LDC + k4;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = tq[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = tj[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+      for (int s = 0; s < KC / 4; ++s)
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)pa[4 * s], (double)pb[4 * s], acc[b], 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = a.gpart + (int64_t)slab * a.t * a.t;
+  for (int b = 0; b < kGramMaxBlocks; ++b) {
+    const int bi = wave + 16 * b;
+    if (bi >= nblk) break;
+    const int bq = blk[bi] >> 4, bj = blk[bi] & 15;
+    const int jl = bj * 16 + i16;
+    if (jl >= nj) continue;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int q = qt * 64 + ty * 4 + i;
-    if (q >= n_new) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int jj = jt * 64 + tx * 4 + j;
-      if (jj < n_occ) out[(int64_t)q * a.t + jj] = acc[i][j];
+    for (int v = 0; v < 4; ++v) {
+      const int ql = bq * 16 + k4 + 4 * v;
+      if (ql < nq) out[(int64_t)(qt * kGramTile + ql) * a.t + jt * kGramTile + jl] = acc[b][v];
     }
   }
 }
@@ -439,8 +498,15 @@ __global__ void gram_reduce_kernel(UpdArgs a) {
   const DevScalars* sc = a.sc;
   const int q = blockIdx.x, jj = threadIdx.x + blockIdx.y * blockDim.x;
   if (q >= sc->n_new || jj >= sc->n_occ) return;
+  // when every occupied slot is new, only blocks on or above the diagonal
+  // (within a 160-slot tile) were computed: read the transposed pair below it
+  int qq = q, jq = jj;
+  if (sc->n_new == sc->n_occ && q / kGramTile == jj / kGramTile && (jj % kGramTile) / 16 < (q % kGramTile) / 16) {
+    qq = jj;
+    jq = q;
+  }
   double s = 0.0;
-  for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
+  for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + qq) * a.t + jq];
   const int si = sc->new_slot[q], sj = sc->occ_slot[jj];
   a.G[(int64_t)sj * a.t + si] = s;
   a.G[(int64_t)si * a.t + sj] = s;
@@ -570,6 +636,83 @@ __global__ void hutch_prod_kernel(UpdArgs a) {
   }
 }
 
+// The products of the small part of Alg. 8, one thread per output entry.
+// Stage 0: S_J gather.  Stage 1: K^T = (Y1 SJ2^T)^T, YG = Y1 G, A1 = Y1 SJ3^T,
+// A2 = SJ3 Y2^T.  Stage 2: X = YG Y2^T, AA = A1 A2.
+struct HutchWork {
+  double *KT, *X, *AA, *YG, *A1, *A2, *SJ;
+};
+
+__device__ __forceinline__ HutchWork hutch_work(const UpdArgs& a) {
+  HutchWork w;
+  w.KT = a.hw;
+  w.X = w.KT + (int64_t)kMaxEll * kMaxEll / 4;
+  w.AA = w.X + (int64_t)kMaxEll * kMaxEll / 4;
+  w.YG = w.AA + (int64_t)kMaxEll * kMaxEll / 4;
+  w.A1 = w.YG + (int64_t)kMaxEll * kMaxT;
+  w.A2 = w.A1 + (int64_t)kMaxEll * kMaxEll / 4;
+  w.SJ = w.A2 + (int64_t)kMaxEll * kMaxEll / 4;
+  return w;
+}
+
+__global__ void hutch_mid_kernel(UpdArgs a, int stage) {
+  const int n = a.ell, t = a.t, n1 = a.n1, n2 = a.n2, n3 = a.ell - a.n1 - a.n2;
+  const HutchWork w = hutch_work(a);
+  const double* Y = a.Y;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (stage == 0) {
+    if (idx < (int64_t)n * t) {
+      const int j = (int)(idx / n), r = (int)(idx % n);
+      const int64_t Jj = a.J[j];
+      w.SJ[idx] = (Jj >= 0) ? a.S[Jj * n + r] : 0.0;
+    }
+    return;
+  }
+  if (stage == 1) {
+    const int64_t nK = (int64_t)n1 * n2, nYG = (int64_t)n1 * t, nA1 = (int64_t)n1 * n3, nA2 = (int64_t)n3 * n2;
+    if (idx < nK) {
+      const int b = (int)(idx % n2), aa = (int)(idx / n2);
+      double s = 0.0;
+      for (int j = 0; j < t; ++j) s = fma(Y[(int64_t)j * n + aa], w.SJ[(int64_t)j * n + n1 + b], s);
+      w.KT[(int64_t)aa * n2 + b] = s;
+      return;
+    }
+    idx -= nK;
+    if (idx < nYG) {
+      const int aa = (int)(idx % n1), j = (int)(idx / n1);
+      double s = 0.0;
+      for (int i = 0; i < t; ++i) s = fma(Y[(int64_t)i * n + aa], a.G[(int64_t)j * t + i], s);
+      w.YG[(int64_t)j * n1 + aa] = s;
+      return;
+    }
+    idx -= nYG;
+    if (idx < nA1) {
+      const int aa = (int)(idx % n1), c = (int)(idx / n1);
+      double s = 0.0;
+      for (int j = 0; j < t; ++j) s = fma(Y[(int64_t)j * n + aa], w.SJ[(int64_t)j * n + n1 + n2 + c], s);
+      w.A1[(int64_t)c * n1 + aa] = s;
+      return;
+    }
+    idx -= nA1;
+    if (idx < nA2) {
+      const int c = (int)(idx % n3), b = (int)(idx / n3);
+      double s = 0.0;
+      for (int j = 0; j < t; ++j) s = fma(w.SJ[(int64_t)j * n + n1 + n2 + c], Y[(int64_t)j * n + n1 + b], s);
+      w.A2[(int64_t)b * n3 + c] = s;
+    }
+    return;
+  }
+  if (idx < (int64_t)n1 * n2) {
+    const int aa = (int)(idx % n1), b = (int)(idx / n1);
+    double s = 0.0;
+    for (int j = 0; j < t; ++j) s = fma(w.YG[(int64_t)j * n1 + aa], Y[(int64_t)j * n + n1 + b], s);
+    w.X[(int64_t)b * n1 + aa] = s;
+    double s2 = 0.0;
+    for (int c = 0; c < n3; ++c) s2 = fma(w.A1[(int64_t)c * n1 + aa], w.A2[(int64_t)b * n3 + c], s2);
+    w.AA[(int64_t)b * n1 + aa] = s2;
+  }
+}
+
 // The small part of Alg. 8 in one workgroup.  With the row blocks
 // [0,n1), [n1,n1+n2), [n1+n2,l) of S, of S_J = Omega A_J and of Y:
 //   K = Y1 SJ2^T, X = Y1 G Y2^T, A1 = Y1 SJ3^T, A2 = SJ3 Y2^T,
@@ -586,24 +729,15 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
   const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
   const DevScalars* sc = a.sc;
   rid_update* rec = a.recs + a.u;
-  const double F = sc->F;
-  // work layout
-  double* KT = a.hw;                                   // n2 x n1 (ld n2)
-  double* X = KT + (int64_t)kMaxEll * kMaxEll / 4;      // n1 x n2 (ld n1)
-  double* AA = X + (int64_t)kMaxEll * kMaxEll / 4;      // n1 x n2 (ld n1)
-  double* YG = AA + (int64_t)kMaxEll * kMaxEll / 4;     // n1 x t  (ld n1)
-  double* A1 = YG + (int64_t)kMaxEll * kMaxT;           // n1 x n3 (ld n1)
-  double* A2 = A1 + (int64_t)kMaxEll * kMaxEll / 4;     // n3 x n2 (ld n3)
-  double* SJ = A2 + (int64_t)kMaxEll * kMaxEll / 4;     // l x t   (ld l)
+  const double F = a.Fu[a.u];
+  // work layout: KT n2 x n1 (ld n2), X and AA n1 x n2 (ld n1), SJ l x t
+  const HutchWork hwk = hutch_work(a);
+  double* KT = hwk.KT;
+  double* X = hwk.X;
+  double* AA = hwk.AA;
+  const double* SJ = hwk.SJ;
   const double* Y = a.Y;
   const double* G = a.G;
-  // gather S_J (zero columns for empty slots)
-  for (int64_t idx = tid; idx < (int64_t)n * t; idx += nth) {
-    const int j = (int)(idx / n), r = (int)(idx % n);
-    const int64_t Jj = a.J[j];
-    SJ[idx] = (Jj >= 0) ? a.S[Jj * n + r] : 0.0;
-  }
-  __syncthreads();
   // h and gpp
   double hp = 0.0, gp = 0.0;
   for (int64_t idx = tid; idx < (int64_t)n3 * t; idx += nth) {
@@ -616,44 +750,6 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
   double term1 = 0.0, corr = 0.0;
   int trunc = 0;
   if (n1 > 0 && n2 > 0) {
-    // KT(b, a) = K(a, b) = sum_j Y1(a, j) SJ2(b, j)
-    for (int64_t idx = tid; idx < (int64_t)n1 * n2; idx += nth) {
-      const int b = (int)(idx % n2), aa = (int)(idx / n2);
-      double s = 0.0;
-      for (int j = 0; j < t; ++j) s = fma(Y[(int64_t)j * n + aa], SJ[(int64_t)j * n + n1 + b], s);
-      KT[(int64_t)aa * n2 + b] = s;
-    }
-    // YG = Y1 G
-    for (int64_t idx = tid; idx < (int64_t)n1 * t; idx += nth) {
-      const int aa = (int)(idx % n1), j = (int)(idx / n1);
-      double s = 0.0;
-      for (int i = 0; i < t; ++i) s = fma(Y[(int64_t)i * n + aa], G[(int64_t)j * t + i], s);
-      YG[(int64_t)j * n1 + aa] = s;
-    }
-    // A1 = Y1 SJ3^T (n1 x n3), A2 = SJ3 Y2^T (n3 x n2)
-    for (int64_t idx = tid; idx < (int64_t)n1 * n3; idx += nth) {
-      const int aa = (int)(idx % n1), c = (int)(idx / n1);
-      double s = 0.0;
-      for (int j = 0; j < t; ++j) s = fma(Y[(int64_t)j * n + aa], SJ[(int64_t)j * n + n1 + n2 + c], s);
-      A1[(int64_t)c * n1 + aa] = s;
-    }
-    for (int64_t idx = tid; idx < (int64_t)n3 * n2; idx += nth) {
-      const int c = (int)(idx % n3), b = (int)(idx / n3);
-      double s = 0.0;
-      for (int j = 0; j < t; ++j) s = fma(SJ[(int64_t)j * n + n1 + n2 + c], Y[(int64_t)j * n + n1 + b], s);
-      A2[(int64_t)b * n3 + c] = s;
-    }
-    __syncthreads();
-    // X = YG Y2^T and AA = A1 A2 (n1 x n2)
-    for (int64_t idx = tid; idx < (int64_t)n1 * n2; idx += nth) {
-      const int aa = (int)(idx % n1), b = (int)(idx / n1);
-      double s = 0.0;
-      for (int j = 0; j < t; ++j) s = fma(YG[(int64_t)j * n1 + aa], Y[(int64_t)j * n + n1 + b], s);
-      X[(int64_t)b * n1 + aa] = s;
-      double s2 = 0.0;
-      for (int c = 0; c < n3; ++c) s2 = fma(A1[(int64_t)c * n1 + aa], A2[(int64_t)b * n3 + c], s2);
-      AA[(int64_t)b * n1 + aa] = s2;
-    }
     for (int i = tid; i < n1; i += nth) perm[i] = i;
     __syncthreads();
     // column-pivoted Householder QR of KT (n2 x n1)
@@ -774,13 +870,16 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// scores and selection (Alg. 3 steps 11-27)
+// SS^T, F and the ridge of every update of a batch (Alg. 3 steps 11, 13, 17-18)
+hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
+  dim3 grid((b.ell + 15) / 16, (b.ell + 15) / 16, b.nz + 1);
+  hipLaunchKernelGGL(sst_batch_kernel, grid, dim3(16, 16), 0, s, b);
+  hipLaunchKernelGGL(tridiag_kernel, dim3(b.nz), dim3(1024), 0, s, b);
+  return hipGetLastError();
+}
+
+// scores and selection (Alg. 3 steps 17-27)
 hipError_t launch_update_select(const UpdArgs& a, hipStream_t s) {
-  {
-    dim3 grid((a.ell + 15) / 16, (a.ell + 15) / 16);
-    hipLaunchKernelGGL(sst_update_kernel, grid, dim3(16, 16), 0, s, a);
-  }
-  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(scores_kernel, dim3(a.t + a.cnt), dim3(64), 0, s, a);
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
@@ -788,21 +887,12 @@ hipError_t launch_update_select(const UpdArgs& a, hipStream_t s) {
 
 // new basis columns into the column pool and their Gram entries
 hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
-  {
-    const int nb = (int)std::min<int64_t>(1024, (a.m + 1023) / 1024);
-    if (a.data_f64)
-      hipLaunchKernelGGL(copy_new_kernel<double>, dim3(nb, a.t), dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL(copy_new_kernel<float>, dim3(nb, a.t), dim3(256), 0, s, a);
-  }
-  {
-    const int tt = (a.t + 63) / 64;
-    dim3 grid(a.gslabs, tt, tt);
-    if (a.data_f64)
-      hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(256), 0, s, a);
-  }
+  const int tt = (a.t + kGramTile - 1) / kGramTile;
+  dim3 grid(a.gslabs, tt, tt);
+  if (a.data_f64)
+    hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(1024), 0, s, a);
+  else
+    hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(1024), 0, s, a);
   hipLaunchKernelGGL(gram_zero_kernel, dim3(a.t), dim3(kMaxT), 0, s, a);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(a.t, 1), dim3(kMaxT), 0, s, a);
   return hipGetLastError();
@@ -815,6 +905,15 @@ hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
   {
     const int64_t tot = (int64_t)(a.ell + a.t) * a.t;
     hipLaunchKernelGGL(hutch_prod_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+  }
+  {
+    const int n3 = a.ell - a.n1 - a.n2;
+    const int64_t s0 = (int64_t)a.ell * a.t;
+    const int64_t s1 = (int64_t)a.n1 * a.n2 + (int64_t)a.n1 * a.t + (int64_t)a.n1 * n3 + (int64_t)n3 * a.n2;
+    const int64_t s2 = (int64_t)a.n1 * a.n2;
+    hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s0 + 255) / 256)), dim3(256), 0, s, a, 0);
+    hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s1 + 255) / 256)), dim3(256), 0, s, a, 1);
+    hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s2 + 255) / 256)), dim3(256), 0, s, a, 2);
   }
   hipLaunchKernelGGL(hutch_small_kernel, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();

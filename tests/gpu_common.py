@@ -92,6 +92,10 @@ def compare_updates(s, o, tol, log_prefix=""):
 # test matrix (~1e-5).
 SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-5}
 
+# Relative accuracy of the basis Gram G = A_J^T A_J: products of the data are
+# exact in binary64 and the sums are binary64 (another order than the oracle).
+GRAM_ACCURACY = {"f64": 1e-15, "f32": 1e-15, "bf16": 1e-15}
+
 
 def hutch_regrouped(S, SJ, P, G, F, n1, n2):
     """The NA-Hutch++ terms of the oracle's formula with the same products
@@ -139,6 +143,8 @@ def perturbation_tolerances(o, A_cols, sketch, draws=3, factor=10.0, seed=0):
         G = np.zeros((cfg.t, cfg.t))
         if occ.size:
             G[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
+        u_G = GRAM_ACCURACY[sketch]
+        dg = np.sqrt(np.abs(np.diag(G)))
         P0 = coeff_alg4(S, J)
         SJ0 = np.zeros((cfg.ell, cfg.t)); SJ0[:, occ] = S[:, J[occ]]
         h0 = nahutchpp(S, SJ0, P0, G, rec.F, cfg.n1, cfg.n2)
@@ -157,7 +163,9 @@ def perturbation_tolerances(o, A_cols, sketch, draws=3, factor=10.0, seed=0):
                 dtau = max(dtau, float(np.max(np.abs(tD - rec.tau_D) / rec.tau_D)))
             Pp = coeff_alg4(Sp, J)
             SJp = np.zeros((cfg.ell, cfg.t)); SJp[:, occ] = Sp[:, J[occ]]
-            hp = nahutchpp(Sp, SJp, Pp, G, rec.F, cfg.n1, cfg.n2)
+            xi = rng.standard_normal(G.shape)
+            Gp = G + u_G * np.outer(dg, dg) * (xi + xi.T) / 2
+            hp = nahutchpp(Sp, SJp, Pp, Gp, rec.F, cfg.n1, cfg.n2)
             dtr = max(dtr, abs(hp["tr_est"] - h0["tr_est"]))
             dgpp = max(dgpp, abs(hp["gpp"] - h0["gpp"]))
             dE2 = max(dE2, abs(hp["E2"] - h0["E2"]))

@@ -131,7 +131,9 @@ def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True):
             assert d <= tol[key][u], (u, key, g[key], h[key], tol[key][u])
     log("  NA-Hutch++ diff/tol " + " ".join(f"{k} {v:.2e}" for k, v in worst.items()))
     _, _, G = s.debug_state()
-    assert rel_fro(G, o.G) <= 1e-12
+    eg = rel_fro(G, o.G)
+    log(f"  Gram rel fro {eg:.2e}")
+    assert eg <= 1e-12
     # reconstruction of a column range
     n = A.shape[0]
     c0, c = max(0, n // 2 - 5), min(17, n)
@@ -219,3 +221,30 @@ def test_reset_and_rerun_are_bitwise_identical():
     s.finalize()
     assert np.array_equal(s.select(), J1)
     assert np.array_equal(s.coefficients(), P1)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_gram_and_estimate_terms_after_first_update(dtype):
+    # G = A_J^T A_J is formed from exact products in binary64; each NA-Hutch++
+    # term is checked against the oracle separately (well-conditioned data)
+    rng = np.random.default_rng(21)
+    m, t, ell = 4099, 40, 80
+    A = (rng.standard_normal((t, 12)) @ rng.standard_normal((12, m)) + 0.1 * rng.standard_normal((t, m))).astype(dtype)
+    sk = "f64" if dtype == np.float64 else "f32"
+    s = run_gpu(A, ell, t, t, sk, 31, 32)
+    o = run_oracle(A, ell, t, t, sk, 31, 32)
+    _, _, G = s.debug_state()
+    J = s.select()
+    occ = np.flatnonzero(J >= 0)
+    A64 = A.T.astype(np.float64)
+    Gx = np.zeros((t, t))
+    Gx[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
+    err = np.abs(G - Gx) / np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)) + 1e-300)
+    log(f"  Gram max scaled err {err.max():.2e} at {np.unravel_index(np.argmax(err), err.shape)}")
+    g = s.update(0)
+    h = o.records[0].hutch
+    log("  terms gpu " + " ".join(f"{k}={g[k]:.6e}" for k in ("term1", "h", "corr", "gpp", "E2")))
+    log("  terms orc " + " ".join(f"{k}={h[k]:.6e}" for k in ("term1", "h", "corr", "gpp", "E2")))
+    assert err.max() <= 1e-13
+    for k in ("term1", "h", "corr", "gpp"):
+        assert abs(g[k] - h[k]) <= 1e-7 * max(abs(h[k]), o.F), k
