@@ -18,6 +18,7 @@ namespace rid {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 
@@ -44,84 +45,121 @@ __device__ __forceinline__ bool sketch_item(const SketchArgs& a, int bid, int& s
 //
 // A workgroup of 8 waves owns (slab, 64*RBW test-matrix rows, 256 columns),
 // so every snapshot element is read from HBM by exactly one workgroup.  Wave w
-// owns row group w&1 (RBW blocks of 32 rows) and the column pair w>>1 (two
-// blocks of 32 columns): 2*RBW accumulator tiles.  Per 32-row chunk:
-//   * the snapshot chunk (32 rows x 256 columns) is read in 128-byte runs
-//     (8 lanes per column), rounded to bfloat16 and stored in LDS;
-//   * the matching 64*RBW x 32 tile of Omega is generated (one Philox call per
-//     8 rows x 1 data row) into LDS;
-// both double-buffered, so chunk c+1 is loaded and generated while the
-// matrix cores work on chunk c.
+// owns row group w/4 (RBW blocks of 32 rows) and the column pair w%4 (two
+// blocks of 32 columns): 2*RBW accumulator tiles; each SIMD (waves s, s+4)
+// holds one wave of each row group.  Per 32-row chunk:
+//   * the binary32 snapshot chunk (32 rows x 256 columns, 128-byte runs) is
+//     copied HBM -> LDS by the LDS-DMA path (global_load_lds_dwordx4) into a
+//     three-stage ring, so two chunks are in flight while one is consumed,
+//     without holding them in registers (the accumulators fill the register
+//     file); the consumer rounds its operands to bfloat16 and accumulates the
+//     binary64 column norms;
+//   * the matching 64*RBW x 32 tile of Omega is generated into LDS (double
+//     buffered) one chunk ahead.  Row-group-0 waves multiply first and
+//     generate second, row-group-1 waves the other way round, so each SIMD
+//     overlaps the matrix cores of one wave with the VALU work of the other.
+// LDS layout of a data stage: column c at 128*c bytes, its 16-byte slot j
+// holding rows 4(j ^ swz(c)).. (swizzled against bank conflicts of the
+// operand reads).
 // ---------------------------------------------------------------------------
 constexpr int kBf16Cols = 256;
+constexpr int kBf16KC = 32;
+constexpr int kBf16Stages = 3;
+
+__device__ __forceinline__ int bf16_swz(int c) { return (c ^ (c >> 3)) & 7; }
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// Each lane copies the 16 bytes at p to LDS byte address lds_base + 16*lane
+// (lds_base wave-uniform).  The copy is counted by vmcnt; the compiler does
+// not see the LDS write, so the kernel waits for it explicitly.
+__device__ __forceinline__ void lds_dma16(const gmem_t<float>* p, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(p), "s"(lds_base)
+               : "memory", "m0");
+}
+__device__ __forceinline__ void wait_dma_keep4() { asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); }
+__device__ __forceinline__ void wait_dma_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// LDS writes of this wave complete, then the workgroup barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 template <int RBW>
 __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
-  constexpr int KC = 32;                 // rows per chunk
+  constexpr int KC = kBf16KC;            // rows per chunk
   constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
-  constexpr int LDA = KC + 8;            // bf16 per LDS row (80 bytes)
-  constexpr int NGEN = (MROWS / 8) * KC; // Philox calls per chunk
+  constexpr int LDA = KC + 8;            // bf16 per Omega LDS row (80 bytes)
   __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
-  __shared__ __attribute__((aligned(16))) uint16_t dt[2][kBf16Cols * LDA];
+  __shared__ __attribute__((aligned(1024))) float dt[kBf16Stages][kBf16Cols * KC];
+  __shared__ double nsh[kBf16Cols];
   int slab, mt, nt;
   if (!sketch_item(a, blockIdx.x, slab, mt, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
-  const int rg = wave & 1, cp = wave >> 1;
+  const int rg = wave >> 2, cp = wave & 3;
   const int64_t r0 = (int64_t)slab * a.slab_rows;
   const int64_t r1 = min(a.m, r0 + a.slab_rows);
+  const int nch = (int)((r1 - r0 + KC - 1) / KC);
+  const bool ragged = (r1 - r0) % KC != 0;
   const int row_base = mt * MROWS;       // first test-matrix row of this workgroup
 
-  // staging: thread -> columns (tid>>3) + 64 i, rows 4 (tid&7) .. +4 of the chunk
-  const int scol = tid >> 3, srow = 4 * (tid & 7);
-  const gmem_t<float>* sp[4];
-  bool sok[4];
+  // LDS-DMA geometry: instruction i of wave w copies columns 8(4w+i)..+8 of the
+  // tile, 8 lanes per column.  Columns beyond the batch copy the tile's first
+  // column instead: their results are never stored.
+  const gmem_t<float>* dsrc[4];
+  int drow[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int c = nt * kBf16Cols + scol + 64 * i;
-    sok[i] = c < a.b;
-    sp[i] = gload_ptr(sok[i] ? reinterpret_cast<const float*>(a.colptr[a.c0 + c]) : nullptr);
+    const int cl = 8 * (4 * wave + i) + (lane >> 3);
+    const int cg = nt * kBf16Cols + cl;
+    const int cs = cg < a.b ? cg : nt * kBf16Cols;
+    dsrc[i] = gload_ptr(reinterpret_cast<const float*>(a.colptr[a.c0 + cs]));
+    drow[i] = 4 * ((lane & 7) ^ bf16_swz(cl));
   }
-  double nrm[4] = {0.0, 0.0, 0.0, 0.0};
+  // Rows wholly past the slab end are fetched from row r0 (in bounds) and the
+  // fix-up below zeroes them; a 16-byte run that straddles the end of the
+  // snapshot stays inside the 16-byte-aligned block holding its last row.
+  auto issue = [&](int c, int stage) {
+    const int64_t k0 = r0 + (int64_t)c * KC;
+    const uint32_t sb = lds_addr(&dt[stage][0]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int64_t row = k0 + drow[i];
+      if (row >= r1) row = r0;
+      lds_dma16(dsrc[i] + row, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(4 * wave + i) * 1024u));
+    }
+  };
+  // After this wave's copies of chunk c have landed: zero the rows past r1.
+  auto fixup = [&](int c, int stage) {
+    const int64_t k0 = r0 + (int64_t)c * KC;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = k0 + drow[i];
+      float* slot = &dt[stage][(8 * (4 * wave + i) + (lane >> 3)) * KC + 4 * (lane & 7)];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (row + e >= r1) slot[e] = 0.0f;
+    }
+  };
 
-  auto load_chunk = [&](int64_t k0, float4 xr[4]) {
-    const int64_t row = k0 + srow;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (sok[i] && row + 4 <= r1) {
-        xr[i] = gload_f4(sp[i] + row);
-      } else {
-        xr[i].x = (sok[i] && row + 0 < r1) ? sp[i][row + 0] : 0.0f;
-        xr[i].y = (sok[i] && row + 1 < r1) ? sp[i][row + 1] : 0.0f;
-        xr[i].z = (sok[i] && row + 2 < r1) ? sp[i][row + 2] : 0.0f;
-        xr[i].w = (sok[i] && row + 3 < r1) ? sp[i][row + 3] : 0.0f;
-      }
-    }
-  };
-  auto store_chunk = [&](const float4 xr[4], uint16_t* d) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      nrm[i] = fma((double)xr[i].x, (double)xr[i].x, nrm[i]);
-      nrm[i] = fma((double)xr[i].y, (double)xr[i].y, nrm[i]);
-      nrm[i] = fma((double)xr[i].z, (double)xr[i].z, nrm[i]);
-      nrm[i] = fma((double)xr[i].w, (double)xr[i].w, nrm[i]);
-      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-      bf16x4 v = {(__bf16)xr[i].x, (__bf16)xr[i].y, (__bf16)xr[i].z, (__bf16)xr[i].w};
-      *reinterpret_cast<bf16x4*>(&d[(scol + 64 * i) * LDA + srow]) = v;
-    }
-  };
+  // Gaussian tile: item = (row group g of 8 rows, column pair kp of the chunk);
+  // two Philox calls give the 8 x 2 block, written as packed bf16 pairs.
+  // Row groups at or beyond ell stay zero (written once below).
+  const int n_groups = min(MROWS / 8, max(0, (a.ell - row_base + 7) / 8));
+  const int n_items = n_groups * (KC / 2);
   auto gen = [&](int64_t k0, uint16_t* d) {
-    for (int it = tid; it < NGEN; it += 512) {
-      const int g = it / KC, k = it % KC;
-      uint16_t* dst = d + (8 * g) * LDA + k;
-      if (row_base + 8 * g < a.ell) {
-        float z[8];
-        omega8_f32(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), z);
+    for (int it = tid; it < n_items; it += 512) {
+      const int g = it / (KC / 2), kp = it % (KC / 2);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(d + (8 * g) * LDA + 2 * kp);
+      float z0[8], z1[8];
+      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp), (uint32_t)(row_base / 8 + g), z0);
+      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp + 1), (uint32_t)(row_base / 8 + g), z1);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) dst[j * LDA] = __builtin_bit_cast(uint16_t, (__bf16)z[j]);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) dst[j * LDA] = 0;
+      for (int j = 0; j < 8; ++j) {
+        const bf16x2 v = {(__bf16)z0[j], (__bf16)z1[j]};
+        dst[j * (LDA / 2)] = __builtin_bit_cast(uint32_t, v);
       }
     }
   };
@@ -133,43 +171,79 @@ __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.0f;
+  double nrm[2] = {0.0, 0.0};
 
-  {
-    float4 x0[4];
-    load_chunk(r0, x0);
-    store_chunk(x0, dt[0]);
-    gen(r0, om[0]);
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int64_t k0 = r0; k0 < r1; k0 += KC) {
-    const bool more = k0 + KC < r1;
-    float4 xn[4];
-    if (more) {
-      load_chunk(k0 + KC, xn);
-      gen(k0 + KC, om[cur ^ 1]);
-    }
-    const uint16_t* O = om[cur];
-    const uint16_t* D = dt[cur];
+  // One chunk on the matrix cores.  Lane (l32, half) reads rows
+  // 16 s + 8 half .. +8 of column (2 cp + cc) 32 + l32; row group rg squares
+  // the rows of k-step s == rg, so each element enters the norm once.
+  auto mfma_chunk = [&](const uint16_t* O, const float* D) {
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
       bf16x8 bop[2];
 #pragma unroll
-      for (int c = 0; c < 2; ++c)
-        bop[c] = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const u16x8*>(&D[((2 * cp + c) * 32 + l32) * LDA + 16 * s + 8 * half]));
+      for (int cc = 0; cc < 2; ++cc) {
+        const int cl = (2 * cp + cc) * 32 + l32;
+        const int key = bf16_swz(cl);
+        const float* colb = D + cl * KC;
+        const float4 x0 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half) ^ key));
+        const float4 x1 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half + 1) ^ key));
+        if (s == rg) {
+          double t = nrm[cc];
+          t = fma((double)x0.x, (double)x0.x, t);
+          t = fma((double)x0.y, (double)x0.y, t);
+          t = fma((double)x0.z, (double)x0.z, t);
+          t = fma((double)x0.w, (double)x0.w, t);
+          t = fma((double)x1.x, (double)x1.x, t);
+          t = fma((double)x1.y, (double)x1.y, t);
+          t = fma((double)x1.z, (double)x1.z, t);
+          t = fma((double)x1.w, (double)x1.w, t);
+          nrm[cc] = t;
+        }
+        bop[cc] = bf16x8{(__bf16)x0.x, (__bf16)x0.y, (__bf16)x0.z, (__bf16)x0.w,
+                         (__bf16)x1.x, (__bf16)x1.y, (__bf16)x1.z, (__bf16)x1.w};
+      }
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
         const bf16x8 av = __builtin_bit_cast(
             bf16x8, *reinterpret_cast<const u16x8*>(&O[((rg * RBW + r) * 32 + l32) * LDA + 16 * s + 8 * half]));
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-          acc[r][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bop[c], acc[r][c], 0, 0, 0);
+        for (int cc = 0; cc < 2; ++cc)
+          acc[r][cc] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bop[cc], acc[r][cc], 0, 0, 0);
       }
     }
-    if (more) store_chunk(xn, dt[cur ^ 1]);
-    __syncthreads();
-    cur ^= 1;
+  };
+
+  // prologue: chunks 0 and 1 in flight, Omega of chunk 0, zero rows of Omega
+  issue(0, 0);
+  if (nch > 1) issue(1, 1);
+  for (int i = tid + n_groups * 8 * (LDA / 2); i < MROWS * (LDA / 2); i += 512) {
+    reinterpret_cast<uint32_t*>(om[0])[i] = 0u;
+    reinterpret_cast<uint32_t*>(om[1])[i] = 0u;
+  }
+  gen(r0, om[0]);
+  if (nch > 1) wait_dma_keep4(); else wait_dma_all();
+  if (nch == 1 && ragged) fixup(0, 0);
+  lds_barrier();
+
+  int st_cur = 0;
+  for (int c = 0; c < nch; ++c) {
+    const int st_next = st_cur == kBf16Stages - 1 ? 0 : st_cur + 1;
+    const int st_issue = st_next == kBf16Stages - 1 ? 0 : st_next + 1;
+    if (c + 2 < nch) issue(c + 2, st_issue);
+    const int64_t k1 = r0 + (int64_t)(c + 1) * KC;
+    const uint16_t* O = om[c & 1];
+    uint16_t* On = om[(c + 1) & 1];
+    if (rg == 0) {
+      mfma_chunk(O, dt[st_cur]);
+      if (c + 1 < nch) gen(k1, On);
+    } else {
+      if (c + 1 < nch) gen(k1, On);
+      mfma_chunk(O, dt[st_cur]);
+    }
+    if (c + 2 < nch) wait_dma_keep4(); else wait_dma_all();
+    if (ragged && c + 1 == nch - 1) fixup(c + 1, st_next);
+    lds_barrier();
+    st_cur = st_next;
   }
 
   float* part = reinterpret_cast<float*>(a.part);
@@ -188,14 +262,22 @@ __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
       }
   }
   if (mt == 0) {
+    // lanes l and l + 32 hold the two row halves of one column
+    double t[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double t = nrm[i];
-      t += __shfl_xor(t, 1);
-      t += __shfl_xor(t, 2);
-      t += __shfl_xor(t, 4);
-      if (sok[i] && (tid & 7) == 0)
-        a.normpart[(int64_t)slab * a.b_max + nt * kBf16Cols + scol + 64 * i] = t;
+    for (int cc = 0; cc < 2; ++cc) t[cc] = nrm[cc] + __shfl_xor(nrm[cc], 32);
+    if (rg == 0 && half == 0) {
+      nsh[(2 * cp) * 32 + l32] = t[0];
+      nsh[(2 * cp + 1) * 32 + l32] = t[1];
+    }
+    __syncthreads();
+    if (rg == 1 && half == 0) {
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const int cl = (2 * cp + cc) * 32 + l32;
+        const int col = nt * kBf16Cols + cl;
+        if (col < a.b) a.normpart[(int64_t)slab * a.b_max + col] = nsh[cl] + t[cc];
+      }
     }
   }
 }

@@ -92,12 +92,14 @@ def test_sketch_matches_oracle(sketch, m, n, ell, tol):
     assert np.max(np.abs(q - qo) / qo) <= 1e-13
 
 
-def test_sketch_is_independent_of_batching():
+@pytest.mark.parametrize("sketch,ell", [("f32", 64), ("bf16", 64), ("bf16", 300)])
+def test_sketch_is_independent_of_batching(sketch, ell):
+    log("batching independence", sketch, ell)
     rng = np.random.default_rng(5)
     A = rng.standard_normal((200, 50_001)).astype(np.float32)
-    ref = run_gpu(A, 64, 8, 8, "f32", 3, 4, finalize=False, lookahead=256).debug_state()
+    ref = run_gpu(A, ell, 8, 8, sketch, 3, 4, finalize=False, lookahead=256).debug_state()
     for batch, la in [(1, 0), (7, 100), (64, 64)]:
-        got = run_gpu(A, 64, 8, 8, "f32", 3, 4, batch=batch, finalize=False, lookahead=la).debug_state()
+        got = run_gpu(A, ell, 8, 8, sketch, 3, 4, batch=batch, finalize=False, lookahead=la).debug_state()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
