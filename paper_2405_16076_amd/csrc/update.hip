@@ -702,14 +702,15 @@ __global__ void hutch_mid_kernel(UpdArgs a, int stage) {
     }
     return;
   }
+  // X and AA row-major (row aa contiguous), for the reflector sweeps of the small kernel
   if (idx < (int64_t)n1 * n2) {
-    const int aa = (int)(idx % n1), b = (int)(idx / n1);
+    const int b = (int)(idx % n2), aa = (int)(idx / n2);
     double s = 0.0;
     for (int j = 0; j < t; ++j) s = fma(w.YG[(int64_t)j * n1 + aa], Y[(int64_t)j * n + n1 + b], s);
-    w.X[(int64_t)b * n1 + aa] = s;
+    w.X[(int64_t)aa * n2 + b] = s;
     double s2 = 0.0;
     for (int c = 0; c < n3; ++c) s2 = fma(w.A1[(int64_t)c * n1 + aa], w.A2[(int64_t)b * n3 + c], s2);
-    w.AA[(int64_t)b * n1 + aa] = s2;
+    w.AA[(int64_t)aa * n2 + b] = s2;
   }
 }
 
@@ -718,19 +719,21 @@ __global__ void hutch_mid_kernel(UpdArgs a, int stage) {
 //   K = Y1 SJ2^T, X = Y1 G Y2^T, A1 = Y1 SJ3^T, A2 = SJ3 Y2^T,
 //   term1 = tr(K^+ X), corr = tr(K^+ A1 A2), h = <Y3, SJ3>, gpp = <G, P P^T>.
 // K^+ is applied through a column-pivoted Householder QR of K^T truncated to
-// its numerical rank (max(n1, n2) eps |R_00|): K^- = Q_r R11^{-T} [I 0] Pi^T,
-// the pseudo-inverse when K has full row rank.
+// its numerical rank r (max(n1, n2) eps |R_00|): K^- = Q_r R11^{-T} [I 0] Pi^T,
+// the pseudo-inverse when K has full row rank.  With Z = rows Pi_r of X Q_r,
+// tr(K^- X) = tr(R11^{-T} Z) = <R11^{-1}, Z>_F; R11^{-1} is formed in LDS.
 __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
+  constexpr int kMaxN1 = kMaxEll / 4;
   __shared__ double red[16];
   __shared__ double v[kMaxEll];
-  __shared__ double cn[kMaxEll];
-  __shared__ int perm[kMaxEll];
+  __shared__ double cn[kMaxN1];
+  __shared__ int perm[kMaxN1];
+  __shared__ double rinv[kMaxN1 * kMaxN1];
   const int n = a.ell, t = a.t, n1 = a.n1, n2 = a.n2, n3 = a.ell - a.n1 - a.n2;
   const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
-  const DevScalars* sc = a.sc;
   rid_update* rec = a.recs + a.u;
   const double F = a.Fu[a.u];
-  // work layout: KT n2 x n1 (ld n2), X and AA n1 x n2 (ld n1), SJ l x t
+  // work layout: KT n2 x n1 (column-major, ld n2), X and AA n1 x n2 (row-major), SJ l x t
   const HutchWork hwk = hutch_work(a);
   double* KT = hwk.KT;
   double* X = hwk.X;
@@ -766,13 +769,23 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
         if (lane == 0) cn[c] = s;
       }
       __syncthreads();
-      int piv = jj;
-      double best = cn[jj];
-      for (int c = jj + 1; c < n1; ++c)
+      // pivot: the first column of largest norm, found by every wave
+      int piv = n1;
+      double best = -1.0;
+      for (int c = jj + lane; c < n1; c += 64)
         if (cn[c] > best) {
           best = cn[c];
           piv = c;
         }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int op = __shfl_xor(piv, off);
+        if (ob > best || (ob == best && op < piv)) {
+          best = ob;
+          piv = op;
+        }
+      }
       if (jj == 0) r00 = sqrt(best);
       if (!(sqrt(best) > (double)max(n1, n2) * 2.220446049250313e-16 * r00) || best == 0.0) break;
       if (piv != jj) {
@@ -805,9 +818,7 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
       }
       __syncthreads();
       for (int i = 1 + tid; i < len; i += nth) x[i] = v[i];
-      if (tid == 0) {
-        x[0] = beta;
-      }
+      if (tid == 0) x[0] = beta;
       if (tau != 0.0) {
         for (int c = jj + 1 + wv; c < n1; c += nw) {
           double* y = KT + (int64_t)c * n2 + jj;
@@ -816,40 +827,45 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
           const double g = tau * wave_sum(s);
           for (int i = lane; i < len; i += 64) y[i] -= g * v[i];
         }
-        // rows of X and AA: x^T <- x^T H  (apply H to the row vectors)
+        // rows of X and AA: x^T <- x^T H
         for (int rr = wv; rr < 2 * n1; rr += nw) {
-          double* row = (rr < n1) ? X + rr : AA + (rr - n1);
+          double* row = ((rr < n1) ? X + (int64_t)rr * n2 : AA + (int64_t)(rr - n1) * n2) + jj;
           double s = 0.0;
-          for (int i = lane; i < len; i += 64) s = fma(v[i], row[(int64_t)(jj + i) * n1], s);
+          for (int i = lane; i < len; i += 64) s = fma(v[i], row[i], s);
           const double g = tau * wave_sum(s);
-          for (int i = lane; i < len; i += 64) row[(int64_t)(jj + i) * n1] -= g * v[i];
+          for (int i = lane; i < len; i += 64) row[i] -= g * v[i];
         }
       }
       __syncthreads();
       ++rank;
     }
     trunc = (rank < n1);
-    // Z = rows perm[0..rank) of (X Q)(:, 0:rank); W = R11^{-T} Z; trace(W)
-    // One thread per right-hand side b (column of Z) and matrix (X or AA).
+    // R11^{-1} (upper triangular, row-major in LDS), rows from the bottom:
+    // Rinv(i, j) = (delta_ij - sum_{i<k<=j} R(i, k) Rinv(k, j)) / R(i, i),
+    // R(i, k) = KT[k n2 + i].  Eight lanes per entry j.
+    const int r = rank;
+    for (int i = r - 1; i >= 0; --i) {
+      for (int k = i + tid; k < r; k += nth) v[k] = KT[(int64_t)k * n2 + i];
+      __syncthreads();
+      const double rii = v[i];
+      const int j = i + (tid >> 3), q = tid & 7;
+      double s = 0.0;
+      if (j < r)
+        for (int k = i + 1 + q; k <= j; k += 8) s = fma(v[k], rinv[k * r + j], s);
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      if (j < r && q == 0) rinv[i * r + j] = ((j == i ? 1.0 : 0.0) - s) / rii;
+      __syncthreads();
+    }
+    // term1 = <R11^{-1}, Z_X>, corr = <R11^{-1}, Z_AA>, Z(i, j) = M(perm[i], j)
     double tr_x = 0.0, tr_a = 0.0;
-    for (int job = tid; job < 2 * rank; job += nth) {
-      const int b = job % rank;
-      const double* M = (job < rank) ? X : AA;
-      // forward substitution on R11^T w = Z(:, b), only w_b is needed, but
-      // w_b depends on w_0..w_{b-1}
-      double wv_local[kMaxEll / 4];
-      double wb = 0.0;
-      for (int i = 0; i <= b; ++i) {
-        double s = M[(int64_t)b * n1 + perm[i]];
-        for (int kq = 0; kq < i; ++kq) s -= KT[(int64_t)i * n2 + kq] * wv_local[kq];
-        const double wi = s / KT[(int64_t)i * n2 + i];
-        wv_local[i] = wi;
-        wb = wi;
-      }
-      if (job < rank)
-        tr_x += wb;
-      else
-        tr_a += wb;
+    for (int idx = tid; idx < r * r; idx += nth) {
+      const int i = idx / r, j = idx % r;
+      if (j < i) continue;
+      const double ri = rinv[idx];
+      tr_x = fma(ri, X[(int64_t)perm[i] * n2 + j], tr_x);
+      tr_a = fma(ri, AA[(int64_t)perm[i] * n2 + j], tr_a);
     }
     term1 = block_sum(tr_x, red);
     corr = block_sum(tr_a, red);
