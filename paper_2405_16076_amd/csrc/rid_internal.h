@@ -196,6 +196,31 @@ struct DevScalars {
   int32_t slot_src[kMaxT];   // buffer position of a slot filled by the running update, else -1
 };
 
+// ---------------------------------------------------------------------------
+// LDS-DMA staging (global_load_lds_dwordx4) shared by the streaming kernels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// Each lane copies the 16 bytes at p to LDS byte address lds_base + 16*lane
+// (lds_base wave-uniform).  The copy is counted by vmcnt; the compiler does
+// not see the LDS write, so the kernel waits for it explicitly.
+__device__ __forceinline__ void lds_dma16(const gmem_t<float>* p, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(p), "s"(lds_base)
+               : "memory", "m0");
+}
+__device__ __forceinline__ void wait_dma_keep4() { asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); }
+__device__ __forceinline__ void wait_dma_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// LDS writes of this wave complete, then the workgroup barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// 16-byte slot j of a 128-byte staged column c lives at slot j ^ swz(c): the
+// operand reads of 16 consecutive columns then spread over the LDS banks.
+__device__ __forceinline__ int col_swz(int c) { return (c ^ (c >> 3)) & 7; }
+
 struct SketchArgs {
   const uint64_t* colptr;  // device address of every pushed column, by global index
   int64_t c0;              // first global column of the batch

@@ -66,26 +66,6 @@ constexpr int kBf16Cols = 256;
 constexpr int kBf16KC = 32;
 constexpr int kBf16Stages = 3;
 
-__device__ __forceinline__ int bf16_swz(int c) { return (c ^ (c >> 3)) & 7; }
-
-__device__ __forceinline__ uint32_t lds_addr(const void* p) {
-  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
-}
-
-// Each lane copies the 16 bytes at p to LDS byte address lds_base + 16*lane
-// (lds_base wave-uniform).  The copy is counted by vmcnt; the compiler does
-// not see the LDS write, so the kernel waits for it explicitly.
-__device__ __forceinline__ void lds_dma16(const gmem_t<float>* p, uint32_t lds_base) {
-  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(p), "s"(lds_base)
-               : "memory", "m0");
-}
-__device__ __forceinline__ void wait_dma_keep4() { asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); }
-__device__ __forceinline__ void wait_dma_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-// LDS writes of this wave complete, then the workgroup barrier.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
 template <int RBW>
 __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
   constexpr int KC = kBf16KC;            // rows per chunk
@@ -116,7 +96,7 @@ __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
     const int cg = nt * kBf16Cols + cl;
     const int cs = cg < a.b ? cg : nt * kBf16Cols;
     dsrc[i] = gload_ptr(reinterpret_cast<const float*>(a.colptr[a.c0 + cs]));
-    drow[i] = 4 * ((lane & 7) ^ bf16_swz(cl));
+    drow[i] = 4 * ((lane & 7) ^ col_swz(cl));
   }
   // Rows wholly past the slab end are fetched from row r0 (in bounds) and the
   // fix-up below zeroes them; a 16-byte run that straddles the end of the
@@ -183,7 +163,7 @@ __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc) {
         const int cl = (2 * cp + cc) * 32 + l32;
-        const int key = bf16_swz(cl);
+        const int key = col_swz(cl);
         const float* colb = D + cl * KC;
         const float4 x0 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half) ^ key));
         const float4 x1 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half + 1) ^ key));

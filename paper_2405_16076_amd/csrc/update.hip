@@ -481,8 +481,208 @@ __global__ __launch_bounds__(1024) void gram_kernel(UpdArgs a) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int ql = bq * 16 + k4 + 4 * v;
-      if (ql < nq) out[(int64_t)(qt * kGramTile + ql) * a.t + jt * kGramTile + jl] = acc[b][v];
+      if (ql < nq) {
+        out[(int64_t)(qt * kGramTile + ql) * a.t + jt * kGramTile + jl] = acc[b][v];
+        if (sym && bj > bq) out[(int64_t)(jt * kGramTile + jl) * a.t + qt * kGramTile + ql] = acc[b][v];
+      }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gram entries for binary32 data.  One workgroup of 4 waves per (row slab,
+// group of up to 16 output tiles of 32 x 32); a wave owns up to 4 tiles, each
+// as 2 x 2 blocks of v_mfma_f64_16x16x4_f64.  The staged columns (new slots,
+// then occupied slots unless the two lists coincide) are copied HBM -> LDS by
+// LDS-DMA in 32-row chunks, double-buffered, one chunk ahead.  MFMA step s of a
+// chunk pairs lane (i16, k4) with row 8 k4 + s of its column, so a lane's eight
+// operands of one column are one contiguous 32-byte run (two ds_read_b128).
+// Products of binary32 data are exact in binary64 and all sums are binary64.
+// Workgroups of tile group 0 also copy the new columns into the pool.
+// ---------------------------------------------------------------------------
+constexpr int kGramKC = 32;
+constexpr int kGramWaves = 4;
+constexpr int kGramTPW = 4;                        // tiles per wave
+constexpr int kGramGroup = kGramWaves * kGramTPW;  // tiles per workgroup
+
+__host__ __device__ inline int gram_stage_cols(int t) { return (2 * t + 7) / 8 * 8; }
+
+__global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) {
+  extern __shared__ __attribute__((aligned(1024))) float gsm[];
+  const DevScalars* sc = a.sc;
+  const int nq = sc->n_new, nj = sc->n_occ;
+  if (nq == 0) return;
+  const bool sym = (nq == nj);
+  const int TQ = (nq + 31) / 32, TJ = (nj + 31) / 32;
+  const int NT = sym ? TQ * (TQ + 1) / 2 : TQ * TJ;
+  const int g0 = blockIdx.y * kGramGroup;
+  if (g0 >= NT) return;
+  const int ncap = gram_stage_cols(a.t);
+  const int ncol = sym ? nq : nq + nj;
+  const int nblk = (ncol + 7) / 8;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  const int slab = blockIdx.x;
+  const int64_t r0 = (int64_t)slab * a.gslab_rows;
+  const int64_t r1 = min(a.m, r0 + a.gslab_rows);
+  const int nch = (int)((r1 - r0 + kGramKC - 1) / kGramKC);
+  const bool ragged = (r1 - r0) % kGramKC != 0;
+  const int stage_floats = ncap * kGramKC;
+  // column sources (device addresses) of the staged list, in LDS after the two stages
+  uint64_t* srcs = reinterpret_cast<uint64_t*>(gsm + 2 * stage_floats);
+  const float* cpool = reinterpret_cast<const float*>(a.cpool);
+  for (int c = tid; c < nblk * 8; c += kGramWaves * 64) {
+    const int cc = c < ncol ? c : 0;  // columns past the list copy column 0 (results dropped)
+    const float* pc;
+    if (cc < nq) {
+      pc = reinterpret_cast<const float*>(a.colptr[a.c0 + sc->new_src[cc]]);
+    } else {
+      const int slot = sc->occ_slot[cc - nq];
+      const int s = sc->slot_src[slot];
+      pc = (s >= 0) ? reinterpret_cast<const float*>(a.colptr[a.c0 + s]) : cpool + (int64_t)slot * a.ldc;
+    }
+    srcs[c] = reinterpret_cast<uint64_t>(pc);
+  }
+  // pool slots of the new columns
+  int* dslot = reinterpret_cast<int*>(srcs + nblk * 8);
+  for (int q = tid; q < nq; q += kGramWaves * 64) dslot[q] = sc->new_slot[q];
+  __syncthreads();
+  // this wave's DMA blocks: wave, wave + 4, ... (8 columns of 128 bytes each)
+  const int ninst = nblk > wave ? (nblk - wave + kGramWaves - 1) / kGramWaves : 0;
+  auto issue = [&](int c, int st) {
+    const int64_t k0 = r0 + (int64_t)c * kGramKC;
+    const uint32_t sb = lds_addr(gsm + st * stage_floats);
+    for (int i = 0; i < ninst; ++i) {
+      const int col = 8 * (wave + kGramWaves * i) + (lane >> 3);
+      int64_t row = k0 + 4 * ((lane & 7) ^ col_swz(col));
+      if (row >= r1) row = r0;
+      const gmem_t<float>* p = gload_ptr(reinterpret_cast<const float*>(srcs[col]));
+      lds_dma16(p + row, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(wave + kGramWaves * i) * 1024u));
+    }
+  };
+  auto fixup = [&](int c, int st) {
+    const int64_t k0 = r0 + (int64_t)c * kGramKC;
+    for (int i = 0; i < ninst; ++i) {
+      const int col = 8 * (wave + kGramWaves * i) + (lane >> 3);
+      const int64_t row = k0 + 4 * ((lane & 7) ^ col_swz(col));
+      float* slot = gsm + st * stage_floats + col * kGramKC + 4 * (lane & 7);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (row + e >= r1) slot[e] = 0.0f;
+    }
+  };
+
+  // this wave's tiles
+  int tq[kGramTPW], tj[kGramTPW];
+  int ntw = 0;
+#pragma unroll
+  for (int ti = 0; ti < kGramTPW; ++ti) {
+    const int tile = g0 + wave + kGramWaves * ti;
+    tq[ti] = 0;
+    tj[ti] = 0;
+    if (tile < NT && tile < g0 + kGramGroup) {
+      if (sym) {
+        int r = 0, rem = tile;
+        while (rem >= TQ - r) {
+          rem -= TQ - r;
+          ++r;
+        }
+        tq[ti] = r;
+        tj[ti] = r + rem;
+      } else {
+        tq[ti] = tile / TJ;
+        tj[ti] = tile % TJ;
+      }
+      ntw = ti + 1;
+    }
+  }
+  f64x4_g acc[kGramTPW][2][2];
+#pragma unroll
+  for (int ti = 0; ti < kGramTPW; ++ti)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[ti][x][y] = f64x4_g{0.0, 0.0, 0.0, 0.0};
+
+  // eight binary32 rows 8 k4 .. 8 k4 + 7 of staged column c
+  auto frag = [&](int st, int c, float out[8]) {
+    c = min(c, ncap - 1);
+    const float* col = gsm + st * stage_floats + c * kGramKC;
+    const int key = col_swz(c);
+    const float4 x0 = *reinterpret_cast<const float4*>(col + 4 * ((2 * k4) ^ key));
+    const float4 x1 = *reinterpret_cast<const float4*>(col + 4 * ((2 * k4 + 1) ^ key));
+    out[0] = x0.x; out[1] = x0.y; out[2] = x0.z; out[3] = x0.w;
+    out[4] = x1.x; out[5] = x1.y; out[6] = x1.z; out[7] = x1.w;
+  };
+  const bool copy_pool = blockIdx.y == 0;
+  auto pool_copy = [&](int c, int st) {
+    const int64_t k0 = r0 + (int64_t)c * kGramKC;
+    float* pool = reinterpret_cast<float*>(a.cpool);
+    for (int it = tid; it < nq * 8; it += kGramWaves * 64) {
+      const int q = it >> 3, p = it & 7;
+      const int64_t row = k0 + 4 * (p ^ col_swz(q));
+      const float4 x = *reinterpret_cast<const float4*>(gsm + st * stage_floats + q * kGramKC + 4 * p);
+      gmem_t<float>* dst = gstore_ptr(pool + (int64_t)dslot[q] * a.ldc + row);
+      if (row + 4 <= r1) {
+        gstore_f4(dst, x);
+      } else {
+        const float xv[4] = {x.x, x.y, x.z, x.w};
+        for (int e = 0; e < 4; ++e)
+          if (row + e < r1) dst[e] = xv[e];
+      }
+    }
+  };
+
+  issue(0, 0);
+  wait_dma_all();
+  if (nch == 1 && ragged) fixup(0, 0);
+  lds_barrier();
+  for (int c = 0; c < nch; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < nch) issue(c + 1, cur ^ 1);
+    const int st = cur;
+#pragma unroll
+    for (int ti = 0; ti < kGramTPW; ++ti) {
+      if (ti < ntw) {
+        float fa[2][8], fb[2][8];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) frag(st, 32 * tq[ti] + 16 * x + i16, fa[x]);
+#pragma unroll
+        for (int y = 0; y < 2; ++y) frag(st, (sym ? 0 : nq) + 32 * tj[ti] + 16 * y + i16, fb[y]);
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[ti][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)fa[x][s8], (double)fb[y][s8],
+                                                                   acc[ti][x][y], 0, 0, 0);
+      }
+    }
+    if (copy_pool) pool_copy(c, cur);
+    wait_dma_all();
+    if (ragged && c + 1 == nch - 1) fixup(c + 1, cur ^ 1);
+    lds_barrier();
+  }
+
+  double* out = a.gpart + (int64_t)slab * a.t * a.t;
+#pragma unroll
+  for (int ti = 0; ti < kGramTPW; ++ti) {
+    if (ti >= ntw) continue;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int j = 32 * tj[ti] + 16 * y + i16;
+        if (j >= nj) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = 32 * tq[ti] + 16 * x + k4 + 4 * v;
+          if (q >= nq) continue;
+          out[(int64_t)q * a.t + j] = acc[ti][x][y][v];
+          if (sym && tj[ti] > tq[ti]) out[(int64_t)j * a.t + q] = acc[ti][x][y][v];
+        }
+      }
   }
 }
 
@@ -498,15 +698,8 @@ __global__ void gram_reduce_kernel(UpdArgs a) {
   const DevScalars* sc = a.sc;
   const int q = blockIdx.x, jj = threadIdx.x + blockIdx.y * blockDim.x;
   if (q >= sc->n_new || jj >= sc->n_occ) return;
-  // when every occupied slot is new, only blocks on or above the diagonal
-  // (within a 160-slot tile) were computed: read the transposed pair below it
-  int qq = q, jq = jj;
-  if (sc->n_new == sc->n_occ && q / kGramTile == jj / kGramTile && (jj % kGramTile) / 16 < (q % kGramTile) / 16) {
-    qq = jj;
-    jq = q;
-  }
   double s = 0.0;
-  for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + qq) * a.t + jq];
+  for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
   const int si = sc->new_slot[q], sj = sc->occ_slot[jj];
   a.G[(int64_t)sj * a.t + si] = s;
   a.G[(int64_t)si * a.t + sj] = s;
@@ -903,12 +1096,22 @@ hipError_t launch_update_select(const UpdArgs& a, hipStream_t s) {
 
 // new basis columns into the column pool and their Gram entries
 hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
-  const int tt = (a.t + kGramTile - 1) / kGramTile;
-  dim3 grid(a.gslabs, tt, tt);
-  if (a.data_f64)
-    hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(1024), 0, s, a);
-  else
-    hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(1024), 0, s, a);
+  if (a.data_f64) {
+    const int tt = (a.t + kGramTile - 1) / kGramTile;
+    hipLaunchKernelGGL(gram_kernel<double>, dim3(a.gslabs, tt, tt), dim3(1024), 0, s, a);
+  } else {
+    const int tq = (a.t + 31) / 32;
+    const int groups = (tq * tq + kGramGroup - 1) / kGramGroup;
+    const size_t lds = (size_t)2 * gram_stage_cols(a.t) * kGramKC * sizeof(float) +
+                       (size_t)gram_stage_cols(a.t) * sizeof(uint64_t) + (size_t)a.t * sizeof(int);
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(gram_f32_kernel, dim3(a.gslabs, groups), dim3(64 * kGramWaves), lds, s, a);
+  }
   hipLaunchKernelGGL(gram_zero_kernel, dim3(a.t), dim3(kMaxT), 0, s, a);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(a.t, 1), dim3(kMaxT), 0, s, a);
   return hipGetLastError();

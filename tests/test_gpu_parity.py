@@ -250,3 +250,27 @@ def test_gram_and_estimate_terms_after_first_update(dtype):
     assert err.max() <= 1e-13
     for k in ("term1", "h", "corr", "gpp"):
         assert abs(g[k] - h[k]) <= 1e-7 * max(abs(h[k]), o.F), k
+
+
+@pytest.mark.parametrize("growth", [1.0, 1.03])
+def test_gram_incremental_matches_exact_products(growth):
+    # G is built incrementally over several updates (all-new first update, then
+    # new x occupied blocks, possibly two tile groups when many slots refill);
+    # after the last update it must equal A_J^T A_J of the final J.  Columns
+    # growing in norm make old columns lose leverage, so many slots refill.
+    rng = np.random.default_rng(23)
+    m, n, ell, t = 20_011, 600, 300, 150
+    A = (rng.standard_normal((n, m)) * (growth ** np.arange(n))[:, None]).astype(np.float32)
+    s = run_gpu(A, ell, t, t, "f32", 41, 42, batch=100)
+    info = s.info()
+    fills = [s.update(u)["n_filled"] for u in range(int(info.n_updates))]
+    log(f"  growth {growth}: filled per update {fills}")
+    _, _, G = s.debug_state()
+    J = s.select()
+    occ = np.flatnonzero(J >= 0)
+    A64 = A.T.astype(np.float64)
+    Gx = np.zeros((t, t))
+    Gx[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
+    err = np.abs(G - Gx) / np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)) + 1e-300)
+    log(f"  Gram max scaled err {err.max():.2e}")
+    assert err.max() <= 1e-13
