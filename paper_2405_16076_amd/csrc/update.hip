@@ -768,6 +768,142 @@ __global__ __launch_bounds__(1024) void alg4_qr_kernel(UpdArgs a) {
   }
 }
 
+// The same factorization with Omega A_J held in registers: column c lives in
+// wave c % NW (slot c / NW), row r in lane r % 64 (element r / 64).  Step jj:
+// the owner wave of column jj forms the reflector and publishes it in LDS
+// (double-buffered by step parity), one barrier, then every wave applies it to
+// its own columns, with the wave sums of a batch of columns interleaved.
+// E = ceil(l / 64), NS = ceil(t / NW).
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], o);
+}
+
+template <int E, int NS, int NW>
+__global__ __launch_bounds__(64 * NW) void alg4_qr_reg_kernel(UpdArgs a) {
+  __shared__ double vb[2][64 * E];
+  __shared__ double tb[2];
+  const int n = a.ell, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  DevScalars* sc = a.sc;
+  const int no = sc->n_occ;
+  double col[NS][E];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = wave + NW * s;
+    const double* src = (c < no) ? a.S + a.J[sc->occ_slot[c]] * n : nullptr;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int r = lane + 64 * e;
+      col[s][e] = (c < no && r < n) ? src[r] : 0.0;
+    }
+  }
+  const int nsteps = min(no, n);
+  for (int jj = 0; jj < nsteps; ++jj) {
+    const int ow = jj % NW, os = jj / NW, buf = jj & 1;
+    if (wave == ow) {
+      double x[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) x[e] = 0.0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s == os)
+#pragma unroll
+          for (int e = 0; e < E; ++e) x[e] = col[s][e];
+      double part = 0.0, al = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = lane + 64 * e;
+        if (r > jj && r < n) part = fma(x[e], x[e], part);
+        if (e == jj / 64) al = x[e];
+      }
+      const double xn2 = wave_sum(part);
+      const double alpha = __shfl(al, jj & 63);
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (xn2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = lane + 64 * e;
+        const double vr = (r == jj) ? 1.0 : ((r > jj && r < n) ? x[e] * scal : 0.0);
+        vb[buf][r] = vr;
+        if (r == jj) x[e] = beta;
+        else if (r > jj) x[e] = vr;
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (s == os)
+#pragma unroll
+          for (int e = 0; e < E; ++e) col[s][e] = x[e];
+      if (lane == 0) {
+        tb[buf] = tau;
+        a.qr_tau[jj] = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = tb[buf];
+    if (tau != 0.0) {
+      double v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = lane + 64 * e;
+        v[e] = (r >= jj && r < n) ? vb[buf][r] : 0.0;
+      }
+      constexpr int B = (E >= 5) ? 4 : 8;
+#pragma unroll
+      for (int s0 = 0; s0 < NS; s0 += B) {
+        double d[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          d[i] = 0.0;
+          if (s0 + i < NS)
+#pragma unroll
+            for (int e = 0; e < E; ++e) d[i] = fma(v[e], col[s0 + i][e], d[i]);
+        }
+        wave_sum_n(d);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          if (s0 + i < NS) {
+            const int c = wave + NW * (s0 + i);
+            if (c > jj && c < no) {
+              const double g = tau * d[i];
+#pragma unroll
+              for (int e = 0; e < E; ++e) col[s0 + i][e] = fma(-g, v[e], col[s0 + i][e]);
+            }
+          }
+        }
+      }
+    }
+  }
+  double* A = a.QR;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = wave + NW * s;
+    if (c < no)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = lane + 64 * e;
+        if (r < n) A[(int64_t)c * n + r] = col[s][e];
+      }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double rmax = 0.0;
+    const int nd = min(no, n);
+    for (int i = 0; i < nd; ++i) rmax = fmax(rmax, fabs(A[(int64_t)i * n + i]));
+    const double tol = (double)max(n, no) * 2.220446049250313e-16 * rmax;
+    int rank = 0;
+    for (int i = 0; i < nd; ++i) rank += (fabs(A[(int64_t)i * n + i]) > tol);
+    sc->rank = rank;
+    if (rank < no) a.recs[a.u].flags |= RID_UPD_RANK_DEFICIENT;
+  }
+}
+
 // One wave per observed column c: z = Q^T S(:, c), back substitution, scatter.
 __global__ __launch_bounds__(64) void alg4_apply_kernel(UpdArgs a) {
   __shared__ double y[kMaxEll];
@@ -1119,7 +1255,18 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
 
 // Alg. 4 and Alg. 8
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(alg4_qr_kernel, dim3(1), dim3(1024), 0, s, a);
+  // Householder QR of Omega A_J: in registers when it fits, else through L2
+  const int E = (a.ell + 63) / 64;
+  if (E <= 1 && a.t <= 16)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<1, 2, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (E <= 2 && a.t <= 64)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<2, 8, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (E <= 4 && a.t <= 112)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<4, 14, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (E <= 5 && a.t <= 152)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<5, 19, 8>), dim3(1), dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL(alg4_qr_kernel, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(alg4_apply_kernel, dim3((unsigned)a.n_obs), dim3(64), 0, s, a);
   {
     const int64_t tot = (int64_t)(a.ell + a.t) * a.t;

@@ -172,6 +172,15 @@ def test_pipeline_f32_channel():
     _pipeline(A, 60, 30, 30, "f32", 1003, 2003)
 
 
+def test_pipeline_f32_lowrank_large_ell():
+    # l = 300, t = 150 as in the full-size channel workload (register-resident
+    # QR, NA-Hutch++ split 75/150/75), on a well-conditioned stream: the
+    # spectrum decays slowly, so Omega A_J is far from rank-deficient.
+    log("pipeline f32 lowrank 40000 x 450, rank 400, l=300, t=150")
+    A = synth.lowrank(40_000, 450, seed=synth.data_seed(2), rank=400, decay=200.0)
+    _pipeline(A, 300, 150, 150, "f32", 1003, 2003, batch=100)
+
+
 def test_pipeline_bf16_channel_operand_rounding():
     log("pipeline bf16 channel vs oracle with bf16-rounded operands")
     A = synth.channel(24, 17, 24, 300, seed=synth.data_seed(3), n_modes=120)
