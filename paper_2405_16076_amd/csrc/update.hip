@@ -18,10 +18,28 @@ namespace rid {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Sum over the 64 lanes of a wave, returned to every lane, without LDS:
+// DPP moves within 16-lane rows (quad xor 1, quad xor 2, half-row mirror,
+// row mirror), then the four row sums through readlane, added in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_f64(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_mov_f64<0xB1>(v);   // quad_perm(1,0,3,2)
+  v += dpp_mov_f64<0x4E>(v);   // quad_perm(2,3,0,1)
+  v += dpp_mov_f64<0x141>(v);  // row_half_mirror
+  v += dpp_mov_f64<0x140>(v);  // row_mirror
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // Block-wide sum; every thread gets the total.  red must hold blockDim/64 doubles.
@@ -777,9 +795,7 @@ __global__ __launch_bounds__(1024) void alg4_qr_kernel(UpdArgs a) {
 template <int N>
 __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], o);
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
 }
 
 template <int E, int NS, int NW>
