@@ -557,12 +557,15 @@ static rid_status flush_all(rid_stream* h) {
   return RID_OK;
 }
 
-// Sketch only full batches (the lookahead); used after pushes.
+// Sketch full batches of the lookahead once more than a batch is pending
+// (used after pushes).  A batch that is exactly full waits for the next push
+// or for finalize, so that a final partial update can share its eigen-solve
+// launch with the full updates of that batch.
 static rid_status flush_full(rid_stream* h) {
   rid_status st = RID_OK;
-  if (h->n_pushed - h->n_sketched < h->b_max) return RID_OK;
+  if (h->n_pushed - h->n_sketched <= h->b_max) return RID_OK;
   if ((st = upload_colptrs(h)) != RID_OK) return st;
-  while (h->n_pushed - h->n_sketched >= h->b_max) {
+  while (h->n_pushed - h->n_sketched > h->b_max) {
     if ((st = sketch_range(h, h->n_sketched, h->b_max)) != RID_OK) return st;
     h->n_sketched += h->b_max;
     const int full = (int)(h->n_sketched / h->t - h->n_updates);
@@ -639,10 +642,22 @@ rid_status rid_flush(rid_stream* h) {
 rid_status rid_finalize(rid_stream* h) {
   if (!h) return fail(nullptr, RID_EINVAL, "null handle");
   if (h->failed || h->finalized) return fail(h, RID_ESTATE, "stream finalized or failed");
-  rid_status st = flush_all(h);
+  // Sketch what is left; the full updates completed by the last sketch launch
+  // share one batch (one eigen-solve launch) with the final partial update.
+  rid_status st = upload_colptrs(h);
   if (st != RID_OK) return st;
-  const int64_t rem = h->n_pushed - h->n_updates * h->t;
-  if (rem > 0 && (st = run_updates(h, 0, (int)rem)) != RID_OK) return st;
+  while (h->n_sketched < h->n_pushed) {
+    const int b = (int)std::min<int64_t>(h->b_max, h->n_pushed - h->n_sketched);
+    if ((st = sketch_range(h, h->n_sketched, b)) != RID_OK) return st;
+    h->n_sketched += b;
+    if (h->n_sketched < h->n_pushed) {
+      const int full = (int)(h->n_sketched / h->t - h->n_updates);
+      if ((st = run_updates(h, full, 0)) != RID_OK) return st;
+    }
+  }
+  const int full = (int)(h->n_pushed / h->t - h->n_updates);
+  const int64_t rem = h->n_pushed - (h->n_updates + full) * h->t;
+  if ((full > 0 || rem > 0) && (st = run_updates(h, full, (int)rem)) != RID_OK) return st;
   h->finalized = true;
   return RID_OK;
 }

@@ -134,50 +134,78 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) {
     }
     return;
   }
+  // Householder tridiagonalisation, three barriers per step: wave 0 forms the
+  // reflector of column j (wave sums, no barrier) and publishes v; all waves
+  // form p = tau A22 v (four columns per wave in flight); every wave then
+  // forms K = tau/2 p^T v itself and applies A22 -= v w^T + w v^T with
+  // w = p - K v.
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;           // order of the trailing block
     double* x = W + (int64_t)j * n + j + 1;   // column j, rows j+1..n-1
-    double part = 0.0;
-    for (int i = 1 + tid; i < m; i += nth) part += x[i] * x[i];
-    const double xn2 = block_sum(part, red);
-    const double alpha = x[0];
-    double tau = 0.0, beta = alpha;
-    if (xn2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      tau = (beta - alpha) / beta;
-      const double scal = 1.0 / (alpha - beta);
-      for (int i = tid; i < m; i += nth) v[i] = (i == 0) ? 1.0 : x[i] * scal;
-    } else {
-      for (int i = tid; i < m; i += nth) v[i] = (i == 0) ? 1.0 : 0.0;
+    if (wv == 0) {
+      double part = 0.0;
+      for (int i = 1 + lane; i < m; i += 64) part = fma(x[i], x[i], part);
+      const double xn2 = wave_sum(part);
+      const double alpha = x[0];
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (xn2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      for (int i = lane; i < m; i += 64) {
+        const double vi = (i == 0) ? 1.0 : x[i] * scal;
+        v[i] = vi;
+        if (i > 0) x[i] = vi;  // store the reflector
+      }
+      if (lane == 0) {
+        red[0] = tau;
+        htau[j] = tau;
+        e[j] = beta;
+        d[j] = W[(int64_t)j * n + j];
+      }
     }
     __syncthreads();
-    if (tid == 0) {
-      htau[j] = tau;
-      e[j] = beta;
-      d[j] = W[(int64_t)j * n + j];
-    }
-    for (int i = 1 + tid; i < m; i += nth) x[i] = v[i];  // store the reflector
+    const double tau = red[0];
     if (tau != 0.0) {
       // p = tau * A22 v (A22 symmetric: its row i is its column i, contiguous)
       double* A22 = W + (int64_t)(j + 1) * n + (j + 1);
-      for (int i = wv; i < m; i += nw) {
-        const double* col = A22 + (int64_t)i * n;
-        double s = 0.0;
-        for (int kk = lane; kk < m; kk += 64) s = fma(col[kk], v[kk], s);
-        s = wave_sum(s);
-        if (lane == 0) p[i] = tau * s;
+      for (int i0 = wv; i0 < m; i0 += 4 * nw) {
+        double s4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * nw;
+          s4[u] = 0.0;
+          if (i < m) {
+            const double* col = A22 + (int64_t)i * n;
+            for (int kk = lane; kk < m; kk += 64) s4[u] = fma(col[kk], v[kk], s4[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double sv = wave_sum(s4[u]);
+          const int i = i0 + u * nw;
+          if (lane == 0 && i < m) p[i] = tau * sv;
+        }
       }
       __syncthreads();
       double pv = 0.0;
-      for (int i = tid; i < m; i += nth) pv += p[i] * v[i];
-      const double K = 0.5 * tau * block_sum(pv, red);
-      for (int i = tid; i < m; i += nth) p[i] = p[i] - K * v[i];  // p -> w
-      __syncthreads();
-      // A22 -= v w^T + w v^T (one wave per column)
-      for (int col = wv; col < m; col += nw) {
-        double* cp = A22 + (int64_t)col * n;
-        const double vc = v[col], pc = p[col];
-        for (int row = lane; row < m; row += 64) cp[row] -= v[row] * pc + p[row] * vc;
+      for (int i = lane; i < m; i += 64) pv = fma(p[i], v[i], pv);
+      const double K = 0.5 * tau * wave_sum(pv);
+      // A22 -= v w^T + w v^T, w = p - K v (one wave per column, four in flight)
+      for (int c0 = wv; c0 < m; c0 += 4 * nw) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int col = c0 + u * nw;
+          if (col < m) {
+            double* cp = A22 + (int64_t)col * n;
+            const double vc = v[col], wc = p[col] - K * v[col];
+            for (int row = lane; row < m; row += 64) {
+              const double wr = p[row] - K * v[row];
+              cp[row] = fma(-v[row], wc, fma(-wr, vc, cp[row]));
+            }
+          }
+        }
       }
     }
     __syncthreads();
