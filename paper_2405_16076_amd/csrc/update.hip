@@ -1256,6 +1256,274 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
   }
 }
 
+// The same small phase with K^T, X and AA held in registers.  The n1 columns
+// of K^T and the 2 n1 rows of X and AA are vectors of length n2; vector q
+// lives in wave q % NW (slot q / NW), element r in lane r % 64 (e = r / 64).
+// Step jj of the pivoted QR: every wave writes the remaining norms of its
+// K^T vectors to LDS; one barrier; every wave finds the pivot; its owner forms
+// the reflector and publishes it; one barrier; every wave applies it to its
+// unchosen K^T vectors and to all X / AA vectors.  Vectors are never swapped:
+// pos[i] is the K^T column chosen at step i.
+template <int E, int NS, int NW>
+__global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel(UpdArgs a) {
+  constexpr int kMaxN1 = kMaxEll / 4;
+  __shared__ double red[16];
+  __shared__ double vb[2][64 * E];
+  __shared__ double tb[2];
+  __shared__ double cn[kMaxN1];
+  __shared__ int pos[kMaxN1];
+  __shared__ int ipos[kMaxN1];
+  __shared__ double rinv[kMaxN1 * kMaxN1];
+  const int n = a.ell, t = a.t, n1 = a.n1, n2 = a.n2, n3 = a.ell - a.n1 - a.n2;
+  const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  rid_update* rec = a.recs + a.u;
+  const double F = a.Fu[a.u];
+  const HutchWork hwk = hutch_work(a);
+  const double* Y = a.Y;
+  const double* G = a.G;
+  // h and gpp
+  double hp = 0.0, gp = 0.0;
+  for (int64_t idx = tid; idx < (int64_t)n3 * t; idx += nth) {
+    const int c = (int)(idx % n3), j = (int)(idx / n3);
+    hp = fma(Y[(int64_t)j * n + n1 + n2 + c], hwk.SJ[(int64_t)j * n + n1 + n2 + c], hp);
+  }
+  for (int64_t idx = tid; idx < (int64_t)t * t; idx += nth) gp = fma(G[idx], a.PPt[idx], gp);
+  const double h = block_sum(hp, red);
+  const double gpp = block_sum(gp, red);
+  // vectors: [0, n1) columns of K^T, [n1, 2 n1) rows of X, [2 n1, 3 n1) rows of AA
+  const int nv = 3 * n1;
+  double vec[NS][E];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int q = wave + NW * sl;
+    const double* src = nullptr;
+    if (q < n1) src = hwk.KT + (int64_t)q * n2;
+    else if (q < 2 * n1) src = hwk.X + (int64_t)(q - n1) * n2;
+    else if (q < nv) src = hwk.AA + (int64_t)(q - 2 * n1) * n2;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int r = lane + 64 * e;
+      vec[sl][e] = (src && r < n2) ? src[r] : 0.0;
+    }
+  }
+  for (int i = tid; i < n1; i += nth) ipos[i] = -1;
+  __syncthreads();
+  int rank = 0;
+  double r00 = 0.0;
+  const int nsteps = min(n1, n2);
+  for (int jj = 0; jj < nsteps; ++jj) {
+    const int buf = jj & 1;
+    // squared norms (rows jj..) of this wave's unchosen K^T vectors (slots
+    // below nsk hold K^T vectors)
+    {
+      constexpr int B = 8;
+      const int nsk = (n1 + NW - 1) / NW;
+#pragma unroll
+      for (int s0 = 0; s0 < NS; s0 += B) {
+        if (s0 >= nsk) break;
+        double d[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          d[i] = 0.0;
+          if (s0 + i < NS)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              const int r = lane + 64 * e;
+              if (r >= jj && r < n2) d[i] = fma(vec[s0 + i][e], vec[s0 + i][e], d[i]);
+            }
+        }
+        wave_sum_n(d);
+        if (lane == 0)
+#pragma unroll
+          for (int i = 0; i < B; ++i) {
+            const int q = wave + NW * (s0 + i);
+            if (s0 + i < NS && q < n1) cn[q] = (ipos[q] < 0) ? d[i] : -1.0;
+          }
+      }
+    }
+    __syncthreads();
+    // pivot: the first unchosen column of largest norm
+    int piv = n1;
+    double best = -1.0;
+    for (int c = lane; c < n1; c += 64)
+      if (cn[c] > best) {
+        best = cn[c];
+        piv = c;
+      }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ob = __shfl_xor(best, off);
+      const int op = __shfl_xor(piv, off);
+      if (ob > best || (ob == best && op < piv)) {
+        best = ob;
+        piv = op;
+      }
+    }
+    if (jj == 0) r00 = sqrt(best);
+    if (!(sqrt(best) > (double)max(n1, n2) * 2.220446049250313e-16 * r00) || best <= 0.0) break;
+    // reflector of the pivot vector (rows jj..n2-1), formed by its owner
+    if (wave == piv % NW) {
+      const int os = piv / NW;
+      double x[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) x[e] = 0.0;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        if (sl == os)
+#pragma unroll
+          for (int e = 0; e < E; ++e) x[e] = vec[sl][e];
+      double part = 0.0, al = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = lane + 64 * e;
+        if (r > jj && r < n2) part = fma(x[e], x[e], part);
+        if (e == jj / 64) al = x[e];
+      }
+      const double xn2 = wave_sum(part);
+      const double alpha = __shfl(al, jj & 63);
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (xn2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = lane + 64 * e;
+        const double vr = (r == jj) ? 1.0 : ((r > jj && r < n2) ? x[e] * scal : 0.0);
+        vb[buf][r] = vr;
+        if (r == jj) x[e] = beta;
+        else if (r > jj) x[e] = vr;
+      }
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl)
+        if (sl == os)
+#pragma unroll
+          for (int e = 0; e < E; ++e) vec[sl][e] = x[e];
+      if (lane == 0) {
+        tb[buf] = tau;
+        pos[jj] = piv;
+        ipos[piv] = jj;
+      }
+    }
+    __syncthreads();
+    const double tau = tb[buf];
+    if (tau != 0.0) {
+      double v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int r = lane + 64 * e;
+        v[e] = (r >= jj && r < n2) ? vb[buf][r] : 0.0;
+      }
+      constexpr int B = 8;
+#pragma unroll
+      for (int s0 = 0; s0 < NS; s0 += B) {
+        double d[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          d[i] = 0.0;
+          if (s0 + i < NS)
+#pragma unroll
+            for (int e = 0; e < E; ++e) d[i] = fma(v[e], vec[s0 + i][e], d[i]);
+        }
+        wave_sum_n(d);
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+          if (s0 + i >= NS) continue;
+          const int q = wave + NW * (s0 + i);
+          const bool apply = (q < n1) ? (ipos[q] < 0) : (q < nv);
+          if (apply) {
+            const double g = tau * d[i];
+#pragma unroll
+            for (int e = 0; e < E; ++e) vec[s0 + i][e] = fma(-g, v[e], vec[s0 + i][e]);
+          }
+        }
+      }
+    }
+    ++rank;
+  }
+  const int r = rank;
+  const int trunc = (rank < n1);
+  double term1 = 0.0, corr = 0.0;
+  if (r > 0) {
+    // R11 (row-major r x r in LDS): R(i, k) = element i of K^T vector pos[k]
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int q = wave + NW * sl;
+      if (q < n1) {
+        const int k = ipos[q];
+        if (k >= 0)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = lane + 64 * e;
+            if (i <= k) rinv[i * r + k] = vec[sl][e];
+          }
+      }
+    }
+    __syncthreads();
+    // in-place inverse, rows from the bottom: row i of R is read into
+    // registers, then overwritten by row i of R^{-1}; eight lanes per entry
+    constexpr int kPerPass = 64 * NW / 8;  // entries per pass
+    for (int i = r - 1; i >= 0; --i) {
+      const int qq = tid & 7;
+      const double rii = rinv[i * r + i];
+      double sum[kMaxN1 / kPerPass + 1];
+#pragma unroll
+      for (int ps = 0; ps * kPerPass < kMaxN1; ++ps) {
+        const int j = i + ps * kPerPass + (tid >> 3);
+        double sv = 0.0;
+        if (j < r)
+          for (int k = i + 1 + qq; k <= j; k += 8) sv = fma(rinv[i * r + k], rinv[k * r + j], sv);
+        sv += __shfl_xor(sv, 1);
+        sv += __shfl_xor(sv, 2);
+        sv += __shfl_xor(sv, 4);
+        sum[ps] = sv;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ps = 0; ps * kPerPass < kMaxN1; ++ps) {
+        const int j = i + ps * kPerPass + (tid >> 3);
+        if (j < r && qq == 0) rinv[i * r + j] = ((j == i ? 1.0 : 0.0) - sum[ps]) / rii;
+      }
+      __syncthreads();
+    }
+    // term1 = <R11^{-1}, Z_X>, corr = <R11^{-1}, Z_AA>, Z(i, j) = element j of
+    // the X (AA) vector of row pos[i]
+    double tx = 0.0, ta = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int q = wave + NW * sl;
+      if (q >= n1 && q < nv) {
+        const int row = (q < 2 * n1) ? q - n1 : q - 2 * n1;
+        const int i = ipos[row];
+        if (i >= 0) {
+          double part = 0.0;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int j = lane + 64 * e;
+            if (j >= i && j < r) part = fma(rinv[i * r + j], vec[sl][e], part);
+          }
+          if (q < 2 * n1) tx += part;
+          else ta += part;
+        }
+      }
+    }
+    term1 = block_sum(tx, red);
+    corr = block_sum(ta, red);
+  }
+  if (tid == 0) {
+    const double tr_est = term1 + (h - corr) / n3;
+    const double E2 = F - 2.0 * tr_est + gpp;
+    rec->E2 = E2;
+    rec->tr_est = tr_est;
+    rec->gpp = gpp;
+    rec->term1 = term1;
+    rec->h = h;
+    rec->corr = corr;
+    if (trunc) rec->flags |= RID_UPD_PINV_TRUNCATED;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1325,7 +1593,18 @@ hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s1 + 255) / 256)), dim3(256), 0, s, a, 1);
     hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s2 + 255) / 256)), dim3(256), 0, s, a, 2);
   }
-  hipLaunchKernelGGL(hutch_small_kernel, dim3(1), dim3(1024), 0, s, a);
+  // the pivoted QR of K^T in registers when K^T, X and AA fit, else through L2
+  {
+    const int E = (a.n2 + 63) / 64, nv = 3 * a.n1;
+    if (a.n1 > 0 && E <= 1 && nv <= 8 * 4)
+      hipLaunchKernelGGL((hutch_small_reg_kernel<1, 4, 8>), dim3(1), dim3(512), 0, s, a);
+    else if (a.n1 > 0 && E <= 2 && nv <= 8 * 19)
+      hipLaunchKernelGGL((hutch_small_reg_kernel<2, 19, 8>), dim3(1), dim3(512), 0, s, a);
+    else if (a.n1 > 0 && E <= 3 && nv <= 8 * 29)
+      hipLaunchKernelGGL((hutch_small_reg_kernel<3, 29, 8>), dim3(1), dim3(512), 0, s, a);
+    else
+      hipLaunchKernelGGL(hutch_small_kernel, dim3(1), dim3(1024), 0, s, a);
+  }
   return hipGetLastError();
 }
 
