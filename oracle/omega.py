@@ -91,3 +91,62 @@ def round_to_bf16(x):
     bits = f.view(np.uint32).astype(np.uint64)
     bits = (bits + np.uint64(0x7FFF) + ((bits >> np.uint64(16)) & np.uint64(1))) & np.uint64(0xFFFF0000)
     return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# FP8 (OCP e4m3) operands of the fp8 sketch form.
+# e4m3: 1 sign, 4 exponent (bias 7), 3 mantissa bits; no infinities; largest
+# finite magnitude 448 = 1.75 * 2^8; subnormals k * 2^-9, k = 1..7.
+# --------------------------------------------------------------------------
+E4M3_MAX = 448.0
+OMEGA_FP8_EXP = -6     # Omega is stored as e4m3(Omega * 2^6) with scale 2^-6
+MX_BLOCK = 32          # rows per shared scale of the data (microscaling block)
+
+
+def round_to_e4m3(x):
+    """Round-to-nearest-even onto the e4m3 grid, saturating at +-448
+    (float64 in, float64 out)."""
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    with np.errstate(divide="ignore"):
+        _, E = np.frexp(a)                       # a = f * 2^E, f in [0.5, 1)
+    e = np.maximum(E - 1, -6)                    # binade of a; subnormals share 2^-6's spacing
+    step = np.ldexp(1.0, e - 3)
+    q = np.round(a / step) * step                # numpy rounds half to even
+    q = np.minimum(q, E4M3_MAX)
+    return np.where(x < 0, -q, q)
+
+
+def mx_block_exponent(amax):
+    """Shared scale exponent of a block with largest magnitude amax:
+    floor(log2 amax) - 7, so the scaled maximum lies in [128, 256) and no
+    element saturates (with floor(log2 amax) - 8 the maximum could land in
+    (448, 512) and lose up to 12.5%); clamped to the E8M0 range [-127, 127];
+    -127 for an all-zero block."""
+    amax = np.asarray(amax, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        _, E = np.frexp(amax)
+    e = np.where(amax > 0, E - 1 - 7, -127)
+    return np.clip(e, -127, 127)
+
+
+def quantize_fp8_blocks(blk):
+    """e4m3 data operand with one power-of-two scale per 32 consecutive rows of
+    each column (rows counted from the first row of ``blk``, which the callers
+    keep aligned to a multiple of 32); returns the dequantized float64 values."""
+    blk = np.asarray(blk, dtype=np.float64)
+    m, b = blk.shape
+    out = np.empty_like(blk)
+    for r0 in range(0, m, MX_BLOCK):
+        part = blk[r0:r0 + MX_BLOCK]
+        e = mx_block_exponent(np.max(np.abs(part), axis=0))
+        sc = np.ldexp(1.0, e)
+        out[r0:r0 + MX_BLOCK] = round_to_e4m3(part / sc) * sc
+    return out
+
+
+def quantize_fp8_omega(om):
+    """e4m3 test-matrix operand: e4m3(Omega * 2^6) * 2^-6."""
+    sc = math.ldexp(1.0, OMEGA_FP8_EXP)
+    return round_to_e4m3(np.asarray(om, dtype=np.float64) / sc) * sc
+

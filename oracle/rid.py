@@ -43,7 +43,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .omega import omega_block, round_to_bf16
+from .omega import omega_block, quantize_fp8_blocks, quantize_fp8_omega, round_to_bf16
 from .philox import PRUNE_DRAW, decision_uniform
 
 
@@ -61,7 +61,7 @@ class Config:
     ridge_floor: float = 1e-8  # rho of the ridge floor
     hutch_n1: int | None = None
     hutch_n2: int | None = None
-    operand: str = "f64"       # operand rounding of the sketch: f64, f32 or bf16
+    operand: str = "f64"       # operand rounding of the sketch: f64, f32, bf16 or fp8
     row_chunk: int = 1 << 16   # rows of Omega regenerated at a time
 
     @property
@@ -107,13 +107,21 @@ def sketch_columns(cols, omega_seed, ell, operand="f64", row_chunk=1 << 16):
     are always those of the unrounded data, accumulated in binary64."""
     cols = np.asarray(cols)
     m, b = cols.shape
+    if operand == "fp8" and row_chunk % 32:
+        raise ValueError("row_chunk must be a multiple of 32 for the fp8 operands")
     S = np.zeros((ell, b), dtype=np.float64)
     colsq = np.zeros(b, dtype=np.float64)
     for i0 in range(0, m, row_chunk):
         n = min(row_chunk, m - i0)
         blk = cols[i0:i0 + n].astype(np.float64)
         om = omega_block(omega_seed, ell, i0, n)
-        S += _round_operand(om, operand) @ _round_operand(blk, operand)
+        if operand == "fp8":
+            # e4m3 operands: Omega with the fixed scale 2^-6, the data with one
+            # power-of-two scale per 32 rows of each column (row_chunk is a
+            # multiple of 32, so the blocks stay aligned to row 0)
+            S += quantize_fp8_omega(om) @ quantize_fp8_blocks(blk)
+        else:
+            S += _round_operand(om, operand) @ _round_operand(blk, operand)
         colsq += np.einsum("ij,ij->j", blk, blk)
     return S, colsq
 
