@@ -8,9 +8,10 @@ NA-Hutch++ estimate), ending with the final partial update.
 
 Default workload: the channel-flow-shaped stream (4 fields u, v, w, p on a
 192 x 129 x 192 grid: m = 19 021 824 binary32 rows per snapshot, n = 1000
-snapshots), l = 300, k = t = 150, bfloat16 sketch.  The binary32 sketch form
-is measured beside it and both report the relative Frobenius error of the
-reconstruction (exact on sampled snapshots, and the NA-Hutch++ estimate).
+snapshots), l = 300, k = t = 150, bfloat16 sketch.  The binary32 and the fp8
+(e4m3, block-scaled) sketch forms are measured beside it; every form reports
+the relative Frobenius error of its reconstruction (exact on sampled
+snapshots, and the NA-Hutch++ estimate).
 
 Prints one JSON line (rank 0).  `--gpus N` with N > 1 exits: this benchmark
 runs on one GPU.
@@ -101,7 +102,7 @@ def sampled_exact_error(s, D, m, n, blocks=8, width=16):
     return math.sqrt(num / den)
 
 
-def cpu_baseline(wl, seeds, rows=1 << 19, cols=None):
+def cpu_baseline(wl, seeds, operand, rows=1 << 19, cols=None):
     """The oracle timed on the host on a bounded sample of the same stream."""
     import numpy as np
     import synth
@@ -111,7 +112,7 @@ def cpu_baseline(wl, seeds, rows=1 << 19, cols=None):
     B = synth.channel_spatial_rows(modes, (wl["nx"], wl["ny"], wl["nz"]), 0, np.arange(rows))
     A = (B @ synth.channel_temporal(modes, cols)).astype(np.float32)
     cfg = Config(m=rows, ell=wl["ell"], k=wl["t"], t=wl["t"], omega_seed=seeds[0], select_seed=seeds[1],
-                 operand="bf16")
+                 operand=operand)
     o = OracleRID(cfg, n_max=cols)
     try:
         from threadpoolctl import threadpool_info
@@ -124,7 +125,7 @@ def cpu_baseline(wl, seeds, rows=1 << 19, cols=None):
     dt = time.perf_counter() - t0
     return {"value": A.nbytes / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": f"rows 0..{rows} of field u, snapshots 0..{cols} (one full update of the method, "
-                      f"bf16-rounded operands, binary64) in {dt:.1f} s on {threads} BLAS threads"}
+                      f"{operand} operands, binary64 sums) in {dt:.1f} s on {threads} BLAS threads"}
 
 
 def main():
@@ -132,10 +133,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sketch", default="bf16", choices=["bf16", "f32"])
+    ap.add_argument("--sketch", default="bf16", choices=["bf16", "f32", "fp8"])
     ap.add_argument("--push", type=int, default=100, help="snapshots per push call")
     ap.add_argument("--small", action="store_true", help="a small stream (quick check)")
-    ap.add_argument("--no-compare", action="store_true", help="skip the binary32 comparison form")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other sketch forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -199,19 +200,24 @@ def main():
     }
     J_main, P_main = s.select(), None
     s.close()
-    if not args.no_compare and args.sketch != "f32":
-        s2, ms2, prof2 = run_form(D, m, wl, "f32", max(1, min(2, args.steps)), 1, args.push, seeds)
+    for other in ([] if args.no_compare else [f for f in ("f32", "bf16", "fp8") if f != args.sketch]):
+        s2, ms2, prof2 = run_form(D, m, wl, other, max(1, min(2, args.steps)), 1, args.push, seeds)
         est2 = s2.error_estimate()
         exact2 = sampled_exact_error(s2, D, m, n)
-        line["compare_f32"] = {"value": round(B_snap / (ms2 / 1000.0) / 1e9, 2), "ms_per_step": round(ms2, 3),
-                               "rel_frobenius_error": {"nahutchpp_estimate": est2["rel"], "exact_sampled": exact2},
-                               "same_J_as_bf16": bool((s2.select() == J_main).all())}
-        log(f"  [f32] estimate rel {est2['rel']:.4e}, exact (sampled) rel {exact2:.4e}")
+        pl = prof2["sketch_ms"] / max(prof2["sketch_launches"], 1)
+        line[f"compare_{other}"] = {
+            "value": round(B_snap / (ms2 / 1000.0) / 1e9, 2), "ms_per_step": round(ms2, 3),
+            "sketch_ms_per_launch": round(pl, 4),
+            "sketch_frac": round(prof2["sketch_bytes"] / max(prof2["sketch_launches"], 1) / (pl / 1000.0) / 1e9
+                                 / HBM_PEAK_GBS, 4),
+            "rel_frobenius_error": {"nahutchpp_estimate": est2["rel"], "exact_sampled": exact2},
+            f"same_J_as_{args.sketch}": bool((s2.select() == J_main).all())}
+        log(f"  [{other}] estimate rel {est2['rel']:.4e}, exact (sampled) rel {exact2:.4e}")
         s2.close()
     del D
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
-        line["cpu_baseline"] = cpu_baseline(wl, seeds)
+        line["cpu_baseline"] = cpu_baseline(wl, seeds, args.sketch)
     print(json.dumps(line), flush=True)
 
 

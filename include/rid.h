@@ -63,7 +63,10 @@ typedef enum rid_dtype { RID_F32 = 0, RID_F64 = 1 } rid_dtype;
 typedef enum rid_sketch_prec {
   RID_SKETCH_F64 = 0,   /* binary64 test matrix and products */
   RID_SKETCH_F32 = 1,   /* binary32 test matrix and data, matrix cores */
-  RID_SKETCH_BF16 = 2   /* bfloat16-rounded test matrix and data, matrix cores */
+  RID_SKETCH_BF16 = 2,  /* bfloat16-rounded test matrix and data, matrix cores */
+  RID_SKETCH_FP8 = 3    /* e4m3 test matrix (scale 2^-6) and e4m3 data with one
+                           power-of-two scale per 32 rows of each column,
+                           scaled fp8 matrix cores */
 } rid_sketch_prec;
 
 /* Push flags. */
@@ -259,9 +262,10 @@ rid_status rid_debug_state(rid_stream* h, double* S, int64_t lds, int64_t cap_co
 /* Writes Omega(0:ell, i0:i0+count) of the given seed into the device buffer
  * d_out (ell x count, column-major, column stride ld >= ell), evaluated the way
  * the sketch form `prec` evaluates it (binary32 for RID_SKETCH_F32 and
- * RID_SKETCH_BF16, binary64 for RID_SKETCH_F64; the element type of d_out is
- * float for the former and double for the latter, and RID_SKETCH_BF16 values
- * are rounded to bfloat16 before being widened).  Alg. 3 step 2.
+ * RID_SKETCH_BF16 and RID_SKETCH_FP8, binary64 for RID_SKETCH_F64; the element
+ * type of d_out is float for the former and double for the latter;
+ * RID_SKETCH_BF16 values are rounded to bfloat16 and RID_SKETCH_FP8 values are
+ * e4m3(64 Omega) / 64, both widened back to float).  Alg. 3 step 2.
  * Asynchronous on `stream`.  Errors: RID_EINVAL, RID_EDEVICE. */
 rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64_t i0,
                            int64_t count, void* d_out, int64_t ld, void* stream);

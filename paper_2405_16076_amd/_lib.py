@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "librid.so")
 
 RID_OK, RID_EINVAL, RID_ENOMEM, RID_EDEVICE, RID_ESTATE, RID_ECAPACITY, RID_ENUMERIC, RID_ENOTSUP = range(8)
 RID_F32, RID_F64 = 0, 1
-RID_SKETCH_F64, RID_SKETCH_F32, RID_SKETCH_BF16 = 0, 1, 2
+RID_SKETCH_F64, RID_SKETCH_F32, RID_SKETCH_BF16, RID_SKETCH_FP8 = 0, 1, 2, 3
 RID_COPY, RID_BORROW = 0, 1
 RID_HOST, RID_DEVICE = 0, 1
 RID_UPD_SKIPPED, RID_UPD_RANK_DEFICIENT, RID_UPD_PINV_TRUNCATED = 1, 2, 4

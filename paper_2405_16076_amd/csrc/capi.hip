@@ -240,7 +240,7 @@ static rid_status validate(const rid_config* c) {
   if (c->n_max < 1) return fail(nullptr, RID_EINVAL, "n_max must be >= 1");
   if (c->data_dtype != RID_F32 && c->data_dtype != RID_F64)
     return fail(nullptr, RID_EINVAL, "unknown data dtype");
-  if (c->sketch_prec < RID_SKETCH_F64 || c->sketch_prec > RID_SKETCH_BF16)
+  if (c->sketch_prec < RID_SKETCH_F64 || c->sketch_prec > RID_SKETCH_FP8)
     return fail(nullptr, RID_EINVAL, "unknown sketch precision");
   if ((c->sketch_prec == RID_SKETCH_F64) != (c->data_dtype == RID_F64))
     return fail(nullptr, RID_EINVAL, "the f64 sketch needs f64 data and the others f32 data");
@@ -284,7 +284,7 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     h->fill_mult = cfg->c_sample * (k * log(k) + k * log(1.0 / cfg->delta) / cfg->eps) / cfg->t;
   }
   // sketch geometry
-  if (h->prec == RID_SKETCH_BF16) {
+  if (h->prec == RID_SKETCH_BF16 || h->prec == RID_SKETCH_FP8) {
     // all test-matrix rows in one workgroup up to 320 rows, else split
     const int rows = (h->ell + 63) / 64 * 64;
     h->n_mt = (rows + 319) / 320;
@@ -299,7 +299,8 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
   h->b_max = auto_lookahead(cfg);
   {
     const int n_nt = (h->b_max + h->cols_per_wg - 1) / h->cols_per_wg;
-    const int64_t cap = (h->prec == RID_SKETCH_BF16) ? 65536 : (h->prec == RID_SKETCH_F32 ? 32768 : 16384);
+    const int64_t cap = (h->prec == RID_SKETCH_BF16 || h->prec == RID_SKETCH_FP8)
+                            ? 65536 : (h->prec == RID_SKETCH_F32 ? 32768 : 16384);
     const int64_t target = std::max<int64_t>(1, 2048 / (h->n_mt * n_nt));
     int64_t rows = (h->m + target - 1) / target;
     rows = (rows + 255) / 256 * 256;
@@ -847,7 +848,7 @@ rid_status rid_destroy(rid_stream* h) {
 
 rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64_t i0, int64_t count,
                            void* d_out, int64_t ld, void* stream) {
-  if (prec < RID_SKETCH_F64 || prec > RID_SKETCH_BF16 || ell < 1 || ell > kMaxEll || i0 < 0 ||
+  if (prec < RID_SKETCH_F64 || prec > RID_SKETCH_FP8 || ell < 1 || ell > kMaxEll || i0 < 0 ||
       count < 0 || (count > 0 && !d_out) || ld < ell)
     return fail(nullptr, RID_EINVAL, "bad omega block arguments");
   if (count == 0) return RID_OK;

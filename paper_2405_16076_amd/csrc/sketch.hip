@@ -263,6 +263,269 @@ __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// fp8 form: e4m3 operands with power-of-two block scales on
+// v_mfma_scale_f32_32x32x64_f8f6f4 (binary32 accumulation).
+//   * Omega is e4m3(Omega * 2^6) with the fixed scale 2^-6 (E8M0 121).
+//   * The data carries one scale per 32 rows of each column: 2^(floor(log2
+//     max|x|) - 7), so the scaled block maximum lies in [128, 256).
+// Operand layout of the instruction (e4m3, 8 VGPRs per lane): lane l holds
+// row (A) / column (B) l%32; its bytes 0..15 lie in k-block 0 (k < 32) and
+// bytes 16..31 in k-block 1; the E8M0 scale given by lane l applies to row /
+// column l%32 within k-block l/32.  Here lane (c, h = l/32) carries rows
+// 16h..16h+15 of each 32-row block (bytes 0..15: block 0, bytes 16..31:
+// block 1) for both operands, so A and B agree on k.
+//
+// One workgroup per (slab, 64*RBW sketch rows, 256 columns) as in the bfloat16
+// form.  A step consumes 64 data rows = two 32-row chunks (one scale block
+// each) of a four-stage LDS-DMA ring, in three phases split by barriers:
+//   quantize  thread t takes column t%256 of chunk t/256: it reads the 32
+//             binary32 values (zeroing rows past the slab), adds their squares
+//             to its binary64 norm, picks the block scale and writes the 32
+//             e4m3 codes back over the first 32 bytes of the same column run
+//             (16-byte halves at slots swz(c) and swz(c)^4), its E8M0 code to
+//             a table;
+//   multiply  each wave runs its 2*RBW scaled MFMAs on the quantized step and
+//             the Omega tile (64*RBW rows x 64 data rows, 80-byte rows);
+//   refill    the two consumed chunks are re-issued four chunks ahead and the
+//             next Omega tile is generated.
+// Quantizing once per column (not once per consuming wave) keeps the binary32
+// values out of the registers of the multiply phase, where the 2*RBW
+// accumulator tiles fill the register file.
+// ---------------------------------------------------------------------------
+typedef int v8i_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int fp8_block_exp(float amax) {
+  if (!(amax > 0.0f)) return -127;
+  const int e = ilogbf(amax) - 7;  // floor(log2 amax) - 7
+  return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+__device__ __forceinline__ void wait_dma_keep(int n) {
+  if (n >= 8) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+  else if (n >= 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+template <int RBW>
+__global__ __launch_bounds__(512, 1) void sketch_fp8_kernel(SketchArgs a) {
+  constexpr int KC = 32;                 // rows per DMA chunk (one scale block)
+  constexpr int NST = 4;                 // DMA stages
+  constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
+  constexpr int LDO = 80;                // bytes per Omega tile row (64 + pad)
+  __shared__ __attribute__((aligned(16))) uint8_t om[MROWS * LDO];
+  __shared__ __attribute__((aligned(1024))) float dt[NST][kBf16Cols * KC];
+  __shared__ uint64_t csrc[kBf16Cols];
+  __shared__ int scl[2][kBf16Cols];      // E8M0 code of (chunk of the step, column)
+  int slab, mt, nt;
+  if (!sketch_item(a, blockIdx.x, slab, mt, nt)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int rg = wave >> 2, cp = wave & 3;
+  const int64_t r0 = (int64_t)slab * a.slab_rows;
+  const int64_t r1 = min(a.m, r0 + a.slab_rows);
+  const int nch = (int)((r1 - r0 + KC - 1) / KC);
+  const int nsteps = (nch + 1) / 2;
+  const int row_base = mt * MROWS;
+
+  for (int cl = tid; cl < kBf16Cols; cl += 512) {
+    const int cg = nt * kBf16Cols + cl;
+    csrc[cl] = a.colptr[a.c0 + (cg < a.b ? cg : nt * kBf16Cols)];
+  }
+  __syncthreads();
+  // LDS-DMA: copy i of wave w fills columns 8(4w+i)..+8 of a chunk.  Rows
+  // wholly past the slab end are fetched from row r0 (in bounds) and zeroed by
+  // the quantize phase; a 16-byte run that straddles the end of the snapshot
+  // stays inside the 16-byte-aligned block holding its last row.
+  auto issue = [&](int c) {
+    if (c >= nch) return;
+    const int64_t k0 = r0 + (int64_t)c * KC;
+    const uint32_t sb = lds_addr(&dt[c % NST][0]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cl = 8 * (4 * wave + i) + (lane >> 3);
+      int64_t row = k0 + 4 * ((lane & 7) ^ col_swz(cl));
+      if (row >= r1) row = r0;
+      const gmem_t<float>* src = gload_ptr(reinterpret_cast<const float*>(csrc[cl]));
+      lds_dma16(src + row, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(4 * wave + i) * 1024u));
+    }
+  };
+  // copies issued after chunk c (they may still be in flight when c is needed)
+  auto later = [&](int c) { return max(0, min(nch - 1, c + 2) - c) * 4; };
+
+  // Omega tile of step q: item = (row group g, four data rows 4 kq..); four
+  // Philox calls give 8 x 4 entries, written as one 32-bit word per row.
+  // Row groups at or beyond ell stay zero (written once below).
+  const int n_groups = min(MROWS / 8, max(0, (a.ell - row_base + 7) / 8));
+  const int n_items = n_groups * 16;
+  auto gen = [&](int q) {
+    const int64_t k0 = r0 + (int64_t)q * 64;
+    for (int it = tid; it < n_items; it += 512) {
+      const int g = it >> 4, kq = it & 15;
+      int w[8];
+      {
+        float z0[8], z1[8];
+        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq), (uint32_t)(row_base / 8 + g), z0);
+        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq + 1), (uint32_t)(row_base / 8 + g), z1);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[j] = __builtin_amdgcn_cvt_pk_fp8_f32(z0[j] * 64.0f, z1[j] * 64.0f, 0, false);
+      }
+      {
+        float z0[8], z1[8];
+        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq + 2), (uint32_t)(row_base / 8 + g), z0);
+        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq + 3), (uint32_t)(row_base / 8 + g), z1);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) w[j] = __builtin_amdgcn_cvt_pk_fp8_f32(z0[j] * 64.0f, z1[j] * 64.0f, w[j], true);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) *reinterpret_cast<int*>(&om[(8 * g + j) * LDO + 4 * kq]) = w[j];
+    }
+  };
+
+  // quantize phase of step s (see above); nrm is this thread's column norm
+  const int qcl = tid & (kBf16Cols - 1), qcb = tid >> 8;
+  const int qswz = col_swz(qcl);
+  double nrm = 0.0;
+  auto quantize = [&](int s) {
+    const int c = 2 * s + qcb;
+    float* col = &dt[c % NST][qcl * KC];
+    float x[32];
+    if (c < nch) {
+      const int64_t k0 = r0 + (int64_t)c * KC;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float4 v = *reinterpret_cast<const float4*>(col + 4 * (q ^ qswz));
+        x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+      }
+      if (k0 + KC > r1) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q)
+          if (k0 + q >= r1) x[q] = 0.0f;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 32; ++q) x[q] = 0.0f;
+    }
+    double t = nrm;
+    float mx = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      t = fma((double)x[q], (double)x[q], t);
+      mx = fmaxf(mx, fabsf(x[q]));
+    }
+    nrm = t;
+    const int e = fp8_block_exp(mx);
+    const float inv = __builtin_ldexpf(1.0f, -e);
+    int w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      int v = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q] * inv, x[4 * q + 1] * inv, 0, false);
+      w[q] = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q + 2] * inv, x[4 * q + 3] * inv, v, true);
+    }
+    *reinterpret_cast<int4*>(col + 4 * qswz) = make_int4(w[0], w[1], w[2], w[3]);
+    *reinterpret_cast<int4*>(col + 4 * (qswz ^ 4)) = make_int4(w[4], w[5], w[6], w[7]);
+    scl[qcb][qcl] = e + 127;
+  };
+
+  f32x16 acc[RBW][2];
+#pragma unroll
+  for (int r = 0; r < RBW; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.0f;
+
+  // multiply phase of step s: lane (l32, half) supplies rows 16 half..+16 of
+  // both chunks of column (2 cp + cc) 32 + l32 and the scale of chunk `half`.
+  // The Omega operand of block r + 1 is loaded while block r multiplies; the
+  // scheduling fences keep the compiler from hoisting all of them at once.
+  auto load_a = [&](int r) {
+    const uint8_t* orow = &om[((rg * RBW + r) * 32 + l32) * LDO];
+    const int4 lo = *reinterpret_cast<const int4*>(orow + 16 * half);
+    const int4 hi = *reinterpret_cast<const int4*>(orow + 32 + 16 * half);
+    return v8i_t{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  };
+  auto multiply = [&](int s) {
+    v8i_t bop[2];
+    int bsc[2];
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const int cl = (2 * cp + cc) * 32 + l32;
+      const int slot = col_swz(cl) ^ (4 * half);
+      const int4 b0 = *reinterpret_cast<const int4*>(&dt[(2 * s) % NST][cl * KC + 4 * slot]);
+      const int4 b1 = *reinterpret_cast<const int4*>(&dt[(2 * s + 1) % NST][cl * KC + 4 * slot]);
+      bop[cc] = v8i_t{b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+      bsc[cc] = scl[half][cl];
+    }
+    v8i_t av = load_a(0);
+#pragma unroll
+    for (int r = 0; r < RBW; ++r) {
+      v8i_t an = av;
+      if (r + 1 < RBW) an = load_a(r + 1);
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+        acc[r][cc] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bop[cc], acc[r][cc], 0, 0, 0, 121, 0,
+                                                                     bsc[cc]);
+      __builtin_amdgcn_sched_barrier(0);
+      av = an;
+    }
+    // keep the products in this phase (not sunk past the barrier, where the
+    // operands would stay live across the refill code)
+#pragma unroll
+    for (int r = 0; r < RBW; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) asm volatile("" ::"v"(acc[r][cc][0]));
+  };
+
+  // prologue: chunks 0..3 in flight, zero rows of Omega, Omega of step 0,
+  // quantized step 0
+#pragma unroll
+  for (int c = 0; c < NST; ++c) issue(c);
+  for (int i = tid + n_groups * 8 * (LDO / 4); i < MROWS * (LDO / 4); i += 512)
+    reinterpret_cast<int*>(om)[i] = 0;
+  gen(0);
+  wait_dma_keep(later(1));               // chunks 0 and 1 have landed
+  lds_barrier();
+  quantize(0);
+  lds_barrier();
+  for (int s = 0; s < nsteps; ++s) {
+    multiply(s);
+    lds_barrier();                       // Omega tile and chunks 2s, 2s+1 are free
+    issue(2 * s + 4);
+    issue(2 * s + 5);
+    if (s + 1 < nsteps) gen(s + 1);
+    wait_dma_keep(later(2 * s + 3));     // chunks 2s+2, 2s+3 have landed
+    lds_barrier();
+    if (s + 1 < nsteps) quantize(s + 1);
+    lds_barrier();
+  }
+
+  float* part = reinterpret_cast<float*>(a.part);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int col = nt * kBf16Cols + (2 * cp + c) * 32 + l32;
+    if (col >= a.b) continue;
+    float* dst = part + ((int64_t)slab * a.b_max + col) * a.ell_pad + row_base;
+#pragma unroll
+    for (int r = 0; r < RBW; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float4 v = make_float4(acc[r][c][4 * q], acc[r][c][4 * q + 1], acc[r][c][4 * q + 2],
+                               acc[r][c][4 * q + 3]);
+        *reinterpret_cast<float4*>(dst + (rg * RBW + r) * 32 + 8 * q + 4 * half) = v;
+      }
+  }
+  if (mt == 0) {
+    // the two chunk parities of a column meet in LDS (the ring is idle now)
+    double* nsh = reinterpret_cast<double*>(&dt[0][0]);
+    if (qcb == 1) nsh[qcl] = nrm;
+    __syncthreads();
+    if (qcb == 0) {
+      const int col = nt * kBf16Cols + qcl;
+      if (col < a.b) a.normpart[(int64_t)slab * a.b_max + col] = nrm + nsh[qcl];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // binary32 form: v_mfma_f32_32x32x2_f32 (A lane l: row l%32, k = l/32; B lane
 // l: column l%32, k = l/32).  Within a 16-row chunk lane half h reads rows
 // 8h..8h+7 of its column and MFMA step s uses row 8h+s of both operands.
@@ -476,6 +739,10 @@ __global__ void omega_block_kernel(int prec, uint64_t seed, int ell, int64_t i0,
     for (int j = 0; j < 8; ++j) {
       float v = z[j];
       if (prec == RID_SKETCH_BF16) v = __uint_as_float((uint32_t)bf16_bits_rne(v) << 16);
+      if (prec == RID_SKETCH_FP8) {
+        const int w = __builtin_amdgcn_cvt_pk_fp8_f32(v * 64.0f, 0.0f, 0, false);
+        v = __builtin_amdgcn_cvt_f32_fp8(w, 0) * (1.0f / 64.0f);
+      }
       if (8 * g + j < ell) reinterpret_cast<float*>(out)[i * ld + 8 * g + j] = v;
     }
   }
@@ -487,7 +754,7 @@ __global__ void omega_block_kernel(int prec, uint64_t seed, int ell, int64_t i0,
 constexpr int kNcbF32 = 2;
 
 int sketch_cols_per_wg(int prec) {
-  if (prec == RID_SKETCH_BF16) return kBf16Cols;
+  if (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) return kBf16Cols;
   if (prec == RID_SKETCH_F32) return 4 * kNcbF32 * 32;
   return 64;
 }
@@ -502,6 +769,16 @@ hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s) {
       case 3: hipLaunchKernelGGL(sketch_bf16_kernel<3>, dim3(grid), dim3(512), 0, s, a); break;
       case 4: hipLaunchKernelGGL(sketch_bf16_kernel<4>, dim3(grid), dim3(512), 0, s, a); break;
       case 5: hipLaunchKernelGGL(sketch_bf16_kernel<5>, dim3(grid), dim3(512), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  else if (prec == RID_SKETCH_FP8) {
+    switch (a.rbw) {
+      case 1: hipLaunchKernelGGL(sketch_fp8_kernel<1>, dim3(grid), dim3(512), 0, s, a); break;
+      case 2: hipLaunchKernelGGL(sketch_fp8_kernel<2>, dim3(grid), dim3(512), 0, s, a); break;
+      case 3: hipLaunchKernelGGL(sketch_fp8_kernel<3>, dim3(grid), dim3(512), 0, s, a); break;
+      case 4: hipLaunchKernelGGL(sketch_fp8_kernel<4>, dim3(grid), dim3(512), 0, s, a); break;
+      case 5: hipLaunchKernelGGL(sketch_fp8_kernel<5>, dim3(grid), dim3(512), 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
   }

@@ -15,7 +15,7 @@ import torch
 from . import _lib as L
 
 _DTYPE = {torch.float32: L.RID_F32, torch.float64: L.RID_F64}
-PREC = {"f64": L.RID_SKETCH_F64, "f32": L.RID_SKETCH_F32, "bf16": L.RID_SKETCH_BF16}
+PREC = {"f64": L.RID_SKETCH_F64, "f32": L.RID_SKETCH_F32, "bf16": L.RID_SKETCH_BF16, "fp8": L.RID_SKETCH_FP8}
 
 
 @dataclass

@@ -44,7 +44,7 @@ def run_gpu(A_cols, ell, k, t, sketch, omega_seed, select_seed, batch=None, borr
 
 def run_oracle(A_cols, ell, k, t, sketch, omega_seed, select_seed, finalize=True, n1=None, n2=None):
     n, m = A_cols.shape
-    operand = {"f64": "f64", "f32": "f32", "bf16": "bf16"}[sketch]
+    operand = {"f64": "f64", "f32": "f32", "bf16": "bf16", "fp8": "fp8"}[sketch]
     cfg = Config(m=m, ell=ell, k=k, t=t, omega_seed=omega_seed, select_seed=select_seed, operand=operand,
                  hutch_n1=n1, hutch_n2=n2)
     o = OracleRID(cfg, n_max=n)
@@ -89,12 +89,13 @@ def compare_updates(s, o, tol, log_prefix=""):
 # same operands: binary64 sums in another order (~sqrt(m) 2^-53); binary32
 # accumulation within a slab plus binary32 transcendentals (~1e-6); bfloat16
 # operands: binary32 accumulation and rare one-ulp differences of the rounded
-# test matrix (~1e-5).
-SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-5}
+# test matrix (~1e-5); e4m3 operands: the scaled MFMA rounds inside each
+# 64-term product (a few 1e-5 of the sum of magnitudes, ~1e-4 of S).
+SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-5, "fp8": 3e-4}
 
 # Relative accuracy of the basis Gram G = A_J^T A_J: products of the data are
 # exact in binary64 and the sums are binary64 (another order than the oracle).
-GRAM_ACCURACY = {"f64": 1e-15, "f32": 1e-15, "bf16": 1e-15}
+GRAM_ACCURACY = {"f64": 1e-15, "f32": 1e-15, "bf16": 1e-15, "fp8": 1e-15}
 
 
 def hutch_regrouped(S, SJ, P, G, F, n1, n2):

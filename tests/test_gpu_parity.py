@@ -8,7 +8,9 @@ Tolerances:
   entries may land one bfloat16 ulp away from the oracle's rounding.
 * Sketch S: binary64 sums in another order (1e-12 relative Frobenius);
   binary32 accumulation within a row slab (2e-5); bfloat16 against the
-  oracle's product of bfloat16-rounded operands (1e-4).
+  oracle's product of bfloat16-rounded operands (1e-4); fp8 against the
+  oracle's product of the same e4m3 codes and block scales (1e-3: the scaled
+  MFMA rounds inside each 64-term product).
 * Everything downstream of S (scores, coefficients, NA-Hutch++ terms,
   reconstruction) is compared with a forward-error tolerance computed by the
   oracle itself: its own S is perturbed at the sketch accuracy of the form and
@@ -67,6 +69,20 @@ def test_omega_f32_and_bf16_match_oracle():
     assert np.max(np.abs(gb - ob)) <= 2.0 ** -7 * (1 + np.abs(ob).max())
 
 
+def test_omega_fp8_matches_oracle():
+    # e4m3(64 z) / 64 of the hardware-transcendental binary32 z against the
+    # oracle's rounding of the binary64 z: a code differs only where z lies
+    # within a few binary32 ulp of a rounding boundary, and then by one step
+    from paper_2405_16076_amd import omega_block
+    seed, ell, cnt = 2024, 320, 20000
+    o = oracle.quantize_fp8_omega(oracle.omega_block(seed, ell, 0, cnt))
+    g = omega_block("fp8", seed, ell, 0, cnt).cpu().numpy().astype(np.float64)
+    mism = np.mean(g != o)
+    log("omega fp8 mismatch fraction", mism)
+    assert mism <= 1e-3
+    assert np.all(np.abs(g - o) <= 0.125 * np.maximum(np.abs(g), np.abs(o)) + 2.0 ** -15)
+
+
 # ---------------------------------------------------------------------------
 # sketch S = Omega A and ||a_j||^2
 # ---------------------------------------------------------------------------
@@ -77,6 +93,10 @@ def test_omega_f32_and_bf16_match_oracle():
     ("f32", 70_000, 70, 300, 2e-5),
     ("bf16", 100_003, 300, 40, 1e-4),
     ("bf16", 65_536, 600, 300, 1e-4),
+    # fp8: same e4m3 codes and scales as the oracle; the scaled MFMA rounds
+    # inside each 64-term product (~1e-4 of S, see SKETCH_ACCURACY)
+    ("fp8", 100_003, 300, 40, 1e-3),
+    ("fp8", 65_536, 600, 300, 1e-3),
 ])
 def test_sketch_matches_oracle(sketch, m, n, ell, tol):
     log("sketch", sketch, m, n, ell)
@@ -92,7 +112,7 @@ def test_sketch_matches_oracle(sketch, m, n, ell, tol):
     assert np.max(np.abs(q - qo) / qo) <= 1e-13
 
 
-@pytest.mark.parametrize("sketch,ell", [("f32", 64), ("bf16", 64), ("bf16", 300)])
+@pytest.mark.parametrize("sketch,ell", [("f32", 64), ("bf16", 64), ("bf16", 300), ("fp8", 300)])
 def test_sketch_is_independent_of_batching(sketch, ell):
     log("batching independence", sketch, ell)
     rng = np.random.default_rng(5)
@@ -185,6 +205,12 @@ def test_pipeline_bf16_channel_operand_rounding():
     log("pipeline bf16 channel vs oracle with bf16-rounded operands")
     A = synth.channel(24, 17, 24, 300, seed=synth.data_seed(3), n_modes=120)
     _pipeline(A, 60, 30, 30, "bf16", 1003, 2003)
+
+
+def test_pipeline_fp8_channel_operand_rounding():
+    log("pipeline fp8 channel vs oracle with e4m3 operands")
+    A = synth.channel(24, 17, 24, 300, seed=synth.data_seed(3), n_modes=120)
+    _pipeline(A, 60, 30, 30, "fp8", 1003, 2003)
 
 
 def test_fewer_columns_than_slots_gives_zero_error():
