@@ -270,6 +270,85 @@ rid_status rid_debug_state(rid_stream* h, double* S, int64_t lds, int64_t cap_co
 rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64_t i0,
                            int64_t count, void* d_out, int64_t ld, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched streams.
+ *
+ * Many independent streams (fields, spatial blocks) of uneven m advanced
+ * together on one device; not part of the paper, whose method handles one
+ * stream.  Each member is an ordinary stream (Alg. 3 with Alg. 4 and Alg. 8,
+ * its own configuration, seeds and results); the batch only changes how its
+ * work is launched: per round, one persistent sketch launch whose workgroups
+ * walk the (member, row slab, sketch rows, column tile) work items of every
+ * member, one reduction launch, and each update kernel launched once for all
+ * members with an update due.  The launches of a round are captured into one
+ * HIP graph, updated in place from round to round.  The row slab of the
+ * sketch (the tile height) is chosen by timing the candidates on the first
+ * round's columns, once per batch shape in the process.
+ *
+ * A member's results are bitwise independent of the other members.  They
+ * equal those of a stand-alone stream with the same slab: the slab fixes the
+ * order of the binary64 sums over slabs, so the sketch can differ from a
+ * stand-alone stream's in the last bits.
+ * ------------------------------------------------------------------------- */
+typedef struct rid_batch rid_batch;
+
+#define RID_BATCH_NO_GRAPH 1u  /* launch each round directly (no graph capture) */
+#define RID_BATCH_NO_TUNE  2u  /* keep the default slab of 16384 rows */
+
+typedef struct rid_batch_info {
+  int32_t ns;                    /* members */
+  int32_t failed;                /* 1 after a device error */
+  int64_t rounds;                /* rounds run so far */
+  int64_t graph_launches;        /* rounds launched as a graph */
+  int64_t graph_instantiations;  /* executable graphs built */
+  int64_t graph_updates;         /* rounds that updated the executable in place */
+  int64_t slab_rows;             /* sketch rows per work item (tuned or default) */
+  int32_t tuned;                 /* 1 once the slab has been chosen by timing */
+  int32_t reserved0;
+  double tune_ms;                /* device time spent timing candidates */
+} rid_batch_info;
+
+/* Creates ns member streams from cfgs[0..ns-1] (each validated as by
+ * rid_init_stream; every member keeps its own sizes, precision and seeds).
+ * All batch work runs on an internal stream that is ordered after the work
+ * enqueued on `stream` before each batch call, and `stream` waits for it at
+ * the end of each call.  flags: RID_BATCH_NO_GRAPH, RID_BATCH_NO_TUNE.
+ * 1 <= ns <= 4096.  Errors: RID_EINVAL, RID_ENOMEM, RID_EDEVICE. */
+rid_status rid_init_batch(int32_t ns, const rid_config* cfgs, void* stream, uint32_t flags,
+                          rid_batch** out);
+
+/* One push round: member i receives b[i] >= 0 snapshots, d_cols[i] a device
+ * buffer of b[i] columns with column stride ld[i] >= m_i (as for
+ * rid_push_snapshots; d_cols[i] may be NULL when b[i] = 0).  flags:
+ * RID_COPY or RID_BORROW for every member of this call.  Full lookahead
+ * batches are sketched and their updates enqueued; a member whose pending
+ * columns fit in one lookahead batch waits for a later round or for
+ * rid_finalize_batch.  Asynchronous.  Errors: RID_EINVAL, RID_ECAPACITY,
+ * RID_ESTATE (batch failed or a member finalized), RID_EDEVICE. */
+rid_status rid_push_batch(rid_batch* bt, const void* const* d_cols, const int64_t* ld, const int32_t* b,
+                          uint32_t flags);
+
+/* Sketches everything pending and runs every member's remaining updates,
+ * the last one over its partial buffer (as rid_finalize).  Asynchronous. */
+rid_status rid_finalize_batch(rid_batch* bt);
+
+/* Member i as a stream handle owned by the batch: valid for rid_select,
+ * rid_coefficients, rid_error_estimate, rid_reconstruct (ordered before later
+ * work on the batch's caller stream), rid_get_info, rid_get_update,
+ * rid_debug_state and rid_last_error; rid_push_snapshots, rid_finalize,
+ * rid_reset and rid_destroy on it return RID_ESTATE. */
+rid_status rid_batch_stream(rid_batch* bt, int32_t i, rid_stream** out);
+
+/* Counters of the batch (synchronises its internal stream). */
+rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info);
+
+/* Message of the batch's last error (or of the last failed creation when bt
+ * is NULL). */
+rid_status rid_batch_last_error(rid_batch* bt, char* buf, size_t n);
+
+/* Waits for the batch's work and frees it with all its members. */
+rid_status rid_destroy_batch(rid_batch* bt);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,15 @@ class rid_profile(C.Structure):
                 ("gram_ms", C.c_double), ("gram_bytes", C.c_double)]
 
 
+RID_BATCH_NO_GRAPH, RID_BATCH_NO_TUNE = 1, 2
+
+
+class rid_batch_info(C.Structure):
+    _fields_ = [("ns", C.c_int32), ("failed", C.c_int32), ("rounds", C.c_int64), ("graph_launches", C.c_int64),
+                ("graph_instantiations", C.c_int64), ("graph_updates", C.c_int64), ("slab_rows", C.c_int64),
+                ("tuned", C.c_int32), ("reserved0", C.c_int32), ("tune_ms", C.c_double)]
+
+
 # name -> (restype, argtypes); every function declared in include/rid.h
 SIGNATURES = {
     "rid_config_default": (C.c_int, [C.POINTER(rid_config)]),
@@ -77,6 +86,14 @@ SIGNATURES = {
     "rid_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "rid_profile_read": (C.c_int, [C.c_void_p, C.POINTER(rid_profile)]),
     "rid_omega_block": (C.c_int, [C.c_int32, C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "rid_init_batch": (C.c_int, [C.c_int32, C.POINTER(rid_config), C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "rid_push_batch": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                 C.c_uint32]),
+    "rid_finalize_batch": (C.c_int, [C.c_void_p]),
+    "rid_batch_stream": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "rid_batch_get_info": (C.c_int, [C.c_void_p, C.POINTER(rid_batch_info)]),
+    "rid_batch_last_error": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
+    "rid_destroy_batch": (C.c_int, [C.c_void_p]),
 }
 
 _lib = None
@@ -104,8 +121,11 @@ class RIDError(RuntimeError):
         self.status = status
 
 
-def check(status, handle=None):
+def check(status, handle=None, batch=None):
     if status != RID_OK:
         buf = C.create_string_buffer(512)
-        lib().rid_last_error(handle, buf, 512)
+        if batch is not None:
+            lib().rid_batch_last_error(batch, buf, 512)
+        else:
+            lib().rid_last_error(handle, buf, 512)
         raise RIDError(status, buf.value.decode(errors="replace"))

@@ -78,6 +78,8 @@ __global__ void init_state_kernel(int64_t* J, double* tau_old, int t, DevScalars
 
 using namespace rid;
 
+struct rid_batch;
+
 struct rid_stream {
   rid_config cfg;
   hipStream_t s = nullptr;
@@ -93,6 +95,7 @@ struct rid_stream {
   int64_t ldc = 0;
   // device memory
   std::vector<void*> allocs;
+  std::vector<size_t> alloc_bytes;
   size_t dev_bytes = 0;
   double *S = nullptr, *colsq = nullptr, *W = nullptr, *hv = nullptr;
   double* SST[2] = {nullptr, nullptr};  // SS^T after the last enqueued update (ping-pong)
@@ -129,6 +132,11 @@ struct rid_stream {
   bool profiling = false;
   std::vector<Mark> marks;
   std::vector<hipEvent_t> event_pool;
+  // member of a batch: pushes go through the batch; results reach the
+  // caller's stream `join` through `join_ev`
+  rid_batch* owner = nullptr;
+  hipStream_t join = nullptr;
+  hipEvent_t join_ev = nullptr;
 };
 
 static thread_local std::string g_last_err;
@@ -162,6 +170,7 @@ static rid_status dalloc(rid_stream* h, void** p, size_t bytes) {
     return fail(h, RID_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
   h->allocs.push_back(*p);
+  h->alloc_bytes.push_back(bytes);
   h->dev_bytes += bytes;
   return RID_OK;
 }
@@ -174,6 +183,17 @@ static rid_status dalloc_t(rid_stream* h, T** p, size_t count) {
   return st;
 }
 
+static void dfree(rid_stream* h, void* p) {
+  for (size_t i = 0; i < h->allocs.size(); ++i)
+    if (h->allocs[i] == p) {
+      (void)hipFree(p);
+      h->dev_bytes -= h->alloc_bytes[i];
+      h->allocs.erase(h->allocs.begin() + (long)i);
+      h->alloc_bytes.erase(h->alloc_bytes.begin() + (long)i);
+      return;
+    }
+}
+
 static void free_all(rid_stream* h) {
   for (auto& mk : h->marks) {
     (void)hipEventDestroy(mk.a);
@@ -184,6 +204,7 @@ static void free_all(rid_stream* h) {
   h->event_pool.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
+  h->alloc_bytes.clear();
   if (h->colptr_host) (void)hipHostFree(h->colptr_host);
   h->colptr_host = nullptr;
 }
@@ -430,7 +451,7 @@ static rid_status upload_colptrs(rid_stream* h) {
   return RID_OK;
 }
 
-static rid_status sketch_range(rid_stream* h, int64_t c0, int b) {
+static SketchArgs sketch_args(rid_stream* h, int64_t c0, int b) {
   SketchArgs a;
   a.colptr = h->colptr_dev;
   a.c0 = c0;
@@ -447,21 +468,27 @@ static rid_status sketch_range(rid_stream* h, int64_t c0, int b) {
   a.seed = h->cfg.omega_seed;
   a.part = h->part;
   a.normpart = h->normpart;
+  a.S = h->S;
+  a.colsq = h->colsq;
+  a.nonfinite = &h->sc->nonfinite;
+  return a;
+}
+
+static rid_status sketch_range(rid_stream* h, int64_t c0, int b) {
+  const SketchArgs a = sketch_args(h, c0, b);
   int mk = mark_begin(h, 0, (double)b * (double)h->m * h->esize);
   RID_HIP(h, launch_sketch(h->prec, a, h->s));
   mark_end(h, mk);
   mk = mark_begin(h, 1, 0.0);
-  RID_HIP(h, launch_sketch_reduce(h->prec, a, h->ell, h->S, h->colsq, &h->sc->nonfinite, h->s));
+  RID_HIP(h, launch_sketch_reduce(h->prec, a, h->s));
   mark_end(h, mk);
   return RID_OK;
 }
 
 // Enqueues updates n_updates .. n_updates + nz - 1: n_full of t columns and,
 // when last > 0, one more of `last` columns.
-static rid_status run_updates(rid_stream* h, int n_full, int last) {
+static BatchArgs batch_args(rid_stream* h, int n_full, int last) {
   const int nz = n_full + (last > 0 ? 1 : 0);
-  if (nz == 0) return RID_OK;
-  if (nz > h->nzmax) return fail(h, RID_EDEVICE, "internal: update batch larger than its slots");
   BatchArgs b;
   b.ell = h->ell;
   b.k = h->k;
@@ -480,19 +507,20 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   b.Fu = h->Fu;
   b.skipu = h->skipu;
   b.recs = h->recs;
-  int mk = mark_begin(h, 2, 0.0);
-  RID_HIP(h, launch_update_batch(b, h->s));
-  mark_end(h, mk);
-  h->sst_cur ^= 1;
-  for (int z = 0; z < nz; ++z) {
-    UpdArgs a;
+  return b;
+}
+
+// Arguments of update n_updates + z of a batch of n_full full updates.
+static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
+  UpdArgs a;
+  {
     a.ell = h->ell;
     a.k = h->k;
     a.t = h->t;
     a.n1 = h->n1;
     a.n2 = h->n2;
-    a.u = h->n_updates;
-    a.c0 = h->n_updates * h->t;
+    a.u = h->n_updates + z;
+    a.c0 = a.u * h->t;
     a.cnt = (z < n_full) ? h->t : last;
     a.n_obs = a.c0 + a.cnt;
     a.fill_mult = h->fill_mult;
@@ -528,6 +556,21 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
     a.hw = h->hw;
     a.sc = h->sc;
     a.recs = h->recs;
+  }
+  return a;
+}
+
+static rid_status run_updates(rid_stream* h, int n_full, int last) {
+  const int nz = n_full + (last > 0 ? 1 : 0);
+  if (nz == 0) return RID_OK;
+  if (nz > h->nzmax) return fail(h, RID_EDEVICE, "internal: update batch larger than its slots");
+  const BatchArgs b = batch_args(h, n_full, last);
+  int mk = mark_begin(h, 2, 0.0);
+  RID_HIP(h, launch_update_batch(b, h->s));
+  mark_end(h, mk);
+  h->sst_cur ^= 1;
+  for (int z = 0; z < nz; ++z) {
+    const UpdArgs a = upd_args(h, z, n_full, last);
     mk = mark_begin(h, 2, (double)a.u);
     RID_HIP(h, launch_update_select(a, h->s));
     mark_end(h, mk);
@@ -537,9 +580,9 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
     mk = mark_begin(h, 2, (double)a.u);
     RID_HIP(h, launch_update_coeff(a, h->s));
     mark_end(h, mk);
-    h->n_updates += 1;
     h->last_nobs = a.n_obs;
   }
+  h->n_updates += nz;
   return RID_OK;
 }
 
@@ -585,8 +628,24 @@ static rid_status sync_check(rid_stream* h) {
 
 extern "C" {
 
+static rid_status push_columns(rid_stream* h, const void* d_cols, int64_t ld, int32_t b, uint32_t flags,
+                               bool flush);
+
 rid_status rid_push_snapshots(rid_stream* h, const void* d_cols, int64_t ld, int32_t b, uint32_t flags) {
   if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  if (h->owner) return fail(h, RID_ESTATE, "the stream belongs to a batch: push through rid_push_batch");
+  return push_columns(h, d_cols, ld, b, flags, true);
+}
+
+}  // extern "C"
+
+// Appends b columns to the stream's column table (BORROW) or ring (COPY).
+// With `flush`, full lookahead batches are sketched and their updates
+// enqueued as they complete; a batch member leaves that to the batch.
+static rid_status batch_make_room(rid_batch* bt);
+
+static rid_status push_columns(rid_stream* h, const void* d_cols, int64_t ld, int32_t b, uint32_t flags,
+                               bool flush) {
   if (h->failed || h->finalized) return fail(h, RID_ESTATE, "stream finalized or failed");
   if (b < 0 || ld < h->m || (b > 0 && !d_cols) || (flags != RID_COPY && flags != RID_BORROW))
     return fail(h, RID_EINVAL, "bad push arguments");
@@ -600,7 +659,7 @@ rid_status rid_push_snapshots(rid_stream* h, const void* d_cols, int64_t ld, int
       return fail(h, RID_EINVAL, "BORROW needs 16-byte aligned columns (pointer and ld * size)");
     for (int j = 0; j < b; ++j) h->colptr_host[h->n_pushed + j] = base + (uint64_t)j * ld * es;
     h->n_pushed += b;
-    return flush_full(h);
+    return flush ? flush_full(h) : RID_OK;
   }
   // COPY: stage the columns in the ring, never overwriting a column that an
   // enqueued update has not consumed yet.
@@ -615,7 +674,8 @@ rid_status rid_push_snapshots(rid_stream* h, const void* d_cols, int64_t ld, int
     const int64_t consumed = h->n_updates * h->t;
     int64_t space = h->ring_cap - (h->n_pushed - consumed);
     if (space <= 0) {
-      if ((st = flush_all(h)) != RID_OK) return st;
+      if ((st = (h->owner ? batch_make_room(h->owner) : flush_all(h))) != RID_OK) return st;
+      if (h->failed) return fail(h, RID_ESTATE, "stream failed");
       continue;
     }
     const int64_t slot = h->n_pushed % h->ring_cap;
@@ -628,11 +688,13 @@ rid_status rid_push_snapshots(rid_stream* h, const void* d_cols, int64_t ld, int
       h->colptr_host[h->n_pushed + j] = reinterpret_cast<uint64_t>(dst) + (uint64_t)j * h->ring_ld * es;
     h->n_pushed += chunk;
     done += (int)chunk;
-    if (h->n_pushed - h->n_sketched >= h->b_max || h->n_pushed - consumed >= h->ring_cap)
+    if (flush && (h->n_pushed - h->n_sketched >= h->b_max || h->n_pushed - consumed >= h->ring_cap))
       if ((st = flush_all(h)) != RID_OK) return st;
   }
   return RID_OK;
 }
+
+extern "C" {
 
 rid_status rid_flush(rid_stream* h) {
   if (!h) return fail(nullptr, RID_EINVAL, "null handle");
@@ -642,6 +704,7 @@ rid_status rid_flush(rid_stream* h) {
 
 rid_status rid_finalize(rid_stream* h) {
   if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  if (h->owner) return fail(h, RID_ESTATE, "the stream belongs to a batch: use rid_finalize_batch");
   if (h->failed || h->finalized) return fail(h, RID_ESTATE, "stream finalized or failed");
   // Sketch what is left; the full updates completed by the last sketch launch
   // share one batch (one eigen-solve launch) with the final partial update.
@@ -665,6 +728,7 @@ rid_status rid_finalize(rid_stream* h) {
 
 rid_status rid_reset(rid_stream* h) {
   if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  if (h->owner) return fail(h, RID_ESTATE, "the stream belongs to a batch");
   if (h->failed) return fail(h, RID_ESTATE, "stream failed");
   RID_HIP(h, hipStreamSynchronize(h->s));
   const size_t ell = h->ell, t = h->t;
@@ -744,6 +808,10 @@ rid_status rid_reconstruct(rid_stream* h, int64_t j0, int32_t c, void* d_out, in
                        reinterpret_cast<const float*>(h->cpool), h->ldc, h->P, h->t, h->J, h->m, j0, c,
                        reinterpret_cast<float*>(d_out), ld);
   RID_HIP(h, hipGetLastError());
+  if (h->join) {  // a batch member: the caller's stream waits for the result
+    RID_HIP(h, hipEventRecord(h->join_ev, h->s));
+    RID_HIP(h, hipStreamWaitEvent(h->join, h->join_ev, 0));
+  }
   return RID_OK;
 }
 
@@ -837,8 +905,17 @@ rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
   return RID_OK;
 }
 
+static void destroy_stream(rid_stream* h) {
+  (void)hipStreamSynchronize(h->s);
+  (void)hipGetLastError();
+  if (h->join_ev) (void)hipEventDestroy(h->join_ev);
+  free_all(h);
+  delete h;
+}
+
 rid_status rid_destroy(rid_stream* h) {
   if (!h) return RID_EINVAL;
+  if (h->owner) return fail(h, RID_ESTATE, "the stream belongs to a batch: use rid_destroy_batch");
   (void)hipStreamSynchronize(h->s);
   (void)hipGetLastError();
   free_all(h);
@@ -855,6 +932,524 @@ rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64
   hipError_t e = launch_omega_block(prec, omega_seed, ell, i0, count, d_out, ld,
                                     reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(nullptr, RID_EDEVICE, hipGetErrorString(e));
+  return RID_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched streams.
+//
+// A batch owns ns member streams and an internal HIP stream on which all of
+// their work runs.  A round advances every member by at most one lookahead
+// batch: one persistent sketch launch walks the (stream, row slab, sketch
+// rows, column tile) items of all members, one launch reduces them, and each
+// update kernel runs once for all members with an update due (grid y = the
+// member).  The argument tables of a round go to the device in one copy; the
+// launches of a round are captured into a HIP graph whose executable is
+// updated in place from round to round.  The row slab of the sketch is picked
+// once per batch shape by timing the candidates on the first round's columns.
+// ---------------------------------------------------------------------------
+struct rid_batch {
+  int ns = 0;
+  uint32_t flags = 0;
+  hipStream_t user = nullptr;  // the caller's stream
+  hipStream_t s = nullptr;     // internal stream
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<rid_stream*> st;
+  static constexpr int kSlots = 4;
+  char* host_slot[kSlots] = {};
+  hipEvent_t slot_ev[kSlots] = {};
+  bool slot_used[kSlots] = {};
+  int slot = 0;
+  char* dev_tab = nullptr;
+  size_t tab_cap = 0;
+  hipGraphExec_t exec = nullptr;
+  int64_t rounds = 0, graph_launches = 0, graph_instantiations = 0, graph_updates = 0;
+  int64_t slab_rows = 0, min_slab_rows = 0;
+  bool tuned = false;
+  double tune_ms = 0.0;
+  int n_cu = 0;
+  bool failed = false;
+  std::string last_err;
+};
+
+static rid_status bfail(rid_batch* bt, rid_status st, const std::string& msg) {
+  if (bt) {
+    bt->last_err = msg;
+    if (st == RID_EDEVICE || st == RID_ENUMERIC) {
+      bt->failed = true;
+      for (rid_stream* h : bt->st) fail(h, st, msg);
+    }
+  }
+  g_last_err = msg;
+  return st;
+}
+
+#define BT_HIP(bt, expr)                                                                   \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return bfail((bt), RID_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// slab candidates of the sketch (rows per work item)
+static std::vector<int64_t> slab_candidates(int prec) {
+  const int64_t cap = (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) ? 65536
+                      : (prec == RID_SKETCH_F32 ? 32768 : 16384);
+  std::vector<int64_t> v;
+  for (int64_t r = 4096; r <= cap; r *= 2) v.push_back(r);
+  return v;
+}
+
+static void set_slab(rid_stream* h, int64_t rows) {
+  h->slab_rows = rows;
+  h->n_slabs = (int)((h->m + rows - 1) / rows);
+}
+
+// Bytes of the argument tables of one round (upper bound).
+static size_t table_bytes(int ns, int nzmax) {
+  const size_t launches = 8 + (size_t)nzmax * 24;
+  const size_t per_stream = 4 * sizeof(SketchArgs) + 4 * sizeof(BatchArgs) + 64 +
+                            (size_t)nzmax * 24 * (sizeof(UpdArgs) + sizeof(int4));
+  return (size_t)ns * per_stream + launches * 2 * 256 + (64 << 10);
+}
+
+// The next host staging slot (waits until the copy that last read it is done).
+static rid_status take_slot(rid_batch* bt, Stage& stg) {
+  bt->slot = (bt->slot + 1) % rid_batch::kSlots;
+  if (bt->slot_used[bt->slot]) BT_HIP(bt, hipEventSynchronize(bt->slot_ev[bt->slot]));
+  stg.host = bt->host_slot[bt->slot];
+  stg.dev = bt->dev_tab;
+  stg.cap = bt->tab_cap;
+  stg.used = 0;
+  stg.overflow = false;
+  return RID_OK;
+}
+
+static rid_status copy_slot(rid_batch* bt, const Stage& stg) {
+  if (stg.overflow) return bfail(bt, RID_EINVAL, "internal: argument tables exceed their staging buffer");
+  if (stg.used) BT_HIP(bt, hipMemcpyAsync(bt->dev_tab, stg.host, stg.used, hipMemcpyHostToDevice, bt->s));
+  BT_HIP(bt, hipEventRecord(bt->slot_ev[bt->slot], bt->s));
+  bt->slot_used[bt->slot] = true;
+  return RID_OK;
+}
+
+// Largest number of resident workgroups of a persistent sketch kernel.
+static int sketch_grid_cap(rid_batch* bt, int prec) {
+  return bt->n_cu * ((prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) ? 1 : 4);
+}
+
+static void plan_sketches(rid_batch* bt, const std::vector<SketchArgs>& args, const std::vector<int>& prec,
+                          Stage& stg, std::vector<BLaunch>& out, bool with_reduce) {
+  for (int p = RID_SKETCH_F64; p <= RID_SKETCH_FP8; ++p) {
+    std::vector<SketchArgs> g;
+    for (size_t i = 0; i < args.size(); ++i)
+      if (prec[i] == p) g.push_back(args[i]);
+    if (g.empty()) continue;
+    plan_sketch_multi(p, g.data(), (int)g.size(), sketch_grid_cap(bt, p), stg, out);
+    if (with_reduce) plan_sketch_reduce_b(p, g.data(), (int)g.size(), stg, out);
+  }
+}
+
+// Runs the launches of a round: captured into the batch's graph (updated in
+// place when the round has the same shape as the last one), or directly.
+static rid_status batch_exec(rid_batch* bt, const std::vector<BLaunch>& L) {
+  if (L.empty()) return RID_OK;
+  if (bt->flags & RID_BATCH_NO_GRAPH) {
+    BT_HIP(bt, run_launches(L, bt->s));
+    return RID_OK;
+  }
+  hipGraph_t g = nullptr;
+  BT_HIP(bt, hipStreamBeginCapture(bt->s, hipStreamCaptureModeThreadLocal));
+  const hipError_t e1 = run_launches(L, bt->s);
+  const hipError_t e2 = hipStreamEndCapture(bt->s, &g);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return bfail(bt, RID_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+  }
+  if (bt->exec) {
+    hipGraphNode_t en = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateSuccess;
+    if (hipGraphExecUpdate(bt->exec, g, &en, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      bt->graph_updates += 1;
+    } else {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(bt->exec);
+      bt->exec = nullptr;
+    }
+  }
+  if (!bt->exec) {
+    const hipError_t e = hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      bt->exec = nullptr;
+      (void)hipGraphDestroy(g);
+      return bfail(bt, RID_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    bt->graph_instantiations += 1;
+  }
+  const hipError_t e = hipGraphLaunch(bt->exec, bt->s);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return bfail(bt, RID_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  bt->graph_launches += 1;
+  return RID_OK;
+}
+
+// Picks the sketch slab of the batch by timing each candidate on the columns
+// `args` (outside any graph); every candidate writes the same partial buffers,
+// which the real sketch of the round overwrites afterwards.
+static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const std::vector<int64_t>& c0,
+                             const std::vector<int>& b) {
+  static std::vector<std::pair<std::string, int64_t>> cache;
+  int64_t msum = 0;
+  int prec = bt->st[0]->prec;
+  for (rid_stream* h : bt->st) msum += h->m;
+  char key[160];
+  snprintf(key, sizeof(key), "p%d r%d ns%d m%lld b%d", prec, bt->st[0]->rbw, bt->ns,
+           (long long)(msum >> 16), bt->st[0]->b_max);
+  for (auto& kv : cache)
+    if (kv.first == key) {
+      bt->slab_rows = kv.second;
+      for (rid_stream* h : bt->st) set_slab(h, bt->slab_rows);
+      bt->tuned = true;
+      return RID_OK;
+    }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BT_HIP(bt, hipEventCreate(&e0));
+  BT_HIP(bt, hipEventCreate(&e1));
+  double best = 1e300;
+  int64_t best_rows = bt->slab_rows;
+  for (int64_t rows : slab_candidates(prec)) {
+    if (rows < bt->min_slab_rows) continue;
+    for (rid_stream* h : bt->st) set_slab(h, rows);
+    std::vector<SketchArgs> args;
+    std::vector<int> precs;
+    for (size_t i = 0; i < who.size(); ++i) {
+      args.push_back(sketch_args(bt->st[who[i]], c0[i], b[i]));
+      precs.push_back(bt->st[who[i]]->prec);
+    }
+    float ms_last = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      Stage stg;
+      rid_status sts = take_slot(bt, stg);
+      if (sts != RID_OK) return sts;
+      std::vector<BLaunch> L;
+      plan_sketches(bt, args, precs, stg, L, false);
+      if ((sts = copy_slot(bt, stg)) != RID_OK) return sts;
+      BT_HIP(bt, hipEventRecord(e0, bt->s));
+      BT_HIP(bt, run_launches(L, bt->s));
+      BT_HIP(bt, hipEventRecord(e1, bt->s));
+      BT_HIP(bt, hipEventSynchronize(e1));
+      BT_HIP(bt, hipEventElapsedTime(&ms_last, e0, e1));
+    }
+    bt->tune_ms += ms_last;
+    if (ms_last < best) {
+      best = ms_last;
+      best_rows = rows;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  bt->slab_rows = best_rows;
+  for (rid_stream* h : bt->st) set_slab(h, best_rows);
+  cache.emplace_back(key, best_rows);
+  bt->tuned = true;
+  return RID_OK;
+}
+
+enum RoundMode { ROUND_FULL = 0, ROUND_ALL = 1, ROUND_FINAL = 2 };
+
+// One round; *worked is false when no member had anything to do.
+static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
+  *worked = false;
+  const int ns = bt->ns;
+  std::vector<int> sk_who, up_who;
+  std::vector<int64_t> sk_c0;
+  std::vector<int> sk_b, nfull(ns, 0), nlast(ns, 0), bsk(ns, 0);
+  for (int i = 0; i < ns; ++i) {
+    rid_stream* h = bt->st[i];
+    if (h->finalized) continue;
+    const int64_t pending = h->n_pushed - h->n_sketched;
+    int b = 0;
+    if (mode == ROUND_FULL) b = pending > h->b_max ? h->b_max : 0;
+    else b = (int)std::min<int64_t>(h->b_max, pending);
+    const int64_t nsk = h->n_sketched + b;
+    // after the final partial update n_updates * t exceeds n_pushed: no more
+    const int full = (int)std::max<int64_t>(0, nsk / h->t - h->n_updates);
+    int last = 0;
+    if (mode == ROUND_FINAL && nsk == h->n_pushed)
+      last = (int)std::max<int64_t>(0, h->n_pushed - (h->n_updates + full) * h->t);
+    bsk[i] = b;
+    nfull[i] = full;
+    nlast[i] = last;
+    if (b > 0) {
+      sk_who.push_back(i);
+      sk_c0.push_back(h->n_sketched);
+      sk_b.push_back(b);
+    }
+    if (full + (last > 0 ? 1 : 0) > 0) up_who.push_back(i);
+  }
+  if (sk_who.empty() && up_who.empty()) return RID_OK;
+  *worked = true;
+  rid_status sts;
+  for (int i : sk_who)
+    if ((sts = upload_colptrs(bt->st[i])) != RID_OK) return bfail(bt, RID_EDEVICE, bt->st[i]->last_err);
+  if (!sk_who.empty() && !bt->tuned && !(bt->flags & RID_BATCH_NO_TUNE))
+    if ((sts = batch_tune(bt, sk_who, sk_c0, sk_b)) != RID_OK) return sts;
+
+  Stage stg;
+  if ((sts = take_slot(bt, stg)) != RID_OK) return sts;
+  std::vector<BLaunch> L;
+  {
+    std::vector<SketchArgs> args;
+    std::vector<int> precs;
+    for (size_t q = 0; q < sk_who.size(); ++q) {
+      args.push_back(sketch_args(bt->st[sk_who[q]], sk_c0[q], sk_b[q]));
+      precs.push_back(bt->st[sk_who[q]]->prec);
+    }
+    plan_sketches(bt, args, precs, stg, L, true);
+  }
+  int max_nz = 0;
+  if (!up_who.empty()) {
+    std::vector<BatchArgs> ba;
+    for (int i : up_who) {
+      rid_stream* h = bt->st[i];
+      const int nz = nfull[i] + (nlast[i] > 0 ? 1 : 0);
+      if (nz > h->nzmax) return bfail(bt, RID_EDEVICE, "internal: update batch larger than its slots");
+      max_nz = std::max(max_nz, nz);
+      ba.push_back(batch_args(h, nfull[i], nlast[i]));
+    }
+    plan_update_batch_b(ba.data(), (int)ba.size(), stg, L);
+    for (int z = 0; z < max_nz; ++z) {
+      std::vector<UpdArgs> ua;
+      for (int i : up_who)
+        if (z < nfull[i] + (nlast[i] > 0 ? 1 : 0)) ua.push_back(upd_args(bt->st[i], z, nfull[i], nlast[i]));
+      plan_update_select_b(ua.data(), (int)ua.size(), stg, L);
+      plan_update_gram_b(ua.data(), (int)ua.size(), stg, L);
+      plan_update_coeff_b(ua.data(), (int)ua.size(), stg, L);
+    }
+  }
+  if ((sts = copy_slot(bt, stg)) != RID_OK) return sts;
+  if ((sts = batch_exec(bt, L)) != RID_OK) return sts;
+  for (int i = 0; i < ns; ++i) {
+    rid_stream* h = bt->st[i];
+    h->n_sketched += bsk[i];
+    const int nz = nfull[i] + (nlast[i] > 0 ? 1 : 0);
+    if (nz > 0) {
+      h->sst_cur ^= 1;
+      h->n_updates += nz;
+      h->last_nobs = (h->n_updates - 1) * h->t + (nlast[i] > 0 ? nlast[i] : h->t);
+    }
+  }
+  bt->rounds += 1;
+  return RID_OK;
+}
+
+// COPY pushes: free ring space by sketching everything pending.
+static rid_status batch_make_room(rid_batch* bt) {
+  bool worked = true;
+  while (worked) {
+    rid_status st = batch_round(bt, ROUND_ALL, &worked);
+    if (st != RID_OK) return st;
+  }
+  return RID_OK;
+}
+
+static rid_status batch_enter(rid_batch* bt) {
+  BT_HIP(bt, hipEventRecord(bt->ev_in, bt->user));
+  BT_HIP(bt, hipStreamWaitEvent(bt->s, bt->ev_in, 0));
+  return RID_OK;
+}
+
+static rid_status batch_leave(rid_batch* bt) {
+  BT_HIP(bt, hipEventRecord(bt->ev_out, bt->s));
+  BT_HIP(bt, hipStreamWaitEvent(bt->user, bt->ev_out, 0));
+  return RID_OK;
+}
+
+static void batch_free(rid_batch* bt) {
+  if (bt->s) (void)hipStreamSynchronize(bt->s);
+  (void)hipGetLastError();
+  for (rid_stream* h : bt->st) {
+    h->owner = nullptr;
+    destroy_stream(h);
+  }
+  bt->st.clear();
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  for (int i = 0; i < rid_batch::kSlots; ++i) {
+    if (bt->host_slot[i]) (void)hipHostFree(bt->host_slot[i]);
+    if (bt->slot_ev[i]) (void)hipEventDestroy(bt->slot_ev[i]);
+  }
+  if (bt->dev_tab) (void)hipFree(bt->dev_tab);
+  if (bt->ev_in) (void)hipEventDestroy(bt->ev_in);
+  if (bt->ev_out) (void)hipEventDestroy(bt->ev_out);
+  if (bt->s) (void)hipStreamDestroy(bt->s);
+  (void)hipGetLastError();
+  delete bt;
+}
+
+extern "C" {
+
+rid_status rid_init_batch(int32_t ns, const rid_config* cfgs, void* stream, uint32_t flags, rid_batch** out) {
+  if (!cfgs || !out) return fail(nullptr, RID_EINVAL, "null argument");
+  *out = nullptr;
+  if (ns < 1 || ns > kMaxBatchStreams) return fail(nullptr, RID_EINVAL, "ns must be in [1, 4096]");
+  if (flags & ~(RID_BATCH_NO_GRAPH | RID_BATCH_NO_TUNE)) return fail(nullptr, RID_EINVAL, "unknown batch flags");
+  for (int i = 0; i < ns; ++i) {
+    rid_status st = validate(&cfgs[i]);
+    if (st != RID_OK) return st;
+  }
+  rid_batch* bt = new rid_batch();
+  bt->ns = ns;
+  bt->flags = flags;
+  bt->user = reinterpret_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      hipStreamCreateWithFlags(&bt->s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&bt->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&bt->ev_out, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    batch_free(bt);
+    return fail(nullptr, RID_EDEVICE, "batch stream or event creation failed");
+  }
+  bt->n_cu = prop.multiProcessorCount;
+  int nzmax = 0;
+  int64_t min_rows = 1 << 30;
+  for (int i = 0; i < ns; ++i) {
+    rid_stream* h = nullptr;
+    rid_status st = rid_init_stream(&cfgs[i], bt->s, &h);
+    if (st != RID_OK) {
+      const std::string msg = g_last_err;
+      batch_free(bt);
+      g_last_err = "member " + std::to_string(i) + ": " + msg;
+      return st;
+    }
+    h->owner = bt;
+    h->join = bt->user;
+    bt->st.push_back(h);
+    if (hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      batch_free(bt);
+      return fail(nullptr, RID_EDEVICE, "event creation failed");
+    }
+    nzmax = std::max(nzmax, h->nzmax);
+    min_rows = std::min(min_rows, slab_candidates(h->prec).front());
+  }
+  // every member keeps the slab geometry of the batch: partial buffers sized
+  // for the smallest candidate, the default slab until the tuner has run
+  bt->min_slab_rows = (flags & RID_BATCH_NO_TUNE) ? 16384 : min_rows;
+  bt->slab_rows = 16384;
+  for (rid_stream* h : bt->st) {
+    const int64_t rows = std::min<int64_t>(bt->min_slab_rows, slab_candidates(h->prec).back());
+    set_slab(h, rows);
+    void* part = nullptr;
+    double* normpart = nullptr;
+    const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
+    rid_status st = dalloc(h, &part, (size_t)h->n_slabs * h->b_max * h->ell_pad * psize);
+    if (st == RID_OK) st = dalloc_t(h, &normpart, (size_t)h->n_slabs * h->b_max);
+    if (st != RID_OK) {
+      batch_free(bt);
+      return st;
+    }
+    dfree(h, h->part);
+    dfree(h, h->normpart);
+    h->part = part;
+    h->normpart = normpart;
+    set_slab(h, std::min<int64_t>(bt->slab_rows, slab_candidates(h->prec).back()));
+  }
+  bt->tab_cap = table_bytes(ns, nzmax);
+  if (hipMalloc(reinterpret_cast<void**>(&bt->dev_tab), bt->tab_cap) != hipSuccess) {
+    (void)hipGetLastError();
+    batch_free(bt);
+    return fail(nullptr, RID_ENOMEM, "argument table allocation failed");
+  }
+  for (int i = 0; i < rid_batch::kSlots; ++i)
+    if (hipHostMalloc(reinterpret_cast<void**>(&bt->host_slot[i]), bt->tab_cap, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&bt->slot_ev[i], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      batch_free(bt);
+      return fail(nullptr, RID_ENOMEM, "staging allocation failed");
+    }
+  *out = bt;
+  return RID_OK;
+}
+
+rid_status rid_push_batch(rid_batch* bt, const void* const* d_cols, const int64_t* ld, const int32_t* b,
+                          uint32_t flags) {
+  if (!bt) return fail(nullptr, RID_EINVAL, "null batch");
+  if (bt->failed) return bfail(bt, RID_ESTATE, "batch failed");
+  if (!d_cols || !ld || !b) return bfail(bt, RID_EINVAL, "null argument");
+  if (flags != RID_COPY && flags != RID_BORROW) return bfail(bt, RID_EINVAL, "bad flags");
+  for (int i = 0; i < bt->ns; ++i) {
+    rid_stream* h = bt->st[i];
+    if (b[i] < 0 || (b[i] > 0 && (!d_cols[i] || ld[i] < h->m))) return bfail(bt, RID_EINVAL, "bad push arguments");
+    if (b[i] > 0 && h->finalized) return bfail(bt, RID_ESTATE, "stream finalized");
+    if (h->n_pushed + b[i] > h->n_max) return bfail(bt, RID_ECAPACITY, "push exceeds n_max");
+    if (flags == RID_BORROW && b[i] > 0 &&
+        (reinterpret_cast<uintptr_t>(d_cols[i]) % 16 != 0 || (ld[i] * h->esize) % 16 != 0))
+      return bfail(bt, RID_EINVAL, "BORROW needs 16-byte aligned columns (pointer and ld * size)");
+  }
+  rid_status st = batch_enter(bt);
+  if (st != RID_OK) return st;
+  for (int i = 0; i < bt->ns; ++i)
+    if (b[i] > 0 && (st = push_columns(bt->st[i], d_cols[i], ld[i], b[i], flags, false)) != RID_OK)
+      return bfail(bt, st == RID_EDEVICE ? RID_EDEVICE : st, bt->st[i]->last_err);
+  bool worked = true;
+  while (worked)
+    if ((st = batch_round(bt, ROUND_FULL, &worked)) != RID_OK) return st;
+  return batch_leave(bt);
+}
+
+rid_status rid_finalize_batch(rid_batch* bt) {
+  if (!bt) return fail(nullptr, RID_EINVAL, "null batch");
+  if (bt->failed) return bfail(bt, RID_ESTATE, "batch failed");
+  rid_status st = batch_enter(bt);
+  if (st != RID_OK) return st;
+  bool worked = true;
+  while (worked)
+    if ((st = batch_round(bt, ROUND_FINAL, &worked)) != RID_OK) return st;
+  for (rid_stream* h : bt->st) h->finalized = true;
+  return batch_leave(bt);
+}
+
+rid_status rid_batch_stream(rid_batch* bt, int32_t i, rid_stream** out) {
+  if (!bt || !out) return fail(nullptr, RID_EINVAL, "null argument");
+  if (i < 0 || i >= bt->ns) return bfail(bt, RID_EINVAL, "member index out of range");
+  *out = bt->st[i];
+  return RID_OK;
+}
+
+rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info) {
+  if (!bt || !info) return fail(nullptr, RID_EINVAL, "null argument");
+  if (!bt->failed) {
+    hipError_t e = hipStreamSynchronize(bt->s);
+    if (e != hipSuccess) bfail(bt, RID_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  }
+  memset(info, 0, sizeof(*info));
+  info->ns = bt->ns;
+  info->failed = bt->failed ? 1 : 0;
+  info->rounds = bt->rounds;
+  info->graph_launches = bt->graph_launches;
+  info->graph_instantiations = bt->graph_instantiations;
+  info->graph_updates = bt->graph_updates;
+  info->slab_rows = bt->slab_rows;
+  info->tuned = bt->tuned ? 1 : 0;
+  info->tune_ms = bt->tune_ms;
+  return RID_OK;
+}
+
+rid_status rid_batch_last_error(rid_batch* bt, char* buf, size_t n) {
+  if (!buf || n == 0) return RID_EINVAL;
+  snprintf(buf, n, "%s", bt ? bt->last_err.c_str() : g_last_err.c_str());
+  return RID_OK;
+}
+
+rid_status rid_destroy_batch(rid_batch* bt) {
+  if (!bt) return RID_EINVAL;
+  batch_free(bt);
   return RID_OK;
 }
 

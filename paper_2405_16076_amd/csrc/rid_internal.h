@@ -6,6 +6,9 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <vector>
 
 #include "../../include/rid.h"
 
@@ -13,6 +16,7 @@ namespace rid {
 
 constexpr int kMaxEll = 512;     // sketch rows supported
 constexpr int kMaxT = 256;       // basis slots supported
+constexpr int kMaxBatchStreams = 4096;  // streams per batch
 constexpr int kMTile = 64;       // test-matrix rows per sketch workgroup
 constexpr int kOmegaRowsPerCall = 8;
 
@@ -234,6 +238,9 @@ struct SketchArgs {
   uint64_t seed;
   void* part;              // [n_slabs][b_max][ell_pad] float (double for F64)
   double* normpart;        // [n_slabs][b_max]
+  double* S;               // reduce: l x n_max sketch
+  double* colsq;           // reduce: ||a_j||^2 by global column
+  int32_t* nonfinite;      // reduce: set when a column norm is not finite
 };
 
 // The updates enqueued by one flush share one launch of the SS^T kernel and
@@ -297,11 +304,115 @@ struct UpdArgs {
   rid_update* recs;
 };
 
+// ---------------------------------------------------------------------------
+// Batched launches over several streams.
+//
+// A kernel body takes its arguments by reference and its block coordinates
+// as a Blk.  The single-stream kernel passes its own launch's coordinates;
+// the batched kernel runs on a grid (max blocks over the streams, streams)
+// and block (x, y) decodes x into the coordinates of stream y's own grid,
+// whose arguments and grid sit in device tables.  Blocks past a stream's own
+// grid exit at once.
+// ---------------------------------------------------------------------------
+struct Blk {
+  int x, y, z;
+};
+__device__ __forceinline__ Blk own_block() {
+  return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
+}
+
+template <typename A>
+struct Batched {
+  const A* args;     // [streams]
+  const int4* dims;  // [streams]: grid x, y, z of each stream's own launch
+};
+
+template <typename A>
+__device__ __forceinline__ bool batched_block(const Batched<A>& L, const A*& a, Blk& bk) {
+  const int4 d = L.dims[blockIdx.y];
+  int r = (int)blockIdx.x;
+  if (r >= d.x * d.y * d.z) return false;
+  bk.x = r % d.x;
+  r /= d.x;
+  bk.y = r % d.y;
+  bk.z = r / d.y;
+  a = L.args + blockIdx.y;
+  return true;
+}
+
+// Persistent sketch over several streams: work item q (0 <= q < total) is
+// item q - start[s] of stream s, start[] holding the prefix sums of the
+// streams' items (n_slabs * n_mt * n_nt); within a stream mt runs fastest,
+// then nt, then the slab.
+struct MultiSketch {
+  const SketchArgs* args;  // [ns]
+  const int* start;        // [ns + 1]
+  int ns, total;
+};
+
+__device__ __forceinline__ void multi_item(const MultiSketch& ms, int q, const SketchArgs*& a, int& slab,
+                                           int& mt, int& nt) {
+  int lo = 0, hi = ms.ns;  // the last s with start[s] <= q
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (ms.start[mid] <= q) lo = mid;
+    else hi = mid;
+  }
+  a = ms.args + lo;
+  const int r = q - ms.start[lo];
+  mt = r % a->n_mt;
+  nt = (r / a->n_mt) % a->n_nt;
+  slab = r / (a->n_mt * a->n_nt);
+}
+
+// Host side of batched launches: the argument and grid tables of a round are
+// written into pinned host memory (`host`), copied to the device mirror
+// (`dev`) in one transfer, and the launches reference the device copies.
+struct Stage {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0, used = 0;
+  bool overflow = false;
+  // copies n items to the stage; returns their device address
+  template <typename T>
+  const T* put(const T* src, size_t n) {
+    const size_t at = (used + 255) / 256 * 256;
+    if (at + n * sizeof(T) > cap) {
+      overflow = true;
+      return nullptr;
+    }
+    memcpy(host + at, src, n * sizeof(T));
+    used = at + n * sizeof(T);
+    return reinterpret_cast<const T*>(dev + at);
+  }
+};
+
+// One batched launch, ready to go once the stage has been copied.
+struct BLaunch {
+  const void* func;
+  dim3 grid, block;
+  size_t lds;
+  const void* args;  // device table (Batched::args, MultiSketch::args)
+  const void* aux;   // Batched::dims or MultiSketch::start
+  int ns, total;     // MultiSketch only
+  int extra;         // trailing int argument (hutch_mid_kernel stage), -1 if none
+  bool multi;        // MultiSketch (else Batched)
+};
+hipError_t run_launches(const std::vector<BLaunch>& v, hipStream_t s);
+
+// planners of the batched launches (sketch.hip, update.hip); the host
+// argument arrays hold one entry per stream taking part
+void plan_sketch_multi(int prec, const SketchArgs* h, int ns, int grid_cap, Stage& st, std::vector<BLaunch>& out);
+void plan_sketch_reduce_b(int prec, const SketchArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+
 // launchers (sketch.hip, update.hip)
 int sketch_cols_per_wg(int prec);
 hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s);
-hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, int ell, double* S, double* colsq,
-                                int32_t* nonfinite, hipStream_t s);
+hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s);
 hipError_t launch_omega_block(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,
                               void* out, int64_t ld, hipStream_t s);
 hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s);

@@ -14,6 +14,8 @@
 // LDS, and every wave of the workgroup multiplies it with its own columns.
 #include "rid_internal.h"
 
+#include <algorithm>
+
 namespace rid {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -67,15 +69,13 @@ constexpr int kBf16KC = 32;
 constexpr int kBf16Stages = 3;
 
 template <int RBW>
-__global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
+__device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, int mt, int nt) {
   constexpr int KC = kBf16KC;            // rows per chunk
   constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
   constexpr int LDA = KC + 8;            // bf16 per Omega LDS row (80 bytes)
   __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
   __shared__ __attribute__((aligned(1024))) float dt[kBf16Stages][kBf16Cols * KC];
   __shared__ double nsh[kBf16Cols];
-  int slab, mt, nt;
-  if (!sketch_item(a, blockIdx.x, slab, mt, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int rg = wave >> 2, cp = wave & 3;
@@ -262,6 +262,23 @@ __global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
   }
 }
 
+template <int RBW>
+__global__ __launch_bounds__(512, 1) void sketch_bf16_kernel(SketchArgs a) {
+  int slab, mt, nt;
+  if (sketch_item(a, blockIdx.x, slab, mt, nt)) sketch_bf16_body<RBW>(a, slab, mt, nt);
+}
+
+template <int RBW>
+__global__ __launch_bounds__(512, 1) void sketch_bf16_multi(MultiSketch ms) {
+  int slab, mt, nt;
+  const SketchArgs* a;
+  for (int q = blockIdx.x; q < ms.total; q += gridDim.x) {
+    multi_item(ms, q, a, slab, mt, nt);
+    sketch_bf16_body<RBW>(*a, slab, mt, nt);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // fp8 form: e4m3 operands with power-of-two block scales on
 // v_mfma_scale_f32_32x32x64_f8f6f4 (binary32 accumulation).
@@ -306,7 +323,7 @@ __device__ __forceinline__ void wait_dma_keep(int n) {
 }
 
 template <int RBW>
-__global__ __launch_bounds__(512, 1) void sketch_fp8_kernel(SketchArgs a) {
+__device__ __forceinline__ void sketch_fp8_body(const SketchArgs& a, int slab, int mt, int nt) {
   constexpr int KC = 32;                 // rows per DMA chunk (one scale block)
   constexpr int NST = 4;                 // DMA stages
   constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
@@ -315,8 +332,6 @@ __global__ __launch_bounds__(512, 1) void sketch_fp8_kernel(SketchArgs a) {
   __shared__ __attribute__((aligned(1024))) float dt[NST][kBf16Cols * KC];
   __shared__ uint64_t csrc[kBf16Cols];
   __shared__ int scl[2][kBf16Cols];      // E8M0 code of (chunk of the step, column)
-  int slab, mt, nt;
-  if (!sketch_item(a, blockIdx.x, slab, mt, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int rg = wave >> 2, cp = wave & 3;
@@ -525,18 +540,33 @@ __global__ __launch_bounds__(512, 1) void sketch_fp8_kernel(SketchArgs a) {
   }
 }
 
+template <int RBW>
+__global__ __launch_bounds__(512, 1) void sketch_fp8_kernel(SketchArgs a) {
+  int slab, mt, nt;
+  if (sketch_item(a, blockIdx.x, slab, mt, nt)) sketch_fp8_body<RBW>(a, slab, mt, nt);
+}
+
+template <int RBW>
+__global__ __launch_bounds__(512, 1) void sketch_fp8_multi(MultiSketch ms) {
+  int slab, mt, nt;
+  const SketchArgs* a;
+  for (int q = blockIdx.x; q < ms.total; q += gridDim.x) {
+    multi_item(ms, q, a, slab, mt, nt);
+    sketch_fp8_body<RBW>(*a, slab, mt, nt);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // binary32 form: v_mfma_f32_32x32x2_f32 (A lane l: row l%32, k = l/32; B lane
 // l: column l%32, k = l/32).  Within a 16-row chunk lane half h reads rows
 // 8h..8h+7 of its column and MFMA step s uses row 8h+s of both operands.
 // ---------------------------------------------------------------------------
 template <int NCB>
-__global__ __launch_bounds__(256) void sketch_f32_kernel(SketchArgs a) {
+__device__ __forceinline__ void sketch_f32_body(const SketchArgs& a, int slab, int mt, int nt) {
   constexpr int KC = 16;
   constexpr int LD = KC + 4;  // floats per LDS tile row (80 bytes)
   __shared__ __attribute__((aligned(16))) float om[kMTile * LD];
-  int slab, mt, nt;
-  if (!sketch_item(a, blockIdx.x, slab, mt, nt)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int64_t r0 = (int64_t)slab * a.slab_rows;
@@ -625,16 +655,31 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(SketchArgs a) {
   }
 }
 
+template <int NCB>
+__global__ __launch_bounds__(256) void sketch_f32_kernel(SketchArgs a) {
+  int slab, mt, nt;
+  if (sketch_item(a, blockIdx.x, slab, mt, nt)) sketch_f32_body<NCB>(a, slab, mt, nt);
+}
+
+template <int NCB>
+__global__ __launch_bounds__(256) void sketch_f32_multi(MultiSketch ms) {
+  int slab, mt, nt;
+  const SketchArgs* a;
+  for (int q = blockIdx.x; q < ms.total; q += gridDim.x) {
+    multi_item(ms, q, a, slab, mt, nt);
+    sketch_f32_body<NCB>(*a, slab, mt, nt);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // binary64 form: 64 test-matrix rows x 64 columns per workgroup, 16-row
 // chunks staged in LDS, 4 x 4 outputs per thread, binary64 FMA.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void sketch_f64_kernel(SketchArgs a) {
+__device__ __forceinline__ void sketch_f64_body(const SketchArgs& a, int slab, int mt, int nt) {
   constexpr int KC = 16, NTC = 64;
   __shared__ double om[KC][kMTile + 1];
   __shared__ double dt[KC][NTC + 1];
-  int slab, mt, nt;
-  if (!sketch_item(a, blockIdx.x, slab, mt, nt)) return;
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
   const int64_t r0 = (int64_t)slab * a.slab_rows;
@@ -697,27 +742,53 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(SketchArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void sketch_f64_kernel(SketchArgs a) {
+  int slab, mt, nt;
+  if (sketch_item(a, blockIdx.x, slab, mt, nt)) sketch_f64_body(a, slab, mt, nt);
+}
+
+__global__ __launch_bounds__(256) void sketch_f64_multi(MultiSketch ms) {
+  int slab, mt, nt;
+  const SketchArgs* a;
+  for (int q = blockIdx.x; q < ms.total; q += gridDim.x) {
+    multi_item(ms, q, a, slab, mt, nt);
+    sketch_f64_body(*a, slab, mt, nt);
+    __syncthreads();
+  }
+}
+
 // Fixed-order binary64 sum of the slab partials into S(:, c0:c0+b) and
 // ||a_j||^2; a non-finite norm (a non-finite snapshot value) sets the flag.
+// Block (x, y): rows 64 x.., column y of the batch.
 template <typename T>
-__global__ void sketch_reduce_kernel(const T* __restrict__ part, const double* __restrict__ normpart,
-                                     int n_slabs, int b_max, int ell_pad, int ell, int b, int64_t c0,
-                                     double* __restrict__ S, double* __restrict__ colsq,
-                                     int32_t* nonfinite) {
-  const int c = blockIdx.y;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= b) return;
-  if (r < ell) {
+__device__ __forceinline__ void sketch_reduce_body(const SketchArgs& a, const Blk bk) {
+  const T* __restrict__ part = reinterpret_cast<const T*>(a.part);
+  const int c = bk.y;
+  const int r = bk.x * 64 + threadIdx.x;
+  if (c >= a.b) return;
+  if (r < a.ell) {
     double s = 0.0;
-    for (int sl = 0; sl < n_slabs; ++sl) s += (double)part[((int64_t)sl * b_max + c) * ell_pad + r];
-    S[(c0 + c) * ell + r] = s;
+    for (int sl = 0; sl < a.n_slabs; ++sl) s += (double)part[((int64_t)sl * a.b_max + c) * a.ell_pad + r];
+    a.S[(a.c0 + c) * a.ell + r] = s;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bk.x == 0 && threadIdx.x == 0) {
     double q = 0.0;
-    for (int sl = 0; sl < n_slabs; ++sl) q += normpart[(int64_t)sl * b_max + c];
-    colsq[c0 + c] = q;
-    if (!isfinite(q)) *nonfinite = 1;
+    for (int sl = 0; sl < a.n_slabs; ++sl) q += a.normpart[(int64_t)sl * a.b_max + c];
+    a.colsq[a.c0 + c] = q;
+    if (!isfinite(q)) *a.nonfinite = 1;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void sketch_reduce_kernel(SketchArgs a) {
+  sketch_reduce_body<T>(a, own_block());
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void sketch_reduce_kernel_b(Batched<SketchArgs> L) {
+  const SketchArgs* a;
+  Blk bk;
+  if (batched_block(L, a, bk)) sketch_reduce_body<T>(*a, bk);
 }
 
 __global__ void omega_block_kernel(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,
@@ -789,18 +860,91 @@ hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, int ell, double* S, double* colsq,
-                                int32_t* nonfinite, hipStream_t s) {
-  dim3 grid((ell + 63) / 64, a.b);
+hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s) {
+  dim3 grid((a.ell + 63) / 64, a.b);
   if (prec == RID_SKETCH_F64)
-    hipLaunchKernelGGL(sketch_reduce_kernel<double>, grid, dim3(64), 0, s,
-                       reinterpret_cast<const double*>(a.part), a.normpart, a.n_slabs, a.b_max,
-                       a.ell_pad, ell, a.b, a.c0, S, colsq, nonfinite);
+    hipLaunchKernelGGL(sketch_reduce_kernel<double>, grid, dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL(sketch_reduce_kernel<float>, grid, dim3(64), 0, s,
-                       reinterpret_cast<const float*>(a.part), a.normpart, a.n_slabs, a.b_max,
-                       a.ell_pad, ell, a.b, a.c0, S, colsq, nonfinite);
+    hipLaunchKernelGGL(sketch_reduce_kernel<float>, grid, dim3(64), 0, s, a);
   return hipGetLastError();
+}
+
+namespace {
+const void* multi_func(int prec, int rbw) {
+  if (prec == RID_SKETCH_BF16) {
+    switch (rbw) {
+      case 1: return reinterpret_cast<const void*>(sketch_bf16_multi<1>);
+      case 2: return reinterpret_cast<const void*>(sketch_bf16_multi<2>);
+      case 3: return reinterpret_cast<const void*>(sketch_bf16_multi<3>);
+      case 4: return reinterpret_cast<const void*>(sketch_bf16_multi<4>);
+      case 5: return reinterpret_cast<const void*>(sketch_bf16_multi<5>);
+      default: return nullptr;
+    }
+  }
+  if (prec == RID_SKETCH_FP8) {
+    switch (rbw) {
+      case 1: return reinterpret_cast<const void*>(sketch_fp8_multi<1>);
+      case 2: return reinterpret_cast<const void*>(sketch_fp8_multi<2>);
+      case 3: return reinterpret_cast<const void*>(sketch_fp8_multi<3>);
+      case 4: return reinterpret_cast<const void*>(sketch_fp8_multi<4>);
+      case 5: return reinterpret_cast<const void*>(sketch_fp8_multi<5>);
+      default: return nullptr;
+    }
+  }
+  if (prec == RID_SKETCH_F32) return reinterpret_cast<const void*>(sketch_f32_multi<kNcbF32>);
+  return reinterpret_cast<const void*>(sketch_f64_multi);
+}
+}  // namespace
+
+// One persistent launch per kernel instance (form, rows per workgroup): its
+// workgroups walk the work items of every stream of the group.
+void plan_sketch_multi(int prec, const SketchArgs* h, int ns, int grid_cap, Stage& st, std::vector<BLaunch>& out) {
+  std::vector<char> done(ns, 0);
+  for (int i = 0; i < ns; ++i) {
+    if (done[i]) continue;
+    const void* f = multi_func(prec, h[i].rbw);
+    std::vector<SketchArgs> g;
+    std::vector<int> start{0};
+    for (int j = i; j < ns; ++j)
+      if (!done[j] && multi_func(prec, h[j].rbw) == f) {
+        done[j] = 1;
+        g.push_back(h[j]);
+        start.push_back(start.back() + h[j].n_slabs * h[j].n_mt * h[j].n_nt);
+      }
+    if (start.back() == 0) continue;
+    BLaunch L{};
+    L.func = f;
+    L.multi = true;
+    L.ns = (int)g.size();
+    L.total = start.back();
+    L.grid = dim3((unsigned)std::min(L.total, grid_cap));
+    L.block = dim3((prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) ? 512 : 256);
+    L.lds = 0;
+    L.extra = -1;
+    L.args = st.put(g.data(), g.size());
+    L.aux = st.put(start.data(), start.size());
+    out.push_back(L);
+  }
+}
+
+void plan_sketch_reduce_b(int prec, const SketchArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+  std::vector<SketchArgs> g(h, h + ns);
+  std::vector<int4> dims;
+  int maxb = 0;
+  for (int i = 0; i < ns; ++i) {
+    dims.push_back(make_int4((h[i].ell + 63) / 64, h[i].b, 1, 0));
+    maxb = std::max(maxb, dims.back().x * dims.back().y);
+  }
+  if (maxb == 0) return;
+  BLaunch L{};
+  L.func = prec == RID_SKETCH_F64 ? reinterpret_cast<const void*>(sketch_reduce_kernel_b<double>)
+                                  : reinterpret_cast<const void*>(sketch_reduce_kernel_b<float>);
+  L.grid = dim3((unsigned)maxb, (unsigned)ns);
+  L.block = dim3(64);
+  L.extra = -1;
+  L.args = st.put(g.data(), g.size());
+  L.aux = st.put(dims.data(), dims.size());
+  out.push_back(L);
 }
 
 hipError_t launch_omega_block(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,

@@ -12,6 +12,8 @@
 //   hutch_*        NA-Hutch++ estimate of ||A_obs - A_J P||_F^2 (Alg. 8)
 #include "rid_internal.h"
 
+#include <algorithm>
+
 namespace rid {
 
 
@@ -60,10 +62,10 @@ __device__ double block_sum(double v, double* red) {
 // and slot nz (sst_out) the state after the last update.  Also starts each
 // update's record.
 // ---------------------------------------------------------------------------
-__global__ void sst_batch_kernel(BatchArgs b) {
-  const int r1 = blockIdx.x * 16 + threadIdx.x;
-  const int r2 = blockIdx.y * 16 + threadIdx.y;
-  const int z = blockIdx.z;
+__device__ __forceinline__ void sst_batch_body(const BatchArgs& b, const Blk bk) {
+  const int r1 = bk.x * 16 + threadIdx.x;
+  const int r2 = bk.y * 16 + threadIdx.y;
+  const int z = bk.z;
   const int zz = min(z, b.nz - 1);
   const int64_t cend = b.c0 + min((int64_t)(zz + 1) * b.t, b.total);
   if (r1 < b.ell && r2 < b.ell) {
@@ -75,7 +77,7 @@ __global__ void sst_batch_kernel(BatchArgs b) {
     double* dst = (z < b.nz) ? b.W + (int64_t)z * b.ell * b.ell : b.sst_out;
     dst[(int64_t)r2 * b.ell + r1] = s;
   }
-  if (z < b.nz && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+  if (z < b.nz && bk.x == 0 && bk.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
     const int64_t u = b.u0 + z;
     // F of update u0 - 1 was written by an earlier launch
     double F = (b.u0 > 0) ? b.Fu[b.u0 - 1] : 0.0;
@@ -89,6 +91,14 @@ __global__ void sst_batch_kernel(BatchArgs b) {
     rec->F = F;
     rec->flags = (F > 0.0) ? 0 : RID_UPD_SKIPPED;
   }
+}
+
+__global__ void sst_batch_kernel(BatchArgs b) { sst_batch_body(b, own_block()); }
+
+__global__ void sst_batch_kernel_b(Batched<BatchArgs> L) {
+  const BatchArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) sst_batch_body(*p, bk);
 }
 
 // ---------------------------------------------------------------------------
@@ -109,13 +119,13 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
   return cnt;
 }
 
-__global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) {
+__device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   __shared__ double v[kMaxEll];
   __shared__ double p[kMaxEll];
   __shared__ double red[16];
   __shared__ double e2s[kMaxEll];
   __shared__ double ds[kMaxEll];
-  const int z = blockIdx.x;
+  const int z = bk.x;
   const int64_t u = b.u0 + z;
   const int n = b.ell, tid = threadIdx.x, nth = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
@@ -275,14 +285,22 @@ __global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) {
   }
 }
 
+__global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) { tridiag_body(b, own_block()); }
+
+__global__ __launch_bounds__(1024) void tridiag_kernel_b(Batched<BatchArgs> L) {
+  const BatchArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) tridiag_body(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // Scores.  One wave per scored column: y = Q^T s (reflectors in order), then
 // tau = sum_i z_i^2 / D_i with L z = y.
 // Items [0, t): basis slots; items [t, t + cnt): buffered columns.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void scores_kernel(UpdArgs a) {
+__device__ __forceinline__ void scores_body(const UpdArgs& a, const Blk bk) {
   __shared__ double y[kMaxEll];
-  const int item = blockIdx.x, lane = threadIdx.x, n = a.ell;
+  const int item = bk.x, lane = threadIdx.x, n = a.ell;
   if (a.skipu[a.u]) return;
   int64_t col;
   if (item < a.t) {
@@ -332,11 +350,19 @@ __global__ __launch_bounds__(64) void scores_kernel(UpdArgs a) {
   }
 }
 
+__global__ __launch_bounds__(64) void scores_kernel(UpdArgs a) { scores_body(a, own_block()); }
+
+__global__ __launch_bounds__(64) void scores_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) scores_body(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // Prune / fill.  One wave; slots in order; the fill scan evaluates 64
 // candidate draws at once and takes the first success.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void select_kernel(UpdArgs a) {
+__device__ __forceinline__ void select_body(const UpdArgs& a, const Blk bk) {
   __shared__ int used[kMaxT];
   const int lane = threadIdx.x;
   DevScalars* sc = a.sc;
@@ -406,6 +432,14 @@ __global__ __launch_bounds__(64) void select_kernel(UpdArgs a) {
   }
 }
 
+__global__ __launch_bounds__(64) void select_kernel(UpdArgs a) { select_body(a, own_block()); }
+
+__global__ __launch_bounds__(64) void select_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) select_body(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // Gram entries of the new basis columns, fused with their copy into the pool.
 // One workgroup of 16 waves per (row slab, tile of up to 160 new slots, tile
@@ -425,7 +459,7 @@ constexpr int kGramTile = 160;
 constexpr int kGramMaxBlocks = 7;   // ceil(10 * 10 / 16)
 
 template <typename T>
-__global__ __launch_bounds__(1024) void gram_kernel(UpdArgs a) {
+__device__ __forceinline__ void gram_body(const UpdArgs& a, const Blk bk) {
   constexpr int KC = (sizeof(T) == 4) ? 32 : 16;  // rows per chunk
   constexpr int LDC = KC + 1;
   __shared__ T sq[kGramTile * LDC];
@@ -434,7 +468,7 @@ __global__ __launch_bounds__(1024) void gram_kernel(UpdArgs a) {
   __shared__ int nblk;
   const DevScalars* sc = a.sc;
   const int n_new = sc->n_new, n_occ = sc->n_occ;
-  const int qt = blockIdx.y, jt = blockIdx.z, slab = blockIdx.x;
+  const int qt = bk.y, jt = bk.z, slab = bk.x;
   if (qt * kGramTile >= n_new || jt * kGramTile >= n_occ) return;
   const int nq = min(kGramTile, n_new - qt * kGramTile);
   const int nj = min(kGramTile, n_occ - jt * kGramTile);
@@ -535,6 +569,16 @@ __global__ __launch_bounds__(1024) void gram_kernel(UpdArgs a) {
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(1024) void gram_kernel(UpdArgs a) { gram_body<T>(a, own_block()); }
+
+template <typename T>
+__global__ __launch_bounds__(1024) void gram_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) gram_body<T>(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // Gram entries for binary32 data.  One workgroup of 4 waves per (row slab,
 // group of up to 16 output tiles of 32 x 32); a wave owns up to 4 tiles, each
@@ -553,7 +597,7 @@ constexpr int kGramGroup = kGramWaves * kGramTPW;  // tiles per workgroup
 
 __host__ __device__ inline int gram_stage_cols(int t) { return (2 * t + 7) / 8 * 8; }
 
-__global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) {
+__device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
   extern __shared__ __attribute__((aligned(1024))) float gsm[];
   const DevScalars* sc = a.sc;
   const int nq = sc->n_new, nj = sc->n_occ;
@@ -561,14 +605,14 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) {
   const bool sym = (nq == nj);
   const int TQ = (nq + 31) / 32, TJ = (nj + 31) / 32;
   const int NT = sym ? TQ * (TQ + 1) / 2 : TQ * TJ;
-  const int g0 = blockIdx.y * kGramGroup;
+  const int g0 = bk.y * kGramGroup;
   if (g0 >= NT) return;
   const int ncap = gram_stage_cols(a.t);
   const int ncol = sym ? nq : nq + nj;
   const int nblk = (ncol + 7) / 8;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i16 = lane & 15, k4 = lane >> 4;
-  const int slab = blockIdx.x;
+  const int slab = bk.x;
   const int64_t r0 = (int64_t)slab * a.gslab_rows;
   const int64_t r1 = min(a.m, r0 + a.gslab_rows);
   const int nch = (int)((r1 - r0 + kGramKC - 1) / kGramKC);
@@ -660,7 +704,7 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) {
     out[0] = x0.x; out[1] = x0.y; out[2] = x0.z; out[3] = x0.w;
     out[4] = x1.x; out[5] = x1.y; out[6] = x1.z; out[7] = x1.w;
   };
-  const bool copy_pool = blockIdx.y == 0;
+  const bool copy_pool = bk.y == 0;
   auto pool_copy = [&](int c, int st) {
     const int64_t k0 = r0 + (int64_t)c * kGramKC;
     float* pool = reinterpret_cast<float*>(a.cpool);
@@ -732,17 +776,33 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) { gram_f32_body(a, own_block()); }
+
+__global__ __launch_bounds__(256, 2) void gram_f32_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) gram_f32_body(*p, bk);
+}
+
 // Zero the Gram rows/columns of empty slots, then write the new entries
 // (fixed-order sum over slabs), symmetrically.
-__global__ void gram_zero_kernel(UpdArgs a) {
-  const int i = blockIdx.x, j = threadIdx.x;
+__device__ __forceinline__ void gram_zero_body(const UpdArgs& a, const Blk bk) {
+  const int i = bk.x, j = threadIdx.x;
   if (i >= a.t || j >= a.t) return;
   if (a.J[i] < 0 || a.J[j] < 0) a.G[(int64_t)j * a.t + i] = 0.0;
 }
 
-__global__ void gram_reduce_kernel(UpdArgs a) {
+__global__ void gram_zero_kernel(UpdArgs a) { gram_zero_body(a, own_block()); }
+
+__global__ void gram_zero_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) gram_zero_body(*p, bk);
+}
+
+__device__ __forceinline__ void gram_reduce_body(const UpdArgs& a, const Blk bk) {
   const DevScalars* sc = a.sc;
-  const int q = blockIdx.x, jj = threadIdx.x + blockIdx.y * blockDim.x;
+  const int q = bk.x, jj = threadIdx.x + bk.y * blockDim.x;
   if (q >= sc->n_new || jj >= sc->n_occ) return;
   double s = 0.0;
   for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
@@ -751,12 +811,20 @@ __global__ void gram_reduce_kernel(UpdArgs a) {
   a.G[(int64_t)si * a.t + sj] = s;
 }
 
+__global__ void gram_reduce_kernel(UpdArgs a) { gram_reduce_body(a, own_block()); }
+
+__global__ void gram_reduce_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) gram_reduce_body(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // Alg. 4: Householder QR of Omega A_J (occupied slots in slot order), then
 // P = R^{-1} Q^T S column by column.  Columns whose pivot |R_ii| falls to
 // max(l, n) eps max|R| are dropped from the solve (flag RID_UPD_RANK_DEFICIENT).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void alg4_qr_kernel(UpdArgs a) {
+__device__ __forceinline__ void alg4_qr_body(const UpdArgs& a, const Blk bk) {
   __shared__ double red[16];
   __shared__ double v[kMaxEll];
   const int n = a.ell, tid = threadIdx.x, nth = blockDim.x;
@@ -814,6 +882,14 @@ __global__ __launch_bounds__(1024) void alg4_qr_kernel(UpdArgs a) {
   }
 }
 
+__global__ __launch_bounds__(1024) void alg4_qr_kernel(UpdArgs a) { alg4_qr_body(a, own_block()); }
+
+__global__ __launch_bounds__(1024) void alg4_qr_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) alg4_qr_body(*p, bk);
+}
+
 // The same factorization with Omega A_J held in registers: column c lives in
 // wave c % NW (slot c / NW), row r in lane r % 64 (element r / 64).  Step jj:
 // the owner wave of column jj forms the reflector and publishes it in LDS
@@ -827,7 +903,7 @@ __device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
 }
 
 template <int E, int NS, int NW>
-__global__ __launch_bounds__(64 * NW) void alg4_qr_reg_kernel(UpdArgs a) {
+__device__ __forceinline__ void alg4_qr_reg_body(const UpdArgs& a, const Blk bk) {
   __shared__ double vb[2][64 * E];
   __shared__ double tb[2];
   const int n = a.ell, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -948,10 +1024,20 @@ __global__ __launch_bounds__(64 * NW) void alg4_qr_reg_kernel(UpdArgs a) {
   }
 }
 
+template <int E, int NS, int NW>
+__global__ __launch_bounds__(64 * NW) void alg4_qr_reg_kernel(UpdArgs a) { alg4_qr_reg_body<E, NS, NW>(a, own_block()); }
+
+template <int E, int NS, int NW>
+__global__ __launch_bounds__(64 * NW) void alg4_qr_reg_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) alg4_qr_reg_body<E, NS, NW>(*p, bk);
+}
+
 // One wave per observed column c: z = Q^T S(:, c), back substitution, scatter.
-__global__ __launch_bounds__(64) void alg4_apply_kernel(UpdArgs a) {
+__device__ __forceinline__ void alg4_apply_body(const UpdArgs& a, const Blk bk) {
   __shared__ double y[kMaxEll];
-  const int64_t c = blockIdx.x;
+  const int64_t c = bk.x;
   const int lane = threadIdx.x, n = a.ell;
   const DevScalars* sc = a.sc;
   const int no = min(sc->n_occ, n);
@@ -987,12 +1073,20 @@ __global__ __launch_bounds__(64) void alg4_apply_kernel(UpdArgs a) {
   }
 }
 
+__global__ __launch_bounds__(64) void alg4_apply_kernel(UpdArgs a) { alg4_apply_body(a, own_block()); }
+
+__global__ __launch_bounds__(64) void alg4_apply_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) alg4_apply_body(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // NA-Hutch++ (Alg. 8).  Large products first: Y = S P^T (l x t) and
 // PPt = P P^T (t x t), one thread per entry.
 // ---------------------------------------------------------------------------
-__global__ void hutch_prod_kernel(UpdArgs a) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void hutch_prod_body(const UpdArgs& a, const Blk bk) {
+  const int64_t idx = (int64_t)bk.x * blockDim.x + threadIdx.x;
   const int n = a.ell, t = a.t;
   const int64_t nY = (int64_t)n * t, nPP = (int64_t)t * t;
   if (idx < nY) {
@@ -1007,6 +1101,14 @@ __global__ void hutch_prod_kernel(UpdArgs a) {
     for (int64_t c = 0; c < a.n_obs; ++c) s = fma(a.P[c * t + i], a.P[c * t + j], s);
     a.PPt[(int64_t)j * t + i] = s;
   }
+}
+
+__global__ void hutch_prod_kernel(UpdArgs a) { hutch_prod_body(a, own_block()); }
+
+__global__ void hutch_prod_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) hutch_prod_body(*p, bk);
 }
 
 // The products of the small part of Alg. 8, one thread per output entry.
@@ -1028,11 +1130,11 @@ __device__ __forceinline__ HutchWork hutch_work(const UpdArgs& a) {
   return w;
 }
 
-__global__ void hutch_mid_kernel(UpdArgs a, int stage) {
+__device__ __forceinline__ void hutch_mid_body(const UpdArgs& a, const Blk bk, int stage) {
   const int n = a.ell, t = a.t, n1 = a.n1, n2 = a.n2, n3 = a.ell - a.n1 - a.n2;
   const HutchWork w = hutch_work(a);
   const double* Y = a.Y;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t idx = (int64_t)bk.x * blockDim.x + threadIdx.x;
   if (stage == 0) {
     if (idx < (int64_t)n * t) {
       const int j = (int)(idx / n), r = (int)(idx % n);
@@ -1087,6 +1189,14 @@ __global__ void hutch_mid_kernel(UpdArgs a, int stage) {
   }
 }
 
+__global__ void hutch_mid_kernel(UpdArgs a, int stage) { hutch_mid_body(a, own_block(), stage); }
+
+__global__ void hutch_mid_kernel_b(Batched<UpdArgs> L, int stage) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) hutch_mid_body(*p, bk, stage);
+}
+
 // The small part of Alg. 8 in one workgroup.  With the row blocks
 // [0,n1), [n1,n1+n2), [n1+n2,l) of S, of S_J = Omega A_J and of Y:
 //   K = Y1 SJ2^T, X = Y1 G Y2^T, A1 = Y1 SJ3^T, A2 = SJ3 Y2^T,
@@ -1095,7 +1205,7 @@ __global__ void hutch_mid_kernel(UpdArgs a, int stage) {
 // its numerical rank r (max(n1, n2) eps |R_00|): K^- = Q_r R11^{-T} [I 0] Pi^T,
 // the pseudo-inverse when K has full row rank.  With Z = rows Pi_r of X Q_r,
 // tr(K^- X) = tr(R11^{-T} Z) = <R11^{-1}, Z>_F; R11^{-1} is formed in LDS.
-__global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
+__device__ __forceinline__ void hutch_small_body(const UpdArgs& a, const Blk bk) {
   constexpr int kMaxN1 = kMaxEll / 4;
   __shared__ double red[16];
   __shared__ double v[kMaxEll];
@@ -1256,6 +1366,14 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
   }
 }
 
+__global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) { hutch_small_body(a, own_block()); }
+
+__global__ __launch_bounds__(1024) void hutch_small_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) hutch_small_body(*p, bk);
+}
+
 // The same small phase with K^T, X and AA held in registers.  The n1 columns
 // of K^T and the 2 n1 rows of X and AA are vectors of length n2; vector q
 // lives in wave q % NW (slot q / NW), element r in lane r % 64 (e = r / 64).
@@ -1265,7 +1383,7 @@ __global__ __launch_bounds__(1024) void hutch_small_kernel(UpdArgs a) {
 // unchosen K^T vectors and to all X / AA vectors.  Vectors are never swapped:
 // pos[i] is the K^T column chosen at step i.
 template <int E, int NS, int NW>
-__global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel(UpdArgs a) {
+__device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk bk) {
   constexpr int kMaxN1 = kMaxEll / 4;
   __shared__ double red[16];
   __shared__ double vb[2][64 * E];
@@ -1524,6 +1642,16 @@ __global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel(UpdArgs a) {
   }
 }
 
+template <int E, int NS, int NW>
+__global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel(UpdArgs a) { hutch_small_reg_body<E, NS, NW>(a, own_block()); }
+
+template <int E, int NS, int NW>
+__global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) hutch_small_reg_body<E, NS, NW>(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1552,11 +1680,11 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
     const int groups = (tq * tq + kGramGroup - 1) / kGramGroup;
     const size_t lds = (size_t)2 * gram_stage_cols(a.t) * kGramKC * sizeof(float) +
                        (size_t)gram_stage_cols(a.t) * sizeof(uint64_t) + (size_t)a.t * sizeof(int);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static size_t attr_lds = 0;  // raised whenever a larger basis needs more
+    if (lds > attr_lds) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gram_f32_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      attr_set = true;
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr_lds = lds;
     }
     hipLaunchKernelGGL(gram_f32_kernel, dim3(a.gslabs, groups), dim3(64 * kGramWaves), lds, s, a);
   }
@@ -1604,6 +1732,179 @@ hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((hutch_small_reg_kernel<3, 29, 8>), dim3(1), dim3(512), 0, s, a);
     else
       hipLaunchKernelGGL(hutch_small_kernel, dim3(1), dim3(1024), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched planners: the same launches as above for several streams at once,
+// one launch per kernel instance (streams needing another template instance
+// of a kernel get a launch of their own)
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename A>
+struct Group {
+  const void* func;
+  size_t lds;
+  std::vector<A> args;
+  std::vector<int4> dims;
+};
+
+// Collects per-stream (kernel, grid) choices, then emits one launch per kernel.
+template <typename A>
+struct Planner {
+  std::vector<Group<A>> groups;
+  void add(const void* func, const A& a, int4 d, size_t lds = 0) {
+    for (auto& g : groups)
+      if (g.func == func) {
+        g.args.push_back(a);
+        g.dims.push_back(d);
+        g.lds = std::max(g.lds, lds);
+        return;
+      }
+    groups.push_back(Group<A>{func, lds, {a}, {d}});
+  }
+  void emit(dim3 block, int extra, Stage& st, std::vector<BLaunch>& out) {
+    for (auto& g : groups) {
+      int maxb = 0;
+      for (const int4& d : g.dims) maxb = std::max(maxb, d.x * d.y * d.z);
+      if (maxb == 0) continue;
+      BLaunch L{};
+      L.func = g.func;
+      L.grid = dim3((unsigned)maxb, (unsigned)g.args.size());
+      L.block = block;
+      L.lds = g.lds;
+      L.args = st.put(g.args.data(), g.args.size());
+      L.aux = st.put(g.dims.data(), g.dims.size());
+      L.extra = extra;
+      L.multi = false;
+      out.push_back(L);
+    }
+    groups.clear();
+  }
+};
+
+template <typename K>
+const void* fn(K k) {
+  return reinterpret_cast<const void*>(k);
+}
+
+}  // namespace
+
+void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+  Planner<BatchArgs> P;
+  for (int i = 0; i < ns; ++i)
+    P.add(fn(sst_batch_kernel_b), h[i], make_int4((h[i].ell + 15) / 16, (h[i].ell + 15) / 16, h[i].nz + 1, 0));
+  P.emit(dim3(16, 16), -1, st, out);
+  for (int i = 0; i < ns; ++i) P.add(fn(tridiag_kernel_b), h[i], make_int4(h[i].nz, 1, 1, 0));
+  P.emit(dim3(1024), -1, st, out);
+}
+
+void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+  Planner<UpdArgs> P;
+  for (int i = 0; i < ns; ++i) P.add(fn(scores_kernel_b), h[i], make_int4(h[i].t + h[i].cnt, 1, 1, 0));
+  P.emit(dim3(64), -1, st, out);
+  for (int i = 0; i < ns; ++i) P.add(fn(select_kernel_b), h[i], make_int4(1, 1, 1, 0));
+  P.emit(dim3(64), -1, st, out);
+}
+
+void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+  Planner<UpdArgs> P64, P32;
+  for (int i = 0; i < ns; ++i) {
+    const UpdArgs& a = h[i];
+    if (a.data_f64) {
+      const int tt = (a.t + kGramTile - 1) / kGramTile;
+      P64.add(fn(gram_kernel_b<double>), a, make_int4(a.gslabs, tt, tt, 0));
+    } else {
+      const int tq = (a.t + 31) / 32;
+      const int groups = (tq * tq + kGramGroup - 1) / kGramGroup;
+      const size_t lds = (size_t)2 * gram_stage_cols(a.t) * kGramKC * sizeof(float) +
+                         (size_t)gram_stage_cols(a.t) * sizeof(uint64_t) + (size_t)a.t * sizeof(int);
+      P32.add(fn(gram_f32_kernel_b), a, make_int4(a.gslabs, groups, 1, 0), lds);
+    }
+  }
+  P64.emit(dim3(1024), -1, st, out);
+  static size_t attr_lds = 0;
+  for (auto& g : P32.groups)
+    if (g.lds > attr_lds) {
+      (void)hipFuncSetAttribute(fn(gram_f32_kernel_b), hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds);
+      attr_lds = g.lds;
+    }
+  P32.emit(dim3(64 * kGramWaves), -1, st, out);
+  Planner<UpdArgs> P;
+  for (int i = 0; i < ns; ++i) P.add(fn(gram_zero_kernel_b), h[i], make_int4(h[i].t, 1, 1, 0));
+  P.emit(dim3(kMaxT), -1, st, out);
+  for (int i = 0; i < ns; ++i) P.add(fn(gram_reduce_kernel_b), h[i], make_int4(h[i].t, 1, 1, 0));
+  P.emit(dim3(kMaxT), -1, st, out);
+}
+
+void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+  const int4 one = make_int4(1, 1, 1, 0);
+  {
+    Planner<UpdArgs> Preg, Pl2;
+    for (int i = 0; i < ns; ++i) {
+      const UpdArgs& a = h[i];
+      const int E = (a.ell + 63) / 64;
+      if (E <= 1 && a.t <= 16) Preg.add(fn(alg4_qr_reg_kernel_b<1, 2, 8>), a, one);
+      else if (E <= 2 && a.t <= 64) Preg.add(fn(alg4_qr_reg_kernel_b<2, 8, 8>), a, one);
+      else if (E <= 4 && a.t <= 112) Preg.add(fn(alg4_qr_reg_kernel_b<4, 14, 8>), a, one);
+      else if (E <= 5 && a.t <= 152) Preg.add(fn(alg4_qr_reg_kernel_b<5, 19, 8>), a, one);
+      else Pl2.add(fn(alg4_qr_kernel_b), a, one);
+    }
+    Preg.emit(dim3(512), -1, st, out);
+    Pl2.emit(dim3(1024), -1, st, out);
+  }
+  Planner<UpdArgs> P;
+  for (int i = 0; i < ns; ++i) P.add(fn(alg4_apply_kernel_b), h[i], make_int4((int)h[i].n_obs, 1, 1, 0));
+  P.emit(dim3(64), -1, st, out);
+  for (int i = 0; i < ns; ++i) {
+    const int64_t tot = (int64_t)(h[i].ell + h[i].t) * h[i].t;
+    P.add(fn(hutch_prod_kernel_b), h[i], make_int4((int)((tot + 255) / 256), 1, 1, 0));
+  }
+  P.emit(dim3(256), -1, st, out);
+  for (int stage = 0; stage < 3; ++stage) {
+    for (int i = 0; i < ns; ++i) {
+      const UpdArgs& a = h[i];
+      const int n3 = a.ell - a.n1 - a.n2;
+      int64_t sz;
+      if (stage == 0) sz = (int64_t)a.ell * a.t;
+      else if (stage == 1) sz = (int64_t)a.n1 * a.n2 + (int64_t)a.n1 * a.t + (int64_t)a.n1 * n3 + (int64_t)n3 * a.n2;
+      else sz = (int64_t)a.n1 * a.n2;
+      P.add(fn(hutch_mid_kernel_b), a, make_int4((int)((sz + 255) / 256), 1, 1, 0));
+    }
+    P.emit(dim3(256), stage, st, out);
+  }
+  {
+    Planner<UpdArgs> Preg, Pl2;
+    for (int i = 0; i < ns; ++i) {
+      const UpdArgs& a = h[i];
+      const int E = (a.n2 + 63) / 64, nv = 3 * a.n1;
+      if (a.n1 > 0 && E <= 1 && nv <= 8 * 4) Preg.add(fn(hutch_small_reg_kernel_b<1, 4, 8>), a, one);
+      else if (a.n1 > 0 && E <= 2 && nv <= 8 * 19) Preg.add(fn(hutch_small_reg_kernel_b<2, 19, 8>), a, one);
+      else if (a.n1 > 0 && E <= 3 && nv <= 8 * 29) Preg.add(fn(hutch_small_reg_kernel_b<3, 29, 8>), a, one);
+      else Pl2.add(fn(hutch_small_kernel_b), a, one);
+    }
+    Preg.emit(dim3(512), -1, st, out);
+    Pl2.emit(dim3(1024), -1, st, out);
+  }
+}
+
+hipError_t run_launches(const std::vector<BLaunch>& v, hipStream_t s) {
+  for (const BLaunch& L : v) {
+    hipError_t e;
+    if (L.multi) {
+      MultiSketch ms{reinterpret_cast<const SketchArgs*>(L.args), reinterpret_cast<const int*>(L.aux), L.ns,
+                     L.total};
+      void* params[] = {&ms};
+      e = hipLaunchKernel(L.func, L.grid, L.block, params, L.lds, s);
+    } else {
+      Batched<char> b{reinterpret_cast<const char*>(L.args), reinterpret_cast<const int4*>(L.aux)};
+      int extra = L.extra;
+      void* params[] = {&b, &extra};
+      e = hipLaunchKernel(L.func, L.grid, L.block, params, L.lds, s);
+    }
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }

@@ -56,21 +56,26 @@ def _stream_handle(device):
 class OnlineRID:
     """One streaming randomized ID on one GPU (Alg. 3 with Alg. 4 and Alg. 8)."""
 
-    def __init__(self, cfg: StreamConfig, device="cuda:0"):
+    def __init__(self, cfg: StreamConfig, device="cuda:0", _member=None):
         self.cfg = cfg
         self.device = torch.device(device)
+        self._keep = []  # borrowed batches kept alive until release
+        if _member is not None:  # a member of a StreamBatch (owned by it)
+            self._h = _member
+            self._owned = False
+            return
         self._h = C.c_void_p()
+        self._owned = True
         ccfg = cfg.to_c()
         with torch.cuda.device(self.device):
             L.check(L.lib().rid_init_stream(C.byref(ccfg), _stream_handle(self.device), C.byref(self._h)))
-        self._keep = []  # borrowed batches kept alive until release
 
     # -- lifetime ------------------------------------------------------------
     def close(self):
-        if self._h:
+        if self._h and self._owned:
             L.lib().rid_destroy(self._h)
-            self._h = C.c_void_p()
-            self._keep = []
+        self._h = C.c_void_p()
+        self._keep = []
 
     def __del__(self):
         try:
@@ -186,3 +191,69 @@ def omega_block(prec, seed, ell, i0, count, device="cuda:0"):
         L.check(L.lib().rid_omega_block(PREC[prec], seed, ell, i0, count, C.c_void_p(out.data_ptr()), ell,
                                         _stream_handle(torch.device(device))))
     return out.T
+
+
+class StreamBatch:
+    """Many independent streams of uneven m advanced together: one persistent
+    sketch launch per round over every member, batched update launches, the
+    round captured into a HIP graph (rid_init_batch and friends)."""
+
+    def __init__(self, cfgs, device="cuda:0", graph=True, tune=True):
+        self.cfgs = list(cfgs)
+        self.device = torch.device(device)
+        self._b = C.c_void_p()
+        arr = (L.rid_config * len(self.cfgs))(*[c.to_c() for c in self.cfgs])
+        flags = (0 if graph else L.RID_BATCH_NO_GRAPH) | (0 if tune else L.RID_BATCH_NO_TUNE)
+        with torch.cuda.device(self.device):
+            L.check(L.lib().rid_init_batch(len(self.cfgs), arr, _stream_handle(self.device), flags,
+                                           C.byref(self._b)), batch=None)
+        self.members = []
+        for i, c in enumerate(self.cfgs):
+            h = C.c_void_p()
+            self._check(L.lib().rid_batch_stream(self._b, i, C.byref(h)))
+            self.members.append(OnlineRID(c, device, _member=h))
+        self._keep = []
+
+    def _check(self, st):
+        L.check(st, batch=self._b)
+
+    def close(self):
+        if self._b:
+            for mbr in self.members:
+                mbr._h = C.c_void_p()
+            L.lib().rid_destroy_batch(self._b)
+            self._b = C.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, cols, borrow=False):
+        """cols: one (b_i, m_i) CUDA tensor (or None) per member."""
+        ns = len(self.cfgs)
+        if len(cols) != ns:
+            raise ValueError("one tensor (or None) per member")
+        ptrs = (C.c_void_p * ns)()
+        lds = (C.c_int64 * ns)()
+        bs = (C.c_int32 * ns)()
+        for i, (x, c) in enumerate(zip(cols, self.cfgs)):
+            if x is None or x.shape[0] == 0:
+                ptrs[i], lds[i], bs[i] = None, c.m, 0
+                continue
+            if x.device != self.device or x.dtype != c.dtype or x.shape[1] != c.m or x.stride(1) != 1:
+                raise ValueError(f"member {i}: snapshots must be a (b, m) tensor of its dtype, rows contiguous")
+            ptrs[i], lds[i], bs[i] = x.data_ptr(), x.stride(0), x.shape[0]
+        self._check(L.lib().rid_push_batch(self._b, ptrs, lds, bs, L.RID_BORROW if borrow else L.RID_COPY))
+        if borrow:
+            self._keep.append(list(cols))
+
+    def finalize(self):
+        self._check(L.lib().rid_finalize_batch(self._b))
+
+    def info(self):
+        i = L.rid_batch_info()
+        self._check(L.lib().rid_batch_get_info(self._b, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in L.rid_batch_info._fields_}

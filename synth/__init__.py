@@ -159,6 +159,53 @@ def blobs(h, w, n, seed, n_blobs=6, rel_noise=0.01, dtype=np.float32):
     return out
 
 
+def blobs_torch(h, w, n, seed, n_blobs=6, rel_noise=0.01, device="cuda:0", ld=None):
+    """The blob stream generated on a device with torch (same recipe as
+    ``blobs``; blob parameters from the same numpy draws, the noise from a
+    seeded torch generator, so the noise differs from ``blobs``).  Returns an
+    (n, ld) binary32 tensor whose [:, :h w] view holds the frames; ld defaults
+    to h w rounded up to 16 elements."""
+    import torch
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(0.5, 1.5, n_blobs)
+    wid = rng.uniform(0.03, 0.1, n_blobs) * min(h, w)
+    vel = rng.uniform(-1.0, 1.0, (n_blobs, 2)) * 0.002 * max(h, w)
+    pos0 = rng.uniform(0.0, 1.0, (n_blobs, 2)) * np.array([h, w])
+    dev = torch.device(device)
+    m = h * w
+    ld = ld or (m + 15) // 16 * 16
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed) % (1 << 63))
+    yy = torch.arange(h, device=dev, dtype=torch.float32)[:, None]
+    xx = torch.arange(w, device=dev, dtype=torch.float32)[None, :]
+    out = torch.zeros((n, ld), dtype=torch.float32, device=dev)
+    for t in range(n):
+        fr = torch.zeros((h, w), dtype=torch.float32, device=dev)
+        for b in range(n_blobs):
+            cy, cx = pos0[b] + vel[b] * t
+            dy = torch.remainder(yy - float(cy) + h / 2, h) - h / 2
+            dx = torch.remainder(xx - float(cx) + w / 2, w) - w / 2
+            fr += float(amp[b]) * torch.exp(-(dy * dy + dx * dx) / float(2.0 * wid[b] ** 2))
+        rms = torch.sqrt(torch.mean(fr * fr))
+        fr += rel_noise * rms * torch.randn((h, w), generator=g, device=dev, dtype=torch.float32)
+        out[t, :m] = fr.reshape(-1)
+    return out
+
+
+def batch_frame_shapes(ns, seed, lo=1e4, hi=1e6):
+    """Frame sizes of a batch of image streams: m log-uniform in [lo, hi],
+    frames h x w with h = round(sqrt(0.8 m)) and w = round(m / h) (the 4:5
+    aspect of the gas-puff images), m := h w."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(ns):
+        m = int(round(10.0 ** rng.uniform(math.log10(lo), math.log10(hi))))
+        h = max(1, int(round(math.sqrt(0.8 * m))))
+        w = max(1, int(round(m / h)))
+        out.append((h, w))
+    return out
+
+
 def channel_torch(nx, ny, nz, n, seed, fields=4, n_modes=300, device="cuda:0", rows_per_chunk=1 << 20,
                   ld=None):
     """The channel stream generated on a device with torch (same mode table and

@@ -43,8 +43,10 @@ def test_struct_layouts_match_c(L):
 #include <stddef.h>
 #include "rid.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\\n", sizeof(rid_config), sizeof(rid_update), sizeof(rid_info), sizeof(rid_error));
-  printf("%zu %zu %zu\\n", offsetof(rid_config, n_max), offsetof(rid_update, flags), offsetof(rid_info, device_bytes));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(rid_config), sizeof(rid_update), sizeof(rid_info), sizeof(rid_error),
+         sizeof(rid_batch_info));
+  printf("%zu %zu %zu %zu\\n", offsetof(rid_config, n_max), offsetof(rid_update, flags), offsetof(rid_info, device_bytes),
+         offsetof(rid_batch_info, tune_ms));
   return 0;
 }
 """
@@ -55,9 +57,11 @@ int main(void) {
         subprocess.run(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
         lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
     sizes = [int(x) for x in lines[0].split()]
-    assert sizes == [C.sizeof(L.rid_config), C.sizeof(L.rid_update), C.sizeof(L.rid_info), C.sizeof(L.rid_error)]
+    assert sizes == [C.sizeof(L.rid_config), C.sizeof(L.rid_update), C.sizeof(L.rid_info), C.sizeof(L.rid_error),
+                     C.sizeof(L.rid_batch_info)]
     offs = [int(x) for x in lines[1].split()]
-    assert offs == [L.rid_config.n_max.offset, L.rid_update.flags.offset, L.rid_info.device_bytes.offset]
+    assert offs == [L.rid_config.n_max.offset, L.rid_update.flags.offset, L.rid_info.device_bytes.offset,
+                    L.rid_batch_info.tune_ms.offset]
 
 
 def test_status_strings_and_defaults(L):
@@ -96,6 +100,27 @@ def test_null_handles_are_rejected(L):
     assert lib.rid_finalize(None) == L.RID_EINVAL
     assert lib.rid_destroy(None) == L.RID_EINVAL
     assert lib.rid_omega_block(9, 1, 8, 0, 1, None, 8, None) == L.RID_EINVAL
+    assert lib.rid_push_batch(None, None, None, None, 0) == L.RID_EINVAL
+    assert lib.rid_finalize_batch(None) == L.RID_EINVAL
+    assert lib.rid_destroy_batch(None) == L.RID_EINVAL
+    assert lib.rid_batch_stream(None, 0, None) == L.RID_EINVAL
+
+
+def test_invalid_batches_rejected_before_device(L):
+    lib = L.lib()
+    cfgs = (L.rid_config * 2)()
+    for c in cfgs:
+        lib.rid_config_default(C.byref(c))
+        c.m, c.ell, c.k, c.t, c.n_max = 1000, 40, 20, 20, 100
+    b = C.c_void_p()
+    assert lib.rid_init_batch(0, cfgs, None, 0, C.byref(b)) == L.RID_EINVAL
+    assert lib.rid_init_batch(2, cfgs, None, 64, C.byref(b)) == L.RID_EINVAL
+    cfgs[1].k = 41
+    assert lib.rid_init_batch(2, cfgs, None, 0, C.byref(b)) == L.RID_EINVAL
+    buf = C.create_string_buffer(256)
+    lib.rid_batch_last_error(None, buf, 256)
+    assert "k must" in buf.value.decode()
+    assert not b.value
 
 
 def test_product_path_never_imports_the_oracle():

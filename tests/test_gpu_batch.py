@@ -1,0 +1,199 @@
+"""GPU tests of batched streams (rid_init_batch / rid_push_batch /
+rid_finalize_batch), through the C ABI.
+
+Every member of a batch is an ordinary stream with its own configuration and
+seeds, so each member is checked against the oracle run on that member's
+columns alone, with the same tolerances as the single-stream pipelines
+(J exactly, tau, P, the NA-Hutch++ terms and a reconstruction within the
+oracle's forward-error tolerances).  Launch variants of the same batch (graph
+capture or direct launches, COPY or BORROW pushes) must agree bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_common import compare_updates, log, perturbation_tolerances, rel_fro, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_16076_amd import _lib
+    _lib.lib()
+
+
+# members of uneven size and shape: (h, w, ell, t, n, push size per round)
+MEMBERS = [(27, 37, 40, 20, 150, 25), (64, 64, 40, 20, 170, 7), (111, 111, 64, 32, 160, 40),
+           (150, 200, 100, 50, 210, 33), (200, 328, 40, 20, 130, 64)]
+
+
+def _frames(h, w, n, seed):
+    """(n, ld) device tensor of blob frames (rows 16-byte aligned) and the
+    host copy of its [:, :m] part."""
+    A = synth.blobs(h, w, n, seed)
+    m = h * w
+    ld = (m + 15) // 16 * 16
+    X = torch.zeros((n, ld), dtype=torch.float32, device="cuda:0")
+    X[:, :m] = torch.from_numpy(A).to("cuda:0")
+    return X, A
+
+
+def _configs(sketch, lookahead):
+    from paper_2405_16076_amd import StreamConfig
+    cfgs = []
+    for i, (h, w, ell, t, n, _) in enumerate(MEMBERS):
+        cfgs.append(StreamConfig(m=h * w, ell=ell, k=t, t=t, n_max=n, dtype=torch.float32, sketch=sketch,
+                                 omega_seed=4000 + i, select_seed=5000 + i, lookahead=lookahead))
+    return cfgs
+
+
+def _run_batch(sketch, data, graph=True, tune=True, borrow=True, lookahead=0):
+    from paper_2405_16076_amd import StreamBatch
+    B = StreamBatch(_configs(sketch, lookahead), graph=graph, tune=tune)
+    pos = [0] * len(MEMBERS)
+    while any(p < mb[4] for p, mb in zip(pos, MEMBERS)):
+        cols = []
+        for i, (h, w, ell, t, n, step) in enumerate(MEMBERS):
+            c = min(step, n - pos[i])
+            cols.append(data[i][0][pos[i]:pos[i] + c, :h * w] if c > 0 else None)
+            pos[i] += c
+        B.push(cols, borrow=borrow)
+    B.finalize()
+    torch.cuda.synchronize()
+    return B
+
+
+@pytest.fixture(scope="module")
+def data():
+    return [_frames(h, w, n, synth.data_seed(4) + 17 * i) for i, (h, w, _, _, n, _) in enumerate(MEMBERS)]
+
+
+def _check_member(mbr, A, ell, t, sketch, oseed, sseed):
+    o = run_oracle(A, ell, t, t, sketch, oseed, sseed)
+    tol = perturbation_tolerances(o, A, sketch)
+    worst_tau, margin = compare_updates(mbr, o, tol)
+    J = mbr.select()
+    assert np.array_equal(J, o.J)
+    P = mbr.coefficients()
+    e = rel_fro(P, o.P)
+    assert e <= tol["P"], (e, tol["P"])
+    occ = J >= 0
+    assert np.allclose(P[occ][:, J[occ]], np.eye(int(occ.sum())), atol=1e-5)
+    for u, rec in enumerate(o.records):
+        g = mbr.update(u)
+        for key in ("tr_est", "gpp", "E2"):
+            assert abs(g[key] - rec.hutch[key]) <= tol[key][u], (u, key)
+    n = A.shape[0]
+    c0, c = max(0, n // 2 - 5), min(11, n)
+    R = mbr.reconstruct(c0, c).cpu().numpy().astype(np.float64)
+    Ro = (A.T[:, J[occ]].astype(np.float64) @ o.P[occ][:, c0:c0 + c]).T
+    er = rel_fro(R, Ro)
+    assert er <= tol["recon"], (er, tol["recon"])
+    return worst_tau, margin, e, er
+
+
+@pytest.mark.parametrize("sketch", ["f32", "bf16"])
+def test_batch_members_match_oracle(sketch, data):
+    log(f"batch of {len(MEMBERS)} uneven members, {sketch} sketch, lookahead 64")
+    B = _run_batch(sketch, data, lookahead=64)
+    info = B.info()
+    log(f"  info {info}")
+    assert info["tuned"] == 1 and info["slab_rows"] in (4096, 8192, 16384, 32768, 65536)
+    assert info["graph_launches"] == info["rounds"] and info["graph_updates"] >= 1
+    for i, (h, w, ell, t, n, _) in enumerate(MEMBERS):
+        wt, mg, e, er = _check_member(B.members[i], data[i][1], ell, t, sketch, 4000 + i, 5000 + i)
+        log(f"  member {i} m={h * w} l={ell} t={t}: tau/tol {wt:.2e} margin {mg:.2e} P {e:.2e} recon {er:.2e}")
+    B.close()
+
+
+def _state(B):
+    out = []
+    for mbr in B.members:
+        S, q, G = mbr.debug_state()
+        out.append((S, q, G, mbr.select(), mbr.coefficients(), mbr.error_estimate()["E2"]))
+    return out
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        for u, v in zip(x[:5], y[:5]):
+            assert np.array_equal(u, v)
+        assert x[5] == y[5]
+
+
+def test_batch_graph_equals_direct_launches(data):
+    log("graph-captured rounds against direct launches (bf16, default slab)")
+    Bg = _run_batch("bf16", data, graph=True, tune=False, lookahead=40)
+    ig = Bg.info()
+    Bd = _run_batch("bf16", data, graph=False, tune=False, lookahead=40)
+    idr = Bd.info()
+    log(f"  graph {ig}\n  direct {idr}")
+    assert ig["graph_launches"] == ig["rounds"] >= 5 and ig["graph_updates"] >= 1
+    assert idr["graph_launches"] == 0 and idr["rounds"] == ig["rounds"]
+    _same(_state(Bg), _state(Bd))
+    Bg.close()
+    Bd.close()
+
+
+def test_batch_copy_equals_borrow(data):
+    log("COPY pushes against BORROW pushes (f32)")
+    Bb = _run_batch("f32", data, borrow=True, tune=False, lookahead=40)
+    Bc = _run_batch("f32", data, borrow=False, tune=False, lookahead=40)
+    _same(_state(Bb), _state(Bc))
+    Bb.close()
+    Bc.close()
+
+
+def test_batch_member_rejects_direct_use(data):
+    from paper_2405_16076_amd import _lib
+    B = _run_batch("f32", data, tune=False)
+    mbr = B.members[0]
+    x = data[0][0][:1, :MEMBERS[0][0] * MEMBERS[0][1]]
+    import ctypes as C
+    lib = _lib.lib()
+    assert lib.rid_push_snapshots(mbr._h, C.c_void_p(x.data_ptr()), x.stride(0), 1, _lib.RID_BORROW) == _lib.RID_ESTATE
+    assert lib.rid_finalize(mbr._h) == _lib.RID_ESTATE
+    assert lib.rid_destroy(mbr._h) == _lib.RID_ESTATE
+    # the member still answers
+    assert mbr.select().shape == (MEMBERS[0][3],)
+    B.close()
+
+
+def test_batch_image_streams_64_members_sampled():
+    """64 image streams with m log-uniform in [1e4, 1e6] (l = 200, k = t = 100,
+    bf16 sketch), 300 frames each pushed 100 per round.  Every member: J valid
+    and distinct, P(:, J) = I, a finite estimate; the two smallest members
+    against the oracle."""
+    from paper_2405_16076_amd import StreamBatch, StreamConfig
+    shapes = synth.batch_frame_shapes(64, synth.data_seed(4))
+    n, ell, t = 300, 200, 100
+    log(f"64 members, sum m = {sum(h * w for h, w in shapes)}")
+    X = [synth.blobs_torch(h, w, n, synth.data_seed(4) + 31 * i) for i, (h, w) in enumerate(shapes)]
+    cfgs = [StreamConfig(m=h * w, ell=ell, k=t, t=t, n_max=n, dtype=torch.float32, sketch="bf16",
+                         omega_seed=6000 + i, select_seed=7000 + i) for i, (h, w) in enumerate(shapes)]
+    B = StreamBatch(cfgs)
+    for j0 in range(0, n, 100):
+        B.push([x[j0:j0 + 100, :h * w] for x, (h, w) in zip(X, shapes)], borrow=True)
+    B.finalize()
+    info = B.info()
+    log(f"  info {info}")
+    for i, mbr in enumerate(B.members):
+        J = mbr.select()
+        occ = J >= 0
+        assert np.all(J[occ] < n) and len(set(J[occ].tolist())) == int(occ.sum())
+        P = mbr.coefficients()
+        assert P.shape == (t, n)
+        assert np.allclose(P[occ][:, J[occ]], np.eye(int(occ.sum())), atol=1e-5)
+        est = mbr.error_estimate()
+        assert np.isfinite(est["E2"]) and est["n_obs"] == n
+    small = sorted(range(64), key=lambda i: shapes[i][0] * shapes[i][1])[:2]
+    for i in small:
+        h, w = shapes[i]
+        A = X[i][:, :h * w].cpu().numpy()
+        wt, mg, e, er = _check_member(B.members[i], A, ell, t, "bf16", 6000 + i, 7000 + i)
+        log(f"  member {i} m={h * w}: tau/tol {wt:.2e} margin {mg:.2e} P {e:.2e} recon {er:.2e}")
+    B.close()
