@@ -128,6 +128,73 @@ def cpu_baseline(wl, seeds, operand, rows=1 << 19, cols=None):
                       f"{operand} operands, binary64 sums) in {dt:.1f} s on {threads} BLAS threads"}
 
 
+def batched_bench(steps, warmup, n=1000, push=100):
+    """64 image streams of uneven m (log-uniform in [1e4, 1e6]), l = 200,
+    k = t = 100, bf16 sketch, lookahead 4 t, pushed 100 frames per round as
+    one batch (persistent sketch launch, batched updates, one graph per
+    round).  n = 1000 of the configuration's 5000 frames per stream keeps the
+    stream resident in HBM (49.6 GB)."""
+    import torch
+    import synth
+    from paper_2405_16076_amd import StreamBatch, StreamConfig
+    shapes = synth.batch_frame_shapes(64, synth.data_seed(4))
+    ms = [h * w for h, w in shapes]
+    log(f"generating 64 image streams, sum m = {sum(ms)}, n = {n} ({sum(ms) * n * 4 / 1e9:.1f} GB)")
+    X = [synth.blobs_torch(h, w, n, synth.data_seed(4) + 31 * i) for i, (h, w) in enumerate(shapes)]
+    torch.cuda.synchronize()
+    cfgs = [StreamConfig(m=m, ell=200, k=100, t=100, n_max=n, dtype=torch.float32, sketch="bf16",
+                         omega_seed=1004 + i, select_seed=2004 + i, lookahead=400) for i, m in enumerate(ms)]
+    B = StreamBatch(cfgs)
+
+    def step():
+        B.reset()
+        for j0 in range(0, n, push):
+            B.push([x[j0:j0 + push, :m] for x, m in zip(X, ms)], borrow=True)
+        B.finalize()
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"  [batch] warmup step {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1000.0 / steps
+    info = B.info()
+    # one more pass with every launch timed by events (direct launches)
+    B.profile_enable(True)
+    step()
+    prof = B.profile_read()
+    B.profile_enable(False)
+    B_snap = float(sum(ms)) * n * 4
+    per_launch = prof["sketch_bytes"] / max(prof["sketch_launches"], 1)
+    per_ms = prof["sketch_ms"] / max(prof["sketch_launches"], 1)
+    achieved = per_launch / (per_ms / 1000.0) / 1e9
+    est = [mbr.error_estimate()["rel"] for mbr in B.members]
+    log(f"  [batch] {steps} steps: {ms_step:.2f} ms/step; timed pass: sketch {prof['sketch_ms']:.2f} ms in "
+        f"{prof['sketch_launches']} launches, reduce {prof['reduce_ms']:.2f} ms, updates {prof['update_ms']:.2f} ms")
+    out = {
+        "workload": f"64 image streams (advected Gaussian blobs, m log-uniform in [1e4, 1e6], sum m = {sum(ms)}), "
+                    f"n = {n} each, l = 200, k = t = 100, bf16 sketch, pushed {push} frames per round",
+        "value": round(B_snap / (ms_step / 1000.0) / 1e9, 2), "unit": "GB/s", "ms_per_step": round(ms_step, 3),
+        "steps": steps, "warmup": warmup, "rounds_per_step": info["rounds"] // max(1, steps + warmup),
+        "graph_launches": info["graph_launches"], "graph_instantiations": info["graph_instantiations"],
+        "graph_updates": info["graph_updates"], "slab_rows": info["slab_rows"], "tune_ms": round(info["tune_ms"], 2),
+        "timed_pass_ms": {k: round(prof[k], 3) for k in ("sketch_ms", "reduce_ms", "update_ms", "gram_ms")},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "sketch_bf16_multi", "bytes_per_launch": per_launch,
+                     "ms_per_launch": round(per_ms, 4)},
+        "nahutchpp_rel_estimate": {"min": min(est), "median": sorted(est)[len(est) // 2], "max": max(est)},
+    }
+    B.close()
+    del X
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +205,9 @@ def main():
     ap.add_argument("--small", action="store_true", help="a small stream (quick check)")
     ap.add_argument("--no-compare", action="store_true", help="skip the other sketch forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched image-stream measurement")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched image-stream measurement (prints its JSON object)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the stream is row-sharded across GPUs only in the design "
@@ -151,6 +221,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.batch_only:
+        print(json.dumps(batched_bench(args.steps, args.warmup)), flush=True)
+        return
     wl = workload(args.small)
     seeds = (1003, 2003)
     m = wl["fields"] * wl["nx"] * wl["ny"] * wl["nz"]
@@ -215,6 +288,9 @@ def main():
         log(f"  [{other}] estimate rel {est2['rel']:.4e}, exact (sampled) rel {exact2:.4e}")
         s2.close()
     del D
+    torch.cuda.empty_cache()
+    if not args.no_batch and not args.small:
+        line["batched"] = batched_bench(max(1, min(3, args.steps)), 1)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(wl, seeds, args.sketch)

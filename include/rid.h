@@ -332,6 +332,10 @@ rid_status rid_push_batch(rid_batch* bt, const void* const* d_cols, const int64_
  * the last one over its partial buffer (as rid_finalize).  Asynchronous. */
 rid_status rid_finalize_batch(rid_batch* bt);
 
+/* Returns every member to its state right after rid_init_batch (as
+ * rid_reset); the chosen slab and the executable graph are kept. */
+rid_status rid_reset_batch(rid_batch* bt);
+
 /* Member i as a stream handle owned by the batch: valid for rid_select,
  * rid_coefficients, rid_error_estimate, rid_reconstruct (ordered before later
  * work on the batch's caller stream), rid_get_info, rid_get_update,
@@ -345,6 +349,16 @@ rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info);
 /* Message of the batch's last error (or of the last failed creation when bt
  * is NULL). */
 rid_status rid_batch_last_error(rid_batch* bt, char* buf, size_t n);
+
+/* Timing of the batch's launches: while on, rounds run as direct launches
+ * (no graph) with events around each, so the figures cover the same kernels
+ * the graph runs.  rid_batch_profile_read sums them since the last enable:
+ * sketch_ms / sketch_launches / sketch_bytes for the persistent sketch
+ * launches (snapshot bytes they read), reduce_ms, update_ms (every update
+ * kernel, Gram included), gram_ms, and in `updates` the number of rounds
+ * timed; gram_bytes stays 0.  Both synchronise the batch's stream. */
+rid_status rid_batch_profile_enable(rid_batch* bt, int32_t on);
+rid_status rid_batch_profile_read(rid_batch* bt, rid_profile* p);
 
 /* Waits for the batch's work and frees it with all its members. */
 rid_status rid_destroy_batch(rid_batch* bt);

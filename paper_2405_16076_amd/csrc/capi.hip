@@ -726,9 +726,17 @@ rid_status rid_finalize(rid_stream* h) {
   return RID_OK;
 }
 
+static rid_status reset_stream(rid_stream* h);
+
 rid_status rid_reset(rid_stream* h) {
   if (!h) return fail(nullptr, RID_EINVAL, "null handle");
   if (h->owner) return fail(h, RID_ESTATE, "the stream belongs to a batch");
+  return reset_stream(h);
+}
+
+}  // extern "C"
+
+static rid_status reset_stream(rid_stream* h) {
   if (h->failed) return fail(h, RID_ESTATE, "stream failed");
   RID_HIP(h, hipStreamSynchronize(h->s));
   const size_t ell = h->ell, t = h->t;
@@ -742,6 +750,8 @@ rid_status rid_reset(rid_stream* h) {
   h->finalized = false;
   return RID_OK;
 }
+
+extern "C" {
 
 static rid_status getter_prologue(rid_stream* h) {
   if (h->failed) return fail(h, RID_ESTATE, "stream failed");
@@ -972,7 +982,31 @@ struct rid_batch {
   int n_cu = 0;
   bool failed = false;
   std::string last_err;
+  // timing (rounds then run as direct launches with events around each)
+  bool profiling = false;
+  struct Mark {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
+  int64_t prof_rounds = 0;
 };
+
+static hipEvent_t batch_event(rid_batch* bt) {
+  if (!bt->event_pool.empty()) {
+    hipEvent_t e = bt->event_pool.back();
+    bt->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
 
 static rid_status bfail(rid_batch* bt, rid_status st, const std::string& msg) {
   if (bt) {
@@ -1056,6 +1090,18 @@ static void plan_sketches(rid_batch* bt, const std::vector<SketchArgs>& args, co
 // place when the round has the same shape as the last one), or directly.
 static rid_status batch_exec(rid_batch* bt, const std::vector<BLaunch>& L) {
   if (L.empty()) return RID_OK;
+  if (bt->profiling) {
+    for (const BLaunch& x : L) {
+      rid_batch::Mark mk{batch_event(bt), batch_event(bt), x.kind, x.bytes};
+      if (!mk.a || !mk.b) return bfail(bt, RID_EDEVICE, "event creation failed");
+      BT_HIP(bt, hipEventRecord(mk.a, bt->s));
+      BT_HIP(bt, run_launches(std::vector<BLaunch>{x}, bt->s));
+      BT_HIP(bt, hipEventRecord(mk.b, bt->s));
+      bt->marks.push_back(mk);
+    }
+    bt->prof_rounds += 1;
+    return RID_OK;
+  }
   if (bt->flags & RID_BATCH_NO_GRAPH) {
     BT_HIP(bt, run_launches(L, bt->s));
     return RID_OK;
@@ -1271,6 +1317,11 @@ static rid_status batch_leave(rid_batch* bt) {
 static void batch_free(rid_batch* bt) {
   if (bt->s) (void)hipStreamSynchronize(bt->s);
   (void)hipGetLastError();
+  for (auto& mk : bt->marks) {
+    (void)hipEventDestroy(mk.a);
+    (void)hipEventDestroy(mk.b);
+  }
+  for (hipEvent_t e : bt->event_pool) (void)hipEventDestroy(e);
   for (rid_stream* h : bt->st) {
     h->owner = nullptr;
     destroy_stream(h);
@@ -1444,6 +1495,47 @@ rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info) {
 rid_status rid_batch_last_error(rid_batch* bt, char* buf, size_t n) {
   if (!buf || n == 0) return RID_EINVAL;
   snprintf(buf, n, "%s", bt ? bt->last_err.c_str() : g_last_err.c_str());
+  return RID_OK;
+}
+
+rid_status rid_reset_batch(rid_batch* bt) {
+  if (!bt) return fail(nullptr, RID_EINVAL, "null batch");
+  if (bt->failed) return bfail(bt, RID_ESTATE, "batch failed");
+  rid_status st = batch_enter(bt);
+  if (st != RID_OK) return st;
+  for (rid_stream* h : bt->st)
+    if ((st = reset_stream(h)) != RID_OK) return bfail(bt, st, h->last_err);
+  return batch_leave(bt);
+}
+
+rid_status rid_batch_profile_enable(rid_batch* bt, int32_t on) {
+  if (!bt) return fail(nullptr, RID_EINVAL, "null batch");
+  BT_HIP(bt, hipStreamSynchronize(bt->s));
+  for (auto& mk : bt->marks) {
+    bt->event_pool.push_back(mk.a);
+    bt->event_pool.push_back(mk.b);
+  }
+  bt->marks.clear();
+  bt->prof_rounds = 0;
+  bt->profiling = on != 0;
+  return RID_OK;
+}
+
+rid_status rid_batch_profile_read(rid_batch* bt, rid_profile* p) {
+  if (!bt || !p) return fail(nullptr, RID_EINVAL, "null argument");
+  BT_HIP(bt, hipStreamSynchronize(bt->s));
+  memset(p, 0, sizeof(*p));
+  for (auto& mk : bt->marks) {
+    float ms = 0.0f;
+    BT_HIP(bt, hipEventElapsedTime(&ms, mk.a, mk.b));
+    switch (mk.kind) {
+      case 0: p->sketch_ms += ms; p->sketch_launches += 1; p->sketch_bytes += mk.bytes; break;
+      case 1: p->reduce_ms += ms; break;
+      case 3: p->gram_ms += ms; p->update_ms += ms; break;
+      default: p->update_ms += ms; break;
+    }
+  }
+  p->updates = bt->prof_rounds;
   return RID_OK;
 }
 

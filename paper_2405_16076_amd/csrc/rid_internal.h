@@ -397,6 +397,8 @@ struct BLaunch {
   int ns, total;     // MultiSketch only
   int extra;         // trailing int argument (hutch_mid_kernel stage), -1 if none
   bool multi;        // MultiSketch (else Batched)
+  int kind;          // for timing: 0 sketch, 1 reduce, 2 update, 3 Gram
+  double bytes;      // sketch: snapshot bytes the launch reads
 };
 hipError_t run_launches(const std::vector<BLaunch>& v, hipStream_t s);
 

@@ -923,6 +923,9 @@ void plan_sketch_multi(int prec, const SketchArgs* h, int ns, int grid_cap, Stag
     L.extra = -1;
     L.args = st.put(g.data(), g.size());
     L.aux = st.put(start.data(), start.size());
+    L.kind = 0;
+    L.bytes = 0.0;
+    for (const SketchArgs& a : g) L.bytes += (double)a.b * (double)a.m * (prec == RID_SKETCH_F64 ? 8.0 : 4.0);
     out.push_back(L);
   }
 }
@@ -944,6 +947,7 @@ void plan_sketch_reduce_b(int prec, const SketchArgs* h, int ns, Stage& st, std:
   L.extra = -1;
   L.args = st.put(g.data(), g.size());
   L.aux = st.put(dims.data(), dims.size());
+  L.kind = 1;
   out.push_back(L);
 }
 

@@ -1765,6 +1765,7 @@ struct Planner {
       }
     groups.push_back(Group<A>{func, lds, {a}, {d}});
   }
+  int kind = 2;
   void emit(dim3 block, int extra, Stage& st, std::vector<BLaunch>& out) {
     for (auto& g : groups) {
       int maxb = 0;
@@ -1779,6 +1780,7 @@ struct Planner {
       L.aux = st.put(g.dims.data(), g.dims.size());
       L.extra = extra;
       L.multi = false;
+      L.kind = kind;
       out.push_back(L);
     }
     groups.clear();
@@ -1811,6 +1813,7 @@ void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaun
 
 void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
   Planner<UpdArgs> P64, P32;
+  P64.kind = P32.kind = 3;
   for (int i = 0; i < ns; ++i) {
     const UpdArgs& a = h[i];
     if (a.data_f64) {

@@ -253,6 +253,20 @@ class StreamBatch:
     def finalize(self):
         self._check(L.lib().rid_finalize_batch(self._b))
 
+    def reset(self):
+        self._check(L.lib().rid_reset_batch(self._b))
+        self._keep = []
+
+    def profile_enable(self, on=True):
+        self._check(L.lib().rid_batch_profile_enable(self._b, 1 if on else 0))
+
+    def profile_read(self):
+        p = L.rid_profile()
+        self._check(L.lib().rid_batch_profile_read(self._b, C.byref(p)))
+        d = {f: getattr(p, f) for f, _ in L.rid_profile._fields_}
+        d["rounds"] = d.pop("updates")
+        return d
+
     def info(self):
         i = L.rid_batch_info()
         self._check(L.lib().rid_batch_get_info(self._b, C.byref(i)))

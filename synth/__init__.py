@@ -176,19 +176,22 @@ def blobs_torch(h, w, n, seed, n_blobs=6, rel_noise=0.01, device="cuda:0", ld=No
     ld = ld or (m + 15) // 16 * 16
     g = torch.Generator(device=dev)
     g.manual_seed(int(seed) % (1 << 63))
-    yy = torch.arange(h, device=dev, dtype=torch.float32)[:, None]
-    xx = torch.arange(w, device=dev, dtype=torch.float32)[None, :]
+    yy = torch.arange(h, device=dev, dtype=torch.float32)[None, :, None]
+    xx = torch.arange(w, device=dev, dtype=torch.float32)[None, None, :]
     out = torch.zeros((n, ld), dtype=torch.float32, device=dev)
-    for t in range(n):
-        fr = torch.zeros((h, w), dtype=torch.float32, device=dev)
+    chunk = max(1, (1 << 25) // max(m, 1))  # frames per chunk (~128 MB of binary32)
+    for t0 in range(0, n, chunk):
+        t = torch.arange(t0, min(n, t0 + chunk), device=dev, dtype=torch.float64)
+        fr = torch.zeros((t.numel(), h, w), dtype=torch.float32, device=dev)
         for b in range(n_blobs):
-            cy, cx = pos0[b] + vel[b] * t
-            dy = torch.remainder(yy - float(cy) + h / 2, h) - h / 2
-            dx = torch.remainder(xx - float(cx) + w / 2, w) - w / 2
+            cy = (pos0[b, 0] + vel[b, 0] * t).to(torch.float32)[:, None, None]
+            cx = (pos0[b, 1] + vel[b, 1] * t).to(torch.float32)[:, None, None]
+            dy = torch.remainder(yy - cy + h / 2, h) - h / 2
+            dx = torch.remainder(xx - cx + w / 2, w) - w / 2
             fr += float(amp[b]) * torch.exp(-(dy * dy + dx * dx) / float(2.0 * wid[b] ** 2))
-        rms = torch.sqrt(torch.mean(fr * fr))
-        fr += rel_noise * rms * torch.randn((h, w), generator=g, device=dev, dtype=torch.float32)
-        out[t, :m] = fr.reshape(-1)
+        rms = torch.sqrt(torch.mean(fr * fr, dim=(1, 2), keepdim=True))
+        fr += rel_noise * rms * torch.randn(fr.shape, generator=g, device=dev, dtype=torch.float32)
+        out[t0:t0 + t.numel(), :m] = fr.reshape(t.numel(), m)
     return out
 
 
