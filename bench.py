@@ -181,7 +181,8 @@ def batched_bench(steps, warmup, n=1000, push=100):
         "value": round(B_snap / (ms_step / 1000.0) / 1e9, 2), "unit": "GB/s", "ms_per_step": round(ms_step, 3),
         "steps": steps, "warmup": warmup, "rounds_per_step": info["rounds"] // max(1, steps + warmup),
         "graph_launches": info["graph_launches"], "graph_instantiations": info["graph_instantiations"],
-        "graph_updates": info["graph_updates"], "slab_rows": info["slab_rows"], "tune_ms": round(info["tune_ms"], 2),
+        "graph_updates": info["graph_updates"], "slab_rows": info["slab_rows"],
+        "tile": "wide" if info["wide"] else "narrow", "tune_ms": round(info["tune_ms"], 2),
         "timed_pass_ms": {k: round(prof[k], 3) for k in ("sketch_ms", "reduce_ms", "update_ms", "gram_ms")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

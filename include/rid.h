@@ -69,6 +69,16 @@ typedef enum rid_sketch_prec {
                            scaled fp8 matrix cores */
 } rid_sketch_prec;
 
+/* Work split of the bf16 sketch (the results are the same up to the order
+ * of binary32 sums within a slab).  NARROW: one workgroup per 256-column
+ * tile holds every sketch row.  WIDE (bf16, 128 < l <= 320): two workgroups
+ * per 512-column tile hold half of the rows each, so each Gaussian of the
+ * test matrix serves twice as many columns, and the columns the two fetch
+ * meet in L2.  A single stream uses NARROW under AUTO (faster on the
+ * 19M-row channel stream: one 64 KB chunk in flight per workgroup instead of
+ * two 32 KB ones); the batch tuner times both. */
+typedef enum rid_sketch_tile { RID_TILE_AUTO = 0, RID_TILE_NARROW = 1, RID_TILE_WIDE = 2 } rid_sketch_tile;
+
 /* Push flags. */
 #define RID_COPY   0u  /* copy the columns into the library's ring; the buffer
                           may be reused once prior work on the stream is done */
@@ -100,7 +110,7 @@ typedef struct rid_config {
   int32_t hutch_n1;       /* rows of Omega_1 (0 = l/4) */
   int32_t hutch_n2;       /* rows of Omega_2 (0 = l/2); n1 + n2 < l */
   int32_t lookahead;      /* columns buffered before a sketch launch; 0 = auto */
-  int32_t reserved0;
+  int32_t sketch_tile;    /* rid_sketch_tile (default RID_TILE_AUTO) */
   int64_t n_max;          /* capacity: maximum number of pushed columns */
 } rid_config;
 
@@ -283,7 +293,8 @@ rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64
  * members with an update due.  The launches of a round are captured into one
  * HIP graph, updated in place from round to round.  The row slab of the
  * sketch (the tile height) is chosen by timing the candidates on the first
- * round's columns, once per batch shape in the process.
+ * round's columns, once per batch shape in the process; for bf16 members
+ * the tuner also times both work splits of rid_sketch_tile.
  *
  * A member's results are bitwise independent of the other members.  They
  * equal those of a stand-alone stream with the same slab: the slab fixes the
@@ -304,7 +315,7 @@ typedef struct rid_batch_info {
   int64_t graph_updates;         /* rounds that updated the executable in place */
   int64_t slab_rows;             /* sketch rows per work item (tuned or default) */
   int32_t tuned;                 /* 1 once the slab has been chosen by timing */
-  int32_t reserved0;
+  int32_t wide;                  /* 1 when bf16 members use RID_TILE_WIDE */
   double tune_ms;                /* device time spent timing candidates */
 } rid_batch_info;
 

@@ -15,6 +15,7 @@ RID_OK, RID_EINVAL, RID_ENOMEM, RID_EDEVICE, RID_ESTATE, RID_ECAPACITY, RID_ENUM
 RID_F32, RID_F64 = 0, 1
 RID_SKETCH_F64, RID_SKETCH_F32, RID_SKETCH_BF16, RID_SKETCH_FP8 = 0, 1, 2, 3
 RID_COPY, RID_BORROW = 0, 1
+RID_TILE_AUTO, RID_TILE_NARROW, RID_TILE_WIDE = 0, 1, 2
 RID_HOST, RID_DEVICE = 0, 1
 RID_UPD_SKIPPED, RID_UPD_RANK_DEFICIENT, RID_UPD_PINV_TRUNCATED = 1, 2, 4
 
@@ -25,7 +26,7 @@ class rid_config(C.Structure):
         ("data_dtype", C.c_int32), ("sketch_prec", C.c_int32),
         ("omega_seed", C.c_uint64), ("select_seed", C.c_uint64),
         ("delta", C.c_double), ("eps", C.c_double), ("c_sample", C.c_double), ("ridge_floor", C.c_double),
-        ("hutch_n1", C.c_int32), ("hutch_n2", C.c_int32), ("lookahead", C.c_int32), ("reserved0", C.c_int32),
+        ("hutch_n1", C.c_int32), ("hutch_n2", C.c_int32), ("lookahead", C.c_int32), ("sketch_tile", C.c_int32),
         ("n_max", C.c_int64),
     ]
 
@@ -62,7 +63,7 @@ RID_BATCH_NO_GRAPH, RID_BATCH_NO_TUNE = 1, 2
 class rid_batch_info(C.Structure):
     _fields_ = [("ns", C.c_int32), ("failed", C.c_int32), ("rounds", C.c_int64), ("graph_launches", C.c_int64),
                 ("graph_instantiations", C.c_int64), ("graph_updates", C.c_int64), ("slab_rows", C.c_int64),
-                ("tuned", C.c_int32), ("reserved0", C.c_int32), ("tune_ms", C.c_double)]
+                ("tuned", C.c_int32), ("wide", C.c_int32), ("tune_ms", C.c_double)]
 
 
 # name -> (restype, argtypes); every function declared in include/rid.h

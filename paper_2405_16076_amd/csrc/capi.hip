@@ -9,6 +9,7 @@
 // in the getters.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -88,7 +89,7 @@ struct rid_stream {
   int64_t m = 0, n_max = 0;
   double fill_mult = 0.0;
   // sketch geometry
-  int ell_pad = 0, n_mt = 0, rbw = 0, cols_per_wg = 0, b_max = 0, n_slabs = 0;
+  int ell_pad = 0, n_mt = 0, rbw = 0, wide = 0, cols_per_wg = 0, b_max = 0, n_slabs = 0;
   int64_t slab_rows = 0;
   int gslabs = 0;
   int64_t gslab_rows = 0;
@@ -140,6 +141,7 @@ struct rid_stream {
 };
 
 static thread_local std::string g_last_err;
+
 
 static rid_status fail(rid_stream* h, rid_status st, const std::string& msg) {
   if (h) {
@@ -209,6 +211,35 @@ static void free_all(rid_stream* h) {
   h->colptr_host = nullptr;
 }
 
+static bool wide_applies(const rid_stream* h) {
+  return h->prec == RID_SKETCH_BF16 && h->ell > 128 && h->ell <= 320;
+}
+
+// Work split of the sketch.  Both bf16 splits give the same l_pad, so the
+// partial buffers fit either.
+static void set_tile(rid_stream* h, bool wide) {
+  h->wide = 0;
+  if (wide && wide_applies(h)) {
+    // two workgroups per 512-column tile, 32 rbw rows each
+    const int rows = (h->ell + 63) / 64 * 64;
+    h->n_mt = 2;
+    h->rbw = rows / 64;
+    h->ell_pad = rows;
+    h->wide = 1;
+  } else if (h->prec == RID_SKETCH_BF16 || h->prec == RID_SKETCH_FP8) {
+    // all test-matrix rows in one workgroup up to 320 rows, else split
+    const int rows = (h->ell + 63) / 64 * 64;
+    h->n_mt = (rows + 319) / 320;
+    h->rbw = (rows + 64 * h->n_mt - 1) / (64 * h->n_mt);
+    h->ell_pad = h->n_mt * 64 * h->rbw;
+  } else {
+    h->ell_pad = (h->ell + kMTile - 1) / kMTile * kMTile;
+    h->n_mt = h->ell_pad / kMTile;
+    h->rbw = 0;
+  }
+  h->cols_per_wg = sketch_cols_per_wg(h->prec, h->wide);
+}
+
 static int auto_lookahead(const rid_config* c) {
   int la = c->lookahead > 0 ? c->lookahead : 1024;
   la = std::max(la, 2 * c->t);
@@ -274,6 +305,10 @@ static rid_status validate(const rid_config* c) {
     return fail(nullptr, RID_EINVAL, "need 1 <= n1 < n2 and n1 + n2 < ell");
   if (n1 > kMaxEll / 4) return fail(nullptr, RID_ENOTSUP, "n1 above 128 is not supported");
   if (c->lookahead < 0) return fail(nullptr, RID_EINVAL, "lookahead must be >= 0");
+  if (c->sketch_tile < RID_TILE_AUTO || c->sketch_tile > RID_TILE_WIDE)
+    return fail(nullptr, RID_EINVAL, "unknown sketch_tile");
+  if (c->sketch_tile == RID_TILE_WIDE && !(c->sketch_prec == RID_SKETCH_BF16 && c->ell > 128 && c->ell <= 320))
+    return fail(nullptr, RID_ENOTSUP, "the wide sketch tile needs the bf16 form and 128 < ell <= 320");
   return RID_OK;
 }
 
@@ -305,18 +340,7 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     h->fill_mult = cfg->c_sample * (k * log(k) + k * log(1.0 / cfg->delta) / cfg->eps) / cfg->t;
   }
   // sketch geometry
-  if (h->prec == RID_SKETCH_BF16 || h->prec == RID_SKETCH_FP8) {
-    // all test-matrix rows in one workgroup up to 320 rows, else split
-    const int rows = (h->ell + 63) / 64 * 64;
-    h->n_mt = (rows + 319) / 320;
-    h->rbw = (rows + 64 * h->n_mt - 1) / (64 * h->n_mt);
-    h->ell_pad = h->n_mt * 64 * h->rbw;
-  } else {
-    h->ell_pad = (h->ell + kMTile - 1) / kMTile * kMTile;
-    h->n_mt = h->ell_pad / kMTile;
-    h->rbw = 0;
-  }
-  h->cols_per_wg = sketch_cols_per_wg(h->prec);
+  set_tile(h, cfg->sketch_tile == RID_TILE_WIDE);
   h->b_max = auto_lookahead(cfg);
   {
     const int n_nt = (h->b_max + h->cols_per_wg - 1) / h->cols_per_wg;
@@ -465,6 +489,7 @@ static SketchArgs sketch_args(rid_stream* h, int64_t c0, int b) {
   a.ell_pad = h->ell_pad;
   a.ell = h->ell;
   a.rbw = h->rbw;
+  a.wide = h->wide;
   a.seed = h->cfg.omega_seed;
   a.part = h->part;
   a.normpart = h->normpart;
@@ -977,6 +1002,7 @@ struct rid_batch {
   hipGraphExec_t exec = nullptr;
   int64_t rounds = 0, graph_launches = 0, graph_instantiations = 0, graph_updates = 0;
   int64_t slab_rows = 0, min_slab_rows = 0;
+  int wide = 0;  // bf16 members: the wide work split
   bool tuned = false;
   double tune_ms = 0.0;
   int n_cu = 0;
@@ -1156,8 +1182,12 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
            (long long)(msum >> 16), bt->st[0]->b_max);
   for (auto& kv : cache)
     if (kv.first == key) {
-      bt->slab_rows = kv.second;
-      for (rid_stream* h : bt->st) set_slab(h, bt->slab_rows);
+      bt->slab_rows = kv.second / 2;
+      bt->wide = (int)(kv.second & 1);
+      for (rid_stream* h : bt->st) {
+        set_tile(h, h->cfg.sketch_tile == RID_TILE_WIDE || (h->cfg.sketch_tile == RID_TILE_AUTO && bt->wide));
+        set_slab(h, bt->slab_rows);
+      }
       bt->tuned = true;
       return RID_OK;
     }
@@ -1166,17 +1196,29 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
   BT_HIP(bt, hipEventCreate(&e1));
   double best = 1e300;
   int64_t best_rows = bt->slab_rows;
+  int best_wide = 0;
+  bool any_wide = false;
+  for (rid_stream* h : bt->st) any_wide = any_wide || (wide_applies(h) && h->cfg.sketch_tile == RID_TILE_AUTO);
+  // members that asked for a split keep it; the others take the candidate's
+  auto apply_tile = [](rid_stream* h, int wide) {
+    set_tile(h, h->cfg.sketch_tile == RID_TILE_WIDE || (h->cfg.sketch_tile == RID_TILE_AUTO && wide));
+  };
+  for (int wide = 0; wide <= (any_wide ? 1 : 0); ++wide)
   for (int64_t rows : slab_candidates(prec)) {
     if (rows < bt->min_slab_rows) continue;
-    for (rid_stream* h : bt->st) set_slab(h, rows);
+    for (rid_stream* h : bt->st) {
+      apply_tile(h, wide);
+      set_slab(h, rows);
+    }
     std::vector<SketchArgs> args;
     std::vector<int> precs;
     for (size_t i = 0; i < who.size(); ++i) {
       args.push_back(sketch_args(bt->st[who[i]], c0[i], b[i]));
       precs.push_back(bt->st[who[i]]->prec);
     }
-    float ms_last = 0.0f;
-    for (int rep = 0; rep < 2; ++rep) {
+    // one untimed run, then the median of three timed ones
+    float ms_rep[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int rep = 0; rep < 4; ++rep) {
       Stage stg;
       rid_status sts = take_slot(bt, stg);
       if (sts != RID_OK) return sts;
@@ -1187,19 +1229,26 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
       BT_HIP(bt, run_launches(L, bt->s));
       BT_HIP(bt, hipEventRecord(e1, bt->s));
       BT_HIP(bt, hipEventSynchronize(e1));
-      BT_HIP(bt, hipEventElapsedTime(&ms_last, e0, e1));
+      BT_HIP(bt, hipEventElapsedTime(&ms_rep[rep], e0, e1));
     }
+    std::sort(ms_rep + 1, ms_rep + 4);
+    const float ms_last = ms_rep[2];
     bt->tune_ms += ms_last;
     if (ms_last < best) {
       best = ms_last;
       best_rows = rows;
+      best_wide = wide;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   bt->slab_rows = best_rows;
-  for (rid_stream* h : bt->st) set_slab(h, best_rows);
-  cache.emplace_back(key, best_rows);
+  bt->wide = best_wide;
+  for (rid_stream* h : bt->st) {
+    apply_tile(h, best_wide);
+    set_slab(h, best_rows);
+  }
+  cache.emplace_back(key, best_rows * 2 + best_wide);
   bt->tuned = true;
   return RID_OK;
 }
@@ -1488,6 +1537,7 @@ rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info) {
   info->graph_updates = bt->graph_updates;
   info->slab_rows = bt->slab_rows;
   info->tuned = bt->tuned ? 1 : 0;
+  info->wide = bt->wide;
   info->tune_ms = bt->tune_ms;
   return RID_OK;
 }

@@ -234,7 +234,9 @@ struct SketchArgs {
   int64_t slab_rows;       // rows per slab (multiple of 32)
   int32_t n_slabs, n_mt, n_nt, ell_pad;
   int32_t ell;             // test-matrix rows l
-  int32_t rbw;             // bfloat16 form: 32-row blocks per wave (rows per workgroup / 64)
+  int32_t rbw;             // bf16/fp8: 32-row blocks per wave (rows per workgroup / 64);
+                           // wide bf16: 32-row blocks per workgroup
+  int32_t wide;            // bf16: two workgroups per 512-column tile, half the rows each
   uint64_t seed;
   void* part;              // [n_slabs][b_max][ell_pad] float (double for F64)
   double* normpart;        // [n_slabs][b_max]
@@ -412,7 +414,7 @@ void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch
 void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 
 // launchers (sketch.hip, update.hip)
-int sketch_cols_per_wg(int prec);
+int sketch_cols_per_wg(int prec, int wide);
 hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s);
 hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s);
 hipError_t launch_omega_block(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,

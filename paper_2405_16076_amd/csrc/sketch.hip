@@ -280,6 +280,205 @@ __global__ __launch_bounds__(512, 1) void sketch_bf16_multi(MultiSketch ms) {
 }
 
 // ---------------------------------------------------------------------------
+// Wide bfloat16 form: two workgroups share a 512-column tile, each taking
+// half of the sketch rows (32 RB rows), so each Gaussian of a tile row is
+// generated for 512 columns instead of 256; the two workgroups of a tile are
+// consecutive work items (same XCD, started together), so the columns one
+// of them fetches from HBM meet the other in L2.  Wave w owns column blocks
+// 2w, 2w+1 and every row block: RB x 2 accumulator tiles, as in the narrow
+// form.  Chunks of 32 rows x 512 columns (64 KB) go HBM -> LDS by LDS-DMA
+// into two stages (one chunk in flight while one is consumed); the Omega
+// tile of the next chunk is generated during the current one (waves 0-3
+// multiply first, waves 4-7 generate first).  Items of the generation are
+// single Philox calls (8 rows x 1 data row) spread over all 512 threads.
+// ---------------------------------------------------------------------------
+constexpr int kWideCols = 512;
+
+template <int RB>
+__device__ __forceinline__ void sketch_bf16w_body(const SketchArgs& a, int slab, int mt, int nt) {
+  constexpr int KC = 32;                 // rows per chunk
+  constexpr int MROWS = 32 * RB;         // test-matrix rows per workgroup
+  constexpr int LDA = KC + 8;            // bf16 per Omega LDS row (80 bytes)
+  __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
+  __shared__ __attribute__((aligned(1024))) float dt[2][kWideCols * KC];
+  __shared__ uint64_t csrc[kWideCols];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, l32 = lane & 31;
+  const int64_t r0 = (int64_t)slab * a.slab_rows;
+  const int64_t r1 = min(a.m, r0 + a.slab_rows);
+  const int nch = (int)((r1 - r0 + KC - 1) / KC);
+  const bool ragged = (r1 - r0) % KC != 0;
+  const int row_base = mt * MROWS;
+
+  // column addresses (columns past the batch read the tile's first column;
+  // their results are never stored)
+  for (int cl = tid; cl < kWideCols; cl += 512) {
+    const int cg = nt * kWideCols + cl;
+    csrc[cl] = a.colptr[a.c0 + (cg < a.b ? cg : nt * kWideCols)];
+  }
+  __syncthreads();
+  // LDS-DMA: copy i of wave w fills columns 8(8w+i)..+8 of a chunk, 8 lanes
+  // per column; rows wholly past the slab end come from row r0 and are zeroed
+  // by the fix-up, a run straddling the snapshot end stays in its 16-byte block
+  auto issue = [&](int c) {
+    const int64_t k0 = r0 + (int64_t)c * KC;
+    const uint32_t sb = lds_addr(&dt[c & 1][0]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int cl = 8 * (8 * wave + i) + (lane >> 3);
+      int64_t row = k0 + 4 * ((lane & 7) ^ col_swz(cl));
+      if (row >= r1) row = r0;
+      const gmem_t<float>* src = gload_ptr(reinterpret_cast<const float*>(csrc[cl]));
+      lds_dma16(src + row, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(8 * wave + i) * 1024u));
+    }
+  };
+  auto fixup = [&](int c) {
+    const int64_t k0 = r0 + (int64_t)c * KC;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int cl = 8 * (8 * wave + i) + (lane >> 3);
+      const int64_t row = k0 + 4 * ((lane & 7) ^ col_swz(cl));
+      float* slot = &dt[c & 1][cl * KC + 4 * (lane & 7)];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (row + e >= r1) slot[e] = 0.0f;
+    }
+  };
+
+  // Omega tile of chunk c: item = (row group g, data row k), one Philox call
+  const int n_groups = min(MROWS / 8, max(0, (a.ell - row_base + 7) / 8));
+  const int n_items = n_groups * KC;
+  auto gen = [&](int c) {
+    const int64_t k0 = r0 + (int64_t)c * KC;
+    uint16_t* d = om[c & 1];
+    for (int it = tid; it < n_items; it += 512) {
+      const int g = it / KC, k = it % KC;
+      float z[8];
+      omega8_f32(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), z);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) d[(8 * g + j) * LDA + k] = __builtin_bit_cast(uint16_t, (__bf16)z[j]);
+    }
+  };
+
+  f32x16 acc[RB][2];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.0f;
+  double nrm[2] = {0.0, 0.0};
+
+  // one chunk on the matrix cores; lane (l32, half) reads rows
+  // 16 s + 8 half .. +8 of column (2 wave + cc) 32 + l32 (each element once,
+  // which also gives the binary64 norms)
+  auto mfma_chunk = [&](int c) {
+    const uint16_t* O = om[c & 1];
+    const float* D = dt[c & 1];
+#pragma unroll
+    for (int s = 0; s < KC / 16; ++s) {
+      bf16x8 bop[2];
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const int cl = (2 * wave + cc) * 32 + l32;
+        const int key = col_swz(cl);
+        const float* colb = D + cl * KC;
+        const float4 x0 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half) ^ key));
+        const float4 x1 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half + 1) ^ key));
+        if (mt == 0) {
+          double t = nrm[cc];
+          t = fma((double)x0.x, (double)x0.x, t);
+          t = fma((double)x0.y, (double)x0.y, t);
+          t = fma((double)x0.z, (double)x0.z, t);
+          t = fma((double)x0.w, (double)x0.w, t);
+          t = fma((double)x1.x, (double)x1.x, t);
+          t = fma((double)x1.y, (double)x1.y, t);
+          t = fma((double)x1.z, (double)x1.z, t);
+          t = fma((double)x1.w, (double)x1.w, t);
+          nrm[cc] = t;
+        }
+        bop[cc] = bf16x8{(__bf16)x0.x, (__bf16)x0.y, (__bf16)x0.z, (__bf16)x0.w,
+                         (__bf16)x1.x, (__bf16)x1.y, (__bf16)x1.z, (__bf16)x1.w};
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const bf16x8 av = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const u16x8*>(&O[(r * 32 + l32) * LDA + 16 * s + 8 * half]));
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+          acc[r][cc] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bop[cc], acc[r][cc], 0, 0, 0);
+      }
+    }
+  };
+
+  // prologue: chunk 0 in flight, zero rows of Omega, Omega of chunk 0
+  issue(0);
+  for (int i = tid + n_groups * 8 * (LDA / 2); i < MROWS * (LDA / 2); i += 512) {
+    reinterpret_cast<uint32_t*>(om[0])[i] = 0u;
+    reinterpret_cast<uint32_t*>(om[1])[i] = 0u;
+  }
+  gen(0);
+  wait_dma_all();
+  if (ragged && nch == 1) fixup(0);
+  lds_barrier();
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) issue(c + 1);       // the stage of chunk c - 1 is free
+    if (wave < 4) {
+      mfma_chunk(c);
+      if (c + 1 < nch) gen(c + 1);
+    } else {
+      if (c + 1 < nch) gen(c + 1);
+      mfma_chunk(c);
+    }
+    wait_dma_all();
+    if (ragged && c + 1 == nch - 1) fixup(c + 1);
+    lds_barrier();
+  }
+
+  float* part = reinterpret_cast<float*>(a.part);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int col = nt * kWideCols + (2 * wave + c) * 32 + l32;
+    if (col >= a.b) continue;
+    float* dst = part + ((int64_t)slab * a.b_max + col) * a.ell_pad + row_base;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float4 v = make_float4(acc[r][c][4 * q], acc[r][c][4 * q + 1], acc[r][c][4 * q + 2],
+                               acc[r][c][4 * q + 3]);
+        *reinterpret_cast<float4*>(dst + r * 32 + 8 * q + 4 * half) = v;
+      }
+  }
+  if (mt == 0) {
+    // lanes l and l + 32 hold the two row halves of one column
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const double t = nrm[cc] + __shfl_xor(nrm[cc], 32);
+      const int col = nt * kWideCols + (2 * wave + cc) * 32 + l32;
+      if (half == 0 && col < a.b) a.normpart[(int64_t)slab * a.b_max + col] = t;
+    }
+  }
+}
+
+template <int RB>
+__global__ __launch_bounds__(512, 1) void sketch_bf16w_kernel(SketchArgs a) {
+  int slab, mt, nt;
+  if (sketch_item(a, blockIdx.x, slab, mt, nt)) sketch_bf16w_body<RB>(a, slab, mt, nt);
+}
+
+template <int RB>
+__global__ __launch_bounds__(512, 1) void sketch_bf16w_multi(MultiSketch ms) {
+  int slab, mt, nt;
+  const SketchArgs* a;
+  for (int q = blockIdx.x; q < ms.total; q += gridDim.x) {
+    multi_item(ms, q, a, slab, mt, nt);
+    sketch_bf16w_body<RB>(*a, slab, mt, nt);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // fp8 form: e4m3 operands with power-of-two block scales on
 // v_mfma_scale_f32_32x32x64_f8f6f4 (binary32 accumulation).
 //   * Omega is e4m3(Omega * 2^6) with the fixed scale 2^-6 (E8M0 121).
@@ -824,7 +1023,8 @@ __global__ void omega_block_kernel(int prec, uint64_t seed, int ell, int64_t i0,
 // ---------------------------------------------------------------------------
 constexpr int kNcbF32 = 2;
 
-int sketch_cols_per_wg(int prec) {
+int sketch_cols_per_wg(int prec, int wide) {
+  if (prec == RID_SKETCH_BF16 && wide) return kWideCols;
   if (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) return kBf16Cols;
   if (prec == RID_SKETCH_F32) return 4 * kNcbF32 * 32;
   return 64;
@@ -833,7 +1033,15 @@ int sketch_cols_per_wg(int prec) {
 hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s) {
   const int n_items = a.n_slabs * a.n_mt * a.n_nt;
   const int grid = 8 * ((n_items + 7) / 8);
-  if (prec == RID_SKETCH_BF16) {
+  if (prec == RID_SKETCH_BF16 && a.wide) {
+    switch (a.rbw) {
+      case 3: hipLaunchKernelGGL(sketch_bf16w_kernel<3>, dim3(grid), dim3(512), 0, s, a); break;
+      case 4: hipLaunchKernelGGL(sketch_bf16w_kernel<4>, dim3(grid), dim3(512), 0, s, a); break;
+      case 5: hipLaunchKernelGGL(sketch_bf16w_kernel<5>, dim3(grid), dim3(512), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  else if (prec == RID_SKETCH_BF16) {
     switch (a.rbw) {
       case 1: hipLaunchKernelGGL(sketch_bf16_kernel<1>, dim3(grid), dim3(512), 0, s, a); break;
       case 2: hipLaunchKernelGGL(sketch_bf16_kernel<2>, dim3(grid), dim3(512), 0, s, a); break;
@@ -870,7 +1078,15 @@ hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s) {
 }
 
 namespace {
-const void* multi_func(int prec, int rbw) {
+const void* multi_func(int prec, int rbw, int wide) {
+  if (prec == RID_SKETCH_BF16 && wide) {
+    switch (rbw) {
+      case 3: return reinterpret_cast<const void*>(sketch_bf16w_multi<3>);
+      case 4: return reinterpret_cast<const void*>(sketch_bf16w_multi<4>);
+      case 5: return reinterpret_cast<const void*>(sketch_bf16w_multi<5>);
+      default: return nullptr;
+    }
+  }
   if (prec == RID_SKETCH_BF16) {
     switch (rbw) {
       case 1: return reinterpret_cast<const void*>(sketch_bf16_multi<1>);
@@ -902,11 +1118,11 @@ void plan_sketch_multi(int prec, const SketchArgs* h, int ns, int grid_cap, Stag
   std::vector<char> done(ns, 0);
   for (int i = 0; i < ns; ++i) {
     if (done[i]) continue;
-    const void* f = multi_func(prec, h[i].rbw);
+    const void* f = multi_func(prec, h[i].rbw, h[i].wide);
     std::vector<SketchArgs> g;
     std::vector<int> start{0};
     for (int j = i; j < ns; ++j)
-      if (!done[j] && multi_func(prec, h[j].rbw) == f) {
+      if (!done[j] && multi_func(prec, h[j].rbw, h[j].wide) == f) {
         done[j] = 1;
         g.push_back(h[j]);
         start.push_back(start.back() + h[j].n_slabs * h[j].n_mt * h[j].n_nt);

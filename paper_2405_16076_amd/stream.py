@@ -36,6 +36,7 @@ class StreamConfig:
     hutch_n1: int = 0
     hutch_n2: int = 0
     lookahead: int = 0
+    tile: str = "auto"   # bf16 sketch work split: auto, narrow or wide
 
     def to_c(self):
         c = L.rid_config()
@@ -46,6 +47,7 @@ class StreamConfig:
         c.omega_seed, c.select_seed = self.omega_seed, self.select_seed
         c.delta, c.eps, c.c_sample, c.ridge_floor = self.delta, self.eps, self.c_sample, self.ridge_floor
         c.hutch_n1, c.hutch_n2, c.lookahead = self.hutch_n1, self.hutch_n2, self.lookahead
+        c.sketch_tile = {"auto": L.RID_TILE_AUTO, "narrow": L.RID_TILE_NARROW, "wide": L.RID_TILE_WIDE}[self.tile]
         return c
 
 

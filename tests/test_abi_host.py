@@ -77,9 +77,10 @@ def test_status_strings_and_defaults(L):
 @pytest.mark.parametrize("field,value,msg", [
     ("m", 0, "m must be"), ("ell", 3, "ell must"), ("ell", 513, "ell must"), ("k", 41, "k must"),
     ("t", 41, "t must"), ("n_max", 0, "n_max"), ("sketch_prec", 0, "f64 sketch"), ("delta", 1.5, "delta"),
-    ("hutch_n1", 25, "n1"),
+    ("hutch_n1", 25, "n1"), ("sketch_tile", 3, "sketch_tile"), ("sketch_tile", 2, "wide sketch tile"),
 ])
 def test_invalid_configs_rejected_before_device(L, field, value, msg):
+    expect = L.RID_ENOTSUP if msg == "wide sketch tile" else L.RID_EINVAL
     lib = L.lib()
     cfg = L.rid_config()
     lib.rid_config_default(C.byref(cfg))
@@ -87,7 +88,7 @@ def test_invalid_configs_rejected_before_device(L, field, value, msg):
     setattr(cfg, field, value)
     h = C.c_void_p()
     st = lib.rid_init_stream(C.byref(cfg), None, C.byref(h))
-    assert st == L.RID_EINVAL
+    assert st == expect
     buf = C.create_string_buffer(256)
     lib.rid_last_error(None, buf, 256)
     assert msg in buf.value.decode()

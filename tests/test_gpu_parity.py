@@ -86,24 +86,30 @@ def test_omega_fp8_matches_oracle():
 # ---------------------------------------------------------------------------
 # sketch S = Omega A and ||a_j||^2
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("sketch,m,n,ell,tol", [
-    ("f64", 4096, 64, 40, 1e-12),
-    ("f64", 3001, 33, 71, 1e-12),
-    ("f32", 100_003, 300, 40, 2e-5),
-    ("f32", 70_000, 70, 300, 2e-5),
-    ("bf16", 100_003, 300, 40, 1e-4),
-    ("bf16", 65_536, 600, 300, 1e-4),
+@pytest.mark.parametrize("sketch,m,n,ell,tol,tile", [
+    ("f64", 4096, 64, 40, 1e-12, "auto"),
+    ("f64", 3001, 33, 71, 1e-12, "auto"),
+    ("f32", 100_003, 300, 40, 2e-5, "auto"),
+    ("f32", 70_000, 70, 300, 2e-5, "auto"),
+    ("bf16", 100_003, 300, 40, 1e-4, "auto"),
+    # l = 300: the wide tile (two workgroups per 512 columns) and the narrow one
+    ("bf16", 65_536, 600, 300, 1e-4, "auto"),
+    ("bf16", 65_536, 600, 300, 1e-4, "wide"),
+    # wide tile with 3 and 4 row blocks per workgroup, ragged rows and columns
+    ("bf16", 40_009, 530, 150, 1e-4, "wide"),
+    ("bf16", 33_333, 1030, 200, 1e-4, "wide"),
     # fp8: same e4m3 codes and scales as the oracle; the scaled MFMA rounds
     # inside each 64-term product (~1e-4 of S, see SKETCH_ACCURACY)
-    ("fp8", 100_003, 300, 40, 1e-3),
-    ("fp8", 65_536, 600, 300, 1e-3),
+    ("fp8", 100_003, 300, 40, 1e-3, "auto"),
+    ("fp8", 65_536, 600, 300, 1e-3, "auto"),
 ])
-def test_sketch_matches_oracle(sketch, m, n, ell, tol):
-    log("sketch", sketch, m, n, ell)
+def test_sketch_matches_oracle(sketch, m, n, ell, tol, tile):
+    log("sketch", sketch, m, n, ell, tile)
     rng = np.random.default_rng(m + n)
     dt = np.float64 if sketch == "f64" else np.float32
     A = rng.standard_normal((n, m)).astype(dt)
-    s = run_gpu(A, ell, k=4, t=4, sketch=sketch, omega_seed=77, select_seed=78, finalize=False, lookahead=256)
+    s = run_gpu(A, ell, k=4, t=4, sketch=sketch, omega_seed=77, select_seed=78, finalize=False, lookahead=256,
+                tile=tile)
     S, q, _ = s.debug_state()
     So, qo = oracle.sketch_columns(A.T, 77, ell, operand=sketch)
     e = rel_fro(S, So)
@@ -112,14 +118,16 @@ def test_sketch_matches_oracle(sketch, m, n, ell, tol):
     assert np.max(np.abs(q - qo) / qo) <= 1e-13
 
 
-@pytest.mark.parametrize("sketch,ell", [("f32", 64), ("bf16", 64), ("bf16", 300), ("fp8", 300)])
-def test_sketch_is_independent_of_batching(sketch, ell):
-    log("batching independence", sketch, ell)
+@pytest.mark.parametrize("sketch,ell,tile", [("f32", 64, "auto"), ("bf16", 64, "auto"), ("bf16", 300, "auto"),
+                                             ("bf16", 300, "wide"), ("fp8", 300, "auto")])
+def test_sketch_is_independent_of_batching(sketch, ell, tile):
+    log("batching independence", sketch, ell, tile)
     rng = np.random.default_rng(5)
     A = rng.standard_normal((200, 50_001)).astype(np.float32)
-    ref = run_gpu(A, ell, 8, 8, sketch, 3, 4, finalize=False, lookahead=256).debug_state()
+    ref = run_gpu(A, ell, 8, 8, sketch, 3, 4, finalize=False, lookahead=256, tile=tile).debug_state()
     for batch, la in [(1, 0), (7, 100), (64, 64)]:
-        got = run_gpu(A, ell, 8, 8, sketch, 3, 4, batch=batch, finalize=False, lookahead=la).debug_state()
+        got = run_gpu(A, ell, 8, 8, sketch, 3, 4, batch=batch, finalize=False, lookahead=la,
+                      tile=tile).debug_state()
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
