@@ -128,7 +128,7 @@ def cpu_baseline(wl, seeds, operand, rows=1 << 19, cols=None):
                       f"{operand} operands, binary64 sums) in {dt:.1f} s on {threads} BLAS threads"}
 
 
-def batched_bench(steps, warmup, n=1000, push=100):
+def batched_bench(steps, warmup, n=1000, push=100, tile="auto"):
     """64 image streams of uneven m (log-uniform in [1e4, 1e6]), l = 200,
     k = t = 100, bf16 sketch, lookahead 4 t, pushed 100 frames per round as
     one batch (persistent sketch launch, batched updates, one graph per
@@ -143,7 +143,8 @@ def batched_bench(steps, warmup, n=1000, push=100):
     X = [synth.blobs_torch(h, w, n, synth.data_seed(4) + 31 * i) for i, (h, w) in enumerate(shapes)]
     torch.cuda.synchronize()
     cfgs = [StreamConfig(m=m, ell=200, k=100, t=100, n_max=n, dtype=torch.float32, sketch="bf16",
-                         omega_seed=1004 + i, select_seed=2004 + i, lookahead=400) for i, m in enumerate(ms)]
+                         omega_seed=1004 + i, select_seed=2004 + i, lookahead=400, tile=tile)
+            for i, m in enumerate(ms)]
     B = StreamBatch(cfgs)
 
     def step():
@@ -163,6 +164,7 @@ def batched_bench(steps, warmup, n=1000, push=100):
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1000.0 / steps
     info = B.info()
+    tune_table = B.tune_table()
     # one more pass with every launch timed by events (direct launches)
     B.profile_enable(True)
     step()
@@ -183,6 +185,7 @@ def batched_bench(steps, warmup, n=1000, push=100):
         "graph_launches": info["graph_launches"], "graph_instantiations": info["graph_instantiations"],
         "graph_updates": info["graph_updates"], "slab_rows": info["slab_rows"],
         "tile": "wide" if info["wide"] else "narrow", "tune_ms": round(info["tune_ms"], 2),
+        "tune_table_ms": tune_table,
         "timed_pass_ms": {k: round(prof[k], 3) for k in ("sketch_ms", "reduce_ms", "update_ms", "gram_ms")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -209,6 +212,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched image-stream measurement")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched image-stream measurement (prints its JSON object)")
+    ap.add_argument("--batch-tile", default="auto", choices=["auto", "narrow", "wide"],
+                    help="bf16 work split of the batched streams (auto: the tuner picks)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: the stream is row-sharded across GPUs only in the design "
@@ -223,7 +228,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     if args.batch_only:
-        print(json.dumps(batched_bench(args.steps, args.warmup)), flush=True)
+        print(json.dumps(batched_bench(args.steps, args.warmup, tile=args.batch_tile)), flush=True)
         return
     wl = workload(args.small)
     seeds = (1003, 2003)
@@ -291,7 +296,7 @@ def main():
     del D
     torch.cuda.empty_cache()
     if not args.no_batch and not args.small:
-        line["batched"] = batched_bench(max(1, min(3, args.steps)), 1)
+        line["batched"] = batched_bench(max(1, min(3, args.steps)), 1, tile=args.batch_tile)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(wl, seeds, args.sketch)

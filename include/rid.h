@@ -293,8 +293,9 @@ rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64
  * members with an update due.  The launches of a round are captured into one
  * HIP graph, updated in place from round to round.  The row slab of the
  * sketch (the tile height) is chosen by timing the candidates on the first
- * round's columns, once per batch shape in the process; for bf16 members
- * the tuner also times both work splits of rid_sketch_tile.
+ * round's columns (sketch and reduction), once per batch shape in the
+ * process; for bf16 members whose lookahead fills two 512-column tiles the
+ * tuner also times both work splits of rid_sketch_tile.
  *
  * A member's results are bitwise independent of the other members.  They
  * equal those of a stand-alone stream with the same slab: the slab fixes the
@@ -315,7 +316,7 @@ typedef struct rid_batch_info {
   int64_t graph_updates;         /* rounds that updated the executable in place */
   int64_t slab_rows;             /* sketch rows per work item (tuned or default) */
   int32_t tuned;                 /* 1 once the slab has been chosen by timing */
-  int32_t wide;                  /* 1 when bf16 members use RID_TILE_WIDE */
+  int32_t wide;                  /* 1 when some member uses RID_TILE_WIDE */
   double tune_ms;                /* device time spent timing candidates */
 } rid_batch_info;
 
@@ -356,6 +357,12 @@ rid_status rid_batch_stream(rid_batch* bt, int32_t i, rid_stream** out);
 
 /* Counters of the batch (synchronises its internal stream). */
 rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info);
+
+/* Candidate i (0-based, in the order timed) of the slab tuner: its slab
+ * rows, work split (1 = RID_TILE_WIDE) and median time of the round's
+ * persistent sketch in ms.  RID_EINVAL past the last candidate (none when
+ * the shape was tuned earlier in the process or RID_BATCH_NO_TUNE is set). */
+rid_status rid_batch_tune_result(rid_batch* bt, int32_t i, int64_t* slab_rows, int32_t* wide, double* ms);
 
 /* Message of the batch's last error (or of the last failed creation when bt
  * is NULL). */

@@ -95,6 +95,8 @@ SIGNATURES = {
     "rid_batch_stream": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "rid_batch_get_info": (C.c_int, [C.c_void_p, C.POINTER(rid_batch_info)]),
     "rid_batch_last_error": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
+    "rid_batch_tune_result": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double)]),
     "rid_destroy_batch": (C.c_int, [C.c_void_p]),
     "rid_batch_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "rid_batch_profile_read": (C.c_int, [C.c_void_p, C.POINTER(rid_profile)]),

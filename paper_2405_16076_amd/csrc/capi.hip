@@ -98,7 +98,7 @@ struct rid_stream {
   std::vector<void*> allocs;
   std::vector<size_t> alloc_bytes;
   size_t dev_bytes = 0;
-  double *S = nullptr, *colsq = nullptr, *W = nullptr, *hv = nullptr;
+  double *S = nullptr, *colsq = nullptr, *W = nullptr, *hv = nullptr, *Qs = nullptr, *Ys = nullptr;
   double* SST[2] = {nullptr, nullptr};  // SS^T after the last enqueued update (ping-pong)
   int sst_cur = 0;
   int nzmax = 0;                        // updates per batch (slots of W and hv)
@@ -107,6 +107,7 @@ struct rid_stream {
   double *tauC = nullptr, *tauD = nullptr, *tau_old = nullptr, *tauC_hist = nullptr,
          *tauD_hist = nullptr;
   double *G = nullptr, *gpart = nullptr, *QR = nullptr, *qr_tau = nullptr, *P = nullptr;
+  double *Qm = nullptr, *Mm = nullptr;
   double *Y = nullptr, *PPt = nullptr, *hw = nullptr;
   int64_t *J = nullptr, *J_hist = nullptr;
   uint64_t* colptr_dev = nullptr;
@@ -377,6 +378,8 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     ALLOC(h->SST[1], ell * ell);
     ALLOC(h->W, ell * ell * h->nzmax);
     ALLOC(h->hv, 6 * ell * h->nzmax);
+    ALLOC(h->Qs, ell * ell * h->nzmax);
+    ALLOC(h->Ys, ell * 2 * t * h->nzmax);
     ALLOC(h->Fu, (size_t)h->max_updates);
     ALLOC(h->skipu, (size_t)h->max_updates);
     ALLOC(h->tauC, (size_t)kMaxT);
@@ -391,6 +394,8 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     ALLOC(h->QR, ell * t);
     ALLOC(h->qr_tau, (size_t)kMaxT);
     ALLOC(h->P, t * h->n_max);
+    ALLOC(h->Qm, ell * t);
+    ALLOC(h->Mm, t * ell);
     ALLOC(h->Y, ell * t);
     ALLOC(h->PPt, t * t);
     ALLOC(h->hw, hutch_work_doubles());
@@ -558,6 +563,8 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
     a.colsq = h->colsq;
     a.W = h->W + (size_t)z * h->ell * h->ell;
     a.hv = h->hv + (size_t)z * 6 * h->ell;
+    a.Qs = h->Qs + (size_t)z * h->ell * h->ell;
+    a.Ys = h->Ys + (size_t)z * h->ell * 2 * h->t;
     a.Fu = h->Fu;
     a.skipu = h->skipu;
     a.J = h->J;
@@ -576,6 +583,8 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
     a.QR = h->QR;
     a.qr_tau = h->qr_tau;
     a.P = h->P;
+    a.Qm = h->Qm;
+    a.Mm = h->Mm;
     a.Y = h->Y;
     a.PPt = h->PPt;
     a.hw = h->hw;
@@ -1004,6 +1013,12 @@ struct rid_batch {
   int64_t slab_rows = 0, min_slab_rows = 0;
   int wide = 0;  // bf16 members: the wide work split
   bool tuned = false;
+  struct Cand {
+    int64_t rows;
+    int wide;
+    double ms;
+  };
+  std::vector<Cand> tune_table;  // the timed candidates of the tuner
   double tune_ms = 0.0;
   int n_cu = 0;
   bool failed = false;
@@ -1058,7 +1073,7 @@ static std::vector<int64_t> slab_candidates(int prec) {
   const int64_t cap = (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) ? 65536
                       : (prec == RID_SKETCH_F32 ? 32768 : 16384);
   std::vector<int64_t> v;
-  for (int64_t r = 4096; r <= cap; r *= 2) v.push_back(r);
+  for (int64_t r = 2048; r <= cap; r *= 2) v.push_back(r);
   return v;
 }
 
@@ -1168,9 +1183,10 @@ static rid_status batch_exec(rid_batch* bt, const std::vector<BLaunch>& L) {
   return RID_OK;
 }
 
-// Picks the sketch slab of the batch by timing each candidate on the columns
-// `args` (outside any graph); every candidate writes the same partial buffers,
-// which the real sketch of the round overwrites afterwards.
+// Picks the sketch slab of the batch by timing each candidate (sketch and
+// reduction) on the columns of the first round (outside any graph); every
+// candidate writes the same partial buffers, sketch columns and norms, which
+// the real round overwrites afterwards.
 static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const std::vector<int64_t>& c0,
                              const std::vector<int>& b) {
   static std::vector<std::pair<std::string, int64_t>> cache;
@@ -1198,7 +1214,10 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
   int64_t best_rows = bt->slab_rows;
   int best_wide = 0;
   bool any_wide = false;
-  for (rid_stream* h : bt->st) any_wide = any_wide || (wide_applies(h) && h->cfg.sketch_tile == RID_TILE_AUTO);
+  // the wide split pads a round to 512-column tiles: a candidate only when
+  // every lookahead batch fills at least two of them
+  for (rid_stream* h : bt->st)
+    any_wide = any_wide || (wide_applies(h) && h->cfg.sketch_tile == RID_TILE_AUTO && h->b_max >= 1024);
   // members that asked for a split keep it; the others take the candidate's
   auto apply_tile = [](rid_stream* h, int wide) {
     set_tile(h, h->cfg.sketch_tile == RID_TILE_WIDE || (h->cfg.sketch_tile == RID_TILE_AUTO && wide));
@@ -1223,7 +1242,7 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
       rid_status sts = take_slot(bt, stg);
       if (sts != RID_OK) return sts;
       std::vector<BLaunch> L;
-      plan_sketches(bt, args, precs, stg, L, false);
+      plan_sketches(bt, args, precs, stg, L, true);  // the reduction grows with the slab count
       if ((sts = copy_slot(bt, stg)) != RID_OK) return sts;
       BT_HIP(bt, hipEventRecord(e0, bt->s));
       BT_HIP(bt, run_launches(L, bt->s));
@@ -1233,6 +1252,7 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
     }
     std::sort(ms_rep + 1, ms_rep + 4);
     const float ms_last = ms_rep[2];
+    bt->tune_table.push_back(rid_batch::Cand{rows, wide, ms_last});
     bt->tune_ms += ms_last;
     if (ms_last < best) {
       best = ms_last;
@@ -1537,8 +1557,18 @@ rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info) {
   info->graph_updates = bt->graph_updates;
   info->slab_rows = bt->slab_rows;
   info->tuned = bt->tuned ? 1 : 0;
-  info->wide = bt->wide;
+  info->wide = 0;
+  for (rid_stream* h : bt->st) info->wide |= h->wide;
   info->tune_ms = bt->tune_ms;
+  return RID_OK;
+}
+
+rid_status rid_batch_tune_result(rid_batch* bt, int32_t i, int64_t* slab_rows, int32_t* wide, double* ms) {
+  if (!bt || !slab_rows || !wide || !ms) return fail(nullptr, RID_EINVAL, "null argument");
+  if (i < 0 || i >= (int32_t)bt->tune_table.size()) return RID_EINVAL;
+  *slab_rows = bt->tune_table[i].rows;
+  *wide = bt->tune_table[i].wide;
+  *ms = bt->tune_table[i].ms;
   return RID_OK;
 }
 

@@ -281,6 +281,8 @@ struct UpdArgs {
   double* colsq;
   double* W;           // this update's l x l slot: reflectors below the subdiagonal
   double* hv;          // this update's slot: tau (l), d (l), e (l), Dinv (l), L (l), top eigenvalues (l)
+  double* Qs;          // this update's slot: l x l orthogonal factor of the tridiagonalisation
+  double* Ys;          // this update's slot: l x (t + cnt) rotated sketch columns of the score items
   double* Fu;          // ||A_obs||^2 per update
   int32_t* skipu;      // 1 when the update skips selection (F == 0)
   int64_t* J;          // t
@@ -299,6 +301,8 @@ struct UpdArgs {
   double* QR;          // l x t
   double* qr_tau;      // t
   double* P;           // t x n_max
+  double* Qm;          // l x t: thin Q of Omega A_J (Alg. 4 as products)
+  double* Mm;          // t x l: R'^{-1} Q^T
   double* Y;           // l x t  (S P^T)
   double* PPt;         // t x t
   double* hw;          // NA-Hutch++ work

@@ -57,27 +57,104 @@ __device__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
+// Dense binary64 products on the matrix cores (v_mfma_f64_16x16x4f64: A lane
+// l holds A(l % 16, l / 16), B lane l holds B(l / 16, l % 16), D lane l
+// element v is D(l / 16 + 4 v, l % 16)).  One 32 x 32 tile of C per block of
+// four waves; wave w takes the k-steps w, w + 4, ... and the four partial
+// tiles are summed in LDS in wave order, so the result does not depend on
+// scheduling.  la(m, k) and lb(k, n) return 0 outside the operands.
+// ---------------------------------------------------------------------------
+typedef double f64x4_m __attribute__((ext_vector_type(4)));
+
+template <typename LA, typename LB>
+__device__ __forceinline__ void gemm32_f64(int m0, int n0, int K, LA la, LB lb, double (&out)[2][2][4],
+                                           double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  f64x4_m acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f64x4_m{0.0, 0.0, 0.0, 0.0};
+  const int nks = (K + 3) / 4;
+#pragma unroll 4
+  for (int ks = wave; ks < nks; ks += 4) {
+    const int k = 4 * ks + k4;
+    double av[2], bv[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) av[x] = la(m0 + 16 * x + i16, k);
+#pragma unroll
+    for (int y = 0; y < 2; ++y) bv[y] = lb(k, n0 + 16 * y + i16);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(((wave * 2 + x) * 2 + y) * 4 + v) * 64 + lane] = acc[x][y][v];
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) s += red[(((w * 2 + x) * 2 + y) * 4 + v) * 64 + lane];
+        out[x][y][v] = s;
+      }
+}
+
+// ---------------------------------------------------------------------------
 // SS^T and F of every update of a batch: slot z receives
 //   SS^T_{u0-1} + sum of s_c s_c^T over the batch columns up to update u0+z,
 // and slot nz (sst_out) the state after the last update.  Also starts each
 // update's record.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sst_batch_body(const BatchArgs& b, const Blk bk) {
-  const int r1 = bk.x * 16 + threadIdx.x;
-  const int r2 = bk.y * 16 + threadIdx.y;
-  const int z = bk.z;
+  __shared__ double red[4 * 16 * 64];
+  const int n = b.ell;
+  const int nt = (n + 31) / 32;
+  // block x: tile (ti, tj), ti <= tj, of the upper triangle; block y: slot z
+  int ti = 0, rem = bk.x;
+  while (ti < nt && rem >= nt - ti) {
+    rem -= nt - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  const int z = bk.y;
   const int zz = min(z, b.nz - 1);
   const int64_t cend = b.c0 + min((int64_t)(zz + 1) * b.t, b.total);
-  if (r1 < b.ell && r2 < b.ell) {
-    double s = b.sst_in[(int64_t)r2 * b.ell + r1];
-    for (int64_t c = b.c0; c < cend; ++c) {
-      const double* col = b.S + c * b.ell;
-      s = fma(col[r1], col[r2], s);
-    }
-    double* dst = (z < b.nz) ? b.W + (int64_t)z * b.ell * b.ell : b.sst_out;
-    dst[(int64_t)r2 * b.ell + r1] = s;
+  const int K = (int)(cend - b.c0);
+  const double* S0 = b.S + b.c0 * n;
+  double out[2][2][4];
+  gemm32_f64(32 * ti, 32 * tj, K, [&](int r, int k) { return (r < n && k < K) ? S0[(int64_t)k * n + r] : 0.0; },
+             [&](int k, int c) { return (k < K && c < n) ? S0[(int64_t)k * n + c] : 0.0; }, out, red);
+  double* dst = (z < b.nz) ? b.W + (int64_t)z * n * n : b.sst_out;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    const int i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 32 * ti + 16 * x + k4 + 4 * v, c = 32 * tj + 16 * y + i16;
+          if (r < n && c < n && r <= c) {  // the upper triangle, mirrored: exactly symmetric
+            const double val = b.sst_in[(int64_t)c * n + r] + out[x][y][v];
+            dst[(int64_t)c * n + r] = val;
+            dst[(int64_t)r * n + c] = val;
+          }
+        }
   }
-  if (z < b.nz && bk.x == 0 && bk.y == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+  if (z < b.nz && bk.x == 0 && threadIdx.x == 0) {
     const int64_t u = b.u0 + z;
     // F of update u0 - 1 was written by an earlier launch
     double F = (b.u0 > 0) ? b.Fu[b.u0 - 1] : 0.0;
@@ -93,9 +170,9 @@ __device__ __forceinline__ void sst_batch_body(const BatchArgs& b, const Blk bk)
   }
 }
 
-__global__ void sst_batch_kernel(BatchArgs b) { sst_batch_body(b, own_block()); }
+__global__ __launch_bounds__(256) void sst_batch_kernel(BatchArgs b) { sst_batch_body(b, own_block()); }
 
-__global__ void sst_batch_kernel_b(Batched<BatchArgs> L) {
+__global__ __launch_bounds__(256) void sst_batch_kernel_b(Batched<BatchArgs> L) {
   const BatchArgs* p;
   Blk bk;
   if (batched_block(L, p, bk)) sst_batch_body(*p, bk);
@@ -356,6 +433,155 @@ __global__ __launch_bounds__(64) void scores_kernel_b(Batched<UpdArgs> L) {
   const UpdArgs* p;
   Blk bk;
   if (batched_block(L, p, bk)) scores_body(*p, bk);
+}
+
+
+// ---------------------------------------------------------------------------
+// The same scores as products: Y = Q^T [s_item] for every item at once, with
+// Q = H_0 ... H_{l-3} the orthogonal factor of the tridiagonalisation formed
+// explicitly (scores_q_kernel: column i of Q is H_0 ... H_{i-1} e_i, one wave
+// per column), the product on the matrix cores (scores_gemm_kernel), then the
+// L D L^T recurrence per item (scores_fin_kernel).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void scores_q_body(const UpdArgs& a, const Blk bk) {
+  constexpr int EM = kMaxEll / 64;
+  const int i = bk.x, n = a.ell, lane = threadIdx.x;
+  if (a.skipu[a.u] || i >= n) return;
+  const double* htau = a.hv;
+  double e[EM];
+#pragma unroll
+  for (int q = 0; q < EM; ++q) e[q] = (lane + 64 * q == i) ? 1.0 : 0.0;
+  // reflector j acts on rows j+1..: v = [1, W[j+2.., j]]
+  auto fetch = [&](int jr, double (&v)[EM]) {
+    const double* vc = a.W + (int64_t)jr * n;
+#pragma unroll
+    for (int q = 0; q < EM; ++q) {
+      const int r = lane + 64 * q;
+      v[q] = (r == jr + 1) ? 1.0 : ((r > jr + 1 && r < n) ? vc[r] : 0.0);
+    }
+  };
+  const int jtop = min(i - 1, n - 3);
+  double v[EM], vn[EM];
+  double tj = 0.0;
+  if (jtop >= 0) {
+    fetch(jtop, v);
+    tj = htau[jtop];
+  }
+  for (int jr = jtop; jr >= 0; --jr) {
+    double tn = 0.0;
+    if (jr > 0) {
+      fetch(jr - 1, vn);
+      tn = htau[jr - 1];
+    }
+    if (tj != 0.0) {
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < EM; ++q) part = fma(v[q], e[q], part);
+      const double g = tj * wave_sum(part);
+#pragma unroll
+      for (int q = 0; q < EM; ++q) e[q] = fma(-g, v[q], e[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < EM; ++q) v[q] = vn[q];
+    tj = tn;
+  }
+  double* qc = a.Qs + (int64_t)i * n;
+#pragma unroll
+  for (int q = 0; q < EM; ++q) {
+    const int r = lane + 64 * q;
+    if (r < n) qc[r] = e[q];
+  }
+}
+
+// sketch column of score item `item` (-1: empty basis slot)
+__device__ __forceinline__ int64_t score_col(const UpdArgs& a, int item) {
+  return (item < a.t) ? a.J[item] : a.c0 + (item - a.t);
+}
+
+__device__ __forceinline__ void scores_gemm_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double red[4 * 16 * 64];
+  __shared__ int64_t cols[32];
+  const int n = a.ell, items = a.t + a.cnt;
+  if (a.skipu[a.u]) return;
+  const int nmt = (n + 31) / 32;
+  const int m0 = 32 * (bk.x % nmt), n0 = 32 * (bk.x / nmt);
+  if (threadIdx.x < 32) cols[threadIdx.x] = (n0 + (int)threadIdx.x < items) ? score_col(a, n0 + threadIdx.x) : -1;
+  __syncthreads();
+  const double* Q = a.Qs;
+  const double* S = a.S;
+  double out[2][2][4];
+  gemm32_f64(m0, n0, n, [&](int m, int k) { return (m < n && k < n) ? Q[(int64_t)m * n + k] : 0.0; },
+             [&](int k, int c) {
+               const int64_t col = cols[c - n0];
+               return (k < n && col >= 0) ? S[col * n + k] : 0.0;
+             },
+             out, red);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    const int i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = m0 + 16 * x + k4 + 4 * v, c = n0 + 16 * y + i16;
+          if (r < n && c < items) a.Ys[(int64_t)c * n + r] = out[x][y][v];
+        }
+  }
+}
+
+__device__ __forceinline__ void scores_fin_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double y[kMaxEll];
+  const int item = bk.x, lane = threadIdx.x, n = a.ell;
+  if (a.skipu[a.u]) return;
+  if (score_col(a, item) < 0) {
+    if (lane == 0) {
+      a.tauC[item] = __longlong_as_double(0x7FF8000000000000LL);
+      a.tauC_hist[a.u * a.t + item] = __longlong_as_double(0x7FF8000000000000LL);
+    }
+    return;
+  }
+  const double* ys = a.Ys + (int64_t)item * n;
+  for (int i = lane; i < n; i += 64) y[i] = ys[i];
+  __syncthreads();
+  if (lane == 0) {
+    const double* Dinv = a.hv + 3 * n;
+    const double* L = a.hv + 4 * n;
+    double z = y[0];
+    double tau = z * z * Dinv[0];
+    for (int i = 1; i < n; ++i) {
+      z = y[i] - L[i - 1] * z;
+      tau = fma(z * z, Dinv[i], tau);
+    }
+    if (item < a.t) {
+      const double tc = fmin(a.tau_old[item], tau);
+      a.tauC[item] = tc;
+      a.tauC_hist[a.u * a.t + item] = tc;
+    } else {
+      a.tauD[item - a.t] = tau;
+      a.tauD_hist[a.u * a.t + (item - a.t)] = tau;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void scores_q_kernel(UpdArgs a) { scores_q_body(a, own_block()); }
+__global__ __launch_bounds__(64) void scores_q_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) scores_q_body(*p, bk);
+}
+__global__ __launch_bounds__(256) void scores_gemm_kernel(UpdArgs a) { scores_gemm_body(a, own_block()); }
+__global__ __launch_bounds__(256) void scores_gemm_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) scores_gemm_body(*p, bk);
+}
+__global__ __launch_bounds__(64) void scores_fin_kernel(UpdArgs a) { scores_fin_body(a, own_block()); }
+__global__ __launch_bounds__(64) void scores_fin_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) scores_fin_body(*p, bk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1081,6 +1307,227 @@ __global__ __launch_bounds__(64) void alg4_apply_kernel_b(Batched<UpdArgs> L) {
   if (batched_block(L, p, bk)) alg4_apply_body(*p, bk);
 }
 
+
+// ---------------------------------------------------------------------------
+// Alg. 4 as products (t <= kAlg4Gemm): P(occupied, :) = R'^{-1} Q^T S, where
+// Q is the thin orthogonal factor of Omega A_J and R' its triangular factor
+// without the columns of negligible pivot (their rows of P are zero, as in
+// alg4_apply_kernel):
+//   alg4_q_kernel    column j of Q = H_0 ... H_j e_j (one wave per column);
+//   alg4_m_kernel    M = R'^{-1} Q^T, one wave per row of Q, column-oriented
+//                    back substitution against R packed in LDS;
+//   alg4_pgemm       P = M S on the matrix cores, scattered to slot order;
+//                    rows of empty slots are zeroed.
+// ---------------------------------------------------------------------------
+constexpr int kAlg4Gemm = 154;  // packed R of up to 154 columns fits in LDS
+
+__device__ __forceinline__ void alg4_q_body(const UpdArgs& a, const Blk bk) {
+  constexpr int EM = kMaxEll / 64;
+  const int j = bk.x, n = a.ell, lane = threadIdx.x;
+  const int no = min(a.sc->n_occ, n);
+  if (j >= no) return;
+  double e[EM];
+#pragma unroll
+  for (int q = 0; q < EM; ++q) e[q] = (lane + 64 * q == j) ? 1.0 : 0.0;
+  // reflector jj - 1 is fetched while reflector jj is applied
+  auto fetch = [&](int jj, double (&v)[EM]) {
+    const double* vc = a.QR + (int64_t)jj * n;
+#pragma unroll
+    for (int q = 0; q < EM; ++q) {
+      const int r = lane + 64 * q;
+      v[q] = (r == jj) ? 1.0 : ((r > jj && r < n) ? vc[r] : 0.0);
+    }
+  };
+  double v[EM], vn[EM];
+  fetch(j, v);
+  double tj = a.qr_tau[j];
+  for (int jj = j; jj >= 0; --jj) {
+    double tn = 0.0;
+    if (jj > 0) {
+      fetch(jj - 1, vn);
+      tn = a.qr_tau[jj - 1];
+    }
+    if (tj != 0.0) {
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < EM; ++q) part = fma(v[q], e[q], part);
+      const double g = tj * wave_sum(part);
+#pragma unroll
+      for (int q = 0; q < EM; ++q) e[q] = fma(-g, v[q], e[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < EM; ++q) v[q] = vn[q];
+    tj = tn;
+  }
+#pragma unroll
+  for (int q = 0; q < EM; ++q) {
+    const int r = lane + 64 * q;
+    if (r < n) a.Qm[(int64_t)j * n + r] = e[q];
+  }
+}
+
+__device__ __forceinline__ void alg4_m_body(const UpdArgs& a, const Blk bk) {
+  constexpr int EY = (kAlg4Gemm + 63) / 64;
+  __shared__ double rp[kAlg4Gemm * (kAlg4Gemm + 1) / 2];
+  const int n = a.ell, t = a.t;
+  const int no = min(a.sc->n_occ, n);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // R packed by columns: column k at k (k + 1) / 2, rows 0..k
+  const int np = no * (no + 1) / 2;
+  for (int idx = tid; idx < np; idx += 256) {
+    int k = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while (k * (k + 1) / 2 > idx) --k;
+    while ((k + 1) * (k + 2) / 2 <= idx) ++k;
+    const int i = idx - k * (k + 1) / 2;
+    rp[idx] = a.QR[(int64_t)k * n + i];
+  }
+  __syncthreads();
+  double rmax = 0.0;
+  for (int i = lane; i < no; i += 64) rmax = fmax(rmax, fabs(rp[i * (i + 1) / 2 + i]));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, off));
+  const double tol = (double)max(n, a.sc->n_occ) * 2.220446049250313e-16 * rmax;
+  const int r = bk.x * 4 + wave;  // row of Q = column of M
+  if (r >= n) return;
+  double y[EY];
+#pragma unroll
+  for (int q = 0; q < EY; ++q) {
+    const int i = lane + 64 * q;
+    y[q] = (i < no) ? a.Qm[(int64_t)i * n + r] : 0.0;
+  }
+  double* mcol = a.Mm + (int64_t)r * t;
+  for (int i = no - 1; i >= 0; --i) {
+    const int qi = i >> 6;
+    double yq = y[0];
+#pragma unroll
+    for (int q = 1; q < EY; ++q)
+      if (q == qi) yq = y[q];
+    const double yi = readlane_f64(yq, i & 63);
+    const int ci = i * (i + 1) / 2;
+    const double rii = rp[ci + i];
+    const double xi = (fabs(rii) > tol) ? yi / rii : 0.0;
+#pragma unroll
+    for (int q = 0; q < EY; ++q) {
+      const int k = lane + 64 * q;
+      if (k < i) y[q] = fma(-xi, rp[ci + k], y[q]);
+    }
+    if (lane == 0) mcol[i] = xi;
+  }
+}
+
+__device__ __forceinline__ void alg4_pgemm_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double red[4 * 16 * 64];
+  __shared__ int occ[kMaxT];
+  const int n = a.ell, t = a.t;
+  const int no = min(a.sc->n_occ, n);
+  const int nmt = (t + 31) / 32;
+  const int mt = bk.x % nmt, ct = bk.x / nmt;
+  const int m0 = 32 * mt, n0 = 32 * ct;
+  const int64_t nobs = a.n_obs;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (mt == 0) {
+    // rows of empty slots are zero
+    for (int sl = tid; sl < t; sl += 256) occ[sl] = 0;
+    __syncthreads();
+    for (int i = tid; i < no; i += 256) occ[a.sc->occ_slot[i]] = 1;
+    __syncthreads();
+    for (int idx = tid; idx < 32 * t; idx += 256) {
+      const int sl = idx % t, c = n0 + idx / t;
+      if (!occ[sl] && c < nobs) a.P[(int64_t)c * t + sl] = 0.0;
+    }
+  }
+  if (m0 >= no) return;
+  const double* M = a.Mm;
+  const double* S = a.S;
+  double out[2][2][4];
+  gemm32_f64(m0, n0, n,
+             [&](int m, int k) { return (m < no && k < n) ? M[(int64_t)k * t + m] : 0.0; },
+             [&](int k, int c) { return (k < n && c < nobs) ? S[(int64_t)c * n + k] : 0.0; }, out, red);
+  if (wave == 0) {
+    const int i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = m0 + 16 * x + k4 + 4 * v, c = n0 + 16 * y + i16;
+          if (m < no && c < nobs) a.P[(int64_t)c * t + a.sc->occ_slot[m]] = out[x][y][v];
+        }
+  }
+}
+
+// Y = S P^T (l x t) and P P^T (t x t) on the matrix cores: blocks [0, tY)
+// take the tiles of Y, the rest those of P P^T.
+__device__ __forceinline__ void hutch_gemm_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double red[4 * 16 * 64];
+  const int n = a.ell, t = a.t;
+  const int64_t nobs = a.n_obs;
+  const int K = (int)nobs;
+  const int tyM = (n + 31) / 32, tyN = (t + 31) / 32;
+  const int tY = tyM * tyN;
+  const double* S = a.S;
+  const double* P = a.P;
+  double out[2][2][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  if (bk.x < tY) {
+    const int m0 = 32 * (bk.x % tyM), n0 = 32 * (bk.x / tyM);
+    gemm32_f64(m0, n0, K, [&](int r, int c) { return (r < n && c < K) ? S[(int64_t)c * n + r] : 0.0; },
+               [&](int c, int j) { return (c < K && j < t) ? P[(int64_t)c * t + j] : 0.0; }, out, red);
+    if (wave == 0)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = m0 + 16 * x + k4 + 4 * v, j = n0 + 16 * y + i16;
+            if (r < n && j < t) a.Y[(int64_t)j * n + r] = out[x][y][v];
+          }
+  } else {
+    const int b = bk.x - tY;
+    const int m0 = 32 * (b % tyN), n0 = 32 * (b / tyN);
+    gemm32_f64(m0, n0, K, [&](int i, int c) { return (i < t && c < K) ? P[(int64_t)c * t + i] : 0.0; },
+               [&](int c, int j) { return (c < K && j < t) ? P[(int64_t)c * t + j] : 0.0; }, out, red);
+    if (wave == 0)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = m0 + 16 * x + k4 + 4 * v, j = n0 + 16 * y + i16;
+            if (i < t && j < t) a.PPt[(int64_t)j * t + i] = out[x][y][v];
+          }
+  }
+}
+
+__global__ __launch_bounds__(64) void alg4_q_kernel(UpdArgs a) { alg4_q_body(a, own_block()); }
+__global__ __launch_bounds__(64) void alg4_q_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) alg4_q_body(*p, bk);
+}
+__global__ __launch_bounds__(256) void alg4_m_kernel(UpdArgs a) { alg4_m_body(a, own_block()); }
+__global__ __launch_bounds__(256) void alg4_m_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) alg4_m_body(*p, bk);
+}
+__global__ __launch_bounds__(256) void alg4_pgemm_kernel(UpdArgs a) { alg4_pgemm_body(a, own_block()); }
+__global__ __launch_bounds__(256) void alg4_pgemm_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) alg4_pgemm_body(*p, bk);
+}
+__global__ __launch_bounds__(256) void hutch_gemm_kernel(UpdArgs a) { hutch_gemm_body(a, own_block()); }
+__global__ __launch_bounds__(256) void hutch_gemm_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) hutch_gemm_body(*p, bk);
+}
+
 // ---------------------------------------------------------------------------
 // NA-Hutch++ (Alg. 8).  Large products first: Y = S P^T (l x t) and
 // PPt = P P^T (t x t), one thread per entry.
@@ -1657,15 +2104,18 @@ __global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel_b(Batched<UpdA
 // ---------------------------------------------------------------------------
 // SS^T, F and the ridge of every update of a batch (Alg. 3 steps 11, 13, 17-18)
 hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
-  dim3 grid((b.ell + 15) / 16, (b.ell + 15) / 16, b.nz + 1);
-  hipLaunchKernelGGL(sst_batch_kernel, grid, dim3(16, 16), 0, s, b);
+  const int nt = (b.ell + 31) / 32;
+  hipLaunchKernelGGL(sst_batch_kernel, dim3(nt * (nt + 1) / 2, b.nz + 1), dim3(256), 0, s, b);
   hipLaunchKernelGGL(tridiag_kernel, dim3(b.nz), dim3(1024), 0, s, b);
   return hipGetLastError();
 }
 
 // scores and selection (Alg. 3 steps 17-27)
 hipError_t launch_update_select(const UpdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(scores_kernel, dim3(a.t + a.cnt), dim3(64), 0, s, a);
+  const int items = a.t + a.cnt;
+  hipLaunchKernelGGL(scores_q_kernel, dim3(a.ell), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(scores_gemm_kernel, dim3(((a.ell + 31) / 32) * ((items + 31) / 32)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(scores_fin_kernel, dim3(items), dim3(64), 0, s, a);
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
@@ -1707,10 +2157,17 @@ hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((alg4_qr_reg_kernel<5, 19, 8>), dim3(1), dim3(512), 0, s, a);
   else
     hipLaunchKernelGGL(alg4_qr_kernel, dim3(1), dim3(1024), 0, s, a);
-  hipLaunchKernelGGL(alg4_apply_kernel, dim3((unsigned)a.n_obs), dim3(64), 0, s, a);
+  if (a.t <= kAlg4Gemm) {
+    hipLaunchKernelGGL(alg4_q_kernel, dim3(a.t), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(alg4_m_kernel, dim3((a.ell + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(alg4_pgemm_kernel, dim3((unsigned)(((a.t + 31) / 32) * ((a.n_obs + 31) / 32))), dim3(256),
+                       0, s, a);
+  } else {
+    hipLaunchKernelGGL(alg4_apply_kernel, dim3((unsigned)a.n_obs), dim3(64), 0, s, a);
+  }
   {
-    const int64_t tot = (int64_t)(a.ell + a.t) * a.t;
-    hipLaunchKernelGGL(hutch_prod_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+    const int tiles = ((a.ell + 31) / 32) * ((a.t + 31) / 32) + ((a.t + 31) / 32) * ((a.t + 31) / 32);
+    hipLaunchKernelGGL(hutch_gemm_kernel, dim3(tiles), dim3(256), 0, s, a);
   }
   {
     const int n3 = a.ell - a.n1 - a.n2;
@@ -1796,16 +2253,25 @@ const void* fn(K k) {
 
 void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
   Planner<BatchArgs> P;
-  for (int i = 0; i < ns; ++i)
-    P.add(fn(sst_batch_kernel_b), h[i], make_int4((h[i].ell + 15) / 16, (h[i].ell + 15) / 16, h[i].nz + 1, 0));
-  P.emit(dim3(16, 16), -1, st, out);
+  for (int i = 0; i < ns; ++i) {
+    const int nt = (h[i].ell + 31) / 32;
+    P.add(fn(sst_batch_kernel_b), h[i], make_int4(nt * (nt + 1) / 2, h[i].nz + 1, 1, 0));
+  }
+  P.emit(dim3(256), -1, st, out);
   for (int i = 0; i < ns; ++i) P.add(fn(tridiag_kernel_b), h[i], make_int4(h[i].nz, 1, 1, 0));
   P.emit(dim3(1024), -1, st, out);
 }
 
 void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
   Planner<UpdArgs> P;
-  for (int i = 0; i < ns; ++i) P.add(fn(scores_kernel_b), h[i], make_int4(h[i].t + h[i].cnt, 1, 1, 0));
+  for (int i = 0; i < ns; ++i) P.add(fn(scores_q_kernel_b), h[i], make_int4(h[i].ell, 1, 1, 0));
+  P.emit(dim3(64), -1, st, out);
+  for (int i = 0; i < ns; ++i) {
+    const int items = h[i].t + h[i].cnt;
+    P.add(fn(scores_gemm_kernel_b), h[i], make_int4(((h[i].ell + 31) / 32) * ((items + 31) / 32), 1, 1, 0));
+  }
+  P.emit(dim3(256), -1, st, out);
+  for (int i = 0; i < ns; ++i) P.add(fn(scores_fin_kernel_b), h[i], make_int4(h[i].t + h[i].cnt, 1, 1, 0));
   P.emit(dim3(64), -1, st, out);
   for (int i = 0; i < ns; ++i) P.add(fn(select_kernel_b), h[i], make_int4(1, 1, 1, 0));
   P.emit(dim3(64), -1, st, out);
@@ -1859,11 +2325,23 @@ void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunc
     Pl2.emit(dim3(1024), -1, st, out);
   }
   Planner<UpdArgs> P;
-  for (int i = 0; i < ns; ++i) P.add(fn(alg4_apply_kernel_b), h[i], make_int4((int)h[i].n_obs, 1, 1, 0));
+  for (int i = 0; i < ns; ++i)
+    if (h[i].t <= kAlg4Gemm) P.add(fn(alg4_q_kernel_b), h[i], make_int4(h[i].t, 1, 1, 0));
+  P.emit(dim3(64), -1, st, out);
+  for (int i = 0; i < ns; ++i)
+    if (h[i].t <= kAlg4Gemm) P.add(fn(alg4_m_kernel_b), h[i], make_int4((h[i].ell + 3) / 4, 1, 1, 0));
+  P.emit(dim3(256), -1, st, out);
+  for (int i = 0; i < ns; ++i)
+    if (h[i].t <= kAlg4Gemm)
+      P.add(fn(alg4_pgemm_kernel_b), h[i],
+            make_int4((int)(((h[i].t + 31) / 32) * ((h[i].n_obs + 31) / 32)), 1, 1, 0));
+  P.emit(dim3(256), -1, st, out);
+  for (int i = 0; i < ns; ++i)
+    if (h[i].t > kAlg4Gemm) P.add(fn(alg4_apply_kernel_b), h[i], make_int4((int)h[i].n_obs, 1, 1, 0));
   P.emit(dim3(64), -1, st, out);
   for (int i = 0; i < ns; ++i) {
-    const int64_t tot = (int64_t)(h[i].ell + h[i].t) * h[i].t;
-    P.add(fn(hutch_prod_kernel_b), h[i], make_int4((int)((tot + 255) / 256), 1, 1, 0));
+    const int tiles = ((h[i].ell + 31) / 32) * ((h[i].t + 31) / 32) + ((h[i].t + 31) / 32) * ((h[i].t + 31) / 32);
+    P.add(fn(hutch_gemm_kernel_b), h[i], make_int4(tiles, 1, 1, 0));
   }
   P.emit(dim3(256), -1, st, out);
   for (int stage = 0; stage < 3; ++stage) {

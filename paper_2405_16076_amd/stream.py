@@ -269,6 +269,14 @@ class StreamBatch:
         d["rounds"] = d.pop("updates")
         return d
 
+    def tune_table(self):
+        """[(slab_rows, tile, ms)] of the candidates the slab tuner timed."""
+        out = []
+        rows, wide, ms = C.c_int64(), C.c_int32(), C.c_double()
+        while L.lib().rid_batch_tune_result(self._b, len(out), C.byref(rows), C.byref(wide), C.byref(ms)) == L.RID_OK:
+            out.append((rows.value, "wide" if wide.value else "narrow", round(ms.value, 3)))
+        return out
+
     def info(self):
         i = L.rid_batch_info()
         self._check(L.lib().rid_batch_get_info(self._b, C.byref(i)))

@@ -102,7 +102,7 @@ def test_batch_members_match_oracle(sketch, data):
     B = _run_batch(sketch, data, lookahead=64)
     info = B.info()
     log(f"  info {info}")
-    assert info["tuned"] == 1 and info["slab_rows"] in (4096, 8192, 16384, 32768, 65536)
+    assert info["tuned"] == 1 and info["slab_rows"] in (2048, 4096, 8192, 16384, 32768, 65536)
     assert info["graph_launches"] == info["rounds"] and info["graph_updates"] >= 1
     for i, (h, w, ell, t, n, _) in enumerate(MEMBERS):
         wt, mg, e, er = _check_member(B.members[i], data[i][1], ell, t, sketch, 4000 + i, 5000 + i)
