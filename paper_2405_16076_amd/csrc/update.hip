@@ -221,11 +221,17 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     }
     return;
   }
-  // Householder tridiagonalisation, three barriers per step: wave 0 forms the
-  // reflector of column j (wave sums, no barrier) and publishes v; all waves
-  // form p = tau A22 v (four columns per wave in flight); every wave then
-  // forms K = tau/2 p^T v itself and applies A22 -= v w^T + w v^T with
-  // w = p - K v.
+  // Householder tridiagonalisation on the lower triangle only (the trailing
+  // block A22 is read once per step for p = tau A22 v and its lower triangle
+  // read and written once for A22 -= v w^T + w v^T): wave 0 forms the
+  // reflector of column j (wave sums, no barrier) and publishes v; each wave
+  // walks its columns c of A22, forming the dot of column c with v (p_c) and
+  // adding column c times v_c to its partial of p below the diagonal; the
+  // partials meet in LDS in wave order; every wave then forms K = tau/2 p^T v
+  // and applies the update to its columns with w = p - K v.
+  constexpr int EMT = kMaxEll / 64;
+  __shared__ double ppart[16][kMaxEll];
+  __shared__ double pd[kMaxEll];
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;           // order of the trailing block
     double* x = W + (int64_t)j * n + j + 1;   // column j, rows j+1..n-1
@@ -255,43 +261,63 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     __syncthreads();
     const double tau = red[0];
     if (tau != 0.0) {
-      // p = tau * A22 v (A22 symmetric: its row i is its column i, contiguous)
-      double* A22 = W + (int64_t)(j + 1) * n + (j + 1);
-      for (int i0 = wv; i0 < m; i0 += 4 * nw) {
-        double s4[4];
+      double* A22 = W + (int64_t)(j + 1) * n + (j + 1);  // A22(k, c) = A22[c n + k], k >= c
+      double pp[EMT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + u * nw;
-          s4[u] = 0.0;
-          if (i < m) {
-            const double* col = A22 + (int64_t)i * n;
-            for (int kk = lane; kk < m; kk += 64) s4[u] = fma(col[kk], v[kk], s4[u]);
+      for (int q = 0; q < EMT; ++q) pp[q] = 0.0;
+      double vk[EMT];
+#pragma unroll
+      for (int q = 0; q < EMT; ++q) {
+        const int k = lane + 64 * q;
+        vk[q] = (k < m) ? v[k] : 0.0;
+      }
+#pragma unroll 2
+      for (int c = wv; c < m; c += nw) {
+        const double* col = A22 + (int64_t)c * n;
+        const double vc = v[c];
+        double dot = 0.0;
+#pragma unroll
+        for (int q = 0; q < EMT; ++q) {
+          const int k = lane + 64 * q;
+          if (k >= c && k < m) {
+            const double akc = col[k];
+            dot = fma(akc, vk[q], dot);
+            if (k > c) pp[q] = fma(akc, vc, pp[q]);
           }
         }
+        dot = wave_sum(dot);
+        if (lane == 0) pd[c] = dot;
+      }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double sv = wave_sum(s4[u]);
-          const int i = i0 + u * nw;
-          if (lane == 0 && i < m) p[i] = tau * sv;
-        }
+      for (int q = 0; q < EMT; ++q) {
+        const int k = lane + 64 * q;
+        if (k < m) ppart[wv][k] = pp[q];
+      }
+      __syncthreads();
+      for (int k = tid; k < m; k += nth) {
+        double sacc = pd[k];
+        for (int w = 0; w < nw; ++w) sacc += ppart[w][k];
+        p[k] = tau * sacc;
       }
       __syncthreads();
       double pv = 0.0;
       for (int i = lane; i < m; i += 64) pv = fma(p[i], v[i], pv);
       const double K = 0.5 * tau * wave_sum(pv);
-      // A22 -= v w^T + w v^T, w = p - K v (one wave per column, four in flight)
-      for (int c0 = wv; c0 < m; c0 += 4 * nw) {
+      double wk[EMT];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int col = c0 + u * nw;
-          if (col < m) {
-            double* cp = A22 + (int64_t)col * n;
-            const double vc = v[col], wc = p[col] - K * v[col];
-            for (int row = lane; row < m; row += 64) {
-              const double wr = p[row] - K * v[row];
-              cp[row] = fma(-v[row], wc, fma(-wr, vc, cp[row]));
-            }
-          }
+      for (int q = 0; q < EMT; ++q) {
+        const int k = lane + 64 * q;
+        wk[q] = (k < m) ? p[k] - K * v[k] : 0.0;
+      }
+      // A22 -= v w^T + w v^T on the lower triangle (one wave per column)
+#pragma unroll 2
+      for (int c = wv; c < m; c += nw) {
+        double* cp = A22 + (int64_t)c * n;
+        const double vc = v[c], wc = p[c] - K * v[c];
+#pragma unroll
+        for (int q = 0; q < EMT; ++q) {
+          const int k = lane + 64 * q;
+          if (k >= c && k < m) cp[k] = fma(-vk[q], wc, fma(-wk[q], vc, cp[k]));
         }
       }
     }
@@ -1836,6 +1862,7 @@ __device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk
   __shared__ double vb[2][64 * E];
   __shared__ double tb[2];
   __shared__ double cn[kMaxN1];
+  __shared__ double cref[kMaxN1];
   __shared__ int pos[kMaxN1];
   __shared__ int ipos[kMaxN1];
   __shared__ double rinv[kMaxN1 * kMaxN1];
@@ -1876,36 +1903,35 @@ __device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk
   int rank = 0;
   double r00 = 0.0;
   const int nsteps = min(n1, n2);
-  for (int jj = 0; jj < nsteps; ++jj) {
-    const int buf = jj & 1;
-    // squared norms (rows jj..) of this wave's unchosen K^T vectors (slots
-    // below nsk hold K^T vectors)
-    {
-      constexpr int B = 8;
-      const int nsk = (n1 + NW - 1) / NW;
+  // Squared norms (rows jj..) of the K^T vectors in LDS (cn; -1 once
+  // chosen), downdated after each step by the square of the vector's element
+  // jj; recomputed when the downdate has cancelled below sqrt(eps) of the
+  // norm it started from (cref), as in LAPACK's column-pivoted QR.  Slots
+  // below nsk hold K^T vectors.
+  const int nsk = (n1 + NW - 1) / NW;
+  auto norm_rows = [&](int sl, int from) {
+    double part = 0.0;
 #pragma unroll
-      for (int s0 = 0; s0 < NS; s0 += B) {
-        if (s0 >= nsk) break;
-        double d[B];
+    for (int e = 0; e < E; ++e) {
+      const int r = lane + 64 * e;
+      if (r >= from && r < n2) part = fma(vec[sl][e], vec[sl][e], part);
+    }
+    return wave_sum(part);
+  };
 #pragma unroll
-        for (int i = 0; i < B; ++i) {
-          d[i] = 0.0;
-          if (s0 + i < NS)
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-              const int r = lane + 64 * e;
-              if (r >= jj && r < n2) d[i] = fma(vec[s0 + i][e], vec[s0 + i][e], d[i]);
-            }
-        }
-        wave_sum_n(d);
-        if (lane == 0)
-#pragma unroll
-          for (int i = 0; i < B; ++i) {
-            const int q = wave + NW * (s0 + i);
-            if (s0 + i < NS && q < n1) cn[q] = (ipos[q] < 0) ? d[i] : -1.0;
-          }
+  for (int sl = 0; sl < NS; ++sl) {
+    const int q = wave + NW * sl;
+    if (sl < nsk && q < n1) {
+      const double c0 = norm_rows(sl, 0);
+      if (lane == 0) {
+        cn[q] = c0;
+        cref[q] = c0;
       }
     }
+  }
+  constexpr double kTol3z = 1.4901161193847656e-08;  // sqrt(2^-53 * 2)
+  for (int jj = 0; jj < nsteps; ++jj) {
+    const int buf = jj & 1;
     __syncthreads();
     // pivot: the first unchosen column of largest norm
     int piv = n1;
@@ -1969,6 +1995,7 @@ __device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk
         tb[buf] = tau;
         pos[jj] = piv;
         ipos[piv] = jj;
+        cn[piv] = -1.0;
       }
     }
     __syncthreads();
@@ -2001,6 +2028,31 @@ __device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk
             const double g = tau * d[i];
 #pragma unroll
             for (int e = 0; e < E; ++e) vec[s0 + i][e] = fma(-g, v[e], vec[s0 + i][e]);
+          }
+        }
+      }
+    }
+    // downdate the norms of the unchosen K^T vectors to rows jj+1..
+    {
+      const int ej = jj >> 6, lj = jj & 63;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        const int q = wave + NW * sl;
+        if (sl < nsk && q < n1 && ipos[q] < 0) {
+          double xe = vec[sl][0];
+#pragma unroll
+          for (int e = 1; e < E; ++e)
+            if (e == ej) xe = vec[sl][e];
+          const double xj = readlane_f64(xe, lj);
+          const double nn = cn[q] - xj * xj;
+          if (nn <= kTol3z * cref[q]) {
+            const double c1 = norm_rows(sl, jj + 1);
+            if (lane == 0) {
+              cn[q] = c1;
+              cref[q] = c1;
+            }
+          } else if (lane == 0) {
+            cn[q] = nn;
           }
         }
       }
