@@ -124,23 +124,21 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
     }
   };
 
-  // Gaussian tile: item = (row group g of 8 rows, column pair kp of the chunk);
-  // two Philox calls give the 8 x 2 block, written as packed bf16 pairs.
+  // Gaussian tile: item = (row group g of 8 rows, data row k of the chunk).
   // Row groups at or beyond ell stay zero (written once below).
   const int n_groups = min(MROWS / 8, max(0, (a.ell - row_base + 7) / 8));
-  const int n_items = n_groups * (KC / 2);
+  // Items are single Philox calls (8 rows x 1 data row): with 38 row groups
+  // the 1216 calls of a chunk fall on the four SIMDs as 5, 5, 5, 4 wave-calls
+  // (pairs of calls per item gave 6, 6, 4, 4).
+  const int n_items = n_groups * KC;
   auto gen = [&](int64_t k0, uint16_t* d) {
     for (int it = tid; it < n_items; it += 512) {
-      const int g = it / (KC / 2), kp = it % (KC / 2);
-      uint32_t* dst = reinterpret_cast<uint32_t*>(d + (8 * g) * LDA + 2 * kp);
-      float z0[8], z1[8];
-      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp), (uint32_t)(row_base / 8 + g), z0);
-      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp + 1), (uint32_t)(row_base / 8 + g), z1);
+      const int g = it / KC, k = it % KC;
+      uint16_t* dst = d + (8 * g) * LDA + k;
+      float z[8];
+      omega8_f32(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), z);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const bf16x2 v = {(__bf16)z0[j], (__bf16)z1[j]};
-        dst[j * (LDA / 2)] = __builtin_bit_cast(uint32_t, v);
-      }
+      for (int j = 0; j < 8; ++j) dst[j * LDA] = __builtin_bit_cast(uint16_t, (__bf16)z[j]);
     }
   };
 
