@@ -563,32 +563,25 @@ __device__ __forceinline__ void sketch_fp8_body(const SketchArgs& a, int slab, i
   // copies issued after chunk c (they may still be in flight when c is needed)
   auto later = [&](int c) { return max(0, min(nch - 1, c + 2) - c) * 4; };
 
-  // Omega tile of step q: item = (row group g, four data rows 4 kq..); four
-  // Philox calls give 8 x 4 entries, written as one 32-bit word per row.
+  // Omega tile of step q: item = (row group g, data rows 2 kp, 2 kp + 1): two
+  // Philox calls give 8 x 2 entries, written as one 16-bit word per row.
+  // With 38 row groups the 1216 items of a step fall on the four SIMDs as
+  // 10, 10, 10, 8 wave-calls (items of four calls gave 12, 12, 8, 8).
   // Row groups at or beyond ell stay zero (written once below).
   const int n_groups = min(MROWS / 8, max(0, (a.ell - row_base + 7) / 8));
-  const int n_items = n_groups * 16;
+  const int n_items = n_groups * 32;
   auto gen = [&](int q) {
     const int64_t k0 = r0 + (int64_t)q * 64;
     for (int it = tid; it < n_items; it += 512) {
-      const int g = it >> 4, kq = it & 15;
-      int w[8];
-      {
-        float z0[8], z1[8];
-        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq), (uint32_t)(row_base / 8 + g), z0);
-        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq + 1), (uint32_t)(row_base / 8 + g), z1);
+      const int g = it >> 5, kp = it & 31;
+      float z0[8], z1[8];
+      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp), (uint32_t)(row_base / 8 + g), z0);
+      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp + 1), (uint32_t)(row_base / 8 + g), z1);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) w[j] = __builtin_amdgcn_cvt_pk_fp8_f32(z0[j] * 64.0f, z1[j] * 64.0f, 0, false);
+      for (int j = 0; j < 8; ++j) {
+        const int w = __builtin_amdgcn_cvt_pk_fp8_f32(z0[j] * 64.0f, z1[j] * 64.0f, 0, false);
+        *reinterpret_cast<uint16_t*>(&om[(8 * g + j) * LDO + 2 * kp]) = (uint16_t)w;
       }
-      {
-        float z0[8], z1[8];
-        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq + 2), (uint32_t)(row_base / 8 + g), z0);
-        omega8_f32(a.seed, (uint64_t)(k0 + 4 * kq + 3), (uint32_t)(row_base / 8 + g), z1);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) w[j] = __builtin_amdgcn_cvt_pk_fp8_f32(z0[j] * 64.0f, z1[j] * 64.0f, w[j], true);
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) *reinterpret_cast<int*>(&om[(8 * g + j) * LDO + 4 * kq]) = w[j];
     }
   };
 
