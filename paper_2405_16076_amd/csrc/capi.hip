@@ -130,6 +130,7 @@ struct rid_stream {
     hipEvent_t a, b;
     int kind;        // 0 sketch, 1 reduce, 2 update, 3 gram
     double bytes;
+    hipStream_t on;  // stream the events are recorded on
   };
   bool profiling = false;
   std::vector<Mark> marks;
@@ -139,6 +140,14 @@ struct rid_stream {
   rid_batch* owner = nullptr;
   hipStream_t join = nullptr;
   hipEvent_t join_ev = nullptr;
+  // Alg. 4 and Alg. 8 of update u run on `side` against snapshots of the
+  // selection state (sc_hist[u], Ghist[u], J_hist[u]) while `s` goes on with
+  // the selection of update u + 1; side_ev marks the newest side work.
+  hipStream_t side = nullptr;
+  hipEvent_t side_ev = nullptr;
+  bool side_used = false;
+  DevScalars* sc_hist = nullptr;
+  double* Ghist = nullptr;
 };
 
 static thread_local std::string g_last_err;
@@ -210,6 +219,11 @@ static void free_all(rid_stream* h) {
   h->alloc_bytes.clear();
   if (h->colptr_host) (void)hipHostFree(h->colptr_host);
   h->colptr_host = nullptr;
+  if (h->side) (void)hipStreamSynchronize(h->side);
+  if (h->side_ev) (void)hipEventDestroy(h->side_ev);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  h->side_ev = nullptr;
+  h->side = nullptr;
 }
 
 static bool wide_applies(const rid_stream* h) {
@@ -402,12 +416,20 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     ALLOC(h->colptr_dev, (size_t)h->n_max);
     ALLOC(h->normpart, (size_t)h->n_slabs * h->b_max);
     ALLOC(h->sc, (size_t)1);
+    ALLOC(h->sc_hist, (size_t)h->max_updates);
+    ALLOC(h->Ghist, t * t * h->max_updates);
     ALLOC(h->recs, (size_t)h->max_updates);
     if ((st = dalloc(h, &h->part, (size_t)h->n_slabs * h->b_max * h->ell_pad * psize)) != RID_OK)
       goto fail_alloc;
     if ((st = dalloc(h, &h->cpool, (size_t)h->ldc * t * h->esize)) != RID_OK) goto fail_alloc;
   }
 #undef ALLOC
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->side_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    st = fail(nullptr, RID_EDEVICE, "side stream creation failed");
+    goto fail_alloc;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&h->colptr_host), sizeof(uint64_t) * h->n_max,
                     hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
@@ -455,10 +477,10 @@ static hipEvent_t take_event(rid_stream* h) {
 }
 
 // Starts a timed interval on the handle's stream (no-op unless profiling).
-static int mark_begin(rid_stream* h, int kind, double bytes) {
+static int mark_begin(rid_stream* h, int kind, double bytes, hipStream_t on = nullptr) {
   if (!h->profiling) return -1;
-  rid_stream::Mark mk{take_event(h), take_event(h), kind, bytes};
-  if (!mk.a || !mk.b || hipEventRecord(mk.a, h->s) != hipSuccess) {
+  rid_stream::Mark mk{take_event(h), take_event(h), kind, bytes, on ? on : h->s};
+  if (!mk.a || !mk.b || hipEventRecord(mk.a, mk.on) != hipSuccess) {
     (void)hipGetLastError();
     return -1;
   }
@@ -468,7 +490,17 @@ static int mark_begin(rid_stream* h, int kind, double bytes) {
 
 static void mark_end(rid_stream* h, int idx) {
   if (idx < 0) return;
-  if (hipEventRecord(h->marks[idx].b, h->s) != hipSuccess) (void)hipGetLastError();
+  if (hipEventRecord(h->marks[idx].b, h->marks[idx].on) != hipSuccess) (void)hipGetLastError();
+}
+
+// Work enqueued on the handle's stream after this call also waits for the
+// side stream's work so far.
+static rid_status join_side(rid_stream* h) {
+  if (!h->side_used) return RID_OK;
+  RID_HIP(h, hipEventRecord(h->side_ev, h->side));
+  RID_HIP(h, hipStreamWaitEvent(h->s, h->side_ev, 0));
+  h->side_used = false;
+  return RID_OK;
 }
 static rid_status upload_colptrs(rid_stream* h) {
   if (h->n_uploaded < h->n_pushed) {
@@ -611,9 +643,20 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
     mk = mark_begin(h, 3, (double)a.u);
     RID_HIP(h, launch_update_gram(a, h->s));
     mark_end(h, mk);
-    mk = mark_begin(h, 2, (double)a.u);
-    RID_HIP(h, launch_update_coeff(a, h->s));
+    // Alg. 4 and Alg. 8 of this update on the side stream, against snapshots
+    // of the selection state (the next update's selection rewrites J, G and
+    // the slot lists on the main stream meanwhile)
+    UpdArgs ac = a;
+    ac.sc = h->sc_hist + a.u;
+    ac.G = h->Ghist + (size_t)a.u * h->t * h->t;
+    ac.J = h->J_hist + (size_t)a.u * h->t;
+    RID_HIP(h, launch_update_snapshot(a, ac.sc, ac.G, h->s));
+    RID_HIP(h, hipEventRecord(h->side_ev, h->s));
+    RID_HIP(h, hipStreamWaitEvent(h->side, h->side_ev, 0));
+    mk = mark_begin(h, 2, (double)a.u, h->side);
+    RID_HIP(h, launch_update_coeff(ac, h->side));
     mark_end(h, mk);
+    h->side_used = true;
     h->last_nobs = a.n_obs;
   }
   h->n_updates += nz;
@@ -653,6 +696,8 @@ static rid_status flush_full(rid_stream* h) {
 }
 
 static rid_status sync_check(rid_stream* h) {
+  rid_status st = join_side(h);
+  if (st != RID_OK) return st;
   RID_HIP(h, hipStreamSynchronize(h->s));
   int32_t nf = 0;
   RID_HIP(h, hipMemcpy(&nf, &h->sc->nonfinite, sizeof(nf), hipMemcpyDeviceToHost));
@@ -772,7 +817,9 @@ rid_status rid_reset(rid_stream* h) {
 
 static rid_status reset_stream(rid_stream* h) {
   if (h->failed) return fail(h, RID_ESTATE, "stream failed");
+  RID_HIP(h, hipStreamSynchronize(h->side));
   RID_HIP(h, hipStreamSynchronize(h->s));
+  h->side_used = false;
   const size_t ell = h->ell, t = h->t;
   h->sst_cur = 0;
   RID_HIP(h, hipMemsetAsync(h->SST[0], 0, ell * ell * 8, h->s));
@@ -842,6 +889,8 @@ rid_status rid_reconstruct(rid_stream* h, int64_t j0, int32_t c, void* d_out, in
   if (j0 < 0 || c < 0 || j0 + c > h->last_nobs || ld < h->m)
     return fail(h, RID_EINVAL, "columns outside the covered range or ld < m");
   if (c == 0) return RID_OK;
+  rid_status jst = join_side(h);  // P of the last update comes from the side stream
+  if (jst != RID_OK) return jst;
   dim3 grid((unsigned)((h->m + 255) / 256), (unsigned)((c + 15) / 16));
   if (h->data_f64)
     hipLaunchKernelGGL(reconstruct_kernel<double>, grid, dim3(256), 0, h->s,
@@ -862,7 +911,8 @@ rid_status rid_reconstruct(rid_stream* h, int64_t j0, int32_t c, void* d_out, in
 rid_status rid_get_info(rid_stream* h, rid_info* info) {
   if (!h || !info) return fail(h, RID_EINVAL, "null argument");
   if (!h->failed) {
-    hipError_t e = hipStreamSynchronize(h->s);
+    hipError_t e = hipStreamSynchronize(h->side);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->s);
     if (e != hipSuccess) fail(h, RID_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
   }
   info->n_pushed = h->n_pushed;
@@ -911,6 +961,7 @@ rid_status rid_debug_state(rid_stream* h, double* S, int64_t lds, int64_t cap_co
 
 rid_status rid_profile_enable(rid_stream* h, int32_t on) {
   if (!h) return fail(nullptr, RID_EINVAL, "null handle");
+  RID_HIP(h, hipStreamSynchronize(h->side));
   RID_HIP(h, hipStreamSynchronize(h->s));
   for (auto& mk : h->marks) {
     h->event_pool.push_back(mk.a);
@@ -923,6 +974,7 @@ rid_status rid_profile_enable(rid_stream* h, int32_t on) {
 
 rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
   if (!h || !p) return fail(h, RID_EINVAL, "null argument");
+  RID_HIP(h, hipStreamSynchronize(h->side));
   RID_HIP(h, hipStreamSynchronize(h->s));
   memset(p, 0, sizeof(*p));
   for (auto& mk : h->marks) {
@@ -950,6 +1002,7 @@ rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
 }
 
 static void destroy_stream(rid_stream* h) {
+  if (h->side) (void)hipStreamSynchronize(h->side);
   (void)hipStreamSynchronize(h->s);
   (void)hipGetLastError();
   if (h->join_ev) (void)hipEventDestroy(h->join_ev);
@@ -960,6 +1013,7 @@ static void destroy_stream(rid_stream* h) {
 rid_status rid_destroy(rid_stream* h) {
   if (!h) return RID_EINVAL;
   if (h->owner) return fail(h, RID_ESTATE, "the stream belongs to a batch: use rid_destroy_batch");
+  if (h->side) (void)hipStreamSynchronize(h->side);
   (void)hipStreamSynchronize(h->s);
   (void)hipGetLastError();
   free_all(h);

@@ -427,6 +427,7 @@ hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s);
 hipError_t launch_update_select(const UpdArgs& a, hipStream_t s);
 hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s);
+hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* g_out, hipStream_t s);
 size_t hutch_work_doubles();
 
 }  // namespace rid

@@ -196,6 +196,7 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
   return cnt;
 }
 
+template <int EMT>
 __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   __shared__ double v[kMaxEll];
   __shared__ double p[kMaxEll];
@@ -228,8 +229,10 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   // walks its columns c of A22, forming the dot of column c with v (p_c) and
   // adding column c times v_c to its partial of p below the diagonal; the
   // partials meet in LDS in wave order; every wave then forms K = tau/2 p^T v
-  // and applies the update to its columns with w = p - K v.
-  constexpr int EMT = kMaxEll / 64;
+  // and applies the update to its columns with w = p - K v.  EMT = ceil(l /
+  // 64) elements per lane; the columns of a wave go CB at a time, their
+  // loads issued together (the step is bound by L2 latency and bandwidth).
+  constexpr int CB = EMT <= 5 ? 4 : 2;
   __shared__ double ppart[16][kMaxEll];
   __shared__ double pd[kMaxEll];
   for (int j = 0; j + 2 < n; ++j) {
@@ -271,22 +274,37 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
         const int k = lane + 64 * q;
         vk[q] = (k < m) ? v[k] : 0.0;
       }
-#pragma unroll 2
-      for (int c = wv; c < m; c += nw) {
-        const double* col = A22 + (int64_t)c * n;
-        const double vc = v[c];
-        double dot = 0.0;
+      for (int c0 = wv; c0 < m; c0 += CB * nw) {
+        double a[CB][EMT];
 #pragma unroll
-        for (int q = 0; q < EMT; ++q) {
-          const int k = lane + 64 * q;
-          if (k >= c && k < m) {
-            const double akc = col[k];
-            dot = fma(akc, vk[q], dot);
-            if (k > c) pp[q] = fma(akc, vc, pp[q]);
+        for (int u = 0; u < CB; ++u) {
+          const int c = c0 + u * nw;
+          const double* col = A22 + (int64_t)c * n;
+#pragma unroll
+          for (int q = 0; q < EMT; ++q) {
+            const int k = lane + 64 * q;
+            a[u][q] = (c < m && k >= c && k < m) ? col[k] : 0.0;
           }
         }
-        dot = wave_sum(dot);
-        if (lane == 0) pd[c] = dot;
+        double dot[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const int c = c0 + u * nw;
+          const double vc = (c < m) ? v[c] : 0.0;
+          dot[u] = 0.0;
+#pragma unroll
+          for (int q = 0; q < EMT; ++q) {
+            const int k = lane + 64 * q;
+            dot[u] = fma(a[u][q], vk[q], dot[u]);
+            if (k > c) pp[q] = fma(a[u][q], vc, pp[q]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const double sv = wave_sum(dot[u]);
+          const int c = c0 + u * nw;
+          if (lane == 0 && c < m) pd[c] = sv;
+        }
       }
 #pragma unroll
       for (int q = 0; q < EMT; ++q) {
@@ -310,14 +328,29 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
         wk[q] = (k < m) ? p[k] - K * v[k] : 0.0;
       }
       // A22 -= v w^T + w v^T on the lower triangle (one wave per column)
-#pragma unroll 2
-      for (int c = wv; c < m; c += nw) {
-        double* cp = A22 + (int64_t)c * n;
-        const double vc = v[c], wc = p[c] - K * v[c];
+      for (int c0 = wv; c0 < m; c0 += CB * nw) {
+        double a[CB][EMT];
 #pragma unroll
-        for (int q = 0; q < EMT; ++q) {
-          const int k = lane + 64 * q;
-          if (k >= c && k < m) cp[k] = fma(-vk[q], wc, fma(-wk[q], vc, cp[k]));
+        for (int u = 0; u < CB; ++u) {
+          const int c = c0 + u * nw;
+          const double* col = A22 + (int64_t)c * n;
+#pragma unroll
+          for (int q = 0; q < EMT; ++q) {
+            const int k = lane + 64 * q;
+            a[u][q] = (c < m && k >= c && k < m) ? col[k] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const int c = c0 + u * nw;
+          if (c >= m) continue;
+          double* cp = A22 + (int64_t)c * n;
+          const double vc = v[c], wc = p[c] - K * v[c];
+#pragma unroll
+          for (int q = 0; q < EMT; ++q) {
+            const int k = lane + 64 * q;
+            if (k >= c && k < m) cp[k] = fma(-vk[q], wc, fma(-wk[q], vc, a[u][q]));
+          }
         }
       }
     }
@@ -388,12 +421,14 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   }
 }
 
-__global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) { tridiag_body(b, own_block()); }
+template <int EMT>
+__global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) { tridiag_body<EMT>(b, own_block()); }
 
+template <int EMT>
 __global__ __launch_bounds__(1024) void tridiag_kernel_b(Batched<BatchArgs> L) {
   const BatchArgs* p;
   Blk bk;
-  if (batched_block(L, p, bk)) tridiag_body(*p, bk);
+  if (batched_block(L, p, bk)) tridiag_body<EMT>(*p, bk);
 }
 
 // ---------------------------------------------------------------------------
@@ -2158,7 +2193,16 @@ __global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel_b(Batched<UpdA
 hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
   const int nt = (b.ell + 31) / 32;
   hipLaunchKernelGGL(sst_batch_kernel, dim3(nt * (nt + 1) / 2, b.nz + 1), dim3(256), 0, s, b);
-  hipLaunchKernelGGL(tridiag_kernel, dim3(b.nz), dim3(1024), 0, s, b);
+  switch ((b.ell + 63) / 64) {
+    case 1: hipLaunchKernelGGL(tridiag_kernel<1>, dim3(b.nz), dim3(1024), 0, s, b); break;
+    case 2: hipLaunchKernelGGL(tridiag_kernel<2>, dim3(b.nz), dim3(1024), 0, s, b); break;
+    case 3: hipLaunchKernelGGL(tridiag_kernel<3>, dim3(b.nz), dim3(1024), 0, s, b); break;
+    case 4: hipLaunchKernelGGL(tridiag_kernel<4>, dim3(b.nz), dim3(1024), 0, s, b); break;
+    case 5: hipLaunchKernelGGL(tridiag_kernel<5>, dim3(b.nz), dim3(1024), 0, s, b); break;
+    case 6: hipLaunchKernelGGL(tridiag_kernel<6>, dim3(b.nz), dim3(1024), 0, s, b); break;
+    case 7: hipLaunchKernelGGL(tridiag_kernel<7>, dim3(b.nz), dim3(1024), 0, s, b); break;
+    default: hipLaunchKernelGGL(tridiag_kernel<8>, dim3(b.nz), dim3(1024), 0, s, b); break;
+  }
   return hipGetLastError();
 }
 
@@ -2310,7 +2354,20 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
     P.add(fn(sst_batch_kernel_b), h[i], make_int4(nt * (nt + 1) / 2, h[i].nz + 1, 1, 0));
   }
   P.emit(dim3(256), -1, st, out);
-  for (int i = 0; i < ns; ++i) P.add(fn(tridiag_kernel_b), h[i], make_int4(h[i].nz, 1, 1, 0));
+  for (int i = 0; i < ns; ++i) {
+    const void* f;
+    switch ((h[i].ell + 63) / 64) {
+      case 1: f = fn(tridiag_kernel_b<1>); break;
+      case 2: f = fn(tridiag_kernel_b<2>); break;
+      case 3: f = fn(tridiag_kernel_b<3>); break;
+      case 4: f = fn(tridiag_kernel_b<4>); break;
+      case 5: f = fn(tridiag_kernel_b<5>); break;
+      case 6: f = fn(tridiag_kernel_b<6>); break;
+      case 7: f = fn(tridiag_kernel_b<7>); break;
+      default: f = fn(tridiag_kernel_b<8>); break;
+    }
+    P.add(f, h[i], make_int4(h[i].nz, 1, 1, 0));
+  }
   P.emit(dim3(1024), -1, st, out);
 }
 
@@ -2439,6 +2496,24 @@ hipError_t run_launches(const std::vector<BLaunch>& v, hipStream_t s) {
     }
     if (e != hipSuccess) return e;
   }
+  return hipGetLastError();
+}
+
+// Copies the selection state the coefficient phase reads (the slot lists
+// and counters, G) into the update's snapshot slots.
+__global__ void snapshot_kernel(UpdArgs a, DevScalars* sc_out, double* g_out) {
+  const int64_t tt = (int64_t)a.t * a.t;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < tt) g_out[i] = a.G[i];
+  constexpr int nw = (int)(sizeof(DevScalars) / sizeof(int32_t));
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < nw; k += blockDim.x)
+      reinterpret_cast<int32_t*>(sc_out)[k] = reinterpret_cast<const int32_t*>(a.sc)[k];
+}
+
+hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* g_out, hipStream_t s) {
+  const int64_t tt = (int64_t)a.t * a.t;
+  hipLaunchKernelGGL(snapshot_kernel, dim3((unsigned)((tt + 255) / 256)), dim3(256), 0, s, a, sc_out, g_out);
   return hipGetLastError();
 }
 

@@ -209,6 +209,15 @@ def test_pipeline_f32_lowrank_large_ell():
     _pipeline(A, 300, 150, 150, "f32", 1003, 2003, batch=100)
 
 
+def test_pipeline_f32_lowrank_ell400_fallback_kernels():
+    # l = 400, t = 200 (the sizes of the ignition configuration): seven
+    # elements per lane in the tridiagonalisation, Alg. 4 through the L2
+    # QR and the per-column solve (t > 154), NA-Hutch++ through the L2 kernel
+    log("pipeline f32 lowrank 8192 x 500, rank 450, l=400, t=200")
+    A = synth.lowrank(8192, 500, seed=synth.data_seed(5), rank=450, decay=300.0)
+    _pipeline(A, 400, 200, 200, "f32", 1005, 2005, batch=100)
+
+
 def test_pipeline_bf16_channel_operand_rounding():
     log("pipeline bf16 channel vs oracle with bf16-rounded operands")
     A = synth.channel(24, 17, 24, 300, seed=synth.data_seed(3), n_modes=120)
