@@ -130,9 +130,9 @@ def cpu_baseline(wl, seeds, operand, rows=1 << 19, cols=None):
 
 def batched_bench(steps, warmup, n=1000, push=100, tile="auto"):
     """64 image streams of uneven m (log-uniform in [1e4, 1e6]), l = 200,
-    k = t = 100, bf16 sketch, lookahead 4 t, pushed 100 frames per round as
-    one batch (persistent sketch launch, batched updates, one graph per
-    round).  n = 1000 of the configuration's 5000 frames per stream keeps the
+    k = t = 100, bf16 sketch, lookahead 512 (two full 256-column tiles),
+    pushed 100 frames per round as one batch (persistent sketch launch,
+    batched updates, one graph per round).  n = 1000 of the configuration's 5000 frames per stream keeps the
     stream resident in HBM (49.6 GB)."""
     import torch
     import synth
@@ -143,7 +143,7 @@ def batched_bench(steps, warmup, n=1000, push=100, tile="auto"):
     X = [synth.blobs_torch(h, w, n, synth.data_seed(4) + 31 * i) for i, (h, w) in enumerate(shapes)]
     torch.cuda.synchronize()
     cfgs = [StreamConfig(m=m, ell=200, k=100, t=100, n_max=n, dtype=torch.float32, sketch="bf16",
-                         omega_seed=1004 + i, select_seed=2004 + i, lookahead=400, tile=tile)
+                         omega_seed=1004 + i, select_seed=2004 + i, lookahead=512, tile=tile)
             for i, m in enumerate(ms)]
     B = StreamBatch(cfgs)
 
@@ -179,7 +179,7 @@ def batched_bench(steps, warmup, n=1000, push=100, tile="auto"):
         f"{prof['sketch_launches']} launches, reduce {prof['reduce_ms']:.2f} ms, updates {prof['update_ms']:.2f} ms")
     out = {
         "workload": f"64 image streams (advected Gaussian blobs, m log-uniform in [1e4, 1e6], sum m = {sum(ms)}), "
-                    f"n = {n} each, l = 200, k = t = 100, bf16 sketch, pushed {push} frames per round",
+                    f"n = {n} each, l = 200, k = t = 100, bf16 sketch, lookahead 512, pushed {push} frames per round",
         "value": round(B_snap / (ms_step / 1000.0) / 1e9, 2), "unit": "GB/s", "ms_per_step": round(ms_step, 3),
         "steps": steps, "warmup": warmup, "rounds_per_step": info["rounds"] // max(1, steps + warmup),
         "graph_launches": info["graph_launches"], "graph_instantiations": info["graph_instantiations"],

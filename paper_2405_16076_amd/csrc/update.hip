@@ -432,73 +432,11 @@ __global__ __launch_bounds__(1024) void tridiag_kernel_b(Batched<BatchArgs> L) {
 }
 
 // ---------------------------------------------------------------------------
-// Scores.  One wave per scored column: y = Q^T s (reflectors in order), then
-// tau = sum_i z_i^2 / D_i with L z = y.
-// Items [0, t): basis slots; items [t, t + cnt): buffered columns.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void scores_body(const UpdArgs& a, const Blk bk) {
-  __shared__ double y[kMaxEll];
-  const int item = bk.x, lane = threadIdx.x, n = a.ell;
-  if (a.skipu[a.u]) return;
-  int64_t col;
-  if (item < a.t) {
-    col = a.J[item];
-    if (col < 0) {
-      if (lane == 0) {
-        a.tauC[item] = __longlong_as_double(0x7FF8000000000000LL);
-        a.tauC_hist[a.u * a.t + item] = __longlong_as_double(0x7FF8000000000000LL);
-      }
-      return;
-    }
-  } else {
-    col = a.c0 + (item - a.t);
-  }
-  const double* s = a.S + col * n;
-  for (int i = lane; i < n; i += 64) y[i] = s[i];
-  __syncthreads();
-  const double* htau = a.hv;
-  for (int j = 0; j + 2 < n; ++j) {
-    const double tj = htau[j];
-    if (tj == 0.0) continue;
-    const double* vcol = a.W + (int64_t)j * n;  // v = [1, W[j+2.., j]] on rows j+1..
-    double part = 0.0;
-    for (int i = j + 1 + lane; i < n; i += 64) part = fma((i == j + 1) ? 1.0 : vcol[i], y[i], part);
-    const double g = tj * wave_sum(part);
-    __syncthreads();
-    for (int i = j + 1 + lane; i < n; i += 64) y[i] -= g * ((i == j + 1) ? 1.0 : vcol[i]);
-    __syncthreads();
-  }
-  if (lane == 0) {
-    const double* Dinv = a.hv + 3 * n;
-    const double* L = a.hv + 4 * n;
-    double z = y[0];
-    double tau = z * z * Dinv[0];
-    for (int i = 1; i < n; ++i) {
-      z = y[i] - L[i - 1] * z;
-      tau = fma(z * z, Dinv[i], tau);
-    }
-    if (item < a.t) {
-      const double tc = fmin(a.tau_old[item], tau);
-      a.tauC[item] = tc;
-      a.tauC_hist[a.u * a.t + item] = tc;
-    } else {
-      a.tauD[item - a.t] = tau;
-      a.tauD_hist[a.u * a.t + (item - a.t)] = tau;
-    }
-  }
-}
-
-__global__ __launch_bounds__(64) void scores_kernel(UpdArgs a) { scores_body(a, own_block()); }
-
-__global__ __launch_bounds__(64) void scores_kernel_b(Batched<UpdArgs> L) {
-  const UpdArgs* p;
-  Blk bk;
-  if (batched_block(L, p, bk)) scores_body(*p, bk);
-}
-
-
-// ---------------------------------------------------------------------------
-// The same scores as products: Y = Q^T [s_item] for every item at once, with
+// Sketched ridge leverage scores (eq. sketch_ridge_leverage_score; Alg. 3
+// steps 17-19) of the t basis slots (items [0, t)) and the buffered columns
+// (items [t, t + cnt)): tau = s^T (SS^T + l lambda' I)^{-1} s = sum_i z_i^2 /
+// D_i with L z = Q^T s, where Q T Q^T = SS^T is the tridiagonalisation and
+// L D L^T = T + l lambda' I.  Y = Q^T [s_item] for every item at once, with
 // Q = H_0 ... H_{l-3} the orthogonal factor of the tridiagonalisation formed
 // explicitly (scores_q_kernel: column i of Q is H_0 ... H_{i-1} e_i, one wave
 // per column), the product on the matrix cores (scores_gemm_kernel), then the
@@ -1382,6 +1320,9 @@ __global__ __launch_bounds__(64) void alg4_apply_kernel_b(Batched<UpdArgs> L) {
 // ---------------------------------------------------------------------------
 constexpr int kAlg4Gemm = 154;  // packed R of up to 154 columns fits in LDS
 
+// dynamic LDS of alg4_m_kernel: R packed by columns (t of them at most)
+inline size_t alg4_m_lds(int t) { return (size_t)t * (t + 1) / 2 * sizeof(double); }
+
 __device__ __forceinline__ void alg4_q_body(const UpdArgs& a, const Blk bk) {
   constexpr int EM = kMaxEll / 64;
   const int j = bk.x, n = a.ell, lane = threadIdx.x;
@@ -1429,7 +1370,7 @@ __device__ __forceinline__ void alg4_q_body(const UpdArgs& a, const Blk bk) {
 
 __device__ __forceinline__ void alg4_m_body(const UpdArgs& a, const Blk bk) {
   constexpr int EY = (kAlg4Gemm + 63) / 64;
-  __shared__ double rp[kAlg4Gemm * (kAlg4Gemm + 1) / 2];
+  extern __shared__ __attribute__((aligned(16))) double rp[];  // t (t + 1) / 2 doubles
   const int n = a.ell, t = a.t;
   const int no = min(a.sc->n_occ, n);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1590,36 +1531,8 @@ __global__ __launch_bounds__(256) void hutch_gemm_kernel_b(Batched<UpdArgs> L) {
 }
 
 // ---------------------------------------------------------------------------
-// NA-Hutch++ (Alg. 8).  Large products first: Y = S P^T (l x t) and
-// PPt = P P^T (t x t), one thread per entry.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void hutch_prod_body(const UpdArgs& a, const Blk bk) {
-  const int64_t idx = (int64_t)bk.x * blockDim.x + threadIdx.x;
-  const int n = a.ell, t = a.t;
-  const int64_t nY = (int64_t)n * t, nPP = (int64_t)t * t;
-  if (idx < nY) {
-    const int r = (int)(idx % n), j = (int)(idx / n);
-    double s = 0.0;
-    for (int64_t c = 0; c < a.n_obs; ++c) s = fma(a.S[c * n + r], a.P[c * t + j], s);
-    a.Y[(int64_t)j * n + r] = s;
-  } else if (idx < nY + nPP) {
-    const int64_t q = idx - nY;
-    const int i = (int)(q % t), j = (int)(q / t);
-    double s = 0.0;
-    for (int64_t c = 0; c < a.n_obs; ++c) s = fma(a.P[c * t + i], a.P[c * t + j], s);
-    a.PPt[(int64_t)j * t + i] = s;
-  }
-}
-
-__global__ void hutch_prod_kernel(UpdArgs a) { hutch_prod_body(a, own_block()); }
-
-__global__ void hutch_prod_kernel_b(Batched<UpdArgs> L) {
-  const UpdArgs* p;
-  Blk bk;
-  if (batched_block(L, p, bk)) hutch_prod_body(*p, bk);
-}
-
-// The products of the small part of Alg. 8, one thread per output entry.
+// NA-Hutch++ (Alg. 8): the products of its small part, one thread per output
+// entry (Y = S P^T and P P^T come from hutch_gemm_kernel).
 // Stage 0: S_J gather.  Stage 1: K^T = (Y1 SJ2^T)^T, YG = Y1 G, A1 = Y1 SJ3^T,
 // A2 = SJ3 Y2^T.  Stage 2: X = YG Y2^T, AA = A1 A2.
 struct HutchWork {
@@ -2240,7 +2153,18 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
 }
 
 // Alg. 4 and Alg. 8
+static void alg4_m_attributes() {
+  static bool done = false;
+  if (done) return;
+  const int lds = (int)alg4_m_lds(kAlg4Gemm);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(alg4_m_kernel), hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(alg4_m_kernel_b), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds);
+  done = true;
+}
+
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
+  alg4_m_attributes();
   // Householder QR of Omega A_J: in registers when it fits, else through L2
   const int E = (a.ell + 63) / 64;
   if (E <= 1 && a.t <= 16)
@@ -2255,7 +2179,7 @@ hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(alg4_qr_kernel, dim3(1), dim3(1024), 0, s, a);
   if (a.t <= kAlg4Gemm) {
     hipLaunchKernelGGL(alg4_q_kernel, dim3(a.t), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(alg4_m_kernel, dim3((a.ell + 3) / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(alg4_m_kernel, dim3((a.ell + 3) / 4), dim3(256), alg4_m_lds(a.t), s, a);
     hipLaunchKernelGGL(alg4_pgemm_kernel, dim3((unsigned)(((a.t + 31) / 32) * ((a.n_obs + 31) / 32))), dim3(256),
                        0, s, a);
   } else {
@@ -2418,6 +2342,7 @@ void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch
 }
 
 void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+  alg4_m_attributes();
   const int4 one = make_int4(1, 1, 1, 0);
   {
     Planner<UpdArgs> Preg, Pl2;
@@ -2438,7 +2363,8 @@ void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunc
     if (h[i].t <= kAlg4Gemm) P.add(fn(alg4_q_kernel_b), h[i], make_int4(h[i].t, 1, 1, 0));
   P.emit(dim3(64), -1, st, out);
   for (int i = 0; i < ns; ++i)
-    if (h[i].t <= kAlg4Gemm) P.add(fn(alg4_m_kernel_b), h[i], make_int4((h[i].ell + 3) / 4, 1, 1, 0));
+    if (h[i].t <= kAlg4Gemm)
+      P.add(fn(alg4_m_kernel_b), h[i], make_int4((h[i].ell + 3) / 4, 1, 1, 0), alg4_m_lds(h[i].t));
   P.emit(dim3(256), -1, st, out);
   for (int i = 0; i < ns; ++i)
     if (h[i].t <= kAlg4Gemm)
