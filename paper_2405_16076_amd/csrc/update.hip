@@ -964,14 +964,18 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
         for (int x = 0; x < 2; ++x) frag(st, 32 * tq[ti] + 16 * x + i16, fa[x]);
 #pragma unroll
         for (int y = 0; y < 2; ++y) frag(st, (sym ? 0 : nq) + 32 * tj[ti] + 16 * y + i16, fb[y]);
+        // on a diagonal tile of the symmetric case the lower-left block is the
+        // transpose of the upper-right one: it is mirrored at the end instead
+        const bool diag = sym && tq[ti] == tj[ti];
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8)
 #pragma unroll
           for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y)
-              acc[ti][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)fa[x][s8], (double)fb[y][s8],
-                                                                   acc[ti][x][y], 0, 0, 0);
+              if (!(diag && x == 1 && y == 0))
+                acc[ti][x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)fa[x][s8], (double)fb[y][s8],
+                                                                     acc[ti][x][y], 0, 0, 0);
       }
     }
     if (copy_pool) pool_copy(c, cur);
@@ -984,10 +988,12 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
 #pragma unroll
   for (int ti = 0; ti < kGramTPW; ++ti) {
     if (ti >= ntw) continue;
+    const bool diag = sym && tq[ti] == tj[ti];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
+        if (diag && x == 1 && y == 0) continue;  // written as the mirror of (0, 1)
         const int j = 32 * tj[ti] + 16 * y + i16;
         if (j >= nj) continue;
 #pragma unroll
@@ -995,7 +1001,7 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
           const int q = 32 * tq[ti] + 16 * x + k4 + 4 * v;
           if (q >= nq) continue;
           out[(int64_t)q * a.t + j] = acc[ti][x][y][v];
-          if (sym && tj[ti] > tq[ti]) out[(int64_t)j * a.t + q] = acc[ti][x][y][v];
+          if (sym && (tj[ti] > tq[ti] || (x == 0 && y == 1))) out[(int64_t)j * a.t + q] = acc[ti][x][y][v];
         }
       }
   }
