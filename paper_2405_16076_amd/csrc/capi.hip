@@ -148,6 +148,20 @@ struct rid_stream {
   bool side_used = false;
   DevScalars* sc_hist = nullptr;
   double* Ghist = nullptr;
+  // The coefficient phases of the updates of one flush run on `side` as
+  // batched launches, cgroup updates at a time, each with its own slice of
+  // QR, qr_tau, Qm, Mm, Y, PPt and hw; P of every update but the last of the
+  // flush goes to a slice of Pz.  Their argument tables go to ctab_dev from a
+  // ring of pinned host slots.
+  int cgroup = 1;
+  double* Pz = nullptr;
+  static constexpr int kTabSlots = 3;
+  char* ctab_host[kTabSlots] = {nullptr, nullptr, nullptr};
+  hipEvent_t ctab_ev[kTabSlots] = {nullptr, nullptr, nullptr};
+  bool ctab_used[kTabSlots] = {false, false, false};
+  int ctab_slot = 0;
+  char* ctab_dev = nullptr;
+  size_t ctab_cap = 0;
 };
 
 static thread_local std::string g_last_err;
@@ -214,6 +228,13 @@ static void free_all(rid_stream* h) {
   h->marks.clear();
   for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
   h->event_pool.clear();
+  if (h->side) (void)hipStreamSynchronize(h->side);
+  for (int i = 0; i < rid_stream::kTabSlots; ++i) {
+    if (h->ctab_host[i]) (void)hipHostFree(h->ctab_host[i]);
+    if (h->ctab_ev[i]) (void)hipEventDestroy(h->ctab_ev[i]);
+    h->ctab_host[i] = nullptr;
+    h->ctab_ev[i] = nullptr;
+  }
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   h->alloc_bytes.clear();
@@ -327,7 +348,17 @@ static rid_status validate(const rid_config* c) {
   return RID_OK;
 }
 
+static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** out, bool member);
+
 rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out) {
+  return init_stream(cfg, stream, out, false);
+}
+
+}  // extern "C"
+
+// A member of a batch runs its coefficient phases through the batch's own
+// launches, so it needs one slice of the coefficient buffers and no tables.
+static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** out, bool member) {
   if (!cfg || !out) return fail(nullptr, RID_EINVAL, "null argument");
   *out = nullptr;
   rid_status st = validate(cfg);
@@ -381,7 +412,14 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
   h->ldc = (h->m + 63) / 64 * 64;
   h->max_updates = (h->n_max + h->t - 1) / h->t + 1;
   h->nzmax = h->b_max / h->t + 2;
-  const size_t ell = h->ell, t = h->t;
+  {
+    // updates per batched coefficient launch: all of a flush unless their
+    // slices of P (t x n_max each) would pass 1 GiB
+    const double pbytes = (double)h->t * (double)h->n_max * 8.0;
+    const int by_mem = (int)std::max(1.0, std::floor(1073741824.0 / pbytes));
+    h->cgroup = member ? 1 : std::min(h->nzmax, by_mem);
+  }
+  const size_t ell = h->ell, t = h->t, cg = h->cgroup;
   const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
 #define ALLOC(ptr, n) \
   if ((st = dalloc_t(h, &(ptr), (n))) != RID_OK) goto fail_alloc;
@@ -405,14 +443,15 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     ALLOC(h->J_hist, t * h->max_updates);
     ALLOC(h->G, t * t);
     ALLOC(h->gpart, (size_t)h->gslabs * t * t);
-    ALLOC(h->QR, ell * t);
-    ALLOC(h->qr_tau, (size_t)kMaxT);
+    ALLOC(h->QR, ell * t * cg);
+    ALLOC(h->qr_tau, (size_t)kMaxT * cg);
     ALLOC(h->P, t * h->n_max);
-    ALLOC(h->Qm, ell * t);
-    ALLOC(h->Mm, t * ell);
-    ALLOC(h->Y, ell * t);
-    ALLOC(h->PPt, t * t);
-    ALLOC(h->hw, hutch_work_doubles());
+    if (cg > 1) ALLOC(h->Pz, t * h->n_max * cg);
+    ALLOC(h->Qm, ell * t * cg);
+    ALLOC(h->Mm, t * ell * cg);
+    ALLOC(h->Y, ell * t * cg);
+    ALLOC(h->PPt, t * t * cg);
+    ALLOC(h->hw, hutch_work_doubles() * cg);
     ALLOC(h->colptr_dev, (size_t)h->n_max);
     ALLOC(h->normpart, (size_t)h->n_slabs * h->b_max);
     ALLOC(h->sc, (size_t)1);
@@ -436,6 +475,19 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
     st = fail(nullptr, RID_ENOMEM, "pinned host allocation failed");
     goto fail_alloc;
   }
+  if (h->cgroup > 1) {
+    // at most 16 launches per coefficient phase, each with a table of cgroup
+    // argument blocks and grid sizes
+    h->ctab_cap = 16 * ((size_t)h->cgroup * (sizeof(UpdArgs) + sizeof(int4)) + 512);
+    if ((st = dalloc(h, reinterpret_cast<void**>(&h->ctab_dev), h->ctab_cap)) != RID_OK) goto fail_alloc;
+    for (int i = 0; i < rid_stream::kTabSlots; ++i)
+      if (hipHostMalloc(reinterpret_cast<void**>(&h->ctab_host[i]), h->ctab_cap, hipHostMallocDefault) != hipSuccess ||
+          hipEventCreateWithFlags(&h->ctab_ev[i], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        st = fail(nullptr, RID_ENOMEM, "pinned host allocation failed");
+        goto fail_alloc;
+      }
+  }
   if (hipMemsetAsync(h->cpool, 0, (size_t)h->ldc * t * h->esize, h->s) != hipSuccess ||
       hipMemsetAsync(h->SST[0], 0, ell * ell * 8, h->s) != hipSuccess ||
       hipMemsetAsync(h->G, 0, t * t * 8, h->s) != hipSuccess ||
@@ -456,8 +508,6 @@ fail_alloc:
   delete h;
   return st;
 }
-
-}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // internal stream operations
@@ -626,10 +676,38 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
   return a;
 }
 
+// Buffers of the coefficient phase of update z of a flush of nz updates: slice
+// z % cgroup of the per-update scratch; P in place for the last update (the
+// one rid_coefficients reads), else in a slice of Pz.
+static void coeff_slice(rid_stream* h, UpdArgs& a, int z, int nz) {
+  const size_t zz = (size_t)(z % h->cgroup), ell = h->ell, t = h->t;
+  a.QR = h->QR + zz * ell * t;
+  a.qr_tau = h->qr_tau + zz * kMaxT;
+  a.Qm = h->Qm + zz * ell * t;
+  a.Mm = h->Mm + zz * t * ell;
+  a.Y = h->Y + zz * ell * t;
+  a.PPt = h->PPt + zz * t * t;
+  a.hw = h->hw + zz * hutch_work_doubles();
+  a.P = (z == nz - 1) ? h->P : h->Pz + zz * t * (size_t)h->n_max;
+}
+
+// The next pinned host slot for argument tables (its previous copy done).
+static rid_status take_table(rid_stream* h, Stage& stg) {
+  h->ctab_slot = (h->ctab_slot + 1) % rid_stream::kTabSlots;
+  if (h->ctab_used[h->ctab_slot]) RID_HIP(h, hipEventSynchronize(h->ctab_ev[h->ctab_slot]));
+  stg.host = h->ctab_host[h->ctab_slot];
+  stg.dev = h->ctab_dev;
+  stg.cap = h->ctab_cap;
+  stg.used = 0;
+  stg.overflow = false;
+  return RID_OK;
+}
+
 static rid_status run_updates(rid_stream* h, int n_full, int last) {
   const int nz = n_full + (last > 0 ? 1 : 0);
   if (nz == 0) return RID_OK;
   if (nz > h->nzmax) return fail(h, RID_EDEVICE, "internal: update batch larger than its slots");
+  std::vector<UpdArgs> co(nz);
   const BatchArgs b = batch_args(h, n_full, last);
   int mk = mark_begin(h, 2, 0.0);
   RID_HIP(h, launch_update_batch(b, h->s));
@@ -643,22 +721,42 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
     mk = mark_begin(h, 3, (double)a.u);
     RID_HIP(h, launch_update_gram(a, h->s));
     mark_end(h, mk);
-    // Alg. 4 and Alg. 8 of this update on the side stream, against snapshots
-    // of the selection state (the next update's selection rewrites J, G and
-    // the slot lists on the main stream meanwhile)
+    // Alg. 4 and Alg. 8 of this update read snapshots of the selection state
+    // (the next update's selection rewrites J, G and the slot lists)
     UpdArgs ac = a;
     ac.sc = h->sc_hist + a.u;
     ac.G = h->Ghist + (size_t)a.u * h->t * h->t;
     ac.J = h->J_hist + (size_t)a.u * h->t;
+    coeff_slice(h, ac, z, nz);
+    co[z] = ac;
     RID_HIP(h, launch_update_snapshot(a, ac.sc, ac.G, h->s));
-    RID_HIP(h, hipEventRecord(h->side_ev, h->s));
-    RID_HIP(h, hipStreamWaitEvent(h->side, h->side_ev, 0));
-    mk = mark_begin(h, 2, (double)a.u, h->side);
-    RID_HIP(h, launch_update_coeff(ac, h->side));
-    mark_end(h, mk);
-    h->side_used = true;
     h->last_nobs = a.n_obs;
   }
+  // The coefficient phases of the flush, on the side stream once the last
+  // snapshot is taken: each is a chain of small latency-bound kernels (one
+  // workgroup for either QR), so the updates of a group share every launch.
+  RID_HIP(h, hipEventRecord(h->side_ev, h->s));
+  RID_HIP(h, hipStreamWaitEvent(h->side, h->side_ev, 0));
+  mk = mark_begin(h, 2, (double)h->n_updates, h->side);
+  for (int z0 = 0; z0 < nz; z0 += h->cgroup) {
+    const int g = std::min(h->cgroup, nz - z0);
+    if (g == 1) {
+      RID_HIP(h, launch_update_coeff(co[z0], h->side));
+      continue;
+    }
+    Stage stg;
+    rid_status sts = take_table(h, stg);
+    if (sts != RID_OK) return sts;
+    std::vector<BLaunch> L;
+    plan_update_coeff_b(co.data() + z0, g, stg, L);
+    if (stg.overflow) return fail(h, RID_EDEVICE, "internal: coefficient tables exceed their staging buffer");
+    RID_HIP(h, hipMemcpyAsync(h->ctab_dev, stg.host, stg.used, hipMemcpyHostToDevice, h->side));
+    RID_HIP(h, hipEventRecord(h->ctab_ev[h->ctab_slot], h->side));
+    h->ctab_used[h->ctab_slot] = true;
+    RID_HIP(h, run_launches(L, h->side));
+  }
+  mark_end(h, mk);
+  h->side_used = true;
   h->n_updates += nz;
   return RID_OK;
 }
@@ -1493,7 +1591,7 @@ rid_status rid_init_batch(int32_t ns, const rid_config* cfgs, void* stream, uint
   int64_t min_rows = 1 << 30;
   for (int i = 0; i < ns; ++i) {
     rid_stream* h = nullptr;
-    rid_status st = rid_init_stream(&cfgs[i], bt->s, &h);
+    rid_status st = init_stream(&cfgs[i], bt->s, &h, true);
     if (st != RID_OK) {
       const std::string msg = g_last_err;
       batch_free(bt);

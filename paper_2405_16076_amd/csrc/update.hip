@@ -955,6 +955,9 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
     if (c + 1 < nch) issue(c + 1, cur ^ 1);
+    // the pool stores go out before the products, so that the wait for the
+    // next chunk at the end of the step (vmcnt also counts stores) finds them done
+    if (copy_pool) pool_copy(c, cur);
     const int st = cur;
 #pragma unroll
     for (int ti = 0; ti < kGramTPW; ++ti) {
@@ -978,7 +981,6 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
                                                                      acc[ti][x][y], 0, 0, 0);
       }
     }
-    if (copy_pool) pool_copy(c, cur);
     wait_dma_all();
     if (ragged && c + 1 == nch - 1) fixup(c + 1, cur ^ 1);
     lds_barrier();
