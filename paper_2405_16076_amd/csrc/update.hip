@@ -198,9 +198,6 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
 
 template <int EMT>
 __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
-  __shared__ double v[kMaxEll];
-  __shared__ double p[kMaxEll];
-  __shared__ double red[16];
   __shared__ double e2s[kMaxEll];
   __shared__ double ds[kMaxEll];
   const int z = bk.x;
@@ -222,147 +219,192 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     }
     return;
   }
-  // Householder tridiagonalisation on the lower triangle only (the trailing
-  // block A22 is read once per step for p = tau A22 v and its lower triangle
-  // read and written once for A22 -= v w^T + w v^T): wave 0 forms the
-  // reflector of column j (wave sums, no barrier) and publishes v; each wave
-  // walks its columns c of A22, forming the dot of column c with v (p_c) and
-  // adding column c times v_c to its partial of p below the diagonal; the
-  // partials meet in LDS in wave order; every wave then forms K = tau/2 p^T v
-  // and applies the update to its columns with w = p - K v.  EMT = ceil(l /
-  // 64) elements per lane; the columns of a wave go CB at a time, their
-  // loads issued together (the step is bound by L2 latency and bandwidth).
-  constexpr int CB = EMT <= 5 ? 4 : 2;
+  // Householder tridiagonalisation on the lower triangle, one pass over the
+  // trailing block per step: iteration j applies the rank-2 update of step
+  // j - 1 (A -= v w^T + w v^T, pending) while it forms the reflector and the
+  // product p = tau A22 v of step j.  Every wave loads column j, applies the
+  // pending update to it and forms the reflector itself (the same operations
+  // in the same order, so all waves hold the same v); wave 0 stores it.  Each
+  // wave then walks its columns c of the trailing block: loads the column,
+  // applies the pending update, stores it, and forms the dot of the column
+  // with v (p_c) and adds column c times v_c to its partial of p below the
+  // diagonal; the partials meet in LDS in wave order.  Vectors in LDS are
+  // indexed by absolute row; in registers element q of a lane is row
+  // j + 1 + lane + 64 q.  EMT = ceil(l / 64); the columns of a wave go CB at a
+  // time, their loads issued together (the step is bound by L2 latency).
+  constexpr int CB = EMT <= 3 ? 4 : (EMT <= 5 ? 3 : (EMT <= 6 ? 2 : 1));
   __shared__ double ppart[16][kMaxEll];
   __shared__ double pd[kMaxEll];
+  __shared__ double vs[2][kMaxEll];   // reflector of step j at [j & 1]
+  __shared__ double ps[2][kMaxEll];   // p of step j at [j & 1]
+  // value of element q of a wave-uniform row slot `k` of a register vector
+  auto pick = [&](const double (&x)[EMT], int k) {
+    k = __builtin_amdgcn_readfirstlane(k);
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < EMT; ++q)
+      if ((k >> 6) == q) r = readlane_f64(x[q], k & 63);
+    return r;
+  };
+  double Kp = 0.0;   // K of the pending step
   for (int j = 0; j + 2 < n; ++j) {
-    const int m = n - j - 1;           // order of the trailing block
-    double* x = W + (int64_t)j * n + j + 1;   // column j, rows j+1..n-1
+    const int m = n - j - 1;            // order of the trailing block, rows j+1..n-1
+    const int base = j + 1;
+    const bool pend = j > 0;
+    const double* Vp = vs[(j + 1) & 1];  // pending step j - 1
+    const double* Pp = ps[(j + 1) & 1];
+    // pending v and w at this lane's rows
+    double pv[EMT], pw[EMT];
+#pragma unroll
+    for (int q = 0; q < EMT; ++q) {
+      const int k = lane + 64 * q;
+      const double vv = (pend && k < m) ? Vp[base + k] : 0.0;
+      const double pp0 = (pend && k < m) ? Pp[base + k] : 0.0;
+      pv[q] = vv;
+      pw[q] = pp0 - Kp * vv;
+    }
+    // column j with the pending update: diagonal and x = rows j+1..n-1
+    double* colj = W + (int64_t)j * n;
+    double vjc = 0.0, wjc = 0.0;
+    if (pend) {
+      vjc = Vp[j];
+      wjc = Pp[j] - Kp * vjc;
+    }
+    const double dj = fma(-vjc, wjc, fma(-wjc, vjc, colj[j]));
+    double xk[EMT];
+#pragma unroll
+    for (int q = 0; q < EMT; ++q) {
+      const int k = lane + 64 * q;
+      xk[q] = (k < m) ? fma(-pv[q], wjc, fma(-pw[q], vjc, colj[base + k])) : 0.0;
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < EMT; ++q) {
+      const int k = lane + 64 * q;
+      if (k >= 1 && k < m) part = fma(xk[q], xk[q], part);
+    }
+    const double xn2 = wave_sum(part);
+    const double alpha = readlane_f64(xk[0], 0);
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    double cv[EMT];
+#pragma unroll
+    for (int q = 0; q < EMT; ++q) {
+      const int k = lane + 64 * q;
+      cv[q] = (k == 0) ? 1.0 : ((k < m) ? xk[q] * scal : 0.0);
+    }
+    double* vcur = vs[j & 1];
     if (wv == 0) {
-      double part = 0.0;
-      for (int i = 1 + lane; i < m; i += 64) part = fma(x[i], x[i], part);
-      const double xn2 = wave_sum(part);
-      const double alpha = x[0];
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (xn2 > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      for (int i = lane; i < m; i += 64) {
-        const double vi = (i == 0) ? 1.0 : x[i] * scal;
-        v[i] = vi;
-        if (i > 0) x[i] = vi;  // store the reflector
+#pragma unroll
+      for (int q = 0; q < EMT; ++q) {
+        const int k = lane + 64 * q;
+        if (k < m) vcur[base + k] = cv[q];
       }
       if (lane == 0) {
-        red[0] = tau;
         htau[j] = tau;
         e[j] = beta;
-        d[j] = W[(int64_t)j * n + j];
+        d[j] = dj;
       }
     }
-    __syncthreads();
-    const double tau = red[0];
-    if (tau != 0.0) {
-      double* A22 = W + (int64_t)(j + 1) * n + (j + 1);  // A22(k, c) = A22[c n + k], k >= c
-      double pp[EMT];
+    // trailing block: pending update, store, p partials with the new v
+    double* A22 = W + (int64_t)base * n + base;  // A22(k, c) = A22[c n + k], k >= c
+    double pp[EMT];
 #pragma unroll
-      for (int q = 0; q < EMT; ++q) pp[q] = 0.0;
-      double vk[EMT];
+    for (int q = 0; q < EMT; ++q) pp[q] = 0.0;
+    for (int c0 = wv; c0 < m; c0 += CB * nw) {
+      double a[CB][EMT];
 #pragma unroll
-      for (int q = 0; q < EMT; ++q) {
-        const int k = lane + 64 * q;
-        vk[q] = (k < m) ? v[k] : 0.0;
+      for (int u = 0; u < CB; ++u) {
+        const int c = c0 + u * nw;
+        const double* col = A22 + (int64_t)c * n;
+#pragma unroll
+        for (int q = 0; q < EMT; ++q) {
+          const int k = lane + 64 * q;
+          a[u][q] = (c < m && k >= c && k < m) ? col[k] : 0.0;
+        }
       }
-      for (int c0 = wv; c0 < m; c0 += CB * nw) {
-        double a[CB][EMT];
+      double dot[CB];
 #pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          const int c = c0 + u * nw;
-          const double* col = A22 + (int64_t)c * n;
+      for (int u = 0; u < CB; ++u) {
+        const int c = c0 + u * nw;
+        dot[u] = 0.0;
+        if (c >= m) continue;
+        double* col = A22 + (int64_t)c * n;
+        const double vc_p = pend ? Vp[base + c] : 0.0;
+        const double wc_p = pend ? Pp[base + c] - Kp * vc_p : 0.0;
+        const double vc = pick(cv, c);
 #pragma unroll
-          for (int q = 0; q < EMT; ++q) {
-            const int k = lane + 64 * q;
-            a[u][q] = (c < m && k >= c && k < m) ? col[k] : 0.0;
+        for (int q = 0; q < EMT; ++q) {
+          const int k = lane + 64 * q;
+          if (k >= c && k < m) {
+            const double x = pend ? fma(-pv[q], wc_p, fma(-pw[q], vc_p, a[u][q])) : a[u][q];
+            if (pend) col[k] = x;
+            dot[u] = fma(x, cv[q], dot[u]);
+            if (k > c) pp[q] = fma(x, vc, pp[q]);
           }
         }
-        double dot[CB];
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          const int c = c0 + u * nw;
-          const double vc = (c < m) ? v[c] : 0.0;
-          dot[u] = 0.0;
-#pragma unroll
-          for (int q = 0; q < EMT; ++q) {
-            const int k = lane + 64 * q;
-            dot[u] = fma(a[u][q], vk[q], dot[u]);
-            if (k > c) pp[q] = fma(a[u][q], vc, pp[q]);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          const double sv = wave_sum(dot[u]);
-          const int c = c0 + u * nw;
-          if (lane == 0 && c < m) pd[c] = sv;
-        }
       }
 #pragma unroll
-      for (int q = 0; q < EMT; ++q) {
-        const int k = lane + 64 * q;
-        if (k < m) ppart[wv][k] = pp[q];
-      }
-      __syncthreads();
-      for (int k = tid; k < m; k += nth) {
-        double sacc = pd[k];
-        for (int w = 0; w < nw; ++w) sacc += ppart[w][k];
-        p[k] = tau * sacc;
-      }
-      __syncthreads();
-      double pv = 0.0;
-      for (int i = lane; i < m; i += 64) pv = fma(p[i], v[i], pv);
-      const double K = 0.5 * tau * wave_sum(pv);
-      double wk[EMT];
-#pragma unroll
-      for (int q = 0; q < EMT; ++q) {
-        const int k = lane + 64 * q;
-        wk[q] = (k < m) ? p[k] - K * v[k] : 0.0;
-      }
-      // A22 -= v w^T + w v^T on the lower triangle (one wave per column)
-      for (int c0 = wv; c0 < m; c0 += CB * nw) {
-        double a[CB][EMT];
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          const int c = c0 + u * nw;
-          const double* col = A22 + (int64_t)c * n;
-#pragma unroll
-          for (int q = 0; q < EMT; ++q) {
-            const int k = lane + 64 * q;
-            a[u][q] = (c < m && k >= c && k < m) ? col[k] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          const int c = c0 + u * nw;
-          if (c >= m) continue;
-          double* cp = A22 + (int64_t)c * n;
-          const double vc = v[c], wc = p[c] - K * v[c];
-#pragma unroll
-          for (int q = 0; q < EMT; ++q) {
-            const int k = lane + 64 * q;
-            if (k >= c && k < m) cp[k] = fma(-vk[q], wc, fma(-wk[q], vc, a[u][q]));
-          }
-        }
+      for (int u = 0; u < CB; ++u) {
+        const double sv = wave_sum(dot[u]);
+        const int c = c0 + u * nw;
+        if (lane == 0 && c < m) pd[c] = sv;
       }
     }
+#pragma unroll
+    for (int q = 0; q < EMT; ++q) {
+      const int k = lane + 64 * q;
+      if (k < m) ppart[wv][k] = pp[q];
+    }
     __syncthreads();
+    // every wave has read column j: store the reflector below its first row
+    if (wv == 0) {
+#pragma unroll
+      for (int q = 0; q < EMT; ++q) {
+        const int k = lane + 64 * q;
+        if (k > 0 && k < m) colj[base + k] = cv[q];
+      }
+    }
+    double* pcur = ps[j & 1];
+    for (int k = tid; k < m; k += nth) {
+      double sacc = pd[k];
+      for (int w = 0; w < nw; ++w) sacc += ppart[w][k];
+      pcur[base + k] = tau * sacc;
+    }
+    __syncthreads();
+    double pvs = 0.0;
+#pragma unroll
+    for (int q = 0; q < EMT; ++q) {
+      const int k = lane + 64 * q;
+      if (k < m) pvs = fma(pcur[base + k], cv[q], pvs);
+    }
+    Kp = 0.5 * tau * wave_sum(pvs);
   }
   if (tid == 0) {
+    // the last 2 x 2 block with the pending update of step n - 3
     if (n >= 2) {
-      d[n - 2] = W[(int64_t)(n - 2) * n + n - 2];
-      e[n - 2] = W[(int64_t)(n - 2) * n + n - 1];
+      double a00 = W[(int64_t)(n - 2) * n + n - 2], a10 = W[(int64_t)(n - 2) * n + n - 1];
+      double a11 = W[(int64_t)(n - 1) * n + n - 1];
+      if (n >= 3) {
+        const double* Vp = vs[(n - 3) & 1];
+        const double* Pp = ps[(n - 3) & 1];
+        const double v0 = Vp[n - 2], v1 = Vp[n - 1];
+        const double w0 = Pp[n - 2] - Kp * v0, w1 = Pp[n - 1] - Kp * v1;
+        a00 = fma(-v0, w0, fma(-w0, v0, a00));
+        a10 = fma(-v1, w0, fma(-w1, v0, a10));
+        a11 = fma(-v1, w1, fma(-w1, v1, a11));
+      }
+      d[n - 2] = a00;
+      e[n - 2] = a10;
       htau[n - 2] = 0.0;
+      d[n - 1] = a11;
+    } else {
+      d[n - 1] = W[(int64_t)(n - 1) * n + n - 1];
     }
-    d[n - 1] = W[(int64_t)(n - 1) * n + n - 1];
     e[n - 1] = 0.0;
     htau[n - 1] = 0.0;
   }
