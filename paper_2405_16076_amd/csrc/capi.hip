@@ -711,12 +711,14 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   const BatchArgs b = batch_args(h, n_full, last);
   int mk = mark_begin(h, 2, 0.0);
   RID_HIP(h, launch_update_batch(b, h->s));
+  // Q of each update depends on its tridiagonalisation only
+  RID_HIP(h, launch_update_q_all(upd_args(h, 0, n_full, last), nz, h->s));
   mark_end(h, mk);
   h->sst_cur ^= 1;
   for (int z = 0; z < nz; ++z) {
     const UpdArgs a = upd_args(h, z, n_full, last);
     mk = mark_begin(h, 2, (double)a.u);
-    RID_HIP(h, launch_update_select(a, h->s));
+    RID_HIP(h, launch_update_select(a, h->s, false));
     mark_end(h, mk);
     mk = mark_begin(h, 3, (double)a.u);
     RID_HIP(h, launch_update_gram(a, h->s));

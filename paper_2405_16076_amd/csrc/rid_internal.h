@@ -424,7 +424,11 @@ hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s);
 hipError_t launch_omega_block(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,
                               void* out, int64_t ld, hipStream_t s);
 hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s);
-hipError_t launch_update_select(const UpdArgs& a, hipStream_t s);
+// scores and selection of one update; with_q = false when its Q has been
+// formed by launch_update_q_all
+hipError_t launch_update_select(const UpdArgs& a, hipStream_t s, bool with_q = true);
+// the orthogonal factor Q of the tridiagonalisation of updates a0.u .. a0.u + nz - 1
+hipError_t launch_update_q_all(const UpdArgs& a0, int nz, hipStream_t s);
 hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s);
 hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* g_out, hipStream_t s);

@@ -426,20 +426,40 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   lo -= 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   hi += 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  // Multisection: a group of G lanes per eigenvalue, on at most 8 waves (two
+  // per SIMD: the Sturm recurrence is a chain of binary64 divisions, so more
+  // waves would only queue on the same units); lane r = 1..G-1 of the group
+  // counts the eigenvalues below the r-th of the G - 1 equispaced interior
+  // points of the group's interval, and the group keeps the subinterval
+  // holding its target (Sturm counts are monotone in the shift, so the points
+  // with count <= target are a prefix).  Stops at a width of one ulp of the
+  // eigenvalue or 2 eps ||T||, the accuracy of the reduction itself.
   const int kk = min(b.k, n);
-  for (int idx = tid; idx < kk; idx += nth) {
+  const int nwe = min(nw, 8);
+  int G = 2;
+  for (int g = 16; g > 2; --g)
+    if ((64 / g) * nwe >= kk) {
+      G = g;
+      break;
+    }
+  const int gpw = 64 / G, gi = lane / G, r = lane % G;
+  const double atol = 2.0 * 2.220446049250313e-16 * bnd;
+  for (int idx = (gi < gpw && wv < nwe) ? wv * gpw + gi : kk; idx < kk; idx += nwe * gpw) {
     const int target = n - 1 - idx;  // ascending index of the idx-th largest
     double aa = lo, bb = hi;
     for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (aa + bb);
-      if (mid <= aa || mid >= bb) break;
-      if (bb - aa <= 2.220446049250313e-16 * fmax(fabs(aa), fabs(bb))) break;
-      if (sturm_count(ds, e2s, n, mid, pivmin) <= target)
-        aa = mid;
-      else
-        bb = mid;
+      if (bb - aa <= fmax(2.220446049250313e-16 * fmax(fabs(aa), fabs(bb)), atol)) break;
+      const double hs = (bb - aa) / G;
+      if (!(aa + hs > aa) || !(aa + (G - 1) * hs < bb)) break;
+      const bool below = r > 0 && sturm_count(ds, e2s, n, aa + r * hs, pivmin) <= target;
+      const uint64_t bal = __ballot(below);
+      const int cnt = __popcll((bal >> (gi * G)) & ((1ull << G) - 1));
+      const double na = cnt == 0 ? aa : aa + cnt * hs;
+      const double nb = cnt == G - 1 ? bb : aa + (cnt + 1) * hs;
+      aa = na;
+      bb = nb;
     }
-    mu[idx] = 0.5 * (aa + bb);
+    if (r == 0) mu[idx] = 0.5 * (aa + bb);
   }
   __syncthreads();
   if (tid == 0) {
@@ -607,6 +627,18 @@ __device__ __forceinline__ void scores_fin_body(const UpdArgs& a, const Blk bk) 
 }
 
 __global__ __launch_bounds__(64) void scores_q_kernel(UpdArgs a) { scores_q_body(a, own_block()); }
+
+// Q of every update of a flush in one launch: block (i, z) forms column i of
+// the Q of update a.u + z from that update's slices of W, hv and Qs.
+__global__ __launch_bounds__(64) void scores_q_all_kernel(UpdArgs a) {
+  const int z = blockIdx.y;
+  UpdArgs b = a;
+  b.u = a.u + z;
+  b.W = a.W + (int64_t)z * a.ell * a.ell;
+  b.hv = a.hv + (int64_t)z * 6 * a.ell;
+  b.Qs = a.Qs + (int64_t)z * a.ell * a.ell;
+  scores_q_body(b, Blk{(int)blockIdx.x, 0, 0});
+}
 __global__ __launch_bounds__(64) void scores_q_kernel_b(Batched<UpdArgs> L) {
   const UpdArgs* p;
   Blk bk;
@@ -2170,9 +2202,14 @@ hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
 }
 
 // scores and selection (Alg. 3 steps 17-27)
-hipError_t launch_update_select(const UpdArgs& a, hipStream_t s) {
+hipError_t launch_update_q_all(const UpdArgs& a0, int nz, hipStream_t s) {
+  hipLaunchKernelGGL(scores_q_all_kernel, dim3(a0.ell, nz), dim3(64), 0, s, a0);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_select(const UpdArgs& a, hipStream_t s, bool with_q) {
   const int items = a.t + a.cnt;
-  hipLaunchKernelGGL(scores_q_kernel, dim3(a.ell), dim3(64), 0, s, a);
+  if (with_q) hipLaunchKernelGGL(scores_q_kernel, dim3(a.ell), dim3(64), 0, s, a);
   hipLaunchKernelGGL(scores_gemm_kernel, dim3(((a.ell + 31) / 32) * ((items + 31) / 32)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(scores_fin_kernel, dim3(items), dim3(64), 0, s, a);
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a);
