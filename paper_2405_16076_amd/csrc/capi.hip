@@ -357,7 +357,7 @@ rid_status rid_init_stream(const rid_config* cfg, void* stream, rid_stream** out
 }  // extern "C"
 
 // A member of a batch runs its coefficient phases through the batch's own
-// launches, so it needs one slice of the coefficient buffers and no tables.
+// launches (no tables of its own); its slices of P are capped at 256 MiB.
 static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** out, bool member) {
   if (!cfg || !out) return fail(nullptr, RID_EINVAL, "null argument");
   *out = nullptr;
@@ -417,7 +417,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     // slices of P (t x n_max each) would pass 1 GiB
     const double pbytes = (double)h->t * (double)h->n_max * 8.0;
     const int by_mem = (int)std::max(1.0, std::floor(1073741824.0 / pbytes));
-    h->cgroup = member ? 1 : std::min(h->nzmax, by_mem);
+    const int by_mem_member = (int)std::max(1.0, std::floor(268435456.0 / pbytes));
+    h->cgroup = std::min(h->nzmax, member ? by_mem_member : by_mem);
   }
   const size_t ell = h->ell, t = h->t, cg = h->cgroup;
   const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
@@ -475,7 +476,7 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     st = fail(nullptr, RID_ENOMEM, "pinned host allocation failed");
     goto fail_alloc;
   }
-  if (h->cgroup > 1) {
+  if (h->cgroup > 1 && !member) {
     // at most 16 launches per coefficient phase, each with a table of cgroup
     // argument blocks and grid sizes
     h->ctab_cap = 16 * ((size_t)h->cgroup * (sizeof(UpdArgs) + sizeof(int4)) + 512);
@@ -1490,14 +1491,39 @@ static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
       ba.push_back(batch_args(h, nfull[i], nlast[i]));
     }
     plan_update_batch_b(ba.data(), (int)ba.size(), stg, L);
+    // The coefficient phases of the round go last, in one launch per kernel
+    // for every (member, update), against snapshots of each update's
+    // selection state, when every member holds a buffer slice per update of
+    // the round; else each step's phase follows its Gram.
+    bool defer = true;
+    for (int i : up_who)
+      if (bt->st[i]->cgroup < nfull[i] + (nlast[i] > 0 ? 1 : 0)) defer = false;
+    std::vector<UpdArgs> co;
     for (int z = 0; z < max_nz; ++z) {
       std::vector<UpdArgs> ua;
-      for (int i : up_who)
-        if (z < nfull[i] + (nlast[i] > 0 ? 1 : 0)) ua.push_back(upd_args(bt->st[i], z, nfull[i], nlast[i]));
+      std::vector<SnapArgs> sa;
+      for (int i : up_who) {
+        rid_stream* h = bt->st[i];
+        const int nz = nfull[i] + (nlast[i] > 0 ? 1 : 0);
+        if (z >= nz) continue;
+        const UpdArgs a = upd_args(h, z, nfull[i], nlast[i]);
+        ua.push_back(a);
+        if (defer) {
+          UpdArgs ac = a;
+          ac.sc = h->sc_hist + a.u;
+          ac.G = h->Ghist + (size_t)a.u * h->t * h->t;
+          ac.J = h->J_hist + (size_t)a.u * h->t;
+          coeff_slice(h, ac, z, nz);
+          co.push_back(ac);
+          sa.push_back(SnapArgs{a.sc, a.G, ac.sc, ac.G, h->t});
+        }
+      }
       plan_update_select_b(ua.data(), (int)ua.size(), stg, L);
       plan_update_gram_b(ua.data(), (int)ua.size(), stg, L);
-      plan_update_coeff_b(ua.data(), (int)ua.size(), stg, L);
+      if (defer) plan_update_snapshot_b(sa.data(), (int)sa.size(), stg, L);
+      else plan_update_coeff_b(ua.data(), (int)ua.size(), stg, L);
     }
+    if (defer) plan_update_coeff_b(co.data(), (int)co.size(), stg, L);
   }
   if ((sts = copy_slot(bt, stg)) != RID_OK) return sts;
   if ((sts = batch_exec(bt, L)) != RID_OK) return sts;

@@ -416,6 +416,15 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
 void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+// snapshot of the selection state an update's coefficient phase reads
+struct SnapArgs {
+  const DevScalars* sc;  // state after the update's selection and Gram
+  const double* G;
+  DevScalars* sc_out;    // the update's snapshot slots
+  double* g_out;
+  int t;
+};
+void plan_update_snapshot_b(const SnapArgs* h, int n, Stage& st, std::vector<BLaunch>& out);
 
 // launchers (sketch.hip, update.hip)
 int sketch_cols_per_wg(int prec, int wide);

@@ -2530,6 +2530,27 @@ hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* 
   return hipGetLastError();
 }
 
+// The same copies for several updates (one table entry each).
+__global__ void snapshot_kernel_b(Batched<SnapArgs> L) {
+  const SnapArgs* p;
+  Blk bk;
+  if (!batched_block(L, p, bk)) return;
+  const int64_t tt = (int64_t)p->t * p->t;
+  const int64_t i = (int64_t)bk.x * blockDim.x + threadIdx.x;
+  if (i < tt) p->g_out[i] = p->G[i];
+  constexpr int nw = (int)(sizeof(DevScalars) / sizeof(int32_t));
+  if (bk.x == 0)
+    for (int k = threadIdx.x; k < nw; k += blockDim.x)
+      reinterpret_cast<int32_t*>(p->sc_out)[k] = reinterpret_cast<const int32_t*>(p->sc)[k];
+}
+
+void plan_update_snapshot_b(const SnapArgs* h, int n, Stage& st, std::vector<BLaunch>& out) {
+  Planner<SnapArgs> P;
+  for (int i = 0; i < n; ++i)
+    P.add(fn(snapshot_kernel_b), h[i], make_int4((int)(((int64_t)h[i].t * h[i].t + 255) / 256), 1, 1, 0));
+  P.emit(dim3(256), -1, st, out);
+}
+
 size_t hutch_work_doubles() {
   return (size_t)kMaxEll * kMaxEll / 4 * 5 + (size_t)kMaxEll * kMaxT * 2;
 }
