@@ -1491,6 +1491,14 @@ static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
       ba.push_back(batch_args(h, nfull[i], nlast[i]));
     }
     plan_update_batch_b(ba.data(), (int)ba.size(), stg, L);
+    {
+      // Q of every update of the round depends on its tridiagonalisation only
+      std::vector<UpdArgs> qa;
+      for (int i : up_who)
+        for (int z = 0; z < nfull[i] + (nlast[i] > 0 ? 1 : 0); ++z)
+          qa.push_back(upd_args(bt->st[i], z, nfull[i], nlast[i]));
+      plan_update_q_b(qa.data(), (int)qa.size(), stg, L);
+    }
     // The coefficient phases of the round go last, in one launch per kernel
     // for every (member, update), against snapshots of each update's
     // selection state, when every member holds a buffer slice per update of
@@ -1518,7 +1526,7 @@ static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
           sa.push_back(SnapArgs{a.sc, a.G, ac.sc, ac.G, h->t});
         }
       }
-      plan_update_select_b(ua.data(), (int)ua.size(), stg, L);
+      plan_update_select_b(ua.data(), (int)ua.size(), stg, L, false);
       plan_update_gram_b(ua.data(), (int)ua.size(), stg, L);
       if (defer) plan_update_snapshot_b(sa.data(), (int)sa.size(), stg, L);
       else plan_update_coeff_b(ua.data(), (int)ua.size(), stg, L);

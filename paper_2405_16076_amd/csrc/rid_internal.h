@@ -413,7 +413,9 @@ hipError_t run_launches(const std::vector<BLaunch>& v, hipStream_t s);
 void plan_sketch_multi(int prec, const SketchArgs* h, int ns, int grid_cap, Stage& st, std::vector<BLaunch>& out);
 void plan_sketch_reduce_b(int prec, const SketchArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
-void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out, bool with_q = true);
+// Q of the tridiagonalisation of each listed update (any mix of streams and updates)
+void plan_update_q_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 // snapshot of the selection state an update's coefficient phase reads

@@ -2382,10 +2382,15 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
   P.emit(dim3(1024), -1, st, out);
 }
 
-void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+void plan_update_q_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
   Planner<UpdArgs> P;
   for (int i = 0; i < ns; ++i) P.add(fn(scores_q_kernel_b), h[i], make_int4(h[i].ell, 1, 1, 0));
   P.emit(dim3(64), -1, st, out);
+}
+
+void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out, bool with_q) {
+  Planner<UpdArgs> P;
+  if (with_q) plan_update_q_b(h, ns, st, out);
   for (int i = 0; i < ns; ++i) {
     const int items = h[i].t + h[i].cnt;
     P.add(fn(scores_gemm_kernel_b), h[i], make_int4(((h[i].ell + 31) / 32) * ((items + 31) / 32), 1, 1, 0));
