@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "rid_internal.h"
@@ -155,6 +156,11 @@ struct rid_stream {
   // ring of pinned host slots.
   int cgroup = 1;
   double* Pz = nullptr;
+  double* SSTk = nullptr;   // nzmax slots of l x l: each update's SS^T (sst_keep)
+  // the next flush's SS^T batch rewrites SSTk: it waits for the side stream's
+  // coefficient phases of the previous flush (coeff_ev)
+  hipEvent_t coeff_ev = nullptr;
+  bool coeff_pending = false;
   static constexpr int kTabSlots = 3;
   char* ctab_host[kTabSlots] = {nullptr, nullptr, nullptr};
   hipEvent_t ctab_ev[kTabSlots] = {nullptr, nullptr, nullptr};
@@ -242,6 +248,8 @@ static void free_all(rid_stream* h) {
   h->colptr_host = nullptr;
   if (h->side) (void)hipStreamSynchronize(h->side);
   if (h->side_ev) (void)hipEventDestroy(h->side_ev);
+  if (h->coeff_ev) (void)hipEventDestroy(h->coeff_ev);
+  h->coeff_ev = nullptr;
   if (h->side) (void)hipStreamDestroy(h->side);
   h->side_ev = nullptr;
   h->side = nullptr;
@@ -413,12 +421,15 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
   h->max_updates = (h->n_max + h->t - 1) / h->t + 1;
   h->nzmax = h->b_max / h->t + 2;
   {
-    // updates per batched coefficient launch: all of a flush unless their
-    // slices of P (t x n_max each) would pass 1 GiB
-    const double pbytes = (double)h->t * (double)h->n_max * 8.0;
-    const int by_mem = (int)std::max(1.0, std::floor(1073741824.0 / pbytes));
-    const int by_mem_member = (int)std::max(1.0, std::floor(268435456.0 / pbytes));
-    h->cgroup = std::min(h->nzmax, member ? by_mem_member : by_mem);
+    // updates per batched coefficient launch: all of a flush.  Above
+    // kAlg4Gemm every update forms its own P (t x n_max), so the group stops
+    // where those slices would pass 1 GiB (256 MiB for a batch member).
+    h->cgroup = h->nzmax;
+    if (h->t > kAlg4Gemm) {
+      const double pbytes = (double)h->t * (double)h->n_max * 8.0;
+      const int by_mem = (int)std::max(1.0, std::floor((member ? 268435456.0 : 1073741824.0) / pbytes));
+      h->cgroup = std::min(h->nzmax, by_mem);
+    }
   }
   const size_t ell = h->ell, t = h->t, cg = h->cgroup;
   const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
@@ -447,7 +458,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     ALLOC(h->QR, ell * t * cg);
     ALLOC(h->qr_tau, (size_t)kMaxT * cg);
     ALLOC(h->P, t * h->n_max);
-    if (cg > 1) ALLOC(h->Pz, t * h->n_max * cg);
+    if (cg > 1 && h->t > kAlg4Gemm) ALLOC(h->Pz, t * h->n_max * cg);
+    ALLOC(h->SSTk, ell * ell * h->nzmax);
     ALLOC(h->Qm, ell * t * cg);
     ALLOC(h->Mm, t * ell * cg);
     ALLOC(h->Y, ell * t * cg);
@@ -465,7 +477,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
   }
 #undef ALLOC
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->side_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->side_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->coeff_ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     st = fail(nullptr, RID_EDEVICE, "side stream creation failed");
     goto fail_alloc;
@@ -615,6 +628,7 @@ static BatchArgs batch_args(rid_stream* h, int n_full, int last) {
   b.colsq = h->colsq;
   b.sst_in = h->SST[h->sst_cur];
   b.sst_out = h->SST[h->sst_cur ^ 1];
+  b.sst_keep = h->SSTk;
   b.W = h->W;
   b.hv = h->hv;
   b.Fu = h->Fu;
@@ -643,6 +657,7 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
     a.ldc = h->ldc;
     a.data_f64 = h->data_f64;
     a.S = h->S;
+    a.SSTu = h->SSTk + (size_t)z * h->ell * h->ell;
     a.colsq = h->colsq;
     a.W = h->W + (size_t)z * h->ell * h->ell;
     a.hv = h->hv + (size_t)z * 6 * h->ell;
@@ -678,8 +693,9 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
 }
 
 // Buffers of the coefficient phase of update z of a flush of nz updates: slice
-// z % cgroup of the per-update scratch; P in place for the last update (the
-// one rid_coefficients reads), else in a slice of Pz.
+// z % cgroup of the per-update scratch.  P in place for the last update (the
+// one rid_coefficients reads); the others form P only above kAlg4Gemm, in a
+// slice of Pz.
 static void coeff_slice(rid_stream* h, UpdArgs& a, int z, int nz) {
   const size_t zz = (size_t)(z % h->cgroup), ell = h->ell, t = h->t;
   a.QR = h->QR + zz * ell * t;
@@ -689,7 +705,7 @@ static void coeff_slice(rid_stream* h, UpdArgs& a, int z, int nz) {
   a.Y = h->Y + zz * ell * t;
   a.PPt = h->PPt + zz * t * t;
   a.hw = h->hw + zz * hutch_work_doubles();
-  a.P = (z == nz - 1) ? h->P : h->Pz + zz * t * (size_t)h->n_max;
+  a.P = (z == nz - 1 || !h->Pz) ? h->P : h->Pz + zz * t * (size_t)h->n_max;
 }
 
 // The next pinned host slot for argument tables (its previous copy done).
@@ -710,6 +726,7 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   if (nz > h->nzmax) return fail(h, RID_EDEVICE, "internal: update batch larger than its slots");
   std::vector<UpdArgs> co(nz);
   const BatchArgs b = batch_args(h, n_full, last);
+  if (h->coeff_pending) RID_HIP(h, hipStreamWaitEvent(h->s, h->coeff_ev, 0));
   int mk = mark_begin(h, 2, 0.0);
   RID_HIP(h, launch_update_batch(b, h->s));
   // Q of each update depends on its tridiagonalisation only
@@ -744,20 +761,24 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   for (int z0 = 0; z0 < nz; z0 += h->cgroup) {
     const int g = std::min(h->cgroup, nz - z0);
     if (g == 1) {
-      RID_HIP(h, launch_update_coeff(co[z0], h->side));
+      RID_HIP(h, launch_update_coeff(co[z0], h->side, z0 == nz - 1));
       continue;
     }
     Stage stg;
     rid_status sts = take_table(h, stg);
     if (sts != RID_OK) return sts;
     std::vector<BLaunch> L;
-    plan_update_coeff_b(co.data() + z0, g, stg, L);
+    std::unique_ptr<bool[]> want_p(new bool[g]);
+    for (int q = 0; q < g; ++q) want_p[q] = (z0 + q == nz - 1);
+    plan_update_coeff_b(co.data() + z0, g, stg, L, want_p.get());
     if (stg.overflow) return fail(h, RID_EDEVICE, "internal: coefficient tables exceed their staging buffer");
     RID_HIP(h, hipMemcpyAsync(h->ctab_dev, stg.host, stg.used, hipMemcpyHostToDevice, h->side));
     RID_HIP(h, hipEventRecord(h->ctab_ev[h->ctab_slot], h->side));
     h->ctab_used[h->ctab_slot] = true;
     RID_HIP(h, run_launches(L, h->side));
   }
+  RID_HIP(h, hipEventRecord(h->coeff_ev, h->side));
+  h->coeff_pending = true;
   mark_end(h, mk);
   h->side_used = true;
   h->n_updates += nz;
@@ -1507,8 +1528,10 @@ static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
     for (int i : up_who)
       if (bt->st[i]->cgroup < nfull[i] + (nlast[i] > 0 ? 1 : 0)) defer = false;
     std::vector<UpdArgs> co;
+    std::vector<char> co_p;   // the entry forms P (its member's last update of the round)
     for (int z = 0; z < max_nz; ++z) {
       std::vector<UpdArgs> ua;
+      std::vector<char> ua_p;
       std::vector<SnapArgs> sa;
       for (int i : up_who) {
         rid_stream* h = bt->st[i];
@@ -1516,6 +1539,7 @@ static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
         if (z >= nz) continue;
         const UpdArgs a = upd_args(h, z, nfull[i], nlast[i]);
         ua.push_back(a);
+        ua_p.push_back(z == nz - 1);
         if (defer) {
           UpdArgs ac = a;
           ac.sc = h->sc_hist + a.u;
@@ -1523,15 +1547,25 @@ static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
           ac.J = h->J_hist + (size_t)a.u * h->t;
           coeff_slice(h, ac, z, nz);
           co.push_back(ac);
+          co_p.push_back(z == nz - 1);
           sa.push_back(SnapArgs{a.sc, a.G, ac.sc, ac.G, h->t});
         }
       }
       plan_update_select_b(ua.data(), (int)ua.size(), stg, L, false);
       plan_update_gram_b(ua.data(), (int)ua.size(), stg, L);
-      if (defer) plan_update_snapshot_b(sa.data(), (int)sa.size(), stg, L);
-      else plan_update_coeff_b(ua.data(), (int)ua.size(), stg, L);
+      if (defer) {
+        plan_update_snapshot_b(sa.data(), (int)sa.size(), stg, L);
+      } else {
+        std::unique_ptr<bool[]> wp(new bool[ua.size()]);
+        for (size_t q = 0; q < ua.size(); ++q) wp[q] = ua_p[q] != 0;
+        plan_update_coeff_b(ua.data(), (int)ua.size(), stg, L, wp.get());
+      }
     }
-    if (defer) plan_update_coeff_b(co.data(), (int)co.size(), stg, L);
+    if (defer) {
+      std::unique_ptr<bool[]> wp(new bool[co.size()]);
+      for (size_t q = 0; q < co.size(); ++q) wp[q] = co_p[q] != 0;
+      plan_update_coeff_b(co.data(), (int)co.size(), stg, L, wp.get());
+    }
   }
   if ((sts = copy_slot(bt, stg)) != RID_OK) return sts;
   if ((sts = batch_exec(bt, L)) != RID_OK) return sts;

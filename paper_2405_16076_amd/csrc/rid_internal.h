@@ -258,6 +258,7 @@ struct BatchArgs {
   const double* colsq;
   const double* sst_in;   // SS^T after update u0 - 1
   double* sst_out;        // SS^T after the batch's last update
+  double* sst_keep;       // nz slots of l x l: a copy of each update's SS^T (read by Alg. 8)
   double* W;              // nz slots of l x l
   double* hv;             // nz slots of 6 l
   double* Fu;             // ||A_obs||^2 per update
@@ -277,6 +278,7 @@ struct UpdArgs {
   int64_t m, ldc;      // rows and column-pool stride
   int data_f64;
   // state
+  const double* SSTu;  // SS^T of this update (l x l)
   double* S;           // l x n_max
   double* colsq;
   double* W;           // this update's l x l slot: reflectors below the subdiagonal
@@ -417,7 +419,9 @@ void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaun
 // Q of the tridiagonalisation of each listed update (any mix of streams and updates)
 void plan_update_q_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
 void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
-void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out);
+// want_p[i]: entry i forms P (null: every entry)
+void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out,
+                         const bool* want_p = nullptr);
 // snapshot of the selection state an update's coefficient phase reads
 struct SnapArgs {
   const DevScalars* sc;  // state after the update's selection and Gram
@@ -435,13 +439,17 @@ hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s);
 hipError_t launch_omega_block(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,
                               void* out, int64_t ld, hipStream_t s);
 hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s);
+// Alg. 4 forms P = M S (t x n_obs) through M = R'^{-1} Q^T when t is at most
+// this; above it P is formed column by column and Alg. 8 reads P.
+constexpr int kAlg4Gemm = 154;
 // scores and selection of one update; with_q = false when its Q has been
 // formed by launch_update_q_all
 hipError_t launch_update_select(const UpdArgs& a, hipStream_t s, bool with_q = true);
 // the orthogonal factor Q of the tridiagonalisation of updates a0.u .. a0.u + nz - 1
 hipError_t launch_update_q_all(const UpdArgs& a0, int nz, hipStream_t s);
 hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
-hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s);
+// want_p: form P (the last update of a flush; Alg. 8 needs only Y and P P^T)
+hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s, bool want_p = true);
 hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* g_out, hipStream_t s);
 size_t hutch_work_doubles();
 

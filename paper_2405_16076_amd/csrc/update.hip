@@ -112,34 +112,37 @@ __device__ __forceinline__ void gemm32_f64(int m0, int n0, int K, LA la, LB lb, 
 }
 
 // ---------------------------------------------------------------------------
-// SS^T and F of every update of a batch: slot z receives
-//   SS^T_{u0-1} + sum of s_c s_c^T over the batch columns up to update u0+z,
-// and slot nz (sst_out) the state after the last update.  Also starts each
-// update's record.
+// SS^T and F of every update of a batch: SS^T_u = SS^T_{u-1} + S_u S_u^T, S_u
+// the sketches of update u's own columns, in update order, so SS^T_u does not
+// depend on how the updates were grouped into batches.  Slot z of W (and of
+// sst_keep) receives update u0 + z, sst_out the state after the last update.
+// Block x: one 32 x 32 tile of the upper triangle, mirrored (exactly
+// symmetric).  Also starts each update's record.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sst_batch_body(const BatchArgs& b, const Blk bk) {
   __shared__ double red[4 * 16 * 64];
   const int n = b.ell;
   const int nt = (n + 31) / 32;
-  // block x: tile (ti, tj), ti <= tj, of the upper triangle; block y: slot z
   int ti = 0, rem = bk.x;
   while (ti < nt && rem >= nt - ti) {
     rem -= nt - ti;
     ++ti;
   }
   const int tj = ti + rem;
-  const int z = bk.y;
-  const int zz = min(z, b.nz - 1);
-  const int64_t cend = b.c0 + min((int64_t)(zz + 1) * b.t, b.total);
-  const int K = (int)(cend - b.c0);
-  const double* S0 = b.S + b.c0 * n;
-  double out[2][2][4];
-  gemm32_f64(32 * ti, 32 * tj, K, [&](int r, int k) { return (r < n && k < K) ? S0[(int64_t)k * n + r] : 0.0; },
-             [&](int k, int c) { return (k < K && c < n) ? S0[(int64_t)k * n + c] : 0.0; }, out, red);
-  double* dst = (z < b.nz) ? b.W + (int64_t)z * n * n : b.sst_out;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (wave == 0) {
-    const int i16 = lane & 15, k4 = lane >> 4;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  // running sum of this lane's elements of the tile (every wave keeps it)
+  double run[2][2][4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 32 * ti + 16 * x + k4 + 4 * v, c = 32 * tj + 16 * y + i16;
+        run[x][y][v] = (r < n && c < n) ? b.sst_in[(int64_t)c * n + r] : 0.0;
+      }
+  auto store = [&](double* dst) {
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -147,26 +150,50 @@ __device__ __forceinline__ void sst_batch_body(const BatchArgs& b, const Blk bk)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = 32 * ti + 16 * x + k4 + 4 * v, c = 32 * tj + 16 * y + i16;
-          if (r < n && c < n && r <= c) {  // the upper triangle, mirrored: exactly symmetric
-            const double val = b.sst_in[(int64_t)c * n + r] + out[x][y][v];
-            dst[(int64_t)c * n + r] = val;
-            dst[(int64_t)r * n + c] = val;
+          if (r < n && c < n && r <= c) {
+            dst[(int64_t)c * n + r] = run[x][y][v];
+            dst[(int64_t)r * n + c] = run[x][y][v];
           }
         }
+  };
+  for (int z = 0; z < b.nz; ++z) {
+    const int64_t ca = b.c0 + (int64_t)z * b.t;
+    const int K = (int)(min((int64_t)(z + 1) * b.t, b.total) - (int64_t)z * b.t);
+    const double* Sz = b.S + ca * n;
+    double out[2][2][4];
+    if (z > 0) __syncthreads();  // the previous product's partials in red have been read
+    gemm32_f64(32 * ti, 32 * tj, K, [&](int r, int k) { return (r < n && k < K) ? Sz[(int64_t)k * n + r] : 0.0; },
+               [&](int k, int c) { return (k < K && c < n) ? Sz[(int64_t)k * n + c] : 0.0; }, out, red);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) run[x][y][v] += out[x][y][v];
+    if (wave == 0) {
+      store(b.W + (int64_t)z * n * n);
+      if (b.sst_keep) store(b.sst_keep + (int64_t)z * n * n);
+    }
   }
-  if (z < b.nz && bk.x == 0 && threadIdx.x == 0) {
-    const int64_t u = b.u0 + z;
-    // F of update u0 - 1 was written by an earlier launch
+  if (wave == 0) store(b.sst_out);
+  if (bk.x == 0 && threadIdx.x == 0) {
+    // F of update u0 - 1 was written by an earlier launch; the columns are
+    // added one by one in stream order
     double F = (b.u0 > 0) ? b.Fu[b.u0 - 1] : 0.0;
-    for (int64_t c = b.c0; c < cend; ++c) F += b.colsq[c];
-    b.Fu[u] = F;
-    b.skipu[u] = (F > 0.0) ? 0 : 1;
-    rid_update* rec = b.recs + u;
-    rec->update = u;
-    rec->n_obs = cend;
-    rec->count = cend - (b.c0 + (int64_t)zz * b.t);
-    rec->F = F;
-    rec->flags = (F > 0.0) ? 0 : RID_UPD_SKIPPED;
+    for (int z = 0; z < b.nz; ++z) {
+      const int64_t ca = b.c0 + (int64_t)z * b.t;
+      const int64_t cend = b.c0 + min((int64_t)(z + 1) * b.t, b.total);
+      for (int64_t c = ca; c < cend; ++c) F += b.colsq[c];
+      const int64_t u = b.u0 + z;
+      b.Fu[u] = F;
+      b.skipu[u] = (F > 0.0) ? 0 : 1;
+      rid_update* rec = b.recs + u;
+      rec->update = u;
+      rec->n_obs = cend;
+      rec->count = cend - ca;
+      rec->F = F;
+      rec->flags = (F > 0.0) ? 0 : RID_UPD_SKIPPED;
+    }
   }
 }
 
@@ -1400,7 +1427,6 @@ __global__ __launch_bounds__(64) void alg4_apply_kernel_b(Batched<UpdArgs> L) {
 //   alg4_pgemm       P = M S on the matrix cores, scattered to slot order;
 //                    rows of empty slots are zeroed.
 // ---------------------------------------------------------------------------
-constexpr int kAlg4Gemm = 154;  // packed R of up to 154 columns fits in LDS
 
 // dynamic LDS of alg4_m_kernel: R packed by columns (t of them at most)
 inline size_t alg4_m_lds(int t) { return (size_t)t * (t + 1) / 2 * sizeof(double); }
@@ -1585,6 +1611,94 @@ __device__ __forceinline__ void hutch_gemm_body(const UpdArgs& a, const Blk bk) 
             if (i < t && j < t) a.PPt[(int64_t)j * t + i] = out[x][y][v];
           }
   }
+}
+
+// The NA-Hutch++ products without P (t <= kAlg4Gemm): P has rows
+// P(occupied, :) = M S and zero rows for empty slots, so Y = S P^T =
+// (S S^T) M^T and P P^T = M Y, at O(l^2 t) flops instead of O(l t n_obs).
+// Columns of Y and rows and columns of P P^T are slots; occi maps a slot to
+// its row of M (-1: empty).
+__device__ __forceinline__ void hutch_occ_index(const UpdArgs& a, int* occi) {
+  const int t = a.t, no = min(a.sc->n_occ, a.ell);
+  for (int sl = threadIdx.x; sl < t; sl += blockDim.x) occi[sl] = -1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < no; i += blockDim.x) occi[a.sc->occ_slot[i]] = i;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void hutch_y_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double red[4 * 16 * 64];
+  __shared__ int occi[kMaxT];
+  const int n = a.ell, t = a.t;
+  hutch_occ_index(a, occi);
+  const int tyM = (n + 31) / 32;
+  const int m0 = 32 * (bk.x % tyM), n0 = 32 * (bk.x / tyM);
+  const double* SS = a.SSTu;
+  const double* M = a.Mm;
+  double out[2][2][4];
+  gemm32_f64(m0, n0, n, [&](int r, int k) { return (r < n && k < n) ? SS[(int64_t)k * n + r] : 0.0; },
+             [&](int k, int j) {
+               const int o = (j < t) ? occi[j] : -1;
+               return (o >= 0 && k < n) ? M[(int64_t)k * t + o] : 0.0;
+             },
+             out, red);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    const int i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = m0 + 16 * x + k4 + 4 * v, j = n0 + 16 * y + i16;
+          if (r < n && j < t) a.Y[(int64_t)j * n + r] = out[x][y][v];
+        }
+  }
+}
+
+__device__ __forceinline__ void hutch_ppt_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double red[4 * 16 * 64];
+  __shared__ int occi[kMaxT];
+  const int n = a.ell, t = a.t;
+  hutch_occ_index(a, occi);
+  const int tyN = (t + 31) / 32;
+  const int m0 = 32 * (bk.x % tyN), n0 = 32 * (bk.x / tyN);
+  const double* M = a.Mm;
+  const double* Y = a.Y;
+  double out[2][2][4];
+  gemm32_f64(m0, n0, n,
+             [&](int i, int r) {
+               const int o = (i < t) ? occi[i] : -1;
+               return (o >= 0 && r < n) ? M[(int64_t)r * t + o] : 0.0;
+             },
+             [&](int r, int j) { return (r < n && j < t) ? Y[(int64_t)j * n + r] : 0.0; }, out, red);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    const int i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = m0 + 16 * x + k4 + 4 * v, j = n0 + 16 * y + i16;
+          if (i < t && j < t) a.PPt[(int64_t)j * t + i] = out[x][y][v];
+        }
+  }
+}
+
+__global__ __launch_bounds__(256) void hutch_y_kernel(UpdArgs a) { hutch_y_body(a, own_block()); }
+__global__ __launch_bounds__(256) void hutch_y_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) hutch_y_body(*p, bk);
+}
+__global__ __launch_bounds__(256) void hutch_ppt_kernel(UpdArgs a) { hutch_ppt_body(a, own_block()); }
+__global__ __launch_bounds__(256) void hutch_ppt_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) hutch_ppt_body(*p, bk);
 }
 
 __global__ __launch_bounds__(64) void alg4_q_kernel(UpdArgs a) { alg4_q_body(a, own_block()); }
@@ -2187,7 +2301,7 @@ __global__ __launch_bounds__(64 * NW) void hutch_small_reg_kernel_b(Batched<UpdA
 // SS^T, F and the ridge of every update of a batch (Alg. 3 steps 11, 13, 17-18)
 hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
   const int nt = (b.ell + 31) / 32;
-  hipLaunchKernelGGL(sst_batch_kernel, dim3(nt * (nt + 1) / 2, b.nz + 1), dim3(256), 0, s, b);
+  hipLaunchKernelGGL(sst_batch_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, s, b);
   switch ((b.ell + 63) / 64) {
     case 1: hipLaunchKernelGGL(tridiag_kernel<1>, dim3(b.nz), dim3(1024), 0, s, b); break;
     case 2: hipLaunchKernelGGL(tridiag_kernel<2>, dim3(b.nz), dim3(1024), 0, s, b); break;
@@ -2250,7 +2364,7 @@ static void alg4_m_attributes() {
   done = true;
 }
 
-hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
+hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s, bool want_p) {
   alg4_m_attributes();
   // Householder QR of Omega A_J: in registers when it fits, else through L2
   const int E = (a.ell + 63) / 64;
@@ -2267,12 +2381,14 @@ hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s) {
   if (a.t <= kAlg4Gemm) {
     hipLaunchKernelGGL(alg4_q_kernel, dim3(a.t), dim3(64), 0, s, a);
     hipLaunchKernelGGL(alg4_m_kernel, dim3((a.ell + 3) / 4), dim3(256), alg4_m_lds(a.t), s, a);
-    hipLaunchKernelGGL(alg4_pgemm_kernel, dim3((unsigned)(((a.t + 31) / 32) * ((a.n_obs + 31) / 32))), dim3(256),
-                       0, s, a);
+    if (want_p)
+      hipLaunchKernelGGL(alg4_pgemm_kernel, dim3((unsigned)(((a.t + 31) / 32) * ((a.n_obs + 31) / 32))),
+                         dim3(256), 0, s, a);
+    const int ty = (a.ell + 31) / 32, tt = (a.t + 31) / 32;
+    hipLaunchKernelGGL(hutch_y_kernel, dim3(ty * tt), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(hutch_ppt_kernel, dim3(tt * tt), dim3(256), 0, s, a);
   } else {
     hipLaunchKernelGGL(alg4_apply_kernel, dim3((unsigned)a.n_obs), dim3(64), 0, s, a);
-  }
-  {
     const int tiles = ((a.ell + 31) / 32) * ((a.t + 31) / 32) + ((a.t + 31) / 32) * ((a.t + 31) / 32);
     hipLaunchKernelGGL(hutch_gemm_kernel, dim3(tiles), dim3(256), 0, s, a);
   }
@@ -2362,7 +2478,7 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
   Planner<BatchArgs> P;
   for (int i = 0; i < ns; ++i) {
     const int nt = (h[i].ell + 31) / 32;
-    P.add(fn(sst_batch_kernel_b), h[i], make_int4(nt * (nt + 1) / 2, h[i].nz + 1, 1, 0));
+    P.add(fn(sst_batch_kernel_b), h[i], make_int4(nt * (nt + 1) / 2, 1, 1, 0));
   }
   P.emit(dim3(256), -1, st, out);
   for (int i = 0; i < ns; ++i) {
@@ -2433,7 +2549,7 @@ void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch
   P.emit(dim3(kMaxT), -1, st, out);
 }
 
-void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
+void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out, const bool* want_p) {
   alg4_m_attributes();
   const int4 one = make_int4(1, 1, 1, 0);
   {
@@ -2459,16 +2575,23 @@ void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunc
       P.add(fn(alg4_m_kernel_b), h[i], make_int4((h[i].ell + 3) / 4, 1, 1, 0), alg4_m_lds(h[i].t));
   P.emit(dim3(256), -1, st, out);
   for (int i = 0; i < ns; ++i)
-    if (h[i].t <= kAlg4Gemm)
+    if (h[i].t <= kAlg4Gemm && (!want_p || want_p[i]))
       P.add(fn(alg4_pgemm_kernel_b), h[i],
             make_int4((int)(((h[i].t + 31) / 32) * ((h[i].n_obs + 31) / 32)), 1, 1, 0));
   P.emit(dim3(256), -1, st, out);
   for (int i = 0; i < ns; ++i)
     if (h[i].t > kAlg4Gemm) P.add(fn(alg4_apply_kernel_b), h[i], make_int4((int)h[i].n_obs, 1, 1, 0));
   P.emit(dim3(64), -1, st, out);
+  // Y and P P^T: from S S^T and M, or from P above kAlg4Gemm
   for (int i = 0; i < ns; ++i) {
-    const int tiles = ((h[i].ell + 31) / 32) * ((h[i].t + 31) / 32) + ((h[i].t + 31) / 32) * ((h[i].t + 31) / 32);
-    P.add(fn(hutch_gemm_kernel_b), h[i], make_int4(tiles, 1, 1, 0));
+    const int ty = (h[i].ell + 31) / 32, tt = (h[i].t + 31) / 32;
+    if (h[i].t <= kAlg4Gemm) P.add(fn(hutch_y_kernel_b), h[i], make_int4(ty * tt, 1, 1, 0));
+    else P.add(fn(hutch_gemm_kernel_b), h[i], make_int4(ty * tt + tt * tt, 1, 1, 0));
+  }
+  P.emit(dim3(256), -1, st, out);
+  for (int i = 0; i < ns; ++i) {
+    const int tt = (h[i].t + 31) / 32;
+    if (h[i].t <= kAlg4Gemm) P.add(fn(hutch_ppt_kernel_b), h[i], make_int4(tt * tt, 1, 1, 0));
   }
   P.emit(dim3(256), -1, st, out);
   for (int stage = 0; stage < 3; ++stage) {

@@ -131,6 +131,29 @@ def test_sketch_is_independent_of_batching(sketch, ell, tile):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
+@pytest.mark.parametrize("sketch", ["f32", "bf16"])
+def test_pipeline_is_independent_of_batching(sketch):
+    """SS^T of update u is SS^T of update u - 1 plus the products of update
+    u's own columns, so the scores, the selection, P and every NA-Hutch++ term
+    are bitwise the same however the pushes fall into flushes."""
+    log("pipeline batching independence", sketch)
+    A = synth.lowrank(20_011, 260, seed=11, rank=40, rel_noise=1e-3)
+    runs = []
+    for batch, la in [(None, 0), (7, 30), (64, 64), (130, 256)]:
+        s = run_gpu(A, 40, 20, 20, sketch, 21, 22, batch=batch, lookahead=la)
+        recs = [s.update(u) for u in range(int(s.info().n_updates))]
+        runs.append((s.select(), s.coefficients(), recs, (batch, la)))
+    J0, P0, R0, _ = runs[0]
+    for J, P, R, how in runs[1:]:
+        assert np.array_equal(J, J0), how
+        assert np.array_equal(P, P0), how
+        assert len(R) == len(R0)
+        for a, b in zip(R, R0):
+            for key in ("F", "sk2", "lam", "E2", "tr_est", "gpp"):
+                assert a[key] == b[key], (how, a["update"], key, a[key], b[key])
+            assert np.array_equal(a["J"], b["J"]) and np.array_equal(a["tau_C"], b["tau_C"], equal_nan=True)
+
+
 # ---------------------------------------------------------------------------
 # whole stream: J, tau, P, E^2, reconstruction
 # ---------------------------------------------------------------------------
