@@ -464,7 +464,7 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     ALLOC(h->Mm, t * ell * cg);
     ALLOC(h->Y, ell * t * cg);
     ALLOC(h->PPt, t * t * cg);
-    ALLOC(h->hw, hutch_work_doubles() * cg);
+    ALLOC(h->hw, hutch_work_doubles(h->ell, h->t) * cg);
     ALLOC(h->colptr_dev, (size_t)h->n_max);
     ALLOC(h->normpart, (size_t)h->n_slabs * h->b_max);
     ALLOC(h->sc, (size_t)1);
@@ -704,7 +704,7 @@ static void coeff_slice(rid_stream* h, UpdArgs& a, int z, int nz) {
   a.Mm = h->Mm + zz * t * ell;
   a.Y = h->Y + zz * ell * t;
   a.PPt = h->PPt + zz * t * t;
-  a.hw = h->hw + zz * hutch_work_doubles();
+  a.hw = h->hw + zz * hutch_work_doubles(h->ell, h->t);
   a.P = (z == nz - 1 || !h->Pz) ? h->P : h->Pz + zz * t * (size_t)h->n_max;
 }
 

@@ -451,6 +451,9 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
 // want_p: form P (the last update of a flush; Alg. 8 needs only Y and P P^T)
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s, bool want_p = true);
 hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* g_out, hipStream_t s);
-size_t hutch_work_doubles();
+// NA-Hutch++ work per update (doubles) for l and t; hutch_work_quarter(l) is
+// the size of each of its five l^2 / 4 regions
+__host__ __device__ inline int64_t hutch_work_quarter(int ell) { return (int64_t)ell * ell / 4 + 64; }
+size_t hutch_work_doubles(int ell, int t);
 
 }  // namespace rid

@@ -1735,15 +1735,19 @@ struct HutchWork {
   double *KT, *X, *AA, *YG, *A1, *A2, *SJ;
 };
 
+// K^T, X, AA, A1 and A2 are products of two of n1, n2, n3 (pairwise sums
+// below l, so each holds fewer than l^2 / 4 entries); YG and S_J hold at most
+// l t.  The layout follows the stream's l and t (hutch_work_doubles).
 __device__ __forceinline__ HutchWork hutch_work(const UpdArgs& a) {
+  const int64_t e4 = hutch_work_quarter(a.ell), et = (int64_t)a.ell * a.t;
   HutchWork w;
   w.KT = a.hw;
-  w.X = w.KT + (int64_t)kMaxEll * kMaxEll / 4;
-  w.AA = w.X + (int64_t)kMaxEll * kMaxEll / 4;
-  w.YG = w.AA + (int64_t)kMaxEll * kMaxEll / 4;
-  w.A1 = w.YG + (int64_t)kMaxEll * kMaxT;
-  w.A2 = w.A1 + (int64_t)kMaxEll * kMaxEll / 4;
-  w.SJ = w.A2 + (int64_t)kMaxEll * kMaxEll / 4;
+  w.X = w.KT + e4;
+  w.AA = w.X + e4;
+  w.YG = w.AA + e4;
+  w.A1 = w.YG + et;
+  w.A2 = w.A1 + e4;
+  w.SJ = w.A2 + e4;
   return w;
 }
 
@@ -2679,8 +2683,8 @@ void plan_update_snapshot_b(const SnapArgs* h, int n, Stage& st, std::vector<BLa
   P.emit(dim3(256), -1, st, out);
 }
 
-size_t hutch_work_doubles() {
-  return (size_t)kMaxEll * kMaxEll / 4 * 5 + (size_t)kMaxEll * kMaxT * 2;
+size_t hutch_work_doubles(int ell, int t) {
+  return (size_t)hutch_work_quarter(ell) * 5 + (size_t)ell * t * 2;
 }
 
 }  // namespace rid
