@@ -18,13 +18,13 @@ def log(*a):
 
 
 def run_gpu(A_cols, ell, k, t, sketch, omega_seed, select_seed, batch=None, borrow=True, lookahead=0,
-            finalize=True, n1=0, n2=0, tile="auto"):
+            finalize=True, n1=0, n2=0, tile="auto", n_max=None):
     """A_cols: numpy (n, m) (row j = snapshot j).  Returns the stream after
     pushing every snapshot (and finalizing)."""
     from paper_2405_16076_amd import OnlineRID, StreamConfig
     n, m = A_cols.shape
     dt = torch.float64 if A_cols.dtype == np.float64 else torch.float32
-    cfg = StreamConfig(m=m, ell=ell, k=k, t=t, n_max=n, dtype=dt, sketch=sketch, omega_seed=omega_seed,
+    cfg = StreamConfig(m=m, ell=ell, k=k, t=t, n_max=n_max or n, dtype=dt, sketch=sketch, omega_seed=omega_seed,
                        select_seed=select_seed, lookahead=lookahead, hutch_n1=n1, hutch_n2=n2, tile=tile)
     s = OnlineRID(cfg)
     # padded device copy: every column starts on a 64-byte boundary

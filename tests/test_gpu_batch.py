@@ -205,3 +205,37 @@ def test_batch_image_streams_64_members_sampled():
         wt, mg, e, er = _check_member(B.members[i], A, ell, t, "bf16", 6000 + i, 7000 + i)
         log(f"  member {i} m={h * w}: tau/tol {wt:.2e} margin {mg:.2e} P {e:.2e} recon {er:.2e}")
     B.close()
+
+
+def test_batch_coefficients_per_step_when_slices_do_not_fit():
+    """A member whose per-update P slices (t x n_max each) would pass the cap
+    gets each step's Alg. 4 / Alg. 8 phase right after that step's Gram (for
+    every member of the round) instead of all at the end; every member still
+    matches the oracle."""
+    from paper_2405_16076_amd import StreamBatch, StreamConfig
+    log("batch with an l = 400, t = 200, n_max = 400000 member: per-step coefficient phases")
+    # binary64 form: the batch's default slab (16384 rows) sums a whole
+    # 8192-row column in one partial, which binary32 would take past the
+    # tolerances' model of the sketch error
+    A1 = synth.lowrank(8192, 500, seed=synth.data_seed(5), rank=450, decay=300.0).astype(np.float64)
+    A2 = synth.lowrank(5000, 300, seed=synth.data_seed(6), rank=30).astype(np.float64)
+    cfgs = [StreamConfig(m=8192, ell=400, k=200, t=200, n_max=400_000, dtype=torch.float64, sketch="f64",
+                         omega_seed=1005, select_seed=2005, lookahead=1024),
+            StreamConfig(m=5000, ell=40, k=20, t=20, n_max=300, dtype=torch.float64, sketch="f64",
+                         omega_seed=4001, select_seed=5001, lookahead=64)]
+    B = StreamBatch(cfgs, tune=False)
+    X1 = torch.from_numpy(A1).to("cuda:0")
+    X2 = torch.from_numpy(A2).to("cuda:0")
+    p1 = p2 = 0
+    while p1 < 500 or p2 < 300:
+        c1 = X1[p1:p1 + 100] if p1 < 500 else None
+        c2 = X2[p2:p2 + 60] if p2 < 300 else None
+        B.push([c1, c2])
+        p1 += 100
+        p2 += 60
+    B.finalize()
+    torch.cuda.synchronize()
+    for i, (A, ell, t, os_, ss) in enumerate([(A1, 400, 200, 1005, 2005), (A2, 40, 20, 4001, 5001)]):
+        wt, mg, e, er = _check_member(B.members[i], A, ell, t, "f64", os_, ss)
+        log(f"  member {i}: tau/tol {wt:.2e} margin {mg:.2e} P {e:.2e} recon {er:.2e}")
+    B.close()

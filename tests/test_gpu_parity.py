@@ -157,8 +157,8 @@ def test_pipeline_is_independent_of_batching(sketch):
 # ---------------------------------------------------------------------------
 # whole stream: J, tau, P, E^2, reconstruction
 # ---------------------------------------------------------------------------
-def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True):
-    s = run_gpu(A, ell, k, t, sketch, oseed, sseed, batch=batch, borrow=borrow)
+def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True, n_max=None, lookahead=0):
+    s = run_gpu(A, ell, k, t, sketch, oseed, sseed, batch=batch, borrow=borrow, n_max=n_max, lookahead=lookahead)
     o = run_oracle(A, ell, k, t, sketch, oseed, sseed)
     tol = perturbation_tolerances(o, A, sketch)
     worst_tau, margin = compare_updates(s, o, tol)
@@ -239,6 +239,15 @@ def test_pipeline_f32_lowrank_ell400_fallback_kernels():
     log("pipeline f32 lowrank 8192 x 500, rank 450, l=400, t=200")
     A = synth.lowrank(8192, 500, seed=synth.data_seed(5), rank=450, decay=300.0)
     _pipeline(A, 400, 200, 200, "f32", 1005, 2005, batch=100)
+
+
+def test_pipeline_f32_ell400_coefficients_one_update_at_a_time():
+    # n_max so large that one update's P (t x n_max, 640 MB) passes the cap on
+    # the per-update P slices: the Alg. 4 / Alg. 8 phases of the flush's three
+    # updates run one update at a time on the second stream
+    log("pipeline f32 lowrank 8192 x 500, l=400, t=200, n_max=400000, one flush")
+    A = synth.lowrank(8192, 500, seed=synth.data_seed(5), rank=450, decay=300.0)
+    _pipeline(A, 400, 200, 200, "f32", 1005, 2005, n_max=400_000, lookahead=1024)
 
 
 def test_pipeline_bf16_channel_operand_rounding():
