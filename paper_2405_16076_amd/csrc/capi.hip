@@ -113,6 +113,8 @@ struct rid_stream {
   int64_t *J = nullptr, *J_hist = nullptr;
   uint64_t* colptr_dev = nullptr;
   uint64_t* colptr_host = nullptr;  // pinned
+  hipEvent_t colptr_ev = nullptr;   // after the last upload of colptr_host
+  bool colptr_pending = false;
   void* cpool = nullptr;
   void* ring = nullptr;
   int64_t ring_cap = 0, ring_ld = 0;
@@ -250,6 +252,8 @@ static void free_all(rid_stream* h) {
   if (h->side_ev) (void)hipEventDestroy(h->side_ev);
   if (h->coeff_ev) (void)hipEventDestroy(h->coeff_ev);
   h->coeff_ev = nullptr;
+  if (h->colptr_ev) (void)hipEventDestroy(h->colptr_ev);
+  h->colptr_ev = nullptr;
   if (h->side) (void)hipStreamDestroy(h->side);
   h->side_ev = nullptr;
   h->side = nullptr;
@@ -478,7 +482,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
 #undef ALLOC
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->side_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->coeff_ev, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->coeff_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->colptr_ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     st = fail(nullptr, RID_EDEVICE, "side stream creation failed");
     goto fail_alloc;
@@ -571,6 +576,8 @@ static rid_status upload_colptrs(rid_stream* h) {
     const int64_t n = h->n_pushed - h->n_uploaded;
     RID_HIP(h, hipMemcpyAsync(h->colptr_dev + h->n_uploaded, h->colptr_host + h->n_uploaded,
                               n * sizeof(uint64_t), hipMemcpyHostToDevice, h->s));
+    RID_HIP(h, hipEventRecord(h->colptr_ev, h->s));
+    h->colptr_pending = true;
     h->n_uploaded = h->n_pushed;
   }
   return RID_OK;
@@ -937,11 +944,17 @@ rid_status rid_reset(rid_stream* h) {
 
 }  // extern "C"
 
+// Without a host wait for the device: the main stream waits for the second
+// stream's work and clears the state behind the previous pass, so the host
+// can enqueue the next pass meanwhile; it only waits until the last upload
+// of the pinned column-pointer table has been copied, since the next pushes
+// rewrite that table from the start.
 static rid_status reset_stream(rid_stream* h) {
   if (h->failed) return fail(h, RID_ESTATE, "stream failed");
-  RID_HIP(h, hipStreamSynchronize(h->side));
-  RID_HIP(h, hipStreamSynchronize(h->s));
-  h->side_used = false;
+  rid_status st = join_side(h);
+  if (st != RID_OK) return st;
+  if (h->colptr_pending) RID_HIP(h, hipEventSynchronize(h->colptr_ev));
+  h->colptr_pending = false;
   const size_t ell = h->ell, t = h->t;
   h->sst_cur = 0;
   RID_HIP(h, hipMemsetAsync(h->SST[0], 0, ell * ell * 8, h->s));

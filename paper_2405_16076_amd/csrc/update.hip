@@ -907,8 +907,11 @@ __global__ __launch_bounds__(1024) void gram_kernel_b(Batched<UpdArgs> L) {
 
 // ---------------------------------------------------------------------------
 // Gram entries for binary32 data.  One workgroup of 4 waves per (row slab,
-// group of up to 16 output tiles of 32 x 32); a wave owns up to 4 tiles, each
-// as 2 x 2 blocks of v_mfma_f64_16x16x4_f64.  The staged columns (new slots,
+// group of output tiles); a wave owns up to 16 blocks of v_mfma_f64_16x16x4_f64.
+// When every slot is new (the product is symmetric) the tiles are 32 x 32
+// (2 x 2 blocks, 4 per wave, the upper triangle only); otherwise they are
+// 16 new x 32 occupied (1 x 2 blocks, 8 per wave), which pads a few new
+// columns to 16 instead of 32 and spreads them more evenly over the waves.  The staged columns (new slots,
 // then occupied slots unless the two lists coincide) are copied HBM -> LDS by
 // LDS-DMA in 32-row chunks, double-buffered, one chunk ahead.  MFMA step s of a
 // chunk pairs lane (i16, k4) with row 8 k4 + s of its column, so a lane's eight
@@ -918,20 +921,25 @@ __global__ __launch_bounds__(1024) void gram_kernel_b(Batched<UpdArgs> L) {
 // ---------------------------------------------------------------------------
 constexpr int kGramKC = 32;
 constexpr int kGramWaves = 4;
-constexpr int kGramTPW = 4;                        // tiles per wave
-constexpr int kGramGroup = kGramWaves * kGramTPW;  // tiles per workgroup
+constexpr int kGramTPW = 4;                        // 32 x 32 tiles per wave
+constexpr int kGramGroup = kGramWaves * kGramTPW;  // 32 x 32 tiles per workgroup
 
 __host__ __device__ inline int gram_stage_cols(int t) { return (2 * t + 7) / 8 * 8; }
 
-__device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
+// TX: 16-row blocks of new columns per tile (2: square tiles of the symmetric
+// case, 1: the general case).  The launch's tile groups, sized for 32 x 32
+// tiles, also cover the 16 x 32 ones: twice the tiles per group, at most twice
+// as many tile rows.
+template <int TX>
+__device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, const int nq, const int nj,
+                                               const bool sym) {
   extern __shared__ __attribute__((aligned(1024))) float gsm[];
+  constexpr int TPW = 4 * 2 / TX;        // tiles per wave
+  constexpr int GROUP = kGramWaves * TPW;  // tiles per workgroup
   const DevScalars* sc = a.sc;
-  const int nq = sc->n_new, nj = sc->n_occ;
-  if (nq == 0) return;
-  const bool sym = (nq == nj);
-  const int TQ = (nq + 31) / 32, TJ = (nj + 31) / 32;
+  const int TQ = (nq + 16 * TX - 1) / (16 * TX), TJ = (nj + 31) / 32;
   const int NT = sym ? TQ * (TQ + 1) / 2 : TQ * TJ;
-  const int g0 = bk.y * kGramGroup;
+  const int g0 = bk.y * GROUP;
   if (g0 >= NT) return;
   const int ncap = gram_stage_cols(a.t);
   const int ncol = sym ? nq : nq + nj;
@@ -989,14 +997,14 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
   };
 
   // this wave's tiles
-  int tq[kGramTPW], tj[kGramTPW];
+  int tq[TPW], tj[TPW];
   int ntw = 0;
 #pragma unroll
-  for (int ti = 0; ti < kGramTPW; ++ti) {
+  for (int ti = 0; ti < TPW; ++ti) {
     const int tile = g0 + wave + kGramWaves * ti;
     tq[ti] = 0;
     tj[ti] = 0;
-    if (tile < NT && tile < g0 + kGramGroup) {
+    if (tile < NT && tile < g0 + GROUP) {
       if (sym) {
         int r = 0, rem = tile;
         while (rem >= TQ - r) {
@@ -1012,11 +1020,11 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
       ntw = ti + 1;
     }
   }
-  f64x4_g acc[kGramTPW][2][2];
+  f64x4_g acc[TPW][TX][2];
 #pragma unroll
-  for (int ti = 0; ti < kGramTPW; ++ti)
+  for (int ti = 0; ti < TPW; ++ti)
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < TX; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) acc[ti][x][y] = f64x4_g{0.0, 0.0, 0.0, 0.0};
 
@@ -1061,20 +1069,20 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
     if (copy_pool) pool_copy(c, cur);
     const int st = cur;
 #pragma unroll
-    for (int ti = 0; ti < kGramTPW; ++ti) {
+    for (int ti = 0; ti < TPW; ++ti) {
       if (ti < ntw) {
-        float fa[2][8], fb[2][8];
+        float fa[TX][8], fb[2][8];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) frag(st, 32 * tq[ti] + 16 * x + i16, fa[x]);
+        for (int x = 0; x < TX; ++x) frag(st, 16 * TX * tq[ti] + 16 * x + i16, fa[x]);
 #pragma unroll
         for (int y = 0; y < 2; ++y) frag(st, (sym ? 0 : nq) + 32 * tj[ti] + 16 * y + i16, fb[y]);
         // on a diagonal tile of the symmetric case the lower-left block is the
         // transpose of the upper-right one: it is mirrored at the end instead
-        const bool diag = sym && tq[ti] == tj[ti];
+        const bool diag = TX == 2 && sym && tq[ti] == tj[ti];
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8)
 #pragma unroll
-          for (int x = 0; x < 2; ++x)
+          for (int x = 0; x < TX; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y)
               if (!(diag && x == 1 && y == 0))
@@ -1089,11 +1097,11 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
 
   double* out = a.gpart + (int64_t)slab * a.t * a.t;
 #pragma unroll
-  for (int ti = 0; ti < kGramTPW; ++ti) {
+  for (int ti = 0; ti < TPW; ++ti) {
     if (ti >= ntw) continue;
-    const bool diag = sym && tq[ti] == tj[ti];
+    const bool diag = TX == 2 && sym && tq[ti] == tj[ti];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < TX; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         if (diag && x == 1 && y == 0) continue;  // written as the mirror of (0, 1)
@@ -1101,13 +1109,22 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
         if (j >= nj) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int q = 32 * tq[ti] + 16 * x + k4 + 4 * v;
+          const int q = 16 * TX * tq[ti] + 16 * x + k4 + 4 * v;
           if (q >= nq) continue;
           out[(int64_t)q * a.t + j] = acc[ti][x][y][v];
           if (sym && (tj[ti] > tq[ti] || (x == 0 && y == 1))) out[(int64_t)j * a.t + q] = acc[ti][x][y][v];
         }
       }
   }
+}
+
+__device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
+  const int nq = a.sc->n_new, nj = a.sc->n_occ;
+  if (nq == 0) return;
+  if (nq == nj)
+    gram_f32_tiles<2>(a, bk, nq, nj, true);
+  else
+    gram_f32_tiles<1>(a, bk, nq, nj, false);
 }
 
 __global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) { gram_f32_body(a, own_block()); }
