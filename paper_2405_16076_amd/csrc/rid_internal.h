@@ -198,7 +198,13 @@ struct DevScalars {
   int32_t new_src[kMaxT];    // their position in the buffer
   int32_t occ_slot[kMaxT];   // occupied slots in slot order
   int32_t slot_src[kMaxT];   // buffer position of a slot filled by the running update, else -1
+  int32_t old_slot[kMaxT];   // occupied slots not filled by the running update, in slot order
 };
+
+// Column j of the Gram's list: the new slots first, then the other occupied ones.
+__device__ inline int gram_slot(const DevScalars* sc, int j) {
+  return j < sc->n_new ? sc->new_slot[j] : sc->old_slot[j - sc->n_new];
+}
 
 // ---------------------------------------------------------------------------
 // LDS-DMA staging (global_load_lds_dwordx4) shared by the streaming kernels.

@@ -741,13 +741,16 @@ __device__ __forceinline__ void select_body(const UpdArgs& a, const Blk bk) {
   }
   __syncthreads();
   if (lane == 0) {
-    int n_occ = 0;
+    int n_occ = 0, n_old = 0;
     for (int i = 0; i < a.t; ++i) sc->slot_src[i] = -1;
     for (int q = 0; q < n_new; ++q) sc->slot_src[sc->new_slot[q]] = sc->new_src[q];
     for (int i = 0; i < a.t; ++i) {
       const int64_t Ji = a.J[i];
       a.J_hist[a.u * a.t + i] = Ji;
-      if (Ji >= 0) sc->occ_slot[n_occ++] = i;
+      if (Ji >= 0) {
+        sc->occ_slot[n_occ++] = i;
+        if (sc->slot_src[i] < 0) sc->old_slot[n_old++] = i;
+      }
     }
     sc->n_new = n_new;
     sc->n_occ = n_occ;
@@ -770,6 +773,7 @@ __global__ __launch_bounds__(64) void select_kernel_b(Batched<UpdArgs> L) {
 // Gram entries of the new basis columns, fused with their copy into the pool.
 // One workgroup of 16 waves per (row slab, tile of up to 160 new slots, tile
 // of up to 160 occupied slots), so each basis column is read once per slab.
+// Occupied slots are taken in the Gram's list order (new slots first).
 // Per 32-row chunk the q columns (new slots, read from the buffered snapshot)
 // and the j columns (occupied slots: the snapshot for new ones, the pool for
 // kept ones) are staged in LDS in 128-byte runs; 16 x 16 blocks of the tile
@@ -832,7 +836,7 @@ __device__ __forceinline__ void gram_body(const UpdArgs& a, const Blk bk) {
         lds = sq + col * LDC + 4 * rgp;
       } else {
         const int jj = jt * kGramTile + (col - nq);
-        const int slot = sc->occ_slot[jj];
+        const int slot = gram_slot(sc, jj);
         const int s = sc->slot_src[slot];
         src = gload_ptr((s >= 0) ? reinterpret_cast<const T*>(a.colptr[a.c0 + s]) : cpool + (int64_t)slot * a.ldc);
         lds = sj + (col - nq) * LDC + 4 * rgp;
@@ -906,14 +910,17 @@ __global__ __launch_bounds__(1024) void gram_kernel_b(Batched<UpdArgs> L) {
 }
 
 // ---------------------------------------------------------------------------
-// Gram entries for binary32 data.  One workgroup of 4 waves per (row slab,
-// group of output tiles); a wave owns up to 16 blocks of v_mfma_f64_16x16x4_f64.
-// When every slot is new (the product is symmetric) the tiles are 32 x 32
-// (2 x 2 blocks, 4 per wave, the upper triangle only); otherwise they are
-// 16 new x 32 occupied (1 x 2 blocks, 8 per wave), which pads a few new
-// columns to 16 instead of 32 and spreads them more evenly over the waves.  The staged columns (new slots,
-// then occupied slots unless the two lists coincide) are copied HBM -> LDS by
-// LDS-DMA in 32-row chunks, double-buffered, one chunk ahead.  MFMA step s of a
+// Gram entries for binary32 data.  The staged list is the Gram's column list
+// (new slots, then the other occupied ones); the products are its first nq
+// columns against all of it, and the reduction needs only the entries (q, j)
+// with j >= q or j >= nq, the others being mirrors.  One workgroup of 4 waves
+// per (row slab, group of output tiles); a wave owns up to 16 blocks of
+// v_mfma_f64_16x16x4_f64.  When every slot is new the tiles are 32 x 32 (2 x 2
+// blocks, 4 per wave, upper triangle); otherwise 16 x 32 (1 x 2 blocks, 8 per
+// wave, so a few new columns pad to 16 rather than 32), skipping the tiles
+// that lie wholly below the diagonal of the new-by-new part.  The
+// columns are copied HBM -> LDS by LDS-DMA in 32-row chunks, double-buffered,
+// one chunk ahead.  MFMA step s of a
 // chunk pairs lane (i16, k4) with row 8 k4 + s of its column, so a lane's eight
 // operands of one column are one contiguous 32-byte run (two ds_read_b128).
 // Products of binary32 data are exact in binary64 and all sums are binary64.
@@ -924,27 +931,36 @@ constexpr int kGramWaves = 4;
 constexpr int kGramTPW = 4;                        // 32 x 32 tiles per wave
 constexpr int kGramGroup = kGramWaves * kGramTPW;  // 32 x 32 tiles per workgroup
 
-__host__ __device__ inline int gram_stage_cols(int t) { return (2 * t + 7) / 8 * 8; }
+__host__ __device__ inline int gram_stage_cols(int t) { return (t + 7) / 8 * 8; }
 
-// TX: 16-row blocks of new columns per tile (2: square tiles of the symmetric
-// case, 1: the general case).  The launch's tile groups, sized for 32 x 32
+// Leading 16 x 32 tiles of tile row r (new columns 16 r .. 16 r + 15) that lie
+// wholly below the diagonal of the new-by-new part (columns 32 c .. 32 c + 31
+// all new and all before 16 r): they hold no entry the reduction reads.
+__device__ inline int gram_skip_tiles(int r, int nq) { return min(r / 2, nq / 32); }
+
+// TX: 16-row blocks of new columns per tile (2: square tiles when every slot
+// is new, 1: the general case).  The launch's tile groups, sized for 32 x 32
 // tiles, also cover the 16 x 32 ones: twice the tiles per group, at most twice
 // as many tile rows.
 template <int TX>
-__device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, const int nq, const int nj,
-                                               const bool sym) {
+__device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, const int nq, const int nj) {
+  constexpr bool sym = TX == 2;
   extern __shared__ __attribute__((aligned(1024))) float gsm[];
   constexpr int TPW = 4 * 2 / TX;        // tiles per wave
   constexpr int GROUP = kGramWaves * TPW;  // tiles per workgroup
   const DevScalars* sc = a.sc;
   const int TQ = (nq + 16 * TX - 1) / (16 * TX), TJ = (nj + 31) / 32;
-  const int NT = sym ? TQ * (TQ + 1) / 2 : TQ * TJ;
+  int NT = TQ * (TQ + 1) / 2;
+  if (!sym) {
+    NT = 0;
+    for (int r = 0; r < TQ; ++r) NT += TJ - gram_skip_tiles(r, nq);
+  }
   const int g0 = bk.y * GROUP;
   if (g0 >= NT) return;
   const int ncap = gram_stage_cols(a.t);
-  const int ncol = sym ? nq : nq + nj;
+  const int ncol = nj;
   const int nblk = (ncol + 7) / 8;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int i16 = lane & 15, k4 = lane >> 4;
   const int slab = bk.x;
   const int64_t r0 = (int64_t)slab * a.gslab_rows;
@@ -957,14 +973,10 @@ __device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, c
   const float* cpool = reinterpret_cast<const float*>(a.cpool);
   for (int c = tid; c < nblk * 8; c += kGramWaves * 64) {
     const int cc = c < ncol ? c : 0;  // columns past the list copy column 0 (results dropped)
-    const float* pc;
-    if (cc < nq) {
-      pc = reinterpret_cast<const float*>(a.colptr[a.c0 + sc->new_src[cc]]);
-    } else {
-      const int slot = sc->occ_slot[cc - nq];
-      const int s = sc->slot_src[slot];
-      pc = (s >= 0) ? reinterpret_cast<const float*>(a.colptr[a.c0 + s]) : cpool + (int64_t)slot * a.ldc;
-    }
+    const int slot = gram_slot(sc, cc);
+    const int s = sc->slot_src[slot];  // >= 0 exactly for the new slots
+    const float* pc =
+        (s >= 0) ? reinterpret_cast<const float*>(a.colptr[a.c0 + s]) : cpool + (int64_t)slot * a.ldc;
     srcs[c] = reinterpret_cast<uint64_t>(pc);
   }
   // pool slots of the new columns
@@ -1005,8 +1017,8 @@ __device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, c
     tq[ti] = 0;
     tj[ti] = 0;
     if (tile < NT && tile < g0 + GROUP) {
+      int r = 0, rem = tile;
       if (sym) {
-        int r = 0, rem = tile;
         while (rem >= TQ - r) {
           rem -= TQ - r;
           ++r;
@@ -1014,8 +1026,12 @@ __device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, c
         tq[ti] = r;
         tj[ti] = r + rem;
       } else {
-        tq[ti] = tile / TJ;
-        tj[ti] = tile % TJ;
+        while (rem >= TJ - gram_skip_tiles(r, nq)) {
+          rem -= TJ - gram_skip_tiles(r, nq);
+          ++r;
+        }
+        tq[ti] = r;
+        tj[ti] = gram_skip_tiles(r, nq) + rem;
       }
       ntw = ti + 1;
     }
@@ -1075,10 +1091,9 @@ __device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, c
 #pragma unroll
         for (int x = 0; x < TX; ++x) frag(st, 16 * TX * tq[ti] + 16 * x + i16, fa[x]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) frag(st, (sym ? 0 : nq) + 32 * tj[ti] + 16 * y + i16, fb[y]);
-        // on a diagonal tile of the symmetric case the lower-left block is the
-        // transpose of the upper-right one: it is mirrored at the end instead
-        const bool diag = TX == 2 && sym && tq[ti] == tj[ti];
+        for (int y = 0; y < 2; ++y) frag(st, 32 * tj[ti] + 16 * y + i16, fb[y]);
+        // on a diagonal 32 x 32 tile the lower-left block is not needed
+        const bool diag = sym && tq[ti] == tj[ti];
 #pragma unroll
         for (int s8 = 0; s8 < 8; ++s8)
 #pragma unroll
@@ -1099,20 +1114,17 @@ __device__ __forceinline__ void gram_f32_tiles(const UpdArgs& a, const Blk bk, c
 #pragma unroll
   for (int ti = 0; ti < TPW; ++ti) {
     if (ti >= ntw) continue;
-    const bool diag = TX == 2 && sym && tq[ti] == tj[ti];
 #pragma unroll
     for (int x = 0; x < TX; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
-        if (diag && x == 1 && y == 0) continue;  // written as the mirror of (0, 1)
+        if (sym && tq[ti] == tj[ti] && x == 1 && y == 0) continue;  // not computed
         const int j = 32 * tj[ti] + 16 * y + i16;
         if (j >= nj) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int q = 16 * TX * tq[ti] + 16 * x + k4 + 4 * v;
-          if (q >= nq) continue;
-          out[(int64_t)q * a.t + j] = acc[ti][x][y][v];
-          if (sym && (tj[ti] > tq[ti] || (x == 0 && y == 1))) out[(int64_t)j * a.t + q] = acc[ti][x][y][v];
+          if (q < nq) out[(int64_t)q * a.t + j] = acc[ti][x][y][v];
         }
       }
   }
@@ -1122,9 +1134,9 @@ __device__ __forceinline__ void gram_f32_body(const UpdArgs& a, const Blk bk) {
   const int nq = a.sc->n_new, nj = a.sc->n_occ;
   if (nq == 0) return;
   if (nq == nj)
-    gram_f32_tiles<2>(a, bk, nq, nj, true);
+    gram_f32_tiles<2>(a, bk, nq, nj);
   else
-    gram_f32_tiles<1>(a, bk, nq, nj, false);
+    gram_f32_tiles<1>(a, bk, nq, nj);
 }
 
 __global__ __launch_bounds__(256, 2) void gram_f32_kernel(UpdArgs a) { gram_f32_body(a, own_block()); }
@@ -1154,10 +1166,12 @@ __global__ void gram_zero_kernel_b(Batched<UpdArgs> L) {
 __device__ __forceinline__ void gram_reduce_body(const UpdArgs& a, const Blk bk) {
   const DevScalars* sc = a.sc;
   const int q = bk.x, jj = threadIdx.x + bk.y * blockDim.x;
-  if (q >= sc->n_new || jj >= sc->n_occ) return;
+  // jj indexes the Gram's list (new slots first); an entry between two new
+  // slots is taken from the pair with jj >= q
+  if (q >= sc->n_new || jj >= sc->n_occ || (jj < sc->n_new && jj < q)) return;
   double s = 0.0;
   for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
-  const int si = sc->new_slot[q], sj = sc->occ_slot[jj];
+  const int si = sc->new_slot[q], sj = gram_slot(sc, jj);
   a.G[(int64_t)sj * a.t + si] = s;
   a.G[(int64_t)si * a.t + sj] = s;
 }

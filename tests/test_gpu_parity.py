@@ -336,6 +336,40 @@ def test_gram_and_estimate_terms_after_first_update(dtype):
         assert abs(g[k] - h[k]) <= 1e-7 * max(abs(h[k]), o.F), k
 
 
+@pytest.mark.parametrize("dtype,m,t,growth", [(np.float32, 20_011, 150, 1.02), (np.float32, 9_001, 100, 1.0),
+                                              (np.float64, 8_011, 100, 1.0)])
+def test_gram_after_every_update(dtype, m, t, growth):
+    # after each update G must equal A_J^T A_J of that update's J; partial
+    # refills of varied size exercise the new-by-new blocks taken from their
+    # mirrors and the blocks past the ends of the lists
+    from paper_2405_16076_amd import OnlineRID, StreamConfig
+    rng = np.random.default_rng(29)
+    n, ell = 5 * t, 2 * t
+    A = (rng.standard_normal((n, m)) * (growth ** np.arange(n))[:, None]).astype(dtype)
+    dt = torch.float64 if dtype == np.float64 else torch.float32
+    sk = "f64" if dtype == np.float64 else "f32"
+    cfg = StreamConfig(m=m, ell=ell, k=t, t=t, n_max=n, dtype=dt, sketch=sk, omega_seed=51, select_seed=52)
+    s = OnlineRID(cfg)
+    ld = (m + 15) // 16 * 16  # borrowed columns start on 64-byte boundaries
+    Xp = torch.zeros((n, ld), dtype=dt, device="cuda:0")
+    Xp[:, :m] = torch.from_numpy(A).to("cuda:0")
+    X = Xp[:, :m]
+    A64 = A.T.astype(np.float64)
+    fills = []
+    for u, j0 in enumerate(range(0, n, t)):
+        s.push(X[j0:j0 + t], borrow=True)
+        J = s.select()
+        fills.append(s.update(u)["n_filled"])
+        _, _, G = s.debug_state()
+        occ = np.flatnonzero(J >= 0)
+        Gx = np.zeros((t, t))
+        Gx[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
+        err = np.abs(G - Gx) / np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)) + 1e-300)
+        assert err.max() <= 1e-13, (u, fills, float(err.max()))
+    log(f"  filled per update {fills}")
+    assert any(0 < f < t for f in fills[1:]), fills
+
+
 @pytest.mark.parametrize("growth", [1.0, 1.03])
 def test_gram_incremental_matches_exact_products(growth):
     # G is built incrementally over several updates (all-new first update, then
