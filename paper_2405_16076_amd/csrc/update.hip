@@ -1147,6 +1147,8 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel_b(Batched<UpdArgs> L) 
   if (batched_block(L, p, bk)) gram_f32_body(*p, bk);
 }
 
+constexpr int kGramReduceWaves = 4;
+
 // Zero the Gram rows/columns of empty slots, then write the new entries
 // (fixed-order sum over slabs), symmetrically.
 __device__ __forceinline__ void gram_zero_body(const UpdArgs& a, const Blk bk) {
@@ -1163,17 +1165,33 @@ __global__ void gram_zero_kernel_b(Batched<UpdArgs> L) {
   if (batched_block(L, p, bk)) gram_zero_body(*p, bk);
 }
 
+// One workgroup of 4 waves per (new slot q, 64 list entries): wave w sums the
+// w-th quarter of the row slabs in order, then the quarters are added in order.
 __device__ __forceinline__ void gram_reduce_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double part[kGramReduceWaves][64];
   const DevScalars* sc = a.sc;
-  const int q = bk.x, jj = threadIdx.x + bk.y * blockDim.x;
+  const int q = bk.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int jj = bk.y * 64 + lane;
+  const int nq = sc->n_new;
+  if (q >= nq) return;  // the same for the whole workgroup
   // jj indexes the Gram's list (new slots first); an entry between two new
   // slots is taken from the pair with jj >= q
-  if (q >= sc->n_new || jj >= sc->n_occ || (jj < sc->n_new && jj < q)) return;
+  const bool act = jj < sc->n_occ && !(jj < nq && jj < q);
   double s = 0.0;
-  for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
+  if (act) {
+    const int per = (a.gslabs + kGramReduceWaves - 1) / kGramReduceWaves;
+    const int s1 = min(a.gslabs, (w + 1) * per);
+    for (int sl = w * per; sl < s1; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w != 0 || !act) return;
+  double tot = part[0][lane];
+#pragma unroll
+  for (int i = 1; i < kGramReduceWaves; ++i) tot += part[i][lane];
   const int si = sc->new_slot[q], sj = gram_slot(sc, jj);
-  a.G[(int64_t)sj * a.t + si] = s;
-  a.G[(int64_t)si * a.t + sj] = s;
+  a.G[(int64_t)sj * a.t + si] = tot;
+  a.G[(int64_t)si * a.t + sj] = tot;
 }
 
 __global__ void gram_reduce_kernel(UpdArgs a) { gram_reduce_body(a, own_block()); }
@@ -2384,7 +2402,7 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(gram_f32_kernel, dim3(a.gslabs, groups), dim3(64 * kGramWaves), lds, s, a);
   }
   hipLaunchKernelGGL(gram_zero_kernel, dim3(a.t), dim3(kMaxT), 0, s, a);
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(a.t, 1), dim3(kMaxT), 0, s, a);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(a.t, (a.t + 63) / 64), dim3(64 * kGramReduceWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2580,8 +2598,8 @@ void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch
   Planner<UpdArgs> P;
   for (int i = 0; i < ns; ++i) P.add(fn(gram_zero_kernel_b), h[i], make_int4(h[i].t, 1, 1, 0));
   P.emit(dim3(kMaxT), -1, st, out);
-  for (int i = 0; i < ns; ++i) P.add(fn(gram_reduce_kernel_b), h[i], make_int4(h[i].t, 1, 1, 0));
-  P.emit(dim3(kMaxT), -1, st, out);
+  for (int i = 0; i < ns; ++i) P.add(fn(gram_reduce_kernel_b), h[i], make_int4(h[i].t, (h[i].t + 63) / 64, 1, 0));
+  P.emit(dim3(64 * kGramReduceWaves), -1, st, out);
 }
 
 void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out, const bool* want_p) {
