@@ -685,69 +685,87 @@ __global__ __launch_bounds__(64) void scores_fin_kernel_b(Batched<UpdArgs> L) {
 }
 
 // ---------------------------------------------------------------------------
-// Prune / fill.  One wave; slots in order; the fill scan evaluates 64
-// candidate draws at once and takes the first success.
+// Prune / fill (Alg. 3).  One wave: the prune draws of all slots at once,
+// then the fills in slot order; the fill scan evaluates 64 candidate draws at
+// once and takes the first success.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void select_body(const UpdArgs& a, const Blk bk) {
+  // the slot state and the buffer's scores are staged in LDS: the fill scan
+  // below is serial over the slots and would otherwise wait on global loads
   __shared__ int used[kMaxT];
+  __shared__ int64_t sJ[kMaxT];
+  __shared__ double stold[kMaxT], stauD[kMaxT];
   const int lane = threadIdx.x;
   DevScalars* sc = a.sc;
+  const int t = a.t;
+  const bool skip = a.skipu[a.u] != 0;
   for (int r = lane; r < kMaxT; r += 64) used[r] = 0;
+  for (int r = lane; r < a.cnt; r += 64) stauD[r] = a.tauD[r];
+  // prune draws: each slot's decision depends on that slot alone
+  int n_pruned = 0;
+  for (int i = lane; i < t; i += 64) {
+    int64_t Ji = a.J[i];
+    double told = a.tau_old[i];
+    if (!skip && Ji >= 0) {
+      const double tc = a.tauC[i];
+      const double p = 1.0 - tc / told;
+      const double U = decision_uniform(a.select_seed, (uint32_t)a.u, (uint32_t)i, kPruneDraw);
+      if (U < p) {
+        Ji = -1;
+        told = 1.0;
+        ++n_pruned;
+      } else {
+        told = tc;
+      }
+    }
+    sJ[i] = Ji;
+    stold[i] = told;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) n_pruned += __shfl_xor(n_pruned, off);
   __syncthreads();
-  int n_new = 0, n_pruned = 0;
-  if (!a.skipu[a.u]) {
-    for (int i = 0; i < a.t; ++i) {
-      int64_t Ji = a.J[i];
-      if (Ji >= 0) {
-        const double p = 1.0 - a.tauC[i] / a.tau_old[i];
-        const double U = decision_uniform(a.select_seed, (uint32_t)a.u, (uint32_t)i, kPruneDraw);
-        if (U < p) {
-          Ji = -1;
-          ++n_pruned;
+  // fills, in slot order: each empty slot takes the first buffered column,
+  // not taken by an earlier slot, whose draw falls below its probability
+  int n_new = 0;
+  if (!skip) {
+    for (int i = 0; i < t; ++i) {
+      if (sJ[i] >= 0) continue;
+      for (int base = 0; base < a.cnt; base += 64) {
+        const int r = base + lane;
+        bool hit = false;
+        if (r < a.cnt && !used[r]) {
+          const double q = fmin(1.0, a.fill_mult * stauD[r]);
+          hit = decision_uniform(a.select_seed, (uint32_t)a.u, (uint32_t)i, (uint32_t)r) < q;
+        }
+        const uint64_t ball = __ballot(hit);
+        if (ball) {
+          const int rs = base + __ffsll((unsigned long long)ball) - 1;
           if (lane == 0) {
-            a.J[i] = -1;
-            a.tau_old[i] = 1.0;
+            sJ[i] = a.c0 + rs;
+            stold[i] = stauD[rs];
+            used[rs] = 1;
+            sc->new_slot[n_new] = i;
+            sc->new_src[n_new] = rs;
           }
-        } else if (lane == 0) {
-          a.tau_old[i] = a.tauC[i];
+          __syncthreads();
+          ++n_new;
+          break;
         }
       }
-      if (Ji < 0) {
-        for (int base = 0; base < a.cnt; base += 64) {
-          const int r = base + lane;
-          bool hit = false;
-          if (r < a.cnt && !used[r]) {
-            const double q = fmin(1.0, a.fill_mult * a.tauD[r]);
-            hit = decision_uniform(a.select_seed, (uint32_t)a.u, (uint32_t)i, (uint32_t)r) < q;
-          }
-          const uint64_t ball = __ballot(hit);
-          if (ball) {
-            const int rs = base + __ffsll((unsigned long long)ball) - 1;
-            if (lane == 0) {
-              a.J[i] = a.c0 + rs;
-              a.tau_old[i] = a.tauD[rs];
-              used[rs] = 1;
-              sc->new_slot[n_new] = i;
-              sc->new_src[n_new] = rs;
-            }
-            __syncthreads();
-            ++n_new;
-            break;
-          }
-        }
-      }
-      __syncthreads();
     }
   }
   __syncthreads();
+  for (int i = lane; i < t; i += 64) {
+    a.J[i] = sJ[i];
+    a.tau_old[i] = stold[i];
+    a.J_hist[a.u * t + i] = sJ[i];
+  }
   if (lane == 0) {
     int n_occ = 0, n_old = 0;
-    for (int i = 0; i < a.t; ++i) sc->slot_src[i] = -1;
+    for (int i = 0; i < t; ++i) sc->slot_src[i] = -1;
     for (int q = 0; q < n_new; ++q) sc->slot_src[sc->new_slot[q]] = sc->new_src[q];
-    for (int i = 0; i < a.t; ++i) {
-      const int64_t Ji = a.J[i];
-      a.J_hist[a.u * a.t + i] = Ji;
-      if (Ji >= 0) {
+    for (int i = 0; i < t; ++i) {
+      if (sJ[i] >= 0) {
         sc->occ_slot[n_occ++] = i;
         if (sc->slot_src[i] < 0) sc->old_slot[n_old++] = i;
       }
