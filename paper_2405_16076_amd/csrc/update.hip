@@ -10,6 +10,7 @@
 //                  G = A_J^T A_J (Alg. 5 step 1, reused by Alg. 8 step 1)
 //   alg4_qr/apply  P = (Omega A_J)^+ (Omega A_obs) by Householder QR (Alg. 4)
 //   hutch_*        NA-Hutch++ estimate of ||A_obs - A_J P||_F^2 (Alg. 8)
+#include <type_traits>
 #include "rid_internal.h"
 
 #include <algorithm>
@@ -531,8 +532,9 @@ __global__ __launch_bounds__(1024) void tridiag_kernel_b(Batched<BatchArgs> L) {
 // per column), the product on the matrix cores (scores_gemm_kernel), then the
 // L D L^T recurrence per item (scores_fin_kernel).
 // ---------------------------------------------------------------------------
+// EM = ceil(l / 64) elements of a column per lane.
+template <int EM>
 __device__ __forceinline__ void scores_q_body(const UpdArgs& a, const Blk bk) {
-  constexpr int EM = kMaxEll / 64;
   const int i = bk.x, n = a.ell, lane = threadIdx.x;
   if (a.skipu[a.u] || i >= n) return;
   const double* htau = a.hv;
@@ -653,10 +655,12 @@ __device__ __forceinline__ void scores_fin_body(const UpdArgs& a, const Blk bk) 
   }
 }
 
-__global__ __launch_bounds__(64) void scores_q_kernel(UpdArgs a) { scores_q_body(a, own_block()); }
+template <int EM>
+__global__ __launch_bounds__(64) void scores_q_kernel(UpdArgs a) { scores_q_body<EM>(a, own_block()); }
 
 // Q of every update of a flush in one launch: block (i, z) forms column i of
 // the Q of update a.u + z from that update's slices of W, hv and Qs.
+template <int EM>
 __global__ __launch_bounds__(64) void scores_q_all_kernel(UpdArgs a) {
   const int z = blockIdx.y;
   UpdArgs b = a;
@@ -664,12 +668,29 @@ __global__ __launch_bounds__(64) void scores_q_all_kernel(UpdArgs a) {
   b.W = a.W + (int64_t)z * a.ell * a.ell;
   b.hv = a.hv + (int64_t)z * 6 * a.ell;
   b.Qs = a.Qs + (int64_t)z * a.ell * a.ell;
-  scores_q_body(b, Blk{(int)blockIdx.x, 0, 0});
+  scores_q_body<EM>(b, Blk{(int)blockIdx.x, 0, 0});
 }
+template <int EM>
 __global__ __launch_bounds__(64) void scores_q_kernel_b(Batched<UpdArgs> L) {
   const UpdArgs* p;
   Blk bk;
-  if (batched_block(L, p, bk)) scores_q_body(*p, bk);
+  if (batched_block(L, p, bk)) scores_q_body<EM>(*p, bk);
+}
+
+// f(std::integral_constant<int, EM>) with EM = ceil(l / 64), the elements of
+// a column of Q per lane
+template <typename F>
+static void with_em(int ell, F&& f) {
+  switch ((ell + 63) / 64) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    default: f(std::integral_constant<int, 8>{}); break;
+  }
 }
 __global__ __launch_bounds__(256) void scores_gemm_kernel(UpdArgs a) { scores_gemm_body(a, own_block()); }
 __global__ __launch_bounds__(256) void scores_gemm_kernel_b(Batched<UpdArgs> L) {
@@ -2388,13 +2409,18 @@ hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
 
 // scores and selection (Alg. 3 steps 17-27)
 hipError_t launch_update_q_all(const UpdArgs& a0, int nz, hipStream_t s) {
-  hipLaunchKernelGGL(scores_q_all_kernel, dim3(a0.ell, nz), dim3(64), 0, s, a0);
+  with_em(a0.ell, [&](auto em) {
+    hipLaunchKernelGGL((scores_q_all_kernel<decltype(em)::value>), dim3(a0.ell, nz), dim3(64), 0, s, a0);
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_update_select(const UpdArgs& a, hipStream_t s, bool with_q) {
   const int items = a.t + a.cnt;
-  if (with_q) hipLaunchKernelGGL(scores_q_kernel, dim3(a.ell), dim3(64), 0, s, a);
+  if (with_q)
+    with_em(a.ell, [&](auto em) {
+      hipLaunchKernelGGL((scores_q_kernel<decltype(em)::value>), dim3(a.ell), dim3(64), 0, s, a);
+    });
   hipLaunchKernelGGL(scores_gemm_kernel, dim3(((a.ell + 31) / 32) * ((items + 31) / 32)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(scores_fin_kernel, dim3(items), dim3(64), 0, s, a);
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a);
@@ -2571,7 +2597,10 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
 
 void plan_update_q_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
   Planner<UpdArgs> P;
-  for (int i = 0; i < ns; ++i) P.add(fn(scores_q_kernel_b), h[i], make_int4(h[i].ell, 1, 1, 0));
+  for (int i = 0; i < ns; ++i)
+    with_em(h[i].ell, [&](auto em) {
+      P.add(fn(scores_q_kernel_b<decltype(em)::value>), h[i], make_int4(h[i].ell, 1, 1, 0));
+    });
   P.emit(dim3(64), -1, st, out);
 }
 

@@ -309,6 +309,25 @@ def test_reset_and_rerun_are_bitwise_identical():
     assert np.array_equal(s.coefficients(), P1)
 
 
+def test_back_to_back_passes_without_host_sync():
+    # rid_reset does not wait for the device: passes over two streams are
+    # enqueued one after another (copied and borrowed columns, the pinned
+    # column table rewritten each time) and the last one must equal a fresh run
+    A = synth.lowrank(20000, 120, seed=11, rank=30)
+    B = synth.lowrank(20000, 120, seed=12, rank=40)
+    sb = run_gpu(B, 32, 10, 10, "f32", 8, 9, batch=40)
+    JB, PB = sb.select(), sb.coefficients()
+    s = run_gpu(A, 32, 10, 10, "f32", 8, 9, batch=40)
+    XA, XB = s._data, sb._data
+    for X, borrow in ((XB, False), (XA, True), (XB, True), (XA, False), (XB, True)):
+        s.reset()
+        for j0 in range(0, 120, 25):
+            s.push(X[j0:j0 + 25], borrow=borrow)
+        s.finalize()
+    assert np.array_equal(s.select(), JB)
+    assert np.array_equal(s.coefficients(), PB)
+
+
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_gram_and_estimate_terms_after_first_update(dtype):
     # G = A_J^T A_J is formed from exact products in binary64; each NA-Hutch++
