@@ -957,11 +957,11 @@ __global__ __launch_bounds__(1024) void gram_kernel_b(Batched<UpdArgs> L) {
 // v_mfma_f64_16x16x4_f64.  When every slot is new the tiles are 32 x 32 (2 x 2
 // blocks, 4 per wave, upper triangle); otherwise 16 x 32 (1 x 2 blocks, 8 per
 // wave, so a few new columns pad to 16 rather than 32), skipping the tiles
-// that lie wholly below the diagonal of the new-by-new part.  The
-// columns are copied HBM -> LDS by LDS-DMA in 32-row chunks, double-buffered,
-// one chunk ahead.  MFMA step s of a
-// chunk pairs lane (i16, k4) with row 8 k4 + s of its column, so a lane's eight
-// operands of one column are one contiguous 32-byte run (two ds_read_b128).
+// that lie wholly below the diagonal of the new-by-new part.  The columns are
+// copied HBM -> LDS by LDS-DMA in 32-row chunks, double-buffered, one chunk
+// ahead.  MFMA step s of a chunk pairs lane (i16, k4) with row 8 k4 + s of its
+// column, so a lane's eight operands of one column are one contiguous 32-byte
+// run (two ds_read_b128).
 // Products of binary32 data are exact in binary64 and all sums are binary64.
 // Workgroups of tile group 0 also copy the new columns into the pool.
 // ---------------------------------------------------------------------------
