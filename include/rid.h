@@ -186,7 +186,11 @@ rid_status rid_flush(rid_stream* h);
 rid_status rid_finalize(rid_stream* h);
 
 /* Restarts the stream (no columns observed, empty basis) keeping its
- * allocations.  Asynchronous.  Errors: RID_ESTATE (failed). */
+ * allocations.  Asynchronous: the state is cleared in stream order after all
+ * earlier work of the handle; the host waits only until the previous upload
+ * of the column-pointer table has been copied.  Borrowed buffers of the
+ * previous pass stay in use until that earlier work has run.  Errors:
+ * RID_ESTATE (failed). */
 rid_status rid_reset(rid_stream* h);
 
 /* Copies the current index set J (slot order, -1 = empty) into the host array
