@@ -224,7 +224,7 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x, d
   return cnt;
 }
 
-template <int EMT>
+template <int EMT, int NW>
 __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   __shared__ double e2s[kMaxEll];
   __shared__ double ds[kMaxEll];
@@ -261,7 +261,7 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   // j + 1 + lane + 64 q.  EMT = ceil(l / 64); the columns of a wave go CB at a
   // time, their loads issued together (the step is bound by L2 latency).
   constexpr int CB = EMT <= 3 ? 4 : (EMT <= 5 ? 3 : (EMT <= 6 ? 2 : 1));
-  __shared__ double ppart[16][kMaxEll];
+  __shared__ double ppart[NW][kMaxEll];
   __shared__ double pd[kMaxEll];
   __shared__ double vs[2][kMaxEll];   // reflector of step j at [j & 1]
   __shared__ double ps[2][kMaxEll];   // p of step j at [j & 1]
@@ -512,13 +512,15 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
 }
 
 template <int EMT>
-__global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) { tridiag_body<EMT>(b, own_block()); }
+__global__ __launch_bounds__(1024) void tridiag_kernel(BatchArgs b) { tridiag_body<EMT, 16>(b, own_block()); }
 
-template <int EMT>
-__global__ __launch_bounds__(1024) void tridiag_kernel_b(Batched<BatchArgs> L) {
+// NW waves per workgroup: 16 when the launch's workgroups fit on the compute
+// units one each; 8 (two workgroups per compute unit) when they do not.
+template <int EMT, int NW>
+__global__ __launch_bounds__(64 * NW) void tridiag_kernel_b(Batched<BatchArgs> L) {
   const BatchArgs* p;
   Blk bk;
-  if (batched_block(L, p, bk)) tridiag_body<EMT>(*p, bk);
+  if (batched_block(L, p, bk)) tridiag_body<EMT, NW>(*p, bk);
 }
 
 // ---------------------------------------------------------------------------
@@ -2578,21 +2580,31 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
     P.add(fn(sst_batch_kernel_b), h[i], make_int4(nt * (nt + 1) / 2, 1, 1, 0));
   }
   P.emit(dim3(256), -1, st, out);
+  // one workgroup per (stream, update); past one per compute unit the
+  // workgroups go two to a unit at half the waves instead of in turns
+  int total = 0, dev = 0, n_cu = 0;
+  for (int i = 0; i < ns; ++i) total += h[i].nz;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    n_cu = 0;
+  const bool half = n_cu > 0 && total > n_cu;
   for (int i = 0; i < ns; ++i) {
     const void* f;
+#define RID_TRI(E) (half ? fn(tridiag_kernel_b<E, 8>) : fn(tridiag_kernel_b<E, 16>))
     switch ((h[i].ell + 63) / 64) {
-      case 1: f = fn(tridiag_kernel_b<1>); break;
-      case 2: f = fn(tridiag_kernel_b<2>); break;
-      case 3: f = fn(tridiag_kernel_b<3>); break;
-      case 4: f = fn(tridiag_kernel_b<4>); break;
-      case 5: f = fn(tridiag_kernel_b<5>); break;
-      case 6: f = fn(tridiag_kernel_b<6>); break;
-      case 7: f = fn(tridiag_kernel_b<7>); break;
-      default: f = fn(tridiag_kernel_b<8>); break;
+      case 1: f = RID_TRI(1); break;
+      case 2: f = RID_TRI(2); break;
+      case 3: f = RID_TRI(3); break;
+      case 4: f = RID_TRI(4); break;
+      case 5: f = RID_TRI(5); break;
+      case 6: f = RID_TRI(6); break;
+      case 7: f = RID_TRI(7); break;
+      default: f = RID_TRI(8); break;
     }
+#undef RID_TRI
     P.add(f, h[i], make_int4(h[i].nz, 1, 1, 0));
   }
-  P.emit(dim3(1024), -1, st, out);
+  P.emit(dim3(half ? 512 : 1024), -1, st, out);
 }
 
 void plan_update_q_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {

@@ -207,6 +207,40 @@ def test_batch_image_streams_64_members_sampled():
     B.close()
 
 
+def test_batch_many_updates_per_round_half_size_tridiagonalisation():
+    """32 members with ten updates each in one round: 320 tridiagonalisation
+    workgroups, more than one per compute unit, so they run at half the waves,
+    two to a unit.  Every member: J valid and distinct, P(:, J) = I; every
+    fourth member against the oracle."""
+    from paper_2405_16076_amd import StreamBatch, StreamConfig
+    n, ell, t = 240, 96, 24
+    rng = np.random.default_rng(77)
+    ms = [int(x) for x in rng.integers(2000, 9000, size=32)]
+    data = []
+    for i, m in enumerate(ms):
+        A = synth.lowrank(m, n, seed=900 + i, rank=40)
+        ld = (m + 15) // 16 * 16
+        X = torch.zeros((n, ld), dtype=torch.float32, device="cuda:0")
+        X[:, :m] = torch.from_numpy(A).to("cuda:0")
+        data.append((X, A))
+    cfgs = [StreamConfig(m=m, ell=ell, k=t, t=t, n_max=n, dtype=torch.float32, sketch="f32", omega_seed=8000 + i,
+                         select_seed=8100 + i, lookahead=n) for i, m in enumerate(ms)]
+    B = StreamBatch(cfgs)
+    B.push([X[:, :m] for (X, _), m in zip(data, ms)], borrow=True)
+    B.finalize()
+    for i, mbr in enumerate(B.members):
+        J = mbr.select()
+        occ = J >= 0
+        assert np.all(J[occ] < n) and len(set(J[occ].tolist())) == int(occ.sum())
+        assert mbr.info().n_updates == n // t
+        P = mbr.coefficients()
+        assert np.allclose(P[occ][:, J[occ]], np.eye(int(occ.sum())), atol=1e-5)
+    for i in range(0, 32, 4):
+        wt, mg, e, er = _check_member(B.members[i], data[i][1], ell, t, "f32", 8000 + i, 8100 + i)
+        log(f"  member {i} m={ms[i]}: tau/tol {wt:.2e} margin {mg:.2e} P {e:.2e} recon {er:.2e}")
+    B.close()
+
+
 def test_batch_coefficients_per_step_when_slices_do_not_fit():
     """A member whose per-update P slices (t x n_max each) would pass the cap
     gets each step's Alg. 4 / Alg. 8 phase right after that step's Gram (for
