@@ -950,32 +950,52 @@ __global__ __launch_bounds__(256) void sketch_f64_multi(MultiSketch ms) {
 // Fixed-order binary64 sum of the slab partials into S(:, c0:c0+b) and
 // ||a_j||^2; a non-finite norm (a non-finite snapshot value) sets the flag.
 // Block (x, y): rows 64 x.., column y of the batch.
+// One workgroup of kReduceWaves waves per (64 sketch rows, column): wave w
+// sums the w-th share of the slabs in slab order, then the shares are added in
+// wave order.  The column's norm: lane i of wave 1 sums slabs i, i + 64, ...,
+// then a fixed butterfly over the lanes, lane 0's result kept.
+constexpr int kReduceWaves = 4;
+
 template <typename T>
 __device__ __forceinline__ void sketch_reduce_body(const SketchArgs& a, const Blk bk) {
+  __shared__ double share[kReduceWaves][64];
   const T* __restrict__ part = reinterpret_cast<const T*>(a.part);
   const int c = bk.y;
-  const int r = bk.x * 64 + threadIdx.x;
-  if (c >= a.b) return;
-  if (r < a.ell) {
-    double s = 0.0;
-    for (int sl = 0; sl < a.n_slabs; ++sl) s += (double)part[((int64_t)sl * a.b_max + c) * a.ell_pad + r];
-    a.S[(a.c0 + c) * a.ell + r] = s;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = bk.x * 64 + lane;
+  if (c >= a.b) return;  // the same for the whole workgroup
+  const int per = (a.n_slabs + kReduceWaves - 1) / kReduceWaves;
+  const int s1 = min(a.n_slabs, (w + 1) * per);
+  double s = 0.0;
+  if (r < a.ell)
+    for (int sl = w * per; sl < s1; ++sl) s += (double)part[((int64_t)sl * a.b_max + c) * a.ell_pad + r];
+  share[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && r < a.ell) {
+    double tot = share[0][lane];
+#pragma unroll
+    for (int i = 1; i < kReduceWaves; ++i) tot += share[i][lane];
+    a.S[(a.c0 + c) * a.ell + r] = tot;
   }
-  if (bk.x == 0 && threadIdx.x == 0) {
+  if (bk.x == 0 && w == 1) {
     double q = 0.0;
-    for (int sl = 0; sl < a.n_slabs; ++sl) q += a.normpart[(int64_t)sl * a.b_max + c];
-    a.colsq[a.c0 + c] = q;
-    if (!isfinite(q)) *a.nonfinite = 1;
+    for (int sl = lane; sl < a.n_slabs; sl += 64) q += a.normpart[(int64_t)sl * a.b_max + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+    if (lane == 0) {
+      a.colsq[a.c0 + c] = q;
+      if (!isfinite(q)) *a.nonfinite = 1;
+    }
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void sketch_reduce_kernel(SketchArgs a) {
+__global__ __launch_bounds__(64 * kReduceWaves) void sketch_reduce_kernel(SketchArgs a) {
   sketch_reduce_body<T>(a, own_block());
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void sketch_reduce_kernel_b(Batched<SketchArgs> L) {
+__global__ __launch_bounds__(64 * kReduceWaves) void sketch_reduce_kernel_b(Batched<SketchArgs> L) {
   const SketchArgs* a;
   Blk bk;
   if (batched_block(L, a, bk)) sketch_reduce_body<T>(*a, bk);
@@ -1062,9 +1082,9 @@ hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s) {
 hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s) {
   dim3 grid((a.ell + 63) / 64, a.b);
   if (prec == RID_SKETCH_F64)
-    hipLaunchKernelGGL(sketch_reduce_kernel<double>, grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL(sketch_reduce_kernel<double>, grid, dim3(64 * kReduceWaves), 0, s, a);
   else
-    hipLaunchKernelGGL(sketch_reduce_kernel<float>, grid, dim3(64), 0, s, a);
+    hipLaunchKernelGGL(sketch_reduce_kernel<float>, grid, dim3(64 * kReduceWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1150,7 +1170,7 @@ void plan_sketch_reduce_b(int prec, const SketchArgs* h, int ns, Stage& st, std:
   L.func = prec == RID_SKETCH_F64 ? reinterpret_cast<const void*>(sketch_reduce_kernel_b<double>)
                                   : reinterpret_cast<const void*>(sketch_reduce_kernel_b<float>);
   L.grid = dim3((unsigned)maxb, (unsigned)ns);
-  L.block = dim3(64);
+  L.block = dim3(64 * kReduceWaves);
   L.extra = -1;
   L.args = st.put(g.data(), g.size());
   L.aux = st.put(dims.data(), dims.size());
