@@ -85,3 +85,29 @@ def test_unbiased_over_test_matrices():
                                P, G, F, 6, 12)["tr_est"] for s in range(2000)])
     se = ests.std() / math.sqrt(len(ests))
     assert abs(ests.mean() - exact) < 4 * se
+
+
+def test_reused_sketch_reads_the_residual_low_independent_matrix_does_not():
+    # Sec. 4 queries E = A - A_J P through the rows of Omega A that Alg. 4
+    # fitted P to, so the queried residual is a least-squares residual and
+    # carries less than its share of ||E||_F^2; an independent Gaussian test
+    # matrix reads it without that shortfall (averaged over three seeds)
+    from oracle.rid import Config, OnlineRID
+    m, n, ell, t = 2000, 240, 96, 48
+    reused, fresh = [], []
+    for seed in range(3):
+        rng = np.random.default_rng(100 + seed)
+        r = 150
+        A = (rng.standard_normal((m, r)) / np.sqrt(1.0 + np.arange(r))) @ rng.standard_normal((r, n))
+        o = OnlineRID(Config(m=m, ell=ell, k=t, t=t, omega_seed=7 + seed, select_seed=9 + seed, operand="f64"),
+                      n_max=n)
+        o.push(A)
+        o.finalize()
+        occ = o.J >= 0
+        E = A - A[:, o.J[occ]] @ o.P[occ]
+        exact = float(np.sum(E * E))
+        W = rng.standard_normal((ell, m))
+        reused.append(o.records[-1].hutch["E2"] / exact)
+        fresh.append(float(np.sum((W @ E) ** 2)) / ell / exact)
+    assert np.mean(reused) < 0.8, reused
+    assert 0.8 < np.mean(fresh) < 1.2, fresh
