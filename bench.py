@@ -84,7 +84,8 @@ def run_form(D, m, wl, sketch, steps, warmup, push, seeds):
     ms = (t1 - t0) * 1000.0 / steps
     log(f"  [{sketch}] {steps} steps: {ms:.2f} ms/step; sketch {prof['sketch_ms'] / steps:.2f} ms, "
         f"reduce {prof['reduce_ms'] / steps:.2f} ms, updates {prof['update_ms'] / steps:.2f} ms "
-        f"(gram {prof['gram_ms'] / steps:.2f} ms)")
+        f"(gram {prof['gram_ms'] / steps:.2f} ms); coefficient phases on the second stream "
+        f"{prof['coeff_ms'] / steps:.2f} ms (beside the next pass's sketch)")
     return s, ms, prof
 
 
@@ -274,7 +275,8 @@ def main():
                    "push": args.push, "parallelism": "single GPU"},
         "rel_frobenius_error": {"nahutchpp_estimate": est["rel"], "exact_sampled": exact},
         "hbm_frac_whole_step": round((B_snap + prof["gram_bytes"] / args.steps) / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
-        "phase_ms": {k: round(prof[k] / args.steps, 3) for k in ("sketch_ms", "reduce_ms", "update_ms", "gram_ms")},
+        "phase_ms": {k: round(prof[k] / args.steps, 3) for k in ("sketch_ms", "reduce_ms", "update_ms", "gram_ms",
+                                                                  "coeff_ms")},
         "roofline": roofline,
     }
     J_main, P_main = s.select(), None

@@ -249,10 +249,13 @@ typedef struct rid_profile {
   int64_t sketch_launches;  /* number of sketch contraction launches */
   double sketch_bytes;      /* snapshot bytes those launches read (columns x m x size) */
   double reduce_ms;         /* slab reductions of the sketch */
-  double update_ms;         /* per-update phases (Alg. 3 steps 16-32, Alg. 4, Alg. 8) */
+  double update_ms;         /* per-update phases on the main stream (Alg. 3 steps 16-29) */
   int64_t updates;          /* updates timed */
   double gram_ms;           /* basis copy + Gram kernels inside the updates */
   double gram_bytes;        /* bytes the basis copy + Gram kernels must move */
+  double coeff_ms;          /* Alg. 4 and Alg. 8 phases, on the second stream: they run beside
+                               later main-stream work (the next pass's sketch after a reset),
+                               so their span is not additive with the other phases */
 } rid_profile;
 
 /* on != 0 starts recording (and clears earlier records); on == 0 stops.

@@ -131,7 +131,7 @@ struct rid_stream {
   // live timing: event pairs recorded on the stream around launch groups
   struct Mark {
     hipEvent_t a, b;
-    int kind;        // 0 sketch, 1 reduce, 2 update, 3 gram
+    int kind;        // 0 sketch, 1 reduce, 2 update, 3 gram, 4 coefficient phases (second stream)
     double bytes;
     hipStream_t on;  // stream the events are recorded on
   };
@@ -163,6 +163,9 @@ struct rid_stream {
   // coefficient phases of the previous flush (coeff_ev)
   hipEvent_t coeff_ev = nullptr;
   bool coeff_pending = false;
+  // after a reset that left them running: the next sketch reduction, which
+  // rewrites S from column 0, waits for them first
+  bool reduce_wait = false;
   static constexpr int kTabSlots = 3;
   char* ctab_host[kTabSlots] = {nullptr, nullptr, nullptr};
   hipEvent_t ctab_ev[kTabSlots] = {nullptr, nullptr, nullptr};
@@ -612,6 +615,10 @@ static rid_status sketch_range(rid_stream* h, int64_t c0, int b) {
   int mk = mark_begin(h, 0, (double)b * (double)h->m * h->esize);
   RID_HIP(h, launch_sketch(h->prec, a, h->s));
   mark_end(h, mk);
+  if (h->reduce_wait) {
+    RID_HIP(h, hipStreamWaitEvent(h->s, h->coeff_ev, 0));
+    h->reduce_wait = false;
+  }
   mk = mark_begin(h, 1, 0.0);
   RID_HIP(h, launch_sketch_reduce(h->prec, a, h->s));
   mark_end(h, mk);
@@ -764,7 +771,7 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   // workgroup for either QR), so the updates of a group share every launch.
   RID_HIP(h, hipEventRecord(h->side_ev, h->s));
   RID_HIP(h, hipStreamWaitEvent(h->side, h->side_ev, 0));
-  mk = mark_begin(h, 2, (double)h->n_updates, h->side);
+  mk = mark_begin(h, 4, (double)h->n_updates, h->side);
   for (int z0 = 0; z0 < nz; z0 += h->cgroup) {
     const int g = std::min(h->cgroup, nz - z0);
     if (g == 1) {
@@ -944,22 +951,33 @@ rid_status rid_reset(rid_stream* h) {
 
 }  // extern "C"
 
-// Without a host wait for the device: the main stream waits for the second
-// stream's work and clears the state behind the previous pass, so the host
-// can enqueue the next pass meanwhile; it only waits until the last upload
-// of the pinned column-pointer table has been copied, since the next pushes
-// rewrite that table from the start.
+// Without a host wait for the device: the state is cleared in stream order
+// behind the previous pass, so the host can enqueue the next pass meanwhile;
+// it only waits until the last upload of the pinned column-pointer table has
+// been copied, since the next pushes rewrite that table from the start.  The
+// previous pass's coefficient phases may still run on the second stream: they
+// read snapshots, kept copies of SS^T and S, and write the records, P and
+// their own buffers.  The records are cleared behind them on that stream; the
+// next sketch reduction (S) and the next update (snapshots, SS^T, records)
+// wait for them, so the next pass's sketch overlaps them.
 static rid_status reset_stream(rid_stream* h) {
   if (h->failed) return fail(h, RID_ESTATE, "stream failed");
-  rid_status st = join_side(h);
-  if (st != RID_OK) return st;
+  const size_t ell = h->ell, t = h->t;
+  if (h->side_used && !h->owner) {
+    RID_HIP(h, hipMemsetAsync(h->recs, 0, sizeof(rid_update) * h->max_updates, h->side));
+    RID_HIP(h, hipEventRecord(h->coeff_ev, h->side));
+    h->coeff_pending = true;
+    h->reduce_wait = true;
+  } else {
+    rid_status st = join_side(h);
+    if (st != RID_OK) return st;
+    RID_HIP(h, hipMemsetAsync(h->recs, 0, sizeof(rid_update) * h->max_updates, h->s));
+  }
   if (h->colptr_pending) RID_HIP(h, hipEventSynchronize(h->colptr_ev));
   h->colptr_pending = false;
-  const size_t ell = h->ell, t = h->t;
   h->sst_cur = 0;
   RID_HIP(h, hipMemsetAsync(h->SST[0], 0, ell * ell * 8, h->s));
   RID_HIP(h, hipMemsetAsync(h->G, 0, t * t * 8, h->s));
-  RID_HIP(h, hipMemsetAsync(h->recs, 0, sizeof(rid_update) * h->max_updates, h->s));
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc);
   RID_HIP(h, hipGetLastError());
   h->n_pushed = h->n_sketched = h->n_uploaded = h->n_updates = h->last_nobs = 0;
@@ -1119,6 +1137,7 @@ rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
       case 0: p->sketch_ms += ms; p->sketch_launches += 1; p->sketch_bytes += mk.bytes; break;
       case 1: p->reduce_ms += ms; break;
       case 2: p->update_ms += ms; break;
+      case 4: p->coeff_ms += ms; break;
       default: {
         // the Gram phase reads every occupied basis column once and copies
         // the new ones in (one read of the buffered column, one write)
