@@ -10,14 +10,17 @@ on demand without storing it:
   counter (i mod 2^32, i // 2^32, g, 0) and yields four 32-bit words w0..w3;
 * word w_p gives one Box-Muller pair from two 16-bit uniforms:
   u1 = ((w_p & 0xFFFF) + 1) / 2^16 in (0, 1],  u2 = (w_p >> 16) / 2^16 in [0, 1),
-  R = sqrt(-2 ln u1),  z_{2p} = R cos(2 pi u2),  z_{2p+1} = R sin(2 pi u2);
+  R = sqrt(-2 ln u1 / v),  z_{2p} = R cos(2 pi u2),  z_{2p+1} = R sin(2 pi u2);
 * Omega[r, i] = z_{r mod 8}.
 
 Box-Muller (Box and Muller, 1958) turns two uniforms into two independent
-normals; with 16-bit uniforms the entries are centred, symmetric and bounded
-by sqrt(32 ln 2) ~ 4.71, and their variance is the closed form
-``omega_variance()`` = 1 - 9.87e-5 (a sub-Gaussian test matrix, which is what
-NA-Hutch++ requires, Sec. 3.3).  The oracle evaluates the transform in binary64.
+normals.  With 16-bit uniforms the plain transform (v = 1) has variance
+``omega_variance()`` = ln N - ln(N!)/N = 1 - 9.87e-5 (N = 2^16), not 1; the
+radius is therefore divided by sqrt(v) with v = omega_variance(), so that the
+entries have mean 0 and variance exactly 1, as the Hutchinson estimator of
+Sec. 3.3 assumes.  They are centred, symmetric and bounded by
+sqrt(32 ln 2 / v) ~ 4.7098 (a sub-Gaussian test matrix, which is what
+NA-Hutch++ requires).  The oracle evaluates the transform in binary64.
 """
 from __future__ import annotations
 
@@ -33,11 +36,17 @@ _INV16 = 1.0 / 65536.0
 
 
 def omega_variance():
-    """Exact variance of one entry: E[R^2] E[cos^2] with u1 uniform on the
-    grid {1/N, ..., N/N}, N = 2^16, and E[cos^2(2 pi k / N)] = 1/2:
+    """Exact variance of one entry of the plain 16-bit Box-Muller transform
+    (radius sqrt(-2 ln u1)): E[R^2] E[cos^2] with u1 uniform on the grid
+    {1/N, ..., N/N}, N = 2^16, and E[cos^2(2 pi k / N)] = 1/2:
     Var = -(1/N) sum_{j=1..N} ln(j/N) = ln N - ln(N!)/N."""
     n = 1 << UNIFORM_BITS
     return math.log(n) - math.lgamma(n + 1) / n
+
+
+def omega_bound():
+    """Largest |Omega| entry: the radius at u1 = 1/N, sqrt(2 ln N / v)."""
+    return math.sqrt(2.0 * UNIFORM_BITS * math.log(2.0) / omega_variance())
 
 
 def _box_muller(words):
@@ -46,7 +55,7 @@ def _box_muller(words):
     hi = (words >> np.uint64(16)).astype(np.float64)
     u1 = (lo + 1.0) * _INV16
     u2 = hi * _INV16
-    rad = np.sqrt(-2.0 * np.log(u1))
+    rad = np.sqrt(-2.0 * np.log(u1) / omega_variance())
     ang = 2.0 * np.pi * u2
     z = np.empty(words.shape[:-1] + (8,), dtype=np.float64)
     z[..., 0::2] = rad * np.cos(ang)
@@ -78,7 +87,7 @@ def omega_entry_scalar(omega_seed, r, i):
     p = (r % ROWS_PER_CALL) // 2
     u1 = ((w[p] & 0xFFFF) + 1) / 65536.0
     u2 = (w[p] >> 16) / 65536.0
-    rad = math.sqrt(-2.0 * math.log(u1))
+    rad = math.sqrt(-2.0 * math.log(u1) / omega_variance())
     if r % 2 == 0:
         return rad * math.cos(2.0 * math.pi * u2)
     return rad * math.sin(2.0 * math.pi * u2)

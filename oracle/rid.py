@@ -19,10 +19,17 @@ What it computes (Li, Becker, Doostan, "Single-pass randomized ID"):
 Readings taken where the paper is silent or garbled (each is listed, with its
 reason, in the design notes of the repository):
 
-* Omega has unit-variance entries (Alg. 3 step 2, Sec. 3.3); the ridge term
-  compares ||A_obs||_F^2 with ||S_k||_F^2 / l (the energy of the normalised
-  sketch Omega / sqrt(l)), i.e. tau = s^T (SS^T + l*lam I)^{-1} s with
-  lam = max((F - ||S_k||^2 / l) / k, rho F / k).
+* Omega has unit-variance entries (Alg. 3 step 2, Sec. 3.3), so the sketch
+  carries l times the energy of the data; the scores are taken with the
+  normalised sketch Omega / sqrt(l): tau = s^T (SS^T + l*lam I)^{-1} s.
+* The ridge parameter: the printed ridge term (||A_obs||_F^2 - ||S_k||_F^2)/k
+  estimates the rank-k tail energy over k (eq. ridge-leverage-score).  The
+  sketch's top-k energy is put on the scale of F through the sketch's own
+  total energy, lam = max(F (1 - ||S_k||^2 / ||S||^2) / k, rho F / k): the
+  tail fraction of the sketch itself, as the generalised score of
+  eq. g_ridge_leverage_score takes ||B - B_k||^2 from the sketch B.  It is
+  never negative and needs no difference of two independently estimated
+  energies (F against ||S_k||^2 / l), which sketch noise makes cancel.
 * S holds every observed column (l x n_obs), not l x t.
 * The update fires right after the t-th buffered column (and its norm) has
   been added; a partial buffer is flushed by ``finalize``.
@@ -132,10 +139,15 @@ def sketch_columns(cols, omega_seed, ell, operand="f64", row_chunk=1 << 16):
 
 def ridge_lambda(SST, F, k, ell, floor):
     """||S_k||_F^2 (sum of the top min(k, l) eigenvalues of SS^T) and the ridge
-    parameter lam = max((F - ||S_k||^2/l)/k, floor*F/k)."""
+    parameter lam = max(F (tr(SS^T) - ||S_k||^2) / tr(SS^T) / k, floor*F/k)
+    (the rank-k tail fraction of the sketch times F, over k; eqs.
+    sketch_ridge_leverage_score and g_ridge_leverage_score).  ``ell`` only
+    bounds the number of eigenvalues."""
     mu = np.linalg.eigvalsh(SST)[::-1]
     sk2 = float(np.sum(mu[:min(k, ell)]))
-    lam = max((F - sk2 / ell) / k, floor * F / k)
+    tr = float(np.trace(SST))
+    tail = F * (tr - sk2) / tr if tr > 0.0 else 0.0
+    lam = max(tail / k, floor * F / k)
     return sk2, lam, mu
 
 

@@ -5,7 +5,7 @@ import numpy as np
 import scipy.stats as st
 import torch
 
-from oracle.omega import omega_block, omega_entry_scalar, omega_variance, round_to_bf16
+from oracle.omega import _box_muller, omega_block, omega_bound, omega_entry_scalar, omega_variance, round_to_bf16
 
 
 def test_block_matches_scalar_brute_force():
@@ -33,10 +33,35 @@ def test_blocks_are_consistent():
 
 
 def test_variance_closed_form():
+    # the plain 16-bit transform: E[R^2]/2 summed directly over the u1 grid
     n = 1 << 16
     direct = float(np.mean(-np.log((np.arange(n) + 1.0) / n)))
     assert abs(omega_variance() - direct) < 1e-12
     assert abs(omega_variance() - (1.0 - 9.87e-5)) < 1e-6
+
+
+def test_entries_have_exactly_unit_variance():
+    # Sec. 3.3: the test matrix has mean-0, variance-1 entries.  Through the
+    # generator's own transform: for a fixed 16-bit angle, cos^2 + sin^2 = 1,
+    # so the mean of (z0^2 + z1^2) / 2 over every 16-bit radius word is the
+    # exact second moment of an entry (the angle averages cos^2 and sin^2 to
+    # 1/2 each, exactly, over its 2^16 equispaced values).
+    for hi in (0, 1, 12345, 65535):
+        words = (np.arange(1 << 16, dtype=np.uint64) | np.uint64(hi << 16))
+        w4 = np.stack([words, words, words, words], axis=-1)
+        z = _box_muller(w4)
+        m2 = float(np.mean((z[:, 0] ** 2 + z[:, 1] ** 2) / 2.0))
+        assert abs(m2 - 1.0) < 1e-13
+    ang = np.arange(1 << 16) / 65536.0
+    assert abs(np.mean(np.cos(2 * np.pi * ang) ** 2) - 0.5) < 1e-14
+    assert abs(np.mean(np.cos(2 * np.pi * ang))) < 1e-14
+
+
+def test_entry_bound():
+    # the largest radius comes from u1 = 1/N: sqrt(2 ln N / v) = 4.7098
+    assert abs(omega_bound() - 4.7098) < 1e-4
+    z = _box_muller(np.array([[0, 0, 0, 0]], dtype=np.uint64))
+    assert abs(z[0, 0] - omega_bound()) < 1e-15 * omega_bound()
 
 
 def test_moments_and_normality():
@@ -44,10 +69,10 @@ def test_moments_and_normality():
     n = z.size
     assert abs(z.mean()) < 4.0 / math.sqrt(n)
     # Var of the sample variance of a normal: 2 sigma^4 / n
-    assert abs(z.var() - omega_variance()) < 4.0 * math.sqrt(2.0 / n)
+    assert abs(z.var() - 1.0) < 4.0 * math.sqrt(2.0 / n)
     kurt = np.mean(z ** 4) / z.var() ** 2
     assert abs(kurt - 3.0) < 4.0 * math.sqrt(24.0 / n)
-    assert np.max(np.abs(z)) <= math.sqrt(32.0 * math.log(2.0)) + 1e-12
+    assert np.max(np.abs(z)) <= omega_bound() + 1e-12
     d = st.kstest(z[:400000], "norm").statistic
     assert d < 1.63 / math.sqrt(400000)
 

@@ -35,13 +35,57 @@ def test_lambda_formula_and_floor():
     rng = np.random.default_rng(2)
     S = _sketch(rng, 20, 40, 20)
     SST = S @ S.T
-    sk2, _, _ = ridge_lambda(SST, 0.0, 5, 20, 1e-8)
-    F = 2.0 * sk2 / 20
+    sk2, _, mu = ridge_lambda(SST, 0.0, 5, 20, 1e-8)
+    F = 3.7
     _, lam, _ = ridge_lambda(SST, F, 5, 20, 1e-8)
-    assert np.isclose(lam, (F - sk2 / 20) / 5, rtol=1e-14)
-    F = 0.5 * sk2 / 20                       # tail estimate negative -> floor
-    _, lam, _ = ridge_lambda(SST, F, 5, 20, 1e-8)
+    tail = float(np.sum(mu[5:]))
+    assert np.isclose(lam, F * tail / float(np.sum(mu)) / 5, rtol=1e-12)
+    # the sketch's rank is <= k: its tail is zero and the floor holds
+    S = _sketch(rng, 20, 40, 4)
+    _, lam, _ = ridge_lambda(S @ S.T, F, 5, 20, 1e-8)
     assert lam == 1e-8 * F / 5
+
+
+def test_lambda_is_the_rank_k_tail_for_an_isometric_sketch():
+    # eq. ridge-leverage-score sets lam = ||A - A_k||_F^2 / k.  When Omega / sqrt(l)
+    # acts as an isometry on the range of A (Omega = sqrt(l) Q^T with Q an
+    # orthonormal basis of a space holding range(A)), the reading returns
+    # exactly that value, whatever the scale of the sketch.
+    rng = np.random.default_rng(5)
+    m, n, ell, k = 200, 60, 30, 7
+    A = rng.standard_normal((m, 25)) @ np.diag(0.8 ** np.arange(25)) @ rng.standard_normal((25, n))
+    Q, _ = np.linalg.qr(np.hstack([np.linalg.qr(A)[0][:, :25], rng.standard_normal((m, ell - 25))]))
+    sv = np.linalg.svd(A, compute_uv=False)
+    F = float(np.sum(A * A))
+    want = float(np.sum(sv[k:] ** 2)) / k
+    for scale in (1.0, 7.5):
+        S = scale * np.sqrt(ell) * Q.T @ A
+        _, lam, _ = ridge_lambda(S @ S.T, F, k, ell, 1e-8)
+        assert np.isclose(lam, want, rtol=1e-10)
+
+
+def test_lambda_tracks_the_tail_where_the_difference_of_estimates_fails():
+    # A Gaussian sketch of a matrix whose energy sits in a few directions:
+    # ||S||^2 / l fluctuates around F by far more than the rank-k tail, so the
+    # printed form with ||S_k||^2 / l in place of the sketch's own top-k
+    # fraction swings from negative (then the floor) to many times the tail.
+    # The tail fraction of the sketch itself stays near the true
+    # ||A - A_k||_F^2 / k on every seed.
+    m, n, ell, k = 2000, 200, 100, 20
+    negative = 0
+    for seed in range(10):
+        rng = np.random.default_rng(seed)
+        U = np.linalg.qr(rng.standard_normal((m, n)))[0]
+        V = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        sv = 0.85 ** np.arange(n)
+        A = (U * sv) @ V.T
+        F = float(np.sum(sv ** 2))
+        S = rng.standard_normal((ell, m)) @ A
+        sk2, lam, _ = ridge_lambda(S @ S.T, F, k, ell, 1e-8)
+        true = float(np.sum(sv[k:] ** 2)) / k
+        assert 0.5 * true < lam < 1.2 * true
+        negative += (F - sk2 / ell) < 0.0
+    assert negative >= 3
 
 
 def test_sum_of_scores_closed_form_and_bounds():

@@ -5,7 +5,7 @@ import numpy as np
 
 import synth
 from oracle.philox import PRUNE_DRAW, decision_uniform
-from oracle.rid import Config, OnlineRID, select_slots
+from oracle.rid import Config, OnlineRID, fill_factor, select_slots
 
 
 def test_unchanged_scores_never_prune():
@@ -95,3 +95,35 @@ def test_stream_first_update_takes_first_columns_and_F_is_exact():
     o.push(A[:, 8:])
     assert math.isclose(o.F, math.fsum((A.astype(np.float64) ** 2).ravel()), rel_tol=1e-13)
     assert len(o.records) == 8
+
+
+def test_fill_factor_hand_values():
+    # Alg. 3 fill step: c (k log k + k log(1/delta) / eps) / t with the natural
+    # log.  Evaluated by hand with k != t: (10 ln 10 + 10 ln 20 / 0.5) / 25
+    # = (23.02585 + 59.91465) / 25 = 3.317620.
+    cfg = Config(m=1, ell=40, k=10, t=25, delta=0.05, eps=0.5, c_sample=1.0)
+    assert abs(fill_factor(cfg) - 3.317620) < 1e-6
+    # c multiplies; delta and eps enter only through ln(1/delta) / eps
+    assert abs(fill_factor(Config(m=1, ell=40, k=10, t=25, c_sample=2.5)) - 2.5 * 3.317620) < 1e-5
+    cfg = Config(m=1, ell=40, k=10, t=25, delta=0.01, eps=0.25)
+    assert abs(fill_factor(cfg) - (23.02585 + 10 * 4.605170 / 0.25) / 25) < 1e-5
+    # k = t: ln k + 2 ln 20 at delta = 0.05, eps = 0.5 (alpha of the five
+    # workloads: l = 40, 200, 300, 200, 400 with k = t = l / 2)
+    for k, alpha in ((20, 8.99), (100, 10.60), (150, 11.00), (200, 11.29)):
+        assert abs(fill_factor(Config(m=1, ell=2 * k, k=k, t=k)) - alpha) < 0.005
+
+
+def test_fill_frequency_follows_the_fill_factor():
+    # one empty slot, one buffered column with score tau: it is filled with
+    # probability alpha tau (k = 10, t = 25: alpha = 3.3176, tau = 0.1)
+    cfg = Config(m=1, ell=40, k=10, t=25)
+    a = fill_factor(cfg)
+    tau = 0.1
+    n = 6000
+    hits = 0
+    for u in range(n):
+        J2, _, _, _ = select_slots(u, np.array([-1]), np.ones(1), np.full(1, np.nan),
+                                   np.full(1, tau), [0], a, 31)
+        hits += int(J2[0] == 0)
+    p = a * tau
+    assert abs(hits / n - p) < 4 * math.sqrt(p * (1 - p) / n)
