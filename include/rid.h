@@ -131,7 +131,8 @@ typedef struct rid_update {
   int64_t count;        /* buffered columns the update scanned */
   double F;             /* ||A_obs||_F^2 */
   double sk2;           /* ||S_k||_F^2: sum of the top min(k,l) eigenvalues of SS^T */
-  double lam;           /* ridge parameter lam (tau uses SS^T + l*lam*I) */
+  double lam;           /* ridge parameter lam = max(F (tr(SS^T) - sk2) / tr(SS^T) / k,
+                           rho F / k) (tau uses SS^T + l*lam*I) */
   double E2, tr_est, gpp, term1, h, corr;  /* NA-Hutch++ terms (Alg. 8) */
   int32_t n_pruned;     /* slots emptied by the prune draws */
   int32_t n_filled;     /* slots filled from the buffer */
@@ -252,10 +253,13 @@ typedef struct rid_profile {
   double update_ms;         /* per-update phases on the main stream (Alg. 3 steps 16-29) */
   int64_t updates;          /* updates timed */
   double gram_ms;           /* basis copy + Gram kernels inside the updates */
-  double gram_bytes;        /* bytes the basis copy + Gram kernels must move */
+  double gram_bytes;        /* basis columns the Gram reads: every occupied column once per
+                               update that brings new columns (columns x m x size) */
   double coeff_ms;          /* Alg. 4 and Alg. 8 phases, on the second stream: they run beside
                                later main-stream work (the next pass's sketch after a reset),
                                so their span is not additive with the other phases */
+  double pool_copy_bytes;   /* new basis columns written into the pool (columns x m x size);
+                               not part of the method's own traffic (single streams only) */
 } rid_profile;
 
 /* on != 0 starts recording (and clears earlier records); on == 0 stops.
@@ -286,6 +290,32 @@ rid_status rid_debug_state(rid_stream* h, double* S, int64_t lds, int64_t cap_co
  * Asynchronous on `stream`.  Errors: RID_EINVAL, RID_EDEVICE. */
 rid_status rid_omega_block(int32_t prec, uint64_t omega_seed, int32_t ell, int64_t i0,
                            int64_t count, void* d_out, int64_t ld, void* stream);
+
+/* One-shot sketch of a block of b snapshots with no stream state (eq.
+ * random_sketch and the column norms of Alg. 3 step 13): S = Omega A and
+ * colsq[j] = ||a_j||^2, Omega the test matrix of omega_seed evaluated the way
+ * the form sketch_prec evaluates it in a stream (RID_SKETCH_F64 takes binary64
+ * data, the other forms binary32).
+ *   d_cols       device, column-major m x b, column stride ld >= m elements;
+ *                the pointer and ld * element size are multiples of 16 bytes
+ *   d_S          device, l x b binary64, column-major, leading dimension l
+ *   d_colsq      device, b binary64
+ *   d_nonfinite  device int32 or NULL: set to 0, then to 1 if a column holds a
+ *                non-finite value (its norm is then not finite)
+ *   stream       hipStream_t as void* (NULL = the null stream)
+ * The caller owns every buffer and keeps them valid until the work enqueued
+ * on `stream` completes.  The rows of each column are summed in slabs whose
+ * count depends only on (sketch_prec, ell, m, b): the count a stream uses for
+ * a lookahead batch of b columns, lowered until the per-slab partial sketches
+ * fit 128 MiB; the work space (column table, partial sketches and norms, at
+ * most 128 MiB) is allocated stream-ordered (hipMallocAsync) and freed the
+ * same way.  Errors (message via rid_last_error(NULL, ...)): RID_EINVAL
+ * (unknown form, sizes, null pointers, alignment), RID_ECAPACITY (b columns
+ * of m rows need more than 128 MiB of partial sketches even at the largest
+ * slab: pass fewer columns), RID_ENOMEM, RID_EDEVICE. */
+rid_status rid_sketch_columns(int32_t sketch_prec, uint64_t omega_seed, int32_t ell, int64_t m,
+                              const void* d_cols, int64_t ld, int32_t b, double* d_S,
+                              double* d_colsq, int32_t* d_nonfinite, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched streams.

@@ -54,7 +54,8 @@ class rid_info(C.Structure):
 class rid_profile(C.Structure):
     _fields_ = [("sketch_ms", C.c_double), ("sketch_launches", C.c_int64), ("sketch_bytes", C.c_double),
                 ("reduce_ms", C.c_double), ("update_ms", C.c_double), ("updates", C.c_int64),
-                ("gram_ms", C.c_double), ("gram_bytes", C.c_double), ("coeff_ms", C.c_double)]
+                ("gram_ms", C.c_double), ("gram_bytes", C.c_double), ("coeff_ms", C.c_double),
+                ("pool_copy_bytes", C.c_double)]
 
 
 RID_BATCH_NO_GRAPH, RID_BATCH_NO_TUNE = 1, 2
@@ -87,6 +88,8 @@ SIGNATURES = {
     "rid_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "rid_profile_read": (C.c_int, [C.c_void_p, C.POINTER(rid_profile)]),
     "rid_omega_block": (C.c_int, [C.c_int32, C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
+    "rid_sketch_columns": (C.c_int, [C.c_int32, C.c_uint64, C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rid_init_batch": (C.c_int, [C.c_int32, C.POINTER(rid_config), C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p)]),
     "rid_push_batch": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                  C.c_uint32]),

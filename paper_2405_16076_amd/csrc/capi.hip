@@ -178,6 +178,13 @@ struct rid_stream {
 static thread_local std::string g_last_err;
 
 
+// Status of a call that has no handle (its message is read with
+// rid_last_error(NULL, ...)).
+rid_status rid::rid_set_global_error(rid_status st, const std::string& msg) {
+  g_last_err = msg;
+  return st;
+}
+
 static rid_status fail(rid_stream* h, rid_status st, const std::string& msg) {
   if (h) {
     h->last_err = msg;
@@ -269,25 +276,8 @@ static bool wide_applies(const rid_stream* h) {
 // Work split of the sketch.  Both bf16 splits give the same l_pad, so the
 // partial buffers fit either.
 static void set_tile(rid_stream* h, bool wide) {
-  h->wide = 0;
-  if (wide && wide_applies(h)) {
-    // two workgroups per 512-column tile, 32 rbw rows each
-    const int rows = (h->ell + 63) / 64 * 64;
-    h->n_mt = 2;
-    h->rbw = rows / 64;
-    h->ell_pad = rows;
-    h->wide = 1;
-  } else if (h->prec == RID_SKETCH_BF16 || h->prec == RID_SKETCH_FP8) {
-    // all test-matrix rows in one workgroup up to 320 rows, else split
-    const int rows = (h->ell + 63) / 64 * 64;
-    h->n_mt = (rows + 319) / 320;
-    h->rbw = (rows + 64 * h->n_mt - 1) / (64 * h->n_mt);
-    h->ell_pad = h->n_mt * 64 * h->rbw;
-  } else {
-    h->ell_pad = (h->ell + kMTile - 1) / kMTile * kMTile;
-    h->n_mt = h->ell_pad / kMTile;
-    h->rbw = 0;
-  }
+  h->wide = (wide && wide_applies(h)) ? 1 : 0;
+  sketch_tile_geometry(h->prec, h->ell, h->wide, &h->ell_pad, &h->n_mt, &h->rbw);
   h->cols_per_wg = sketch_cols_per_wg(h->prec, h->wide);
 }
 
@@ -405,8 +395,7 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
   h->b_max = auto_lookahead(cfg);
   {
     const int n_nt = (h->b_max + h->cols_per_wg - 1) / h->cols_per_wg;
-    const int64_t cap = (h->prec == RID_SKETCH_BF16 || h->prec == RID_SKETCH_FP8)
-                            ? 65536 : (h->prec == RID_SKETCH_F32 ? 32768 : 16384);
+    const int64_t cap = sketch_slab_cap(h->prec);
     const int64_t target = std::max<int64_t>(1, 2048 / (h->n_mt * n_nt));
     int64_t rows = (h->m + target - 1) / target;
     rows = (rows + 255) / 256 * 256;
@@ -1054,7 +1043,7 @@ rid_status rid_reconstruct(rid_stream* h, int64_t j0, int32_t c, void* d_out, in
                        reinterpret_cast<const float*>(h->cpool), h->ldc, h->P, h->t, h->J, h->m, j0, c,
                        reinterpret_cast<float*>(d_out), ld);
   RID_HIP(h, hipGetLastError());
-  if (h->join) {  // a batch member: the caller's stream waits for the result
+  if (h->owner) {  // a batch member: the caller's stream (possibly the null stream) waits for the result
     RID_HIP(h, hipEventRecord(h->join_ev, h->s));
     RID_HIP(h, hipStreamWaitEvent(h->join, h->join_ev, 0));
   }
@@ -1139,15 +1128,18 @@ rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
       case 2: p->update_ms += ms; break;
       case 4: p->coeff_ms += ms; break;
       default: {
-        // the Gram phase reads every occupied basis column once and copies
-        // the new ones in (one read of the buffered column, one write)
+        // an update that brings new columns reads every occupied basis column
+        // once (the new ones from the snapshots, the others from the pool)
+        // and writes the new ones into the pool
         rid_update r;
         RID_HIP(h, hipMemcpy(&r, h->recs + (int64_t)mk.bytes, sizeof(r), hipMemcpyDeviceToHost));
         p->update_ms += ms;
         p->updates += 1;
         p->gram_ms += ms;
-        if (r.n_filled > 0)
-          p->gram_bytes += (double)(r.n_occupied + 2 * r.n_filled) * (double)h->m * h->esize;
+        if (r.n_filled > 0) {
+          p->gram_bytes += (double)r.n_occupied * (double)h->m * h->esize;
+          p->pool_copy_bytes += (double)r.n_filled * (double)h->m * h->esize;
+        }
         break;
       }
     }
@@ -1278,8 +1270,7 @@ static rid_status bfail(rid_batch* bt, rid_status st, const std::string& msg) {
 
 // slab candidates of the sketch (rows per work item)
 static std::vector<int64_t> slab_candidates(int prec) {
-  const int64_t cap = (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) ? 65536
-                      : (prec == RID_SKETCH_F32 ? 32768 : 16384);
+  const int64_t cap = sketch_slab_cap(prec);
   std::vector<int64_t> v;
   for (int64_t r = 2048; r <= cap; r *= 2) v.push_back(r);
   return v;

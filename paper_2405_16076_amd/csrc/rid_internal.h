@@ -8,6 +8,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <string>
 #include <vector>
 
 #include "../../include/rid.h"
@@ -75,8 +76,16 @@ __device__ __forceinline__ double decision_uniform(uint64_t seed, uint32_t u, ui
 // (i mod 2^32, i / 2^32, r / 8, 0) yields four words; word p gives a Box-Muller
 // pair from the 16-bit uniforms u1 = (lo16 + 1) / 2^16 in (0,1] and
 // u2 = hi16 / 2^16 in [0,1): z_{2p} = R cos(2 pi u2), z_{2p+1} = R sin(2 pi u2),
-// R = sqrt(-2 ln u1); Omega(r, i) = z_{r mod 8}.
+// R = sqrt(-2 ln u1 / v); Omega(r, i) = z_{r mod 8}.  With u1 on the 16-bit
+// grid the plain transform (v = 1) has variance ln 2^16 - ln(2^16!) / 2^16 =
+// 1 - 9.86e-5; dividing the radius by the square root of that v gives the
+// entries mean 0 and variance exactly 1 (the Hutchinson estimator of Sec. 3.3
+// assumes unit variance).
 // ---------------------------------------------------------------------------
+
+constexpr double kBoxMullerVar = 0.9999013653984186;          // v above
+constexpr float kTwoLn2OverVar = (float)(1.3862943611198906 / kBoxMullerVar);
+constexpr float kTwoOverVar = (float)(2.0 / kBoxMullerVar);
 
 // Binary32 evaluation with the hardware transcendentals: v_log_f32 is log2,
 // v_sin_f32 / v_cos_f32 take their argument in turns.  u1 and u2 are exact
@@ -84,7 +93,7 @@ __device__ __forceinline__ double decision_uniform(uint64_t seed, uint32_t u, ui
 __device__ __forceinline__ void box_muller16_f32(uint32_t w, float& z0, float& z1) {
   const float u1 = (float)((w & 0xFFFFu) + 1u) * (1.0f / 65536.0f);
   const float u2 = (float)(w >> 16) * (1.0f / 65536.0f);
-  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  const float rad = __builtin_amdgcn_sqrtf(-kTwoLn2OverVar * __builtin_amdgcn_logf(u1));
   z0 = rad * __builtin_amdgcn_cosf(u2);
   z1 = rad * __builtin_amdgcn_sinf(u2);
 }
@@ -95,7 +104,7 @@ __device__ __forceinline__ void box_muller16_f32(uint32_t w, float& z0, float& z
 __device__ __forceinline__ void box_muller16_f32_accurate(uint32_t w, float& z0, float& z1) {
   const float u1 = (float)((w & 0xFFFFu) + 1u) * (1.0f / 65536.0f);
   const float u2 = (float)(w >> 16) * (1.0f / 65536.0f);
-  const float rad = sqrtf(-2.0f * logf(u1));
+  const float rad = sqrtf(-kTwoOverVar * logf(u1));
   float s, c;
   sincospif(2.0f * u2, &s, &c);
   z0 = rad * c;
@@ -105,7 +114,7 @@ __device__ __forceinline__ void box_muller16_f32_accurate(uint32_t w, float& z0,
 __device__ __forceinline__ void box_muller16_f64(uint32_t w, double& z0, double& z1) {
   const double u1 = (double)((w & 0xFFFFu) + 1u) * (1.0 / 65536.0);
   const double u2 = (double)(w >> 16) * (1.0 / 65536.0);
-  const double rad = sqrt(-2.0 * log(u1));
+  const double rad = sqrt(-2.0 * log(u1) / kBoxMullerVar);
   double s, c;
   sincospi(2.0 * u2, &s, &c);
   z0 = rad * c;
@@ -439,6 +448,15 @@ struct SnapArgs {
 void plan_update_snapshot_b(const SnapArgs* h, int n, Stage& st, std::vector<BLaunch>& out);
 
 // launchers (sketch.hip, update.hip)
+// Records the message of a failed call that has no handle and returns st.
+rid_status rid_set_global_error(rid_status st, const std::string& msg);
+
+// Rows of the padded test matrix, test-matrix row tiles and 32-row blocks per
+// wave of the sketch form `prec` (wide: the bf16 split of a 512-column tile
+// over two workgroups).
+void sketch_tile_geometry(int prec, int ell, int wide, int* ell_pad, int* n_mt, int* rbw);
+// Largest slab (rows summed by one workgroup) of the sketch form `prec`.
+int64_t sketch_slab_cap(int prec);
 int sketch_cols_per_wg(int prec, int wide);
 hipError_t launch_sketch(int prec, const SketchArgs& a, hipStream_t s);
 hipError_t launch_sketch_reduce(int prec, const SketchArgs& a, hipStream_t s);

@@ -1034,6 +1034,30 @@ __global__ void omega_block_kernel(int prec, uint64_t seed, int ell, int64_t i0,
 // ---------------------------------------------------------------------------
 constexpr int kNcbF32 = 2;
 
+void sketch_tile_geometry(int prec, int ell, int wide, int* ell_pad, int* n_mt, int* rbw) {
+  if (prec == RID_SKETCH_BF16 && wide) {
+    // two workgroups per 512-column tile, 32 rbw rows each
+    const int rows = (ell + 63) / 64 * 64;
+    *n_mt = 2;
+    *rbw = rows / 64;
+    *ell_pad = rows;
+  } else if (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) {
+    // all test-matrix rows in one workgroup up to 320 rows, else split
+    const int rows = (ell + 63) / 64 * 64;
+    *n_mt = (rows + 319) / 320;
+    *rbw = (rows + 64 * *n_mt - 1) / (64 * *n_mt);
+    *ell_pad = *n_mt * 64 * *rbw;
+  } else {
+    *ell_pad = (ell + kMTile - 1) / kMTile * kMTile;
+    *n_mt = *ell_pad / kMTile;
+    *rbw = 0;
+  }
+}
+
+int64_t sketch_slab_cap(int prec) {
+  return (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) ? 65536 : (prec == RID_SKETCH_F32 ? 32768 : 16384);
+}
+
 int sketch_cols_per_wg(int prec, int wide) {
   if (prec == RID_SKETCH_BF16 && wide) return kWideCols;
   if (prec == RID_SKETCH_BF16 || prec == RID_SKETCH_FP8) return kBf16Cols;

@@ -247,6 +247,15 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     }
     return;
   }
+  // tr(SS^T), the sketch's total energy, before the reduction overwrites W
+  __shared__ double trace_s;
+  if (wv == 0) {
+    double part = 0.0;
+    for (int k = lane; k < n; k += 64) part += W[(int64_t)k * n + k];
+    part = wave_sum(part);
+    if (lane == 0) trace_s = part;
+  }
+  __syncthreads();
   // Householder tridiagonalisation on the lower triangle, one pass over the
   // trailing block per step: iteration j applies the rank-2 update of step
   // j - 1 (A -= v w^T + w v^T, pending) while it forms the reflector and the
@@ -494,7 +503,13 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     double sk2 = 0.0;
     for (int i = 0; i < kk; ++i) sk2 += mu[i];
     const double F = b.Fu[u];
-    const double lam = fmax((F - sk2 / n) / b.k, b.ridge_floor * F / b.k);
+    // the ridge parameter: the rank-k tail energy over k, the tail taken as
+    // the sketch's own tail fraction (tr(SS^T) - ||S_k||^2) / tr(SS^T) of F
+    // (eqs. ridge-leverage-score, sketch_ridge_leverage_score,
+    // g_ridge_leverage_score), floored at rho F / k
+    const double tr = trace_s;
+    const double tail = tr > 0.0 ? F * (tr - sk2) / tr : 0.0;
+    const double lam = fmax(tail / b.k, b.ridge_floor * F / b.k);
     const double shift = n * lam;
     b.recs[u].sk2 = sk2;
     b.recs[u].lam = lam;

@@ -195,6 +195,29 @@ def omega_block(prec, seed, ell, i0, count, device="cuda:0"):
     return out.T
 
 
+def _sketch_args(X, ell):
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a (b, m) tensor with unit element stride")
+    if X.dtype not in (torch.float32, torch.float64):
+        raise ValueError("X must be float32 or float64")
+    b, m = X.shape
+    S = torch.empty((b, ell), dtype=torch.float64, device=X.device)
+    colsq = torch.empty(b, dtype=torch.float64, device=X.device)
+    flag = torch.empty(1, dtype=torch.int32, device=X.device)
+    return b, m, S, colsq, flag
+
+
+def sketch_columns(X, ell, omega_seed, sketch="bf16"):
+    """S = Omega A (l x b, binary64), ||a_j||^2 and the non-finite flag for the
+    b snapshots held in the rows of X (b, m) (rid_sketch_columns)."""
+    b, m, S, colsq, flag = _sketch_args(X, ell)
+    with torch.cuda.device(X.device):
+        L.check(L.lib().rid_sketch_columns(PREC[sketch], omega_seed, ell, m, C.c_void_p(X.data_ptr()), X.stride(0),
+                                           b, C.c_void_p(S.data_ptr()), C.c_void_p(colsq.data_ptr()),
+                                           C.c_void_p(flag.data_ptr()), _stream_handle(X.device)))
+    return S.T, colsq, flag
+
+
 class StreamBatch:
     """Many independent streams of uneven m advanced together: one persistent
     sketch launch per round over every member, batched update launches, the

@@ -43,8 +43,8 @@ def test_struct_layouts_match_c(L):
 #include <stddef.h>
 #include "rid.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(rid_config), sizeof(rid_update), sizeof(rid_info), sizeof(rid_error),
-         sizeof(rid_batch_info));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(rid_config), sizeof(rid_update), sizeof(rid_info), sizeof(rid_error),
+         sizeof(rid_batch_info), sizeof(rid_profile));
   printf("%zu %zu %zu %zu\\n", offsetof(rid_config, n_max), offsetof(rid_update, flags), offsetof(rid_info, device_bytes),
          offsetof(rid_batch_info, tune_ms));
   return 0;
@@ -58,7 +58,7 @@ int main(void) {
         lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
     sizes = [int(x) for x in lines[0].split()]
     assert sizes == [C.sizeof(L.rid_config), C.sizeof(L.rid_update), C.sizeof(L.rid_info), C.sizeof(L.rid_error),
-                     C.sizeof(L.rid_batch_info)]
+                     C.sizeof(L.rid_batch_info), C.sizeof(L.rid_profile)]
     offs = [int(x) for x in lines[1].split()]
     assert offs == [L.rid_config.n_max.offset, L.rid_update.flags.offset, L.rid_info.device_bytes.offset,
                     L.rid_batch_info.tune_ms.offset]
@@ -105,6 +105,27 @@ def test_null_handles_are_rejected(L):
     assert lib.rid_finalize_batch(None) == L.RID_EINVAL
     assert lib.rid_destroy_batch(None) == L.RID_EINVAL
     assert lib.rid_batch_stream(None, 0, None) == L.RID_EINVAL
+
+
+@pytest.mark.parametrize("args,expect,msg", [
+    ((9, 1, 40, 1000, 16, 1000, 4, 16, 16, None), "EINVAL", "unknown sketch precision"),
+    ((2, 1, 0, 1000, 16, 1000, 4, 16, 16, None), "EINVAL", "bad sizes"),
+    ((2, 1, 40, 1000, 16, 999, 4, 16, 16, None), "EINVAL", "bad sizes"),
+    ((2, 1, 40, 1000, None, 1000, 4, 16, 16, None), "EINVAL", "bad sizes"),
+    ((2, 1, 40, 1000, 8, 1000, 4, 16, 16, None), "EINVAL", "16-byte"),
+    ((2, 1, 40, 1001, 16, 1001, 4, 16, 16, None), "EINVAL", "16-byte"),
+    # 4096 columns of 50M rows at l = 300: the partial sketches cannot fit
+    ((2, 1, 300, 50_000_000, 16, 50_000_000, 4096, 16, 16, None), "ECAPACITY", "MiB work space"),
+])
+def test_sketch_columns_rejects_bad_arguments_before_device(L, args, expect, msg):
+    # every rejected call returns before touching the device (the pointers
+    # below are never dereferenced)
+    lib = L.lib()
+    st = lib.rid_sketch_columns(*args, None)
+    assert st == getattr(L, "RID_" + expect)
+    buf = C.create_string_buffer(256)
+    lib.rid_last_error(None, buf, 256)
+    assert msg in buf.value.decode()
 
 
 def test_invalid_batches_rejected_before_device(L):

@@ -94,7 +94,7 @@ def test_omega_operand_is_the_scaled_grid():
     q = quantize_fp8_omega(om)
     want = np.array([[_nearest(float(v) * 64.0) / 64.0 for v in row] for row in om])
     assert np.array_equal(q, want)
-    assert np.max(np.abs(om)) * 64.0 < 448.0  # Omega is bounded by 4.71: no saturation
+    assert np.max(np.abs(om)) * 64.0 < 448.0  # Omega is bounded by 4.7098: no saturation
 
 
 def test_fp8_sketch_is_the_product_of_quantized_operands():
