@@ -70,6 +70,7 @@ class Config:
     hutch_n2: int | None = None
     operand: str = "f64"       # operand rounding of the sketch: f64, f32, bf16 or fp8
     row_chunk: int = 1 << 16   # rows of Omega regenerated at a time
+    workers: int = 1           # threads that compute the sketch's row chunks
 
     @property
     def n1(self):
@@ -105,31 +106,64 @@ def _round_operand(x, operand):
     raise ValueError(f"unknown operand rounding {operand!r}")
 
 
-def sketch_columns(cols, omega_seed, ell, operand="f64", row_chunk=1 << 16):
+def _sketch_chunk(cols, omega_seed, ell, operand, i0, n):
+    """Omega(:, i0:i0+n) A(i0:i0+n, :) and the chunk's sum of squares per column."""
+    blk = cols[i0:i0 + n].astype(np.float64)
+    om = omega_block(omega_seed, ell, i0, n)
+    if operand == "fp8":
+        # e4m3 operands: Omega with the fixed scale 2^-6, the data with one
+        # power-of-two scale per 32 rows of each column (row_chunk is a
+        # multiple of 32, so the blocks stay aligned to row 0)
+        part = quantize_fp8_omega(om) @ quantize_fp8_blocks(blk)
+    else:
+        part = _round_operand(om, operand) @ _round_operand(blk, operand)
+    return part, np.einsum("ij,ij->j", blk, blk)
+
+
+def sketch_columns(cols, omega_seed, ell, operand="f64", row_chunk=1 << 16, workers=1):
     """S = Omega A for the columns of ``cols`` (m x b), and ||a_j||^2.
 
     Omega is regenerated block by block from its counter.  ``operand`` names
     the rounding applied to both operands before the (exact binary64) product:
     the reduced-precision sketch forms multiply rounded operands.  Column norms
-    are always those of the unrounded data, accumulated in binary64."""
+    are always those of the unrounded data, accumulated in binary64.
+
+    The sum over row chunks is taken in chunk order.  With ``workers`` > 1 the
+    chunks' products are computed by that many threads (numpy releases the
+    interpreter lock inside its array loops) and still added in chunk order,
+    so the result does not depend on ``workers``."""
     cols = np.asarray(cols)
     m, b = cols.shape
     if operand == "fp8" and row_chunk % 32:
         raise ValueError("row_chunk must be a multiple of 32 for the fp8 operands")
     S = np.zeros((ell, b), dtype=np.float64)
     colsq = np.zeros(b, dtype=np.float64)
-    for i0 in range(0, m, row_chunk):
-        n = min(row_chunk, m - i0)
-        blk = cols[i0:i0 + n].astype(np.float64)
-        om = omega_block(omega_seed, ell, i0, n)
-        if operand == "fp8":
-            # e4m3 operands: Omega with the fixed scale 2^-6, the data with one
-            # power-of-two scale per 32 rows of each column (row_chunk is a
-            # multiple of 32, so the blocks stay aligned to row 0)
-            S += quantize_fp8_omega(om) @ quantize_fp8_blocks(blk)
-        else:
-            S += _round_operand(om, operand) @ _round_operand(blk, operand)
-        colsq += np.einsum("ij,ij->j", blk, blk)
+    starts = list(range(0, m, row_chunk))
+
+    def one(i0):
+        return _sketch_chunk(cols, omega_seed, ell, operand, i0, min(row_chunk, m - i0))
+
+    if workers <= 1 or len(starts) <= 1:
+        for i0 in starts:
+            part, sq = one(i0)
+            S += part
+            colsq += sq
+        return S, colsq
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        # a bounded window of chunks in flight keeps the memory in check
+        window = 2 * workers
+        futs = [ex.submit(one, i0) for i0 in starts[:window]]
+        nxt = window
+        for k in range(len(starts)):
+            part, sq = futs[k].result()
+            futs[k] = None
+            S += part
+            colsq += sq
+            if nxt < len(starts):
+                futs.append(ex.submit(one, starts[nxt]))
+                nxt += 1
     return S, colsq
 
 
@@ -341,7 +375,7 @@ class OnlineRID:
             raise FloatingPointError("non-finite snapshot value")
         if self.C is None:
             self.C = np.zeros((cfg.m, cfg.t), dtype=cols.dtype)
-        Sb, sq = sketch_columns(cols, cfg.omega_seed, cfg.ell, cfg.operand, cfg.row_chunk)
+        Sb, sq = sketch_columns(cols, cfg.omega_seed, cfg.ell, cfg.operand, cfg.row_chunk, cfg.workers)
         self._grow(self.n_obs + cols.shape[1])
         for jj in range(cols.shape[1]):
             j = self.n_obs

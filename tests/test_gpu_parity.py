@@ -3,7 +3,7 @@
 Tolerances:
 * Omega: binary64 evaluation differs from the oracle's by a few ulp (4e-15
   absolute); the binary32 form uses the accurate device-library log/sincospi
-  on binary32-exact uniforms (error a few ulp of |z| <= 4.71); the bfloat16
+  on binary32-exact uniforms (error a few ulp of |z| <= 4.7098); the bfloat16
   form rounds hardware-transcendental binary32 values, so a small fraction of
   entries may land one bfloat16 ulp away from the oracle's rounding.
 * Sketch S: binary64 sums in another order (1e-12 relative Frobenius);
@@ -11,12 +11,17 @@ Tolerances:
   oracle's product of bfloat16-rounded operands (1e-4); fp8 against the
   oracle's product of the same e4m3 codes and block scales (1e-3: the scaled
   MFMA rounds inside each 64-term product).
-* Everything downstream of S (scores, coefficients, NA-Hutch++ terms,
-  reconstruction) is compared with a forward-error tolerance computed by the
-  oracle itself: its own S is perturbed at the sketch accuracy of the form and
-  the step is recomputed; the tolerance is 10x the largest change seen
-  (gpu_common.perturbation_tolerances).  The index sets J must match exactly
-  (the smallest decision margin |U - p| is logged).
+* Coefficients P, the reconstruction A_J P and the worst column of S are held
+  to fixed bounds declared per form in gpu_common (P_BOUND, RECON_BOUND,
+  S_COL_BOUND): binary64 1e-10; binary32 1e-5 (P only where cond(Omega A_J)
+  <= 100, else 1e-3, with the reconstruction still at 1e-5); bfloat16 P 1e-3,
+  reconstruction 1e-4; e4m3 P 3e-3, reconstruction 1e-3.
+* The scores tau and the NA-Hutch++ terms are compared with a forward-error
+  tolerance computed by the oracle itself: its own S is perturbed at the
+  sketch accuracy of the form and the step is recomputed; the tolerance is 10x
+  the largest change seen (gpu_common.perturbation_tolerances); the same
+  derived tolerance of P is logged beside its fixed bound.  The index sets J
+  must match exactly (the smallest decision margin |U - p| is logged).
 """
 import math
 
@@ -26,7 +31,7 @@ import torch
 
 import oracle
 import synth
-from gpu_common import compare_updates, log, perturbation_tolerances, rel_fro, run_gpu, run_oracle
+from gpu_common import check_fixed_bounds, compare_updates, log, perturbation_tolerances, rel_fro, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +63,7 @@ def test_omega_f32_and_bf16_match_oracle():
     g = omega_block("f32", seed, ell, 0, cnt).cpu().numpy().astype(np.float64)
     err = np.abs(g - o)
     log("omega f32 max abs err", err.max(), "rms", math.sqrt(np.mean(err ** 2)))
-    # binary32 transcendentals on exact binary32 uniforms: a few ulp of |z| <= 4.71
+    # binary32 transcendentals on exact binary32 uniforms: a few ulp of |z| <= 4.7098
     assert err.max() <= 2e-5
     assert math.sqrt(np.mean(err ** 2)) <= 2e-6
     gb = omega_block("bf16", seed, ell, 0, cnt).cpu().numpy().astype(np.float64)
@@ -167,9 +172,6 @@ def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True, n_max
     J = s.select()
     assert np.array_equal(J, o.J)
     P = s.coefficients()
-    e = rel_fro(P, o.P)
-    log(f"  P rel fro {e:.2e} (tol {tol['P']:.2e}, cond S_J {o.records[-1].cond_SJ:.2e})")
-    assert e <= tol["P"]
     occ = J >= 0
     assert np.allclose(P[occ][:, J[occ]], np.eye(int(occ.sum())), atol=1e-9 if sketch == "f64" else 1e-5)
     # NA-Hutch++ terms of every update
@@ -183,19 +185,17 @@ def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True, n_max
             worst[key] = max(worst.get(key, 0.0), d / tol[key][u])
             assert d <= tol[key][u], (u, key, g[key], h[key], tol[key][u])
     log("  NA-Hutch++ diff/tol " + " ".join(f"{k} {v:.2e}" for k, v in worst.items()))
-    _, _, G = s.debug_state()
+    Sg, _, G = s.debug_state()
     eg = rel_fro(G, o.G)
     log(f"  Gram rel fro {eg:.2e}")
     assert eg <= 1e-12
-    # reconstruction of a column range
+    # S, P and the reconstruction of a column range against fixed bounds
     n = A.shape[0]
     c0, c = max(0, n // 2 - 5), min(17, n)
     R = s.reconstruct(c0, c).cpu().numpy().astype(np.float64)
     occi = np.flatnonzero(occ)
     Ro = (A.T[:, J[occi]].astype(np.float64) @ o.P[occi][:, c0:c0 + c]).T
-    er = rel_fro(R, Ro)
-    log(f"  reconstruct rel fro {er:.2e} (tol {tol['recon']:.2e})")
-    assert er <= tol["recon"]
+    check_fixed_bounds(sketch, Sg[:, :o.n_obs], o.S[:, :o.n_obs], P, o.P, R, Ro, o.records[-1].cond_SJ, tol)
     return s, o
 
 
