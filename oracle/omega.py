@@ -1,66 +1,81 @@
 """The Gaussian test matrix Omega of the oracle (test infrastructure only).
 
 The paper draws Omega (l x m) with i.i.d. standard normal entries (Alg. 3,
-step 2; the Hutchinson estimator of Sec. 3.3 needs mean 0 and variance 1).
-It is realised here from a counter so that any block of it can be regenerated
-on demand without storing it:
+step 2); the Hutchinson estimator of Sec. 3.3 needs mean 0 and variance 1,
+and a sub-Gaussian distribution suffices for NA-Hutch++.  It is realised here
+from a counter so that any block can be regenerated on demand without being
+stored, and from a table of quantiles so that every reduced-precision form
+holds exactly the rounding of the same binary64 value:
 
 * Philox4x32-10, key = omega_seed (low word first);
 * the call for data row ``i`` and sketch-row group ``g = r // 8`` uses the
-  counter (i mod 2^32, i // 2^32, g, 0) and yields four 32-bit words w0..w3;
-* word w_p gives one Box-Muller pair from two 16-bit uniforms:
-  u1 = ((w_p & 0xFFFF) + 1) / 2^16 in (0, 1],  u2 = (w_p >> 16) / 2^16 in [0, 1),
-  R = sqrt(-2 ln u1 / v),  z_{2p} = R cos(2 pi u2),  z_{2p+1} = R sin(2 pi u2);
-* Omega[r, i] = z_{r mod 8}.
+  counter (i mod 2^32, i // 2^32, g, 0) and yields four 32-bit words w0..w3,
+  i.e. eight 16-bit halves h_{2p} = w_p & 0xFFFF, h_{2p+1} = w_p >> 16;
+* Omega[r, i] = (-1)^s T[k] for h = h_{r mod 8}, s = h >> 15 (bit 15) and
+  k = (h >> 5) & 1023 (bits 14..5; bits 4..0 are not used);
+* T[k] = c Phi^{-1}((1 + (k + 1/2) / 1024) / 2), k = 0..1023, the quantile of
+  |N(0, 1)| at the middle of the k-th of 1024 equiprobable bins, with c the
+  constant that makes the mean of T^2 exactly 1.
 
-Box-Muller (Box and Muller, 1958) turns two uniforms into two independent
-normals.  With 16-bit uniforms the plain transform (v = 1) has variance
-``omega_variance()`` = ln N - ln(N!)/N = 1 - 9.87e-5 (N = 2^16), not 1; the
-radius is therefore divided by sqrt(v) with v = omega_variance(), so that the
-entries have mean 0 and variance exactly 1, as the Hutchinson estimator of
-Sec. 3.3 assumes.  They are centred, symmetric and bounded by
-sqrt(32 ln 2 / v) ~ 4.7098 (a sub-Gaussian test matrix, which is what
-NA-Hutch++ requires).  The oracle evaluates the transform in binary64.
+So each entry takes one of 2048 equiprobable values, symmetric about 0: the
+standard normal distribution quantised to 2048 atoms (it is within 1/2048 of
+the normal CDF everywhere), with mean 0 and variance exactly 1 and bounded by
+T[1023] ~ 3.49 (a sub-Gaussian test matrix).  The quantiles are the binary64
+values of ``scipy.special.ndtri``.
 """
 from __future__ import annotations
 
 import math
 
 import numpy as np
+from scipy.special import ndtri
 
 from .philox import DOMAIN_OMEGA, philox4x32, seed_key
 
 ROWS_PER_CALL = 8
-UNIFORM_BITS = 16
-_INV16 = 1.0 / 65536.0
+TABLE_BITS = 10
+TABLE_SIZE = 1 << TABLE_BITS
+INDEX_SHIFT = 5
 
 
-def omega_variance():
-    """Exact variance of one entry of the plain 16-bit Box-Muller transform
-    (radius sqrt(-2 ln u1)): E[R^2] E[cos^2] with u1 uniform on the grid
-    {1/N, ..., N/N}, N = 2^16, and E[cos^2(2 pi k / N)] = 1/2:
-    Var = -(1/N) sum_{j=1..N} ln(j/N) = ln N - ln(N!)/N."""
-    n = 1 << UNIFORM_BITS
-    return math.log(n) - math.lgamma(n + 1) / n
+def _half_normal_quantiles():
+    p = 0.5 * (1.0 + (np.arange(TABLE_SIZE, dtype=np.float64) + 0.5) / TABLE_SIZE)
+    return ndtri(p)
+
+
+def omega_scale():
+    """c = 1 / sqrt(mean_k Q_k^2) for the unscaled quantiles Q_k."""
+    q = _half_normal_quantiles()
+    return 1.0 / math.sqrt(float(np.mean(q * q)))
+
+
+_TABLE = _half_normal_quantiles() * omega_scale()
+
+
+def omega_table():
+    """The 1024 magnitudes T[k] (binary64, increasing)."""
+    return _TABLE.copy()
 
 
 def omega_bound():
-    """Largest |Omega| entry: the radius at u1 = 1/N, sqrt(2 ln N / v)."""
-    return math.sqrt(2.0 * UNIFORM_BITS * math.log(2.0) / omega_variance())
+    """Largest |Omega| entry: T[1023]."""
+    return float(_TABLE[-1])
 
 
-def _box_muller(words):
-    """words: uint64 array (..., 4) of 32-bit words -> float64 (..., 8)."""
-    lo = (words & np.uint64(0xFFFF)).astype(np.float64)
-    hi = (words >> np.uint64(16)).astype(np.float64)
-    u1 = (lo + 1.0) * _INV16
-    u2 = hi * _INV16
-    rad = np.sqrt(-2.0 * np.log(u1) / omega_variance())
-    ang = 2.0 * np.pi * u2
-    z = np.empty(words.shape[:-1] + (8,), dtype=np.float64)
-    z[..., 0::2] = rad * np.cos(ang)
-    z[..., 1::2] = rad * np.sin(ang)
-    return z
+def omega_from_halves(h):
+    """Entries for 16-bit halves h (integer array): (-1)^(h >> 15) T[(h >> 5) & 1023]."""
+    h = np.asarray(h, dtype=np.uint64)
+    k = ((h >> np.uint64(INDEX_SHIFT)) & np.uint64(TABLE_SIZE - 1)).astype(np.int64)
+    z = _TABLE[k]
+    return np.where((h >> np.uint64(15)) & np.uint64(1), -z, z)
+
+
+def _halves(words):
+    """words: uint64 array (..., 4) of 32-bit words -> (..., 8) 16-bit halves."""
+    h = np.empty(words.shape[:-1] + (8,), dtype=np.uint64)
+    h[..., 0::2] = words & np.uint64(0xFFFF)
+    h[..., 1::2] = words >> np.uint64(16)
+    return h
 
 
 def omega_block(omega_seed, ell, i0, count):
@@ -73,24 +88,22 @@ def omega_block(omega_seed, ell, i0, count):
     gg = g[:, None]
     w0, w1, w2, w3 = philox4x32(ii & np.uint64(0xFFFFFFFF), ii >> np.uint64(32), gg, DOMAIN_OMEGA, k0, k1)
     words = np.stack([w0, w1, w2, w3], axis=-1)          # (ngroups, count, 4)
-    z = _box_muller(words)                                # (ngroups, count, 8)
+    z = omega_from_halves(_halves(words))                 # (ngroups, count, 8)
     z = np.transpose(z, (0, 2, 1)).reshape(ngroups * ROWS_PER_CALL, count)
     return np.ascontiguousarray(z[:ell])
 
 
 def omega_entry_scalar(omega_seed, r, i):
-    """One entry, from the scalar Philox and the math module (for brute-force
-    cross-checks of ``omega_block``)."""
+    """One entry, from the scalar Philox and a direct quantile evaluation (for
+    brute-force cross-checks of ``omega_block``)."""
     from .philox import philox4x32_scalar
     key = seed_key(omega_seed)
     w = philox4x32_scalar((i & 0xFFFFFFFF, i >> 32, r // ROWS_PER_CALL, DOMAIN_OMEGA), key)
-    p = (r % ROWS_PER_CALL) // 2
-    u1 = ((w[p] & 0xFFFF) + 1) / 65536.0
-    u2 = (w[p] >> 16) / 65536.0
-    rad = math.sqrt(-2.0 * math.log(u1) / omega_variance())
-    if r % 2 == 0:
-        return rad * math.cos(2.0 * math.pi * u2)
-    return rad * math.sin(2.0 * math.pi * u2)
+    q = r % ROWS_PER_CALL
+    h = (w[q // 2] >> (16 * (q % 2))) & 0xFFFF
+    k = (h >> INDEX_SHIFT) & (TABLE_SIZE - 1)
+    z = omega_scale() * float(ndtri(0.5 * (1.0 + (k + 0.5) / TABLE_SIZE)))
+    return -z if h >> 15 else z
 
 
 def round_to_bf16(x):

@@ -5,7 +5,10 @@ import numpy as np
 import scipy.stats as st
 import torch
 
-from oracle.omega import _box_muller, omega_block, omega_bound, omega_entry_scalar, omega_variance, round_to_bf16
+from scipy.special import ndtr, ndtri
+
+from oracle.omega import (omega_block, omega_bound, omega_entry_scalar, omega_from_halves, omega_scale, omega_table,
+                          round_to_bf16)
 
 
 def test_block_matches_scalar_brute_force():
@@ -32,36 +35,47 @@ def test_blocks_are_consistent():
     assert np.array_equal(omega_block(11, 40, 100, 50)[:30], full)
 
 
-def test_variance_closed_form():
-    # the plain 16-bit transform: E[R^2]/2 summed directly over the u1 grid
-    n = 1 << 16
-    direct = float(np.mean(-np.log((np.arange(n) + 1.0) / n)))
-    assert abs(omega_variance() - direct) < 1e-12
-    assert abs(omega_variance() - (1.0 - 9.87e-5)) < 1e-6
+def test_table_holds_the_half_normal_quantiles():
+    # Phi(T[k] / c) must be the middle of the k-th of 1024 equiprobable bins
+    # of |N(0,1)|; checked through the forward CDF (an independent routine)
+    T = omega_table()
+    c = omega_scale()
+    assert T.shape == (1024,) and np.all(np.diff(T) > 0) and T[0] > 0
+    k = np.arange(1024)
+    p = 0.5 * (1.0 + (k + 0.5) / 1024)
+    assert np.max(np.abs(ndtr(T / c) - p)) < 1e-15
+    # quantising at bin midpoints loses a little variance; c puts it back
+    assert 1.0 < c < 1.001
 
 
-def test_entries_have_exactly_unit_variance():
-    # Sec. 3.3: the test matrix has mean-0, variance-1 entries.  Through the
-    # generator's own transform: for a fixed 16-bit angle, cos^2 + sin^2 = 1,
-    # so the mean of (z0^2 + z1^2) / 2 over every 16-bit radius word is the
-    # exact second moment of an entry (the angle averages cos^2 and sin^2 to
-    # 1/2 each, exactly, over its 2^16 equispaced values).
-    for hi in (0, 1, 12345, 65535):
-        words = (np.arange(1 << 16, dtype=np.uint64) | np.uint64(hi << 16))
-        w4 = np.stack([words, words, words, words], axis=-1)
-        z = _box_muller(w4)
-        m2 = float(np.mean((z[:, 0] ** 2 + z[:, 1] ** 2) / 2.0))
-        assert abs(m2 - 1.0) < 1e-13
-    ang = np.arange(1 << 16) / 65536.0
-    assert abs(np.mean(np.cos(2 * np.pi * ang) ** 2) - 0.5) < 1e-14
-    assert abs(np.mean(np.cos(2 * np.pi * ang))) < 1e-14
+def test_entries_have_mean_zero_and_exactly_unit_variance():
+    # Sec. 3.3: mean 0, variance 1.  Over all 2^16 halves every table entry
+    # appears 64 times with each sign, so these are the exact moments of an
+    # entry of Omega.
+    h = np.arange(1 << 16)
+    z = omega_from_halves(h)
+    assert z.sum() == 0.0
+    assert abs(np.mean(z * z) - 1.0) < 1e-15
+    counts = np.unique(z, return_counts=True)[1]
+    assert counts.size == 2048 and np.all(counts == 32)
+
+
+def test_distribution_is_within_one_atom_of_the_normal():
+    # the CDF of the 2048 equiprobable atoms against Phi: at most the 1/2048
+    # jump at an atom plus the small outward shift of the scale c
+    T = omega_table()
+    atoms = np.concatenate([-T[::-1], T])
+    F_after = np.arange(1, 2049) / 2048.0
+    F_before = np.arange(0, 2048) / 2048.0
+    Phi = ndtr(atoms)
+    d = max(np.max(np.abs(F_after - Phi)), np.max(np.abs(F_before - Phi)))
+    assert d < 0.6 / 1024
 
 
 def test_entry_bound():
-    # the largest radius comes from u1 = 1/N: sqrt(2 ln N / v) = 4.7098
-    assert abs(omega_bound() - 4.7098) < 1e-4
-    z = _box_muller(np.array([[0, 0, 0, 0]], dtype=np.uint64))
-    assert abs(z[0, 0] - omega_bound()) < 1e-15 * omega_bound()
+    # the largest magnitude is the top quantile, Phi^{-1}(1 - 1/4096) scaled
+    assert abs(omega_bound() - omega_scale() * float(ndtri(1.0 - 0.25 / 1024))) < 1e-14
+    assert 3.4 < omega_bound() < 3.6
 
 
 def test_moments_and_normality():
@@ -70,9 +84,13 @@ def test_moments_and_normality():
     assert abs(z.mean()) < 4.0 / math.sqrt(n)
     # Var of the sample variance of a normal: 2 sigma^4 / n
     assert abs(z.var() - 1.0) < 4.0 * math.sqrt(2.0 / n)
+    # the atoms' fourth moment (the tails beyond 3.49 are folded into the
+    # outermost atoms, so it is slightly below the normal's 3)
+    k4 = float(np.mean(omega_table() ** 4))
+    assert 2.97 < k4 < 3.0
     kurt = np.mean(z ** 4) / z.var() ** 2
-    assert abs(kurt - 3.0) < 4.0 * math.sqrt(24.0 / n)
-    assert np.max(np.abs(z)) <= omega_bound() + 1e-12
+    assert abs(kurt - k4) < 4.0 * math.sqrt(24.0 / n)
+    assert np.max(np.abs(z)) <= omega_bound()
     d = st.kstest(z[:400000], "norm").statistic
     assert d < 1.63 / math.sqrt(400000)
 
