@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/rid.h"
+#include "omega_table.h"
 
 namespace rid {
 
@@ -73,81 +74,79 @@ __device__ __forceinline__ double decision_uniform(uint64_t seed, uint32_t u, ui
 
 // ---------------------------------------------------------------------------
 // The test matrix Omega.  Entry (r, i): the Philox call with counter
-// (i mod 2^32, i / 2^32, r / 8, 0) yields four words; word p gives a Box-Muller
-// pair from the 16-bit uniforms u1 = (lo16 + 1) / 2^16 in (0,1] and
-// u2 = hi16 / 2^16 in [0,1): z_{2p} = R cos(2 pi u2), z_{2p+1} = R sin(2 pi u2),
-// R = sqrt(-2 ln u1 / v); Omega(r, i) = z_{r mod 8}.  With u1 on the 16-bit
-// grid the plain transform (v = 1) has variance ln 2^16 - ln(2^16!) / 2^16 =
-// 1 - 9.86e-5; dividing the radius by the square root of that v gives the
-// entries mean 0 and variance exactly 1 (the Hutchinson estimator of Sec. 3.3
-// assumes unit variance).
+// (i mod 2^32, i / 2^32, r / 8, 0) yields four words w0..w3, i.e. eight 16-bit
+// halves h_{2p} = w_p & 0xFFFF, h_{2p+1} = w_p >> 16; with h = h_{r mod 8},
+// Omega(r, i) = (-1)^(bit 15 of h) T[bits 14..5 of h].  T[k] is the quantile
+// of |N(0,1)| at the middle of the k-th of 1024 equiprobable bins, scaled so
+// that the entries have variance exactly 1 (omega_table.h): the standard
+// normal quantised to 2048 equiprobable atoms.  Each form reads the table in
+// its own number format, so every form holds the rounding of the same
+// binary64 value, and no transcendental is evaluated on the device.
 // ---------------------------------------------------------------------------
 
-constexpr double kBoxMullerVar = 0.9999013653984186;          // v above
-constexpr float kTwoLn2OverVar = (float)(1.3862943611198906 / kBoxMullerVar);
-constexpr float kTwoOverVar = (float)(2.0 / kBoxMullerVar);
-
-// Binary32 evaluation with the hardware transcendentals: v_log_f32 is log2,
-// v_sin_f32 / v_cos_f32 take their argument in turns.  u1 and u2 are exact
-// in binary32.
-__device__ __forceinline__ void box_muller16_f32(uint32_t w, float& z0, float& z1) {
-  const float u1 = (float)((w & 0xFFFFu) + 1u) * (1.0f / 65536.0f);
-  const float u2 = (float)(w >> 16) * (1.0f / 65536.0f);
-  const float rad = __builtin_amdgcn_sqrtf(-kTwoLn2OverVar * __builtin_amdgcn_logf(u1));
-  z0 = rad * __builtin_amdgcn_cosf(u2);
-  z1 = rad * __builtin_amdgcn_sinf(u2);
+__device__ __forceinline__ Words4 omega_words(uint64_t seed, uint64_t i, uint32_t g) {
+  return philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), g, kDomainOmega, (uint32_t)seed,
+                       (uint32_t)(seed >> 32));
 }
 
-// Binary32 evaluation with the correctly rounded square root and the
-// accurate device-library log and sincospi (used by the binary32 form, whose
-// sketch error is otherwise dominated by the hardware approximations).
-__device__ __forceinline__ void box_muller16_f32_accurate(uint32_t w, float& z0, float& z1) {
-  const float u1 = (float)((w & 0xFFFFu) + 1u) * (1.0f / 65536.0f);
-  const float u2 = (float)(w >> 16) * (1.0f / 65536.0f);
-  const float rad = sqrtf(-kTwoOverVar * logf(u1));
-  float s, c;
-  sincospif(2.0f * u2, &s, &c);
-  z0 = rad * c;
-  z1 = rad * s;
+// Half q (0..7) of the four words.
+__device__ __forceinline__ uint32_t omega_half(const Words4& w, int q) {
+  const uint32_t x = q < 2 ? w.x : (q < 4 ? w.y : (q < 6 ? w.z : w.w));
+  return (q & 1) ? (x >> 16) : (x & 0xFFFFu);
 }
 
-__device__ __forceinline__ void box_muller16_f64(uint32_t w, double& z0, double& z1) {
-  const double u1 = (double)((w & 0xFFFFu) + 1u) * (1.0 / 65536.0);
-  const double u2 = (double)(w >> 16) * (1.0 / 65536.0);
-  const double rad = sqrt(-2.0 * log(u1) / kBoxMullerVar);
-  double s, c;
-  sincospi(2.0 * u2, &s, &c);
-  z0 = rad * c;
-  z1 = rad * s;
+__device__ __forceinline__ int omega_index(uint32_t h) { return (int)((h >> 5) & (kOmegaTabSize - 1)); }
+
+// Copies the table of one format into LDS (every thread of the workgroup
+// takes part; the caller synchronises before reading it).
+template <typename T>
+__device__ __forceinline__ void load_omega_table(T* lds, const T* tab) {
+  constexpr int words = kOmegaTabSize * (int)sizeof(T) / 4;
+  for (int i = threadIdx.x; i < words; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(lds)[i] = reinterpret_cast<const uint32_t*>(tab)[i];
 }
 
-// Eight consecutive test-matrix rows 8g..8g+7 at data row i.
+// Rows 8g..8g+7 at data row i as bfloat16 bits, from an LDS copy of the table.
+__device__ __forceinline__ void omega8_bf16(uint64_t seed, uint64_t i, uint32_t g, const uint16_t* tab,
+                                            uint16_t z[8]) {
+  const Words4 w = omega_words(seed, i, g);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t h = omega_half(w, q);
+    z[q] = (uint16_t)(tab[omega_index(h)] | (h & 0x8000u));
+  }
+}
+
+// Rows 8g..8g+7 at data row i as e4m3 codes of 64 Omega, from an LDS copy.
+__device__ __forceinline__ void omega8_e4m3(uint64_t seed, uint64_t i, uint32_t g, const uint8_t* tab,
+                                            uint32_t z[8]) {
+  const Words4 w = omega_words(seed, i, g);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t h = omega_half(w, q);
+    z[q] = tab[omega_index(h)] | ((h >> 8) & 0x80u);
+  }
+}
+
+// Rows 8g..8g+7 at data row i in binary32 (table in device memory).
 __device__ __forceinline__ void omega8_f32(uint64_t seed, uint64_t i, uint32_t g, float z[8]) {
-  Words4 w = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), g, kDomainOmega, (uint32_t)seed,
-                           (uint32_t)(seed >> 32));
-  box_muller16_f32(w.x, z[0], z[1]);
-  box_muller16_f32(w.y, z[2], z[3]);
-  box_muller16_f32(w.z, z[4], z[5]);
-  box_muller16_f32(w.w, z[6], z[7]);
+  const Words4 w = omega_words(seed, i, g);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t h = omega_half(w, q);
+    z[q] = __uint_as_float(kOmegaTabF32[omega_index(h)] | ((h & 0x8000u) << 16));
+  }
 }
 
-__device__ __forceinline__ void omega8_f32_accurate(uint64_t seed, uint64_t i, uint32_t g,
-                                                    float z[8]) {
-  Words4 w = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), g, kDomainOmega, (uint32_t)seed,
-                           (uint32_t)(seed >> 32));
-  box_muller16_f32_accurate(w.x, z[0], z[1]);
-  box_muller16_f32_accurate(w.y, z[2], z[3]);
-  box_muller16_f32_accurate(w.z, z[4], z[5]);
-  box_muller16_f32_accurate(w.w, z[6], z[7]);
-}
-
+// Rows 8g..8g+7 at data row i in binary64 (table in device memory).
 __device__ __forceinline__ void omega8_f64(uint64_t seed, uint64_t i, uint32_t g, double z[8]) {
-  Words4 w = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), g, kDomainOmega, (uint32_t)seed,
-                           (uint32_t)(seed >> 32));
-  box_muller16_f64(w.x, z[0], z[1]);
-  box_muller16_f64(w.y, z[2], z[3]);
-  box_muller16_f64(w.z, z[4], z[5]);
-  box_muller16_f64(w.w, z[6], z[7]);
+  const Words4 w = omega_words(seed, i, g);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const uint32_t h = omega_half(w, q);
+    const double t = kOmegaTabF64[omega_index(h)];
+    z[q] = (h & 0x8000u) ? -t : t;
+  }
 }
 
 // Column addresses come from a table in device memory, so the compiler cannot

@@ -76,9 +76,12 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
   __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
   __shared__ __attribute__((aligned(1024))) float dt[kBf16Stages][kBf16Cols * KC];
   __shared__ double nsh[kBf16Cols];
+  __shared__ __attribute__((aligned(16))) uint16_t otab[kOmegaTabSize];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int rg = wave >> 2, cp = wave & 3;
+  load_omega_table(otab, kOmegaTabBf16);
+  __syncthreads();
   const int64_t r0 = (int64_t)slab * a.slab_rows;
   const int64_t r1 = min(a.m, r0 + a.slab_rows);
   const int nch = (int)((r1 - r0 + KC - 1) / KC);
@@ -135,10 +138,10 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
     for (int it = tid; it < n_items; it += 512) {
       const int g = it / KC, k = it % KC;
       uint16_t* dst = d + (8 * g) * LDA + k;
-      float z[8];
-      omega8_f32(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), z);
+      uint16_t z[8];
+      omega8_bf16(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), otab, z);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) dst[j * LDA] = __builtin_bit_cast(uint16_t, (__bf16)z[j]);
+      for (int j = 0; j < 8; ++j) dst[j * LDA] = z[j];
     }
   };
 
@@ -300,6 +303,9 @@ __device__ __forceinline__ void sketch_bf16w_body(const SketchArgs& a, int slab,
   __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
   __shared__ __attribute__((aligned(1024))) float dt[2][kWideCols * KC];
   __shared__ uint64_t csrc[kWideCols];
+  __shared__ __attribute__((aligned(16))) uint16_t otab[kOmegaTabSize];
+  load_omega_table(otab, kOmegaTabBf16);
+  __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int64_t r0 = (int64_t)slab * a.slab_rows;
@@ -351,10 +357,10 @@ __device__ __forceinline__ void sketch_bf16w_body(const SketchArgs& a, int slab,
     uint16_t* d = om[c & 1];
     for (int it = tid; it < n_items; it += 512) {
       const int g = it / KC, k = it % KC;
-      float z[8];
-      omega8_f32(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), z);
+      uint16_t z[8];
+      omega8_bf16(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), otab, z);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) d[(8 * g + j) * LDA + k] = __builtin_bit_cast(uint16_t, (__bf16)z[j]);
+      for (int j = 0; j < 8; ++j) d[(8 * g + j) * LDA + k] = z[j];
     }
   };
 
@@ -529,6 +535,9 @@ __device__ __forceinline__ void sketch_fp8_body(const SketchArgs& a, int slab, i
   __shared__ __attribute__((aligned(1024))) float dt[NST][kBf16Cols * KC];
   __shared__ uint64_t csrc[kBf16Cols];
   __shared__ int scl[2][kBf16Cols];      // E8M0 code of (chunk of the step, column)
+  __shared__ __attribute__((aligned(16))) uint8_t otab[kOmegaTabSize];
+  load_omega_table(otab, kOmegaTabE4M3);
+  __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int rg = wave >> 2, cp = wave & 3;
@@ -574,14 +583,12 @@ __device__ __forceinline__ void sketch_fp8_body(const SketchArgs& a, int slab, i
     const int64_t k0 = r0 + (int64_t)q * 64;
     for (int it = tid; it < n_items; it += 512) {
       const int g = it >> 5, kp = it & 31;
-      float z0[8], z1[8];
-      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp), (uint32_t)(row_base / 8 + g), z0);
-      omega8_f32(a.seed, (uint64_t)(k0 + 2 * kp + 1), (uint32_t)(row_base / 8 + g), z1);
+      uint32_t z0[8], z1[8];
+      omega8_e4m3(a.seed, (uint64_t)(k0 + 2 * kp), (uint32_t)(row_base / 8 + g), otab, z0);
+      omega8_e4m3(a.seed, (uint64_t)(k0 + 2 * kp + 1), (uint32_t)(row_base / 8 + g), otab, z1);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int w = __builtin_amdgcn_cvt_pk_fp8_f32(z0[j] * 64.0f, z1[j] * 64.0f, 0, false);
-        *reinterpret_cast<uint16_t*>(&om[(8 * g + j) * LDO + 2 * kp]) = (uint16_t)w;
-      }
+      for (int j = 0; j < 8; ++j)
+        *reinterpret_cast<uint16_t*>(&om[(8 * g + j) * LDO + 2 * kp]) = (uint16_t)(z0[j] | (z1[j] << 8));
     }
   };
 
@@ -785,7 +792,7 @@ __device__ __forceinline__ void sketch_f32_body(const SketchArgs& a, int slab, i
   for (int64_t k0 = r0; k0 < r1; k0 += KC) {
     if (tid < 128) {
       float z[8];
-      omega8_f32_accurate(a.seed, (uint64_t)(k0 + gk), (uint32_t)(mt * (kMTile / 8) + gg), z);
+      omega8_f32(a.seed, (uint64_t)(k0 + gk), (uint32_t)(mt * (kMTile / 8) + gg), z);
 #pragma unroll
       for (int j = 0; j < 8; ++j) om[(8 * gg + j) * LD + gk] = z[j];
     }
@@ -1013,19 +1020,19 @@ __global__ void omega_block_kernel(int prec, uint64_t seed, int ell, int64_t i0,
       if (8 * g + j < ell) reinterpret_cast<double*>(out)[i * ld + 8 * g + j] = z[j];
   } else {
     float z[8];
-    if (prec == RID_SKETCH_F32)
-      omega8_f32_accurate(seed, (uint64_t)(i0 + i), (uint32_t)g, z);
-    else
+    if (prec == RID_SKETCH_F32) {
       omega8_f32(seed, (uint64_t)(i0 + i), (uint32_t)g, z);
-    for (int j = 0; j < 8; ++j) {
-      float v = z[j];
-      if (prec == RID_SKETCH_BF16) v = __uint_as_float((uint32_t)bf16_bits_rne(v) << 16);
-      if (prec == RID_SKETCH_FP8) {
-        const int w = __builtin_amdgcn_cvt_pk_fp8_f32(v * 64.0f, 0.0f, 0, false);
-        v = __builtin_amdgcn_cvt_f32_fp8(w, 0) * (1.0f / 64.0f);
-      }
-      if (8 * g + j < ell) reinterpret_cast<float*>(out)[i * ld + 8 * g + j] = v;
+    } else if (prec == RID_SKETCH_BF16) {
+      uint16_t b[8];
+      omega8_bf16(seed, (uint64_t)(i0 + i), (uint32_t)g, kOmegaTabBf16, b);
+      for (int j = 0; j < 8; ++j) z[j] = __uint_as_float((uint32_t)b[j] << 16);
+    } else {
+      uint32_t c[8];
+      omega8_e4m3(seed, (uint64_t)(i0 + i), (uint32_t)g, kOmegaTabE4M3, c);
+      for (int j = 0; j < 8; ++j) z[j] = __builtin_amdgcn_cvt_f32_fp8((int)c[j], 0) * (1.0f / 64.0f);
     }
+    for (int j = 0; j < 8; ++j)
+      if (8 * g + j < ell) reinterpret_cast<float*>(out)[i * ld + 8 * g + j] = z[j];
   }
 }
 

@@ -96,12 +96,11 @@ def compare_updates(s, o, tol, log_prefix=""):
 
 
 # Relative accuracy of the sketch S of each form against the oracle's S of the
-# same operands: binary64 sums in another order (~sqrt(m) 2^-53); binary32
-# accumulation within a slab plus binary32 transcendentals (~1e-6); bfloat16
-# operands: binary32 accumulation and rare one-ulp differences of the rounded
-# test matrix (~1e-5); e4m3 operands: the scaled MFMA rounds inside each
-# 64-term product (a few 1e-5 of the sum of magnitudes, ~1e-4 of S).
-SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-5, "fp8": 3e-4}
+# same operands (the test matrices are equal bit for bit): binary64 sums in
+# another order (~sqrt(m) 2^-53); binary32 accumulation within a slab, for the
+# binary32 and bfloat16 forms (~1e-6); e4m3 operands: the scaled MFMA rounds
+# inside each 64-term product (a few 1e-5 of the sum of magnitudes, ~1e-4 of S).
+SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-6, "fp8": 3e-4}
 
 # Fixed bounds on the coefficients P and the reconstruction A_J P, declared
 # before any GPU value is seen: relative Frobenius norm of the difference from
@@ -119,9 +118,14 @@ SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-5, "fp8": 3e-4}
 P_BOUND = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-3, "fp8": 3e-3}
 P_BOUND_F32_ILL_CONDITIONED = 1e-3
 F32_WELL_CONDITIONED = 100.0
+# the worst column of P: binary64 columns of small norm carry relative errors
+# above the matrix's (cond(Omega A_J) up to 2e4 times 1e-15 of S)
+P_COL_FACTOR = {"f64": 10.0, "f32": 1.0, "bf16": 1.0, "fp8": 1.0}
 RECON_BOUND = {"f64": 1e-10, "f32": 1e-5, "bf16": 1e-4, "fp8": 1e-3}
-# worst column of S against the oracle's S of the same operands
-S_COL_BOUND = {"f64": 1e-13, "f32": 2e-6, "bf16": 1e-4, "fp8": 2e-3}
+# worst column of S against the oracle's S of the same operands (the test
+# matrices are equal bit for bit; what is left is the accumulation: binary64,
+# or binary32 within a row slab, and the e4m3 matrix cores' internal rounding)
+S_COL_BOUND = {"f64": 1e-13, "f32": 2e-6, "bf16": 2e-6, "fp8": 2e-3}
 
 
 def p_bound(sketch, cond_SJ):
@@ -130,21 +134,23 @@ def p_bound(sketch, cond_SJ):
     return P_BOUND[sketch]
 
 
-def check_fixed_bounds(sketch, S, So, P, Po, R, Ro, cond_SJ, tol=None, prefix="  "):
+def check_fixed_bounds(sketch, S, So, P, Po, R, Ro, cond_SJ, tol=None, prefix="  ", pb=None, rb=None):
     """Asserts the fixed bounds above on S (worst column), P (relative
     Frobenius and worst column) and the reconstruction; logs the measured
     values, the bound and (if given) the oracle-derived forward-error
-    tolerance as a diagnostic."""
+    tolerance as a diagnostic.  pb / rb replace the form's P and
+    reconstruction bounds where a test declares its own."""
     es, ecs = rel_fro(S, So), col_max_rel(S, So)
     ep, ecp = rel_fro(P, Po), col_max_rel(P, Po)
     er, ecr = rel_fro(R, Ro), col_max_rel(R.T, Ro.T)
-    pb, rb = p_bound(sketch, cond_SJ), RECON_BOUND[sketch]
+    pb = pb or p_bound(sketch, cond_SJ)
+    rb = rb or RECON_BOUND[sketch]
     diag = f" (derived {tol['P']:.2e} / {tol['recon']:.2e})" if tol else ""
     log(f"{prefix}S rel fro {es:.2e} col {ecs:.2e} (bound {S_COL_BOUND[sketch]:.0e}); "
         f"P rel fro {ep:.2e} col {ecp:.2e} (bound {pb:.0e}, cond S_J {cond_SJ:.2e}); "
         f"recon rel fro {er:.2e} col {ecr:.2e} (bound {rb:.0e}){diag}")
     assert ecs <= S_COL_BOUND[sketch], ("S column", ecs)
-    assert ep <= pb and ecp <= pb, ("P", ep, ecp, pb)
+    assert ep <= pb and ecp <= P_COL_FACTOR[sketch] * pb, ("P", ep, ecp, pb)
     assert er <= rb and ecr <= rb, ("reconstruction", er, ecr, rb)
     return ep, er
 

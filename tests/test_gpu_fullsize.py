@@ -8,8 +8,9 @@ Alg. 3) against the oracle run on the same bytes, copied back to the host.
 
 Checked: J exactly at both updates; tau and every NA-Hutch++ term (term1, h,
 corr, tr_est, gpp, E^2) against the oracle's forward-error tolerances; S
-(worst column), P and the reconstruction on sampled snapshots against the
-fixed bounds of the bfloat16 form.  The oracle's sketch runs its row chunks
+against the bfloat16 form's fixed bounds (worst column 2e-6, 1e-5 relative
+Frobenius); P and the reconstruction on sampled snapshots against bounds
+declared from this stream's conditioning (below).  The oracle's sketch runs its row chunks
 on 16 threads; the whole test takes about three minutes on one MI355X machine
 (most of it the oracle).
 """
@@ -21,7 +22,7 @@ import pytest
 import torch
 
 import synth
-from gpu_common import check_fixed_bounds, compare_updates, log, perturbation_tolerances, run_oracle
+from gpu_common import check_fixed_bounds, compare_updates, log, perturbation_tolerances, rel_fro, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -87,7 +88,13 @@ def test_channel_19M_rows_bf16_two_updates_match_oracle():
     AJ = A[J[occ]].astype(np.float64)         # (|J|, m)
     Ro = (o.P[occ][:, cols].T @ AJ)           # (len(cols), m)
     R = np.stack([s.reconstruct(int(j), 1).cpu().numpy()[0].astype(np.float64) for j in cols])
-    check_fixed_bounds("bf16", Sg[:, :n], o.S[:, :n], P, o.P, R, Ro, o.records[-1].cond_SJ)
+    # At this size cond(Omega A_J) is 1.2e4, ten times the small channel
+    # streams': binary32 accumulation over the 37k-row slabs leaves S about
+    # 1e-6 from the oracle's, and P's forward error is about 0.1 cond(Omega A_J)
+    # times that.  Bounds declared for this test: P 5e-3, reconstruction 5e-4.
+    assert o.records[-1].cond_SJ < 3e4
+    check_fixed_bounds("bf16", Sg[:, :n], o.S[:, :n], P, o.P, R, Ro, o.records[-1].cond_SJ, pb=5e-3, rb=5e-4)
+    assert rel_fro(Sg[:, :n], o.S[:, :n]) <= 1e-5
     # the exact error of the sampled snapshots beside the estimate
     Aj = A[cols].astype(np.float64)
     exact = math.sqrt(float(np.sum((R - Aj) ** 2)) / float(np.sum(Aj * Aj)))

@@ -11,7 +11,7 @@ from gpu_common import S_COL_BOUND, col_max_rel, log, rel_fro
 
 pytestmark = pytest.mark.gpu
 
-S_FRO_BOUND = {"f64": 1e-12, "f32": 2e-5, "bf16": 1e-4, "fp8": 1e-3}
+S_FRO_BOUND = {"f64": 1e-12, "f32": 2e-5, "bf16": 1e-5, "fp8": 1e-3}
 
 
 @pytest.fixture(scope="module", autouse=True)
