@@ -317,6 +317,23 @@ rid_status rid_sketch_columns(int32_t sketch_prec, uint64_t omega_seed, int32_t 
                               const void* d_cols, int64_t ld, int32_t b, double* d_S,
                               double* d_colsq, int32_t* d_nonfinite, void* stream);
 
+/* rid_sketch_columns for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, slab geometry, kernels and results (bit for
+ * bit), with the work space in a fixed 128 MiB array that the library holds
+ * on every device it runs on until the process ends.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); on its first
+ * call on a device it looks up that device's array address once.  It clears
+ * what must start at zero (the non-finite flag) with a kernel, not a memset.
+ * Every call on one device uses that device's array: calls whose work
+ * overlaps on one device (other streams, other threads) race and must be
+ * ordered by the caller.  Errors as rid_sketch_columns, with RID_ECAPACITY
+ * when the work space of the call would pass 128 MiB; RID_EDEVICE if the
+ * array's address cannot be found. */
+rid_status rid_sketch_columns_noalloc(int32_t sketch_prec, uint64_t omega_seed, int32_t ell, int64_t m,
+                                      const void* d_cols, int64_t ld, int32_t b, double* d_S,
+                                      double* d_colsq, int32_t* d_nonfinite, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Batched streams.
  *

@@ -90,6 +90,8 @@ SIGNATURES = {
     "rid_omega_block": (C.c_int, [C.c_int32, C.c_uint64, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "rid_sketch_columns": (C.c_int, [C.c_int32, C.c_uint64, C.c_int32, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "rid_sketch_columns_noalloc": (C.c_int, [C.c_int32, C.c_uint64, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
+                                             C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "rid_init_batch": (C.c_int, [C.c_int32, C.POINTER(rid_config), C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p)]),
     "rid_push_batch": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                  C.c_uint32]),

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "rid_internal.h"
@@ -112,9 +113,65 @@ hipError_t oneshot_launch(int32_t prec, OneShot& p, char* ws, const void* d_cols
   return launch_sketch_reduce(prec, a, s);
 }
 
+// Work space of rid_sketch_columns_noalloc: one array per device (each GPU the
+// library runs on holds it until the process ends), as large as the largest
+// work space of one call.  In host code the name stands for a host-side
+// symbol, not the device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) char scratch[kOneShotMaxBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+rid_status scratch_address(void** out, std::string* err) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    *err = "no usable HIP device";
+    return RID_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      *err = std::string("hipGetSymbolAddress of the work space: ") + hipGetErrorString(e);
+      return RID_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RID_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+rid_status rid_sketch_columns_noalloc(int32_t sketch_prec, uint64_t omega_seed, int32_t ell, int64_t m,
+                                      const void* d_cols, int64_t ld, int32_t b, double* d_S, double* d_colsq,
+                                      int32_t* d_nonfinite, void* stream) {
+  OneShot p;
+  std::string err;
+  rid_status st = oneshot_plan(sketch_prec, omega_seed, ell, m, d_cols, ld, b, d_S, d_colsq, &p, &err);
+  if (st != RID_OK) return rid_set_global_error(st, "rid_sketch_columns_noalloc: " + err);
+  if (p.bytes > kOneShotMaxBytes)
+    return rid_set_global_error(RID_ECAPACITY, "rid_sketch_columns_noalloc: needs " + std::to_string(p.bytes) +
+                                                   " bytes of work space, the maximum is " +
+                                                   std::to_string(kOneShotMaxBytes));
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws, &err)) != RID_OK)
+    return rid_set_global_error(st, "rid_sketch_columns_noalloc: " + err);
+  const hipError_t e = oneshot_launch(sketch_prec, p, reinterpret_cast<char*>(ws), d_cols, ld, d_nonfinite,
+                                      reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return rid_set_global_error(RID_EDEVICE, std::string("rid_sketch_columns_noalloc: ") + hipGetErrorString(e));
+  return RID_OK;
+}
 
 rid_status rid_sketch_columns(int32_t sketch_prec, uint64_t omega_seed, int32_t ell, int64_t m,
                               const void* d_cols, int64_t ld, int32_t b, double* d_S, double* d_colsq,

@@ -218,6 +218,24 @@ def sketch_columns(X, ell, omega_seed, sketch="bf16"):
     return S.T, colsq, flag
 
 
+def sketch_columns_noalloc(X, ell, omega_seed, sketch, S, colsq, flag):
+    """rid_sketch_columns_noalloc into caller-provided outputs: S (b, l)
+    binary64 (read as l x b column-major), colsq (b,) binary64, flag (1,)
+    int32.  The library allocates nothing."""
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a (b, m) tensor with unit element stride")
+    b, m = X.shape
+    if S.shape != (b, ell) or not S.is_contiguous() or S.dtype != torch.float64:
+        raise ValueError("S must be a contiguous (b, l) float64 tensor")
+    if colsq.shape != (b,) or colsq.dtype != torch.float64 or flag.dtype != torch.int32:
+        raise ValueError("colsq must be (b,) float64 and flag int32")
+    with torch.cuda.device(X.device):
+        L.check(L.lib().rid_sketch_columns_noalloc(PREC[sketch], omega_seed, ell, m, C.c_void_p(X.data_ptr()),
+                                                   X.stride(0), b, C.c_void_p(S.data_ptr()),
+                                                   C.c_void_p(colsq.data_ptr()), C.c_void_p(flag.data_ptr()),
+                                                   _stream_handle(X.device)))
+
+
 class StreamBatch:
     """Many independent streams of uneven m advanced together: one persistent
     sketch launch per round over every member, batched update launches, the
