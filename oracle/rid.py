@@ -71,6 +71,7 @@ class Config:
     operand: str = "f64"       # operand rounding of the sketch: f64, f32, bf16 or fp8
     row_chunk: int = 1 << 16   # rows of Omega regenerated at a time
     workers: int = 1           # threads that compute the sketch's row chunks
+    coeff: str = "alg4"        # "alg4": Alg. 4 at every update; "best4": the best of Algs. 4-7
 
     @property
     def n1(self):
@@ -303,6 +304,80 @@ def nahutchpp(S, SJ, P, G, F, n1, n2):
 
 
 # --------------------------------------------------------------------------
+# Algs. 5-7 and the best of four (Alg. 3, coefficient steps)
+# --------------------------------------------------------------------------
+
+def _occupied(J):
+    return np.flatnonzero(np.asarray(J) >= 0)
+
+
+def coeff_alg5(S, J, G, ell):
+    """Alg. 5 (partial sketching): P = G^{-1} Y over the occupied slots, with
+    G = A_J^T A_J the exact basis Gram and Y = (Omega A_J)^T (Omega A_obs) / l
+    (the sketch carries l times the data's inner products, reading R1); rows of
+    empty slots are zero.  G^{-1} is the pseudo-inverse when G is singular."""
+    t = len(J)
+    P = np.zeros((t, S.shape[1]))
+    occ = _occupied(J)
+    if occ.size:
+        SJ = S[:, np.asarray(J)[occ]]
+        Y = SJ.T @ S / ell
+        P[occ] = pinv(G[np.ix_(occ, occ)]) @ Y
+    return P
+
+
+def unchanged_slots(J, J_prev):
+    """Slots holding the same snapshot before and after the update."""
+    J, J_prev = np.asarray(J), np.asarray(J_prev)
+    return (J >= 0) & (J == J_prev)
+
+
+def coeff_alg6(S, J, J_prev, P_prev, literal=False):
+    """Alg. 6 (residual of the fully sketched least squares) for the columns
+    that P_prev covers (the first P_prev.shape[1] of S): rows of P_prev for
+    slots that did not keep their column are zeroed (eq.
+    coeff_update_residual_zeroout), r_A = S - S_J P_prev, and
+    delta P = argmin ||S_J X - r_A|| is fitted over the new slots only (the
+    text: the new basis elements fit the residual), or over every occupied
+    slot (``literal``: the algorithm as printed, which equals Alg. 4 when S_J
+    has full column rank); P = P_prev + delta P."""
+    t = len(J)
+    n_prev = P_prev.shape[1]
+    S_old = S[:, :n_prev]
+    keep = unchanged_slots(J, J_prev)
+    Pz = np.where(keep[:, None], P_prev, 0.0)
+    occ = _occupied(J)
+    SJ = np.zeros((S.shape[0], t))
+    SJ[:, occ] = S[:, np.asarray(J)[occ]]
+    rA = S_old - SJ @ Pz
+    fit = occ if literal else np.flatnonzero((np.asarray(J) >= 0) & ~keep)
+    dP = np.zeros((t, n_prev))
+    if fit.size:
+        dP[fit] = pinv(SJ[:, fit]) @ rA
+    return Pz + dP
+
+
+def alg7_transform(C, J, C_prev, J_prev):
+    """T = R^+ Q^T A_{J_prev} with A_J = Q R (Alg. 7): the coefficients of the
+    previous basis columns in the current basis; rows for the current slots,
+    columns for the previous slots (zero for empty slots).  C and C_prev hold
+    the basis columns by slot (m x t)."""
+    t = len(J)
+    T = np.zeros((t, len(J_prev)))
+    occ, occ_p = _occupied(J), _occupied(J_prev)
+    if occ.size and occ_p.size:
+        AJ = C[:, occ].astype(np.float64)
+        Q, R = np.linalg.qr(AJ)
+        T[np.ix_(occ, occ_p)] = pinv(R) @ (Q.T @ C_prev[:, occ_p].astype(np.float64))
+    return T
+
+
+def coeff_alg7(T, P_prev):
+    """Alg. 7: P = T P_prev for the columns P_prev covers."""
+    return T @ P_prev
+
+
+# --------------------------------------------------------------------------
 # The streaming driver (Alg. 3)
 # --------------------------------------------------------------------------
 
@@ -323,6 +398,8 @@ class UpdateRecord:
     n_filled: int = 0
     decisions: list = field(default_factory=list)
     hutch: dict | None = None
+    e2_q: list | None = None        # best4: the NA-Hutch++ estimate of Algs. 4, 5, 6, 7
+    q_star: int = 4                 # the algorithm whose coefficients were kept
     kappa: float = float("nan")     # cond(SS^T + l lam I): diagnostic for tolerances
     cond_SJ: float = float("nan")   # cond(Omega A_J) over occupied slots: diagnostic
 
@@ -422,6 +499,7 @@ class OnlineRID:
         rec.filled = filled
         rec.n_filled = int(filled.sum())
         # basis columns C (Alg. 3 fill step sets c_i = d_r; emptied slots are zero)
+        C_prev = self.C.copy() if cfg.coeff == "best4" else None
         cols_by_idx = {j: col for j, col in self.D}
         for i in range(t):
             if filled[i]:
@@ -429,14 +507,36 @@ class OnlineRID:
             elif self.J[i] < 0:
                 self.C[:, i] = 0
         self.G = basis_gram(self.C, self.J)
-        self.P = coeff_alg4(S, self.J)
+        P4 = coeff_alg4(S, self.J)
         SJ = np.zeros((cfg.ell, t))
         occ = self.J >= 0
         SJ[:, occ] = S[:, self.J[occ]]
         if occ.any():
             sv = np.linalg.svd(SJ[:, occ], compute_uv=False)
             rec.cond_SJ = float(sv[0] / sv[-1]) if sv[-1] > 0 else float("inf")
-        rec.hutch = nahutchpp(S, SJ, self.P, self.G, self.F, cfg.n1, cfg.n2)
+        if cfg.coeff == "best4":
+            # Alg. 3's coefficient steps: Algs. 4-7 each give P_q, NA-Hutch++
+            # estimates its error, the smallest estimate wins (ties: lowest q).
+            # Algs. 6 and 7 update the previous update's P, which covers the
+            # columns observed up to that update; the columns observed since
+            # take the Alg. 4 coefficients.
+            n_prev = self.P.shape[1]
+            P5 = coeff_alg5(S, self.J, self.G, cfg.ell)
+            P6, P7 = P4.copy(), P4.copy()
+            if n_prev:
+                P6[:, :n_prev] = coeff_alg6(S, self.J, self.J_prev, self.P)
+                T = alg7_transform(self.C, self.J, C_prev, self.J_prev)
+                P7[:, :n_prev] = coeff_alg7(T, self.P)
+            cands = [P4, P5, P6, P7]
+            hs = [nahutchpp(S, SJ, Pq, self.G, self.F, cfg.n1, cfg.n2) for Pq in cands]
+            rec.e2_q = [h["E2"] for h in hs]
+            best = int(np.argmin(rec.e2_q))
+            rec.q_star = 4 + best
+            self.P = cands[best]
+            rec.hutch = hs[best]
+        else:
+            self.P = P4
+            rec.hutch = nahutchpp(S, SJ, self.P, self.G, self.F, cfg.n1, cfg.n2)
         rec.J = self.J.copy()
         self.records.append(rec)
         self.J_prev = self.J.copy()
