@@ -79,6 +79,17 @@ typedef enum rid_sketch_prec {
  * two 32 KB ones); the batch tuner times both. */
 typedef enum rid_sketch_tile { RID_TILE_AUTO = 0, RID_TILE_NARROW = 1, RID_TILE_WIDE = 2 } rid_sketch_tile;
 
+/* Coefficients of each update (Alg. 3's coefficient steps, Sec. 3.2):
+ * RID_COEFF_ALG4 computes Alg. 4 (full sketch least squares) only;
+ * RID_COEFF_BEST4 computes Algs. 4, 5, 6 and 7 and keeps the one whose
+ * NA-Hutch++ estimate (Alg. 8) is smallest (ties: the lowest algorithm).
+ * Alg. 5 takes (Omega A_J)^T (Omega A_obs) / l as its approximation of
+ * A_J^T A_obs; Alg. 6 fits the residual with the new basis columns (the
+ * text's reading); Algs. 6 and 7 update the previous update's kept P and give
+ * the columns observed since it Alg. 4's coefficients; Alg. 7's transform is
+ * G^{-1} A_J^T A_{J_prev} from exact Grams. */
+typedef enum rid_coeff_mode { RID_COEFF_ALG4 = 0, RID_COEFF_BEST4 = 1 } rid_coeff_mode;
+
 /* Push flags. */
 #define RID_COPY   0u  /* copy the columns into the library's ring; the buffer
                           may be reused once prior work on the stream is done */
@@ -112,6 +123,9 @@ typedef struct rid_config {
   int32_t lookahead;      /* columns buffered before a sketch launch; 0 = auto */
   int32_t sketch_tile;    /* rid_sketch_tile (default RID_TILE_AUTO) */
   int64_t n_max;          /* capacity: maximum number of pushed columns */
+  int32_t coeff_mode;     /* rid_coeff_mode (default RID_COEFF_ALG4); RID_COEFF_BEST4 needs
+                             t <= 154 and a stream of its own (not a batch member) */
+  int32_t reserved1;      /* 0 */
 } rid_config;
 
 /* Error estimate of the last completed update (Alg. 8). */
@@ -271,6 +285,13 @@ rid_status rid_profile_enable(rid_stream* h, int32_t on);
 rid_status rid_profile_read(rid_stream* h, rid_profile* p);
 
 /* ---- inspection entry points used by the parity tests ------------------ */
+
+/* The choice of update u in RID_COEFF_BEST4 mode: e2[q - 4] = the NA-Hutch++
+ * estimate E^2 of Alg. q's coefficients (q = 4..7, host array of 4) and
+ * *q_star = the algorithm kept.  Synchronises.  Errors: RID_EINVAL (null
+ * arguments, u outside the enqueued updates), RID_ESTATE (another mode,
+ * failed stream). */
+rid_status rid_get_coeff_choice(rid_stream* h, int64_t u, double* e2, int32_t* q_star);
 
 /* Sketch state: S (l x n_sketched, binary64) into the host array S with
  * leading dimension lds >= l and at most cap_cols columns, ||a_j||^2 into

@@ -16,6 +16,7 @@ RID_F32, RID_F64 = 0, 1
 RID_SKETCH_F64, RID_SKETCH_F32, RID_SKETCH_BF16, RID_SKETCH_FP8 = 0, 1, 2, 3
 RID_COPY, RID_BORROW = 0, 1
 RID_TILE_AUTO, RID_TILE_NARROW, RID_TILE_WIDE = 0, 1, 2
+RID_COEFF_ALG4, RID_COEFF_BEST4 = 0, 1
 RID_HOST, RID_DEVICE = 0, 1
 RID_UPD_SKIPPED, RID_UPD_RANK_DEFICIENT, RID_UPD_PINV_TRUNCATED = 1, 2, 4
 
@@ -27,7 +28,7 @@ class rid_config(C.Structure):
         ("omega_seed", C.c_uint64), ("select_seed", C.c_uint64),
         ("delta", C.c_double), ("eps", C.c_double), ("c_sample", C.c_double), ("ridge_floor", C.c_double),
         ("hutch_n1", C.c_int32), ("hutch_n2", C.c_int32), ("lookahead", C.c_int32), ("sketch_tile", C.c_int32),
-        ("n_max", C.c_int64),
+        ("n_max", C.c_int64), ("coeff_mode", C.c_int32), ("reserved1", C.c_int32),
     ]
 
 
@@ -84,6 +85,7 @@ SIGNATURES = {
     "rid_destroy": (C.c_int, [C.c_void_p]),
     "rid_status_string": (C.c_char_p, [C.c_int]),
     "rid_last_error": (C.c_int, [C.c_void_p, C.c_char_p, C.c_size_t]),
+    "rid_get_coeff_choice": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.POINTER(C.c_int32)]),
     "rid_debug_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.POINTER(C.c_int64), C.c_void_p, C.c_void_p]),
     "rid_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "rid_profile_read": (C.c_int, [C.c_void_p, C.POINTER(rid_profile)]),

@@ -157,6 +157,16 @@ struct rid_stream {
   // flush goes to a slice of Pz.  Their argument tables go to ctab_dev from a
   // ring of pinned host slots.
   int cgroup = 1;
+  // RID_COEFF_BEST4: the candidates, the kept P of the previous update and
+  // the work space of Algs. 5-7 (B4Args); Xc has one t x t slot per update of
+  // a flush, recq four records and qstar one choice per update
+  bool best4 = false;
+  double *b4_Pc = nullptr, *b4_Pprev = nullptr, *b4_M5 = nullptr, *b4_L = nullptr, *b4_T = nullptr;
+  double *b4_rA = nullptr, *b4_D6 = nullptr, *b4_QR6 = nullptr, *b4_tau6 = nullptr, *b4_Qm6 = nullptr;
+  double *b4_Mm6 = nullptr, *b4_Xc = nullptr;
+  DevScalars* b4_sc6 = nullptr;
+  rid_update *b4_rec = nullptr, *b4_recq = nullptr;
+  int32_t* b4_qstar = nullptr;
   double* Pz = nullptr;
   double* SSTk = nullptr;   // nzmax slots of l x l: each update's SS^T (sst_keep)
   // the next flush's SS^T batch rewrites SSTk: it waits for the side stream's
@@ -350,6 +360,10 @@ static rid_status validate(const rid_config* c) {
     return fail(nullptr, RID_EINVAL, "unknown sketch_tile");
   if (c->sketch_tile == RID_TILE_WIDE && !(c->sketch_prec == RID_SKETCH_BF16 && c->ell > 128 && c->ell <= 320))
     return fail(nullptr, RID_ENOTSUP, "the wide sketch tile needs the bf16 form and 128 < ell <= 320");
+  if (c->coeff_mode != RID_COEFF_ALG4 && c->coeff_mode != RID_COEFF_BEST4)
+    return fail(nullptr, RID_EINVAL, "unknown coeff_mode");
+  if (c->coeff_mode == RID_COEFF_BEST4 && c->t > kAlg4Gemm)
+    return fail(nullptr, RID_ENOTSUP, "RID_COEFF_BEST4 needs t <= 154");
   return RID_OK;
 }
 
@@ -368,6 +382,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
   *out = nullptr;
   rid_status st = validate(cfg);
   if (st != RID_OK) return st;
+  if (member && cfg->coeff_mode == RID_COEFF_BEST4)
+    return fail(nullptr, RID_ENOTSUP, "RID_COEFF_BEST4 is not supported for batch members");
   rid_stream* h = new rid_stream();
   h->cfg = *cfg;
   h->s = reinterpret_cast<hipStream_t>(stream);
@@ -427,6 +443,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
       h->cgroup = std::min(h->nzmax, by_mem);
     }
   }
+  h->best4 = cfg->coeff_mode == RID_COEFF_BEST4;
+  if (h->best4) h->cgroup = 1;   // each update's choice feeds the next one's Algs. 6 and 7
   const size_t ell = h->ell, t = h->t, cg = h->cgroup;
   const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
 #define ALLOC(ptr, n) \
@@ -466,6 +484,24 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     ALLOC(h->sc, (size_t)1);
     ALLOC(h->sc_hist, (size_t)h->max_updates);
     ALLOC(h->Ghist, t * t * h->max_updates);
+    if (h->best4) {
+      ALLOC(h->b4_Pc, 4 * t * h->n_max);
+      ALLOC(h->b4_Pprev, t * h->n_max);
+      ALLOC(h->b4_M5, t * ell);
+      ALLOC(h->b4_L, t * t);
+      ALLOC(h->b4_T, t * t);
+      ALLOC(h->b4_rA, ell * h->n_max);
+      ALLOC(h->b4_D6, t * h->n_max);
+      ALLOC(h->b4_QR6, ell * t);
+      ALLOC(h->b4_tau6, (size_t)kMaxT);
+      ALLOC(h->b4_Qm6, ell * t);
+      ALLOC(h->b4_Mm6, t * ell);
+      ALLOC(h->b4_Xc, t * t * h->nzmax);
+      ALLOC(h->b4_sc6, (size_t)1);
+      ALLOC(h->b4_rec, (size_t)1);
+      ALLOC(h->b4_recq, 4 * (size_t)h->max_updates);
+      ALLOC(h->b4_qstar, (size_t)h->max_updates);
+    }
     ALLOC(h->recs, (size_t)h->max_updates);
     if ((st = dalloc(h, &h->part, (size_t)h->n_slabs * h->b_max * h->ell_pad * psize)) != RID_OK)
       goto fail_alloc;
@@ -723,6 +759,34 @@ static rid_status take_table(rid_stream* h, Stage& stg) {
   return RID_OK;
 }
 
+// Algs. 5-7 buffers of update u (slot z of the flush).
+static B4Args b4_args(rid_stream* h, int64_t u, int z) {
+  const size_t t = h->t;
+  B4Args b;
+  b.n_prev = u * h->t;   // every update before the last of a stream is full
+  b.J_prev = u > 0 ? h->J_hist + (u - 1) * t : nullptr;
+  b.G_prev = u > 0 ? h->Ghist + (u - 1) * t * t : nullptr;
+  b.Xc = h->b4_Xc + (size_t)z * t * t;
+  b.Pc = h->b4_Pc;
+  b.Pprev = h->b4_Pprev;
+  b.Pout = h->P;
+  b.M5 = h->b4_M5;
+  b.L = h->b4_L;
+  b.T = h->b4_T;
+  b.rA = h->b4_rA;
+  b.D6 = h->b4_D6;
+  b.QR6 = h->b4_QR6;
+  b.tau6 = h->b4_tau6;
+  b.Qm6 = h->b4_Qm6;
+  b.Mm6 = h->b4_Mm6;
+  b.sc6 = h->b4_sc6;
+  b.scratch_rec = h->b4_rec;
+  b.recq = h->b4_recq + 4 * u;
+  b.qstar = h->b4_qstar + u;
+  b.n_max = h->n_max;
+  return b;
+}
+
 static rid_status run_updates(rid_stream* h, int n_full, int last) {
   const int nz = n_full + (last > 0 ? 1 : 0);
   if (nz == 0) return RID_OK;
@@ -742,6 +806,9 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
     RID_HIP(h, launch_update_select(a, h->s, false));
     mark_end(h, mk);
     mk = mark_begin(h, 3, (double)a.u);
+    // Alg. 7 needs the new columns' products with the pruned ones, which the
+    // Gram's pool copy overwrites
+    if (h->best4 && a.u > 0) RID_HIP(h, launch_best4_cross(a, b4_args(h, a.u, z), h->s));
     RID_HIP(h, launch_update_gram(a, h->s));
     mark_end(h, mk);
     // Alg. 4 and Alg. 8 of this update read snapshots of the selection state
@@ -751,6 +818,7 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
     ac.G = h->Ghist + (size_t)a.u * h->t * h->t;
     ac.J = h->J_hist + (size_t)a.u * h->t;
     coeff_slice(h, ac, z, nz);
+    if (h->best4) ac.P = h->b4_Pc;   // Alg. 4's candidate
     co[z] = ac;
     RID_HIP(h, launch_update_snapshot(a, ac.sc, ac.G, h->s));
     h->last_nobs = a.n_obs;
@@ -764,7 +832,8 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   for (int z0 = 0; z0 < nz; z0 += h->cgroup) {
     const int g = std::min(h->cgroup, nz - z0);
     if (g == 1) {
-      RID_HIP(h, launch_update_coeff(co[z0], h->side, z0 == nz - 1));
+      RID_HIP(h, launch_update_coeff(co[z0], h->side, h->best4 || z0 == nz - 1));
+      if (h->best4) RID_HIP(h, launch_best4(co[z0], b4_args(h, co[z0].u, z0), h->side));
       continue;
     }
     Stage stg;
@@ -1047,6 +1116,19 @@ rid_status rid_reconstruct(rid_stream* h, int64_t j0, int32_t c, void* d_out, in
     RID_HIP(h, hipEventRecord(h->join_ev, h->s));
     RID_HIP(h, hipStreamWaitEvent(h->join, h->join_ev, 0));
   }
+  return RID_OK;
+}
+
+rid_status rid_get_coeff_choice(rid_stream* h, int64_t u, double* e2, int32_t* q_star) {
+  if (!h || !e2 || !q_star) return fail(h, RID_EINVAL, "null argument");
+  if (!h->best4) return fail(h, RID_ESTATE, "the stream does not run RID_COEFF_BEST4");
+  rid_status st = getter_prologue(h);
+  if (st != RID_OK) return st;
+  if (u < 0 || u >= h->n_updates) return fail(h, RID_EINVAL, "update index out of range");
+  rid_update rq[4];
+  RID_HIP(h, hipMemcpy(rq, h->b4_recq + 4 * u, sizeof(rq), hipMemcpyDeviceToHost));
+  RID_HIP(h, hipMemcpy(q_star, h->b4_qstar + u, sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int q = 0; q < 4; ++q) e2[q] = rq[q].E2;
   return RID_OK;
 }
 

@@ -474,6 +474,36 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
 // want_p: form P (the last update of a flush; Alg. 8 needs only Y and P P^T)
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s, bool want_p = true);
 hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* g_out, hipStream_t s);
+
+// Algs. 5-7 and the best of four (Alg. 3's coefficient steps).  Buffers of one
+// update; layouts as in UpdArgs (column-major, slot-indexed rows of t).
+struct B4Args {
+  int64_t n_prev;          // columns the previous update's P covers (0 at the first update)
+  const int64_t* J_prev;   // t: J of the previous update (null at the first)
+  const double* G_prev;    // t x t: basis Gram of the previous update
+  double* Xc;              // t x t: products of this update's new columns with the pruned ones
+  double* Pc;              // 4 slices of t x n_max: the candidates of Algs. 4, 5, 6, 7
+  double* Pprev;           // t x n_max: the previous update's kept P
+  double* Pout;            // t x n_max: the stream's P (read by rid_coefficients)
+  double* M5;              // t x l: G^{-1} (Omega A_J)^T / l over the occupied slots (Mm layout)
+  double* L;               // t x t: Cholesky factor of G over the occupied slots (compact)
+  double* T;               // t x t: the Alg. 7 transform (compact current x compact previous slots)
+  double* rA;              // l x n_max: the Alg. 6 residual
+  double* D6;              // t x n_max: the Alg. 6 correction (rows of the new slots)
+  double *QR6, *tau6, *Qm6, *Mm6;  // Alg. 4 factors of the new slots alone
+  DevScalars* sc6;         // the selection state restricted to the new slots
+  rid_update* scratch_rec; // record the factorisation of the new slots may flag
+  rid_update* recq;        // 4: this update's record with each candidate's estimate
+  int32_t* qstar;          // this update's kept algorithm (4..7)
+  int64_t n_max;
+};
+// Main stream, between the selection and the Gram of update u >= 1: the
+// products of the new basis columns with the pruned ones (before the pool
+// copy overwrites the pruned columns).
+hipError_t launch_best4_cross(const UpdArgs& a, const B4Args& b, hipStream_t s);
+// Second stream, after launch_update_coeff(a with P = Pc slice 0): the other
+// three candidates, their estimates and the choice.
+hipError_t launch_best4(const UpdArgs& a, const B4Args& b, hipStream_t s);
 // NA-Hutch++ work per update (doubles) for l and t; hutch_work_quarter(l) is
 // the size of each of its five l^2 / 4 regions
 __host__ __device__ inline int64_t hutch_work_quarter(int ell) { return (int64_t)ell * ell / 4 + 64; }

@@ -2806,6 +2806,449 @@ void plan_update_snapshot_b(const SnapArgs* h, int n, Stage& st, std::vector<BLa
   P.emit(dim3(256), -1, st, out);
 }
 
+// ---------------------------------------------------------------------------
+// Algs. 5-7 and the best of four (Alg. 3's coefficient steps).
+//
+// Per update, after the Alg. 4 phase formed P4 and its NA-Hutch++ record:
+//   Alg. 5  P5 = G^{-1} (Omega A_J)^T (Omega A_obs) / l over the occupied
+//           slots: G = L L^T (Cholesky), M5 = L^{-T} L^{-1} S_J^T / l, P5 = M5 S;
+//   Alg. 6  the previous kept P with the rows of replaced slots zeroed (Pz),
+//           r_A = S - S_J Pz over the columns it covers, the new slots' part
+//           of pinv(S_J) applied to r_A (the Alg. 4 factorisation of the new
+//           slots alone), P6 = Pz + that;
+//   Alg. 7  T = G^{-1} A_J^T A_{J_prev} (equal to R^+ Q^T A_{J_prev} for the QR
+//           of A_J when A_J has full column rank, from the exact Grams: the
+//           current one, the previous one and the new-by-pruned products
+//           taken before the pool copy), P7 = T P_prev;
+// the columns observed since the previous update take P4's coefficients in
+// Algs. 6 and 7.  Each candidate's estimate comes from the same NA-Hutch++
+// kernels (Y = S P^T and P P^T from P); the smallest E^2 wins, ties to the
+// lowest q, and the kept P becomes the stream's P and the next update's P_prev.
+// ---------------------------------------------------------------------------
+
+// Pruned slots (occupied before the update, holding another column or none
+// after it), in slot order, into LDS; returns their count.
+__device__ int best4_pruned(const UpdArgs& a, const B4Args& b, int* pr) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int j = 0; j < a.t; ++j)
+      if (b.J_prev[j] >= 0 && a.J[j] != b.J_prev[j]) pr[n++] = j;
+    cnt = n;
+  }
+  __syncthreads();
+  return cnt;
+}
+
+// New-by-pruned products over one Gram slab: tile (32 new, 32 pruned) of
+// partial sums into gpart[slab][t][t] (compact indices).
+template <typename T>
+__global__ __launch_bounds__(256) void best4_cross_kernel(UpdArgs a, B4Args b) {
+  __shared__ double red[4 * 16 * 64];
+  __shared__ int pr[kMaxT];
+  const int t = a.t;
+  const int npr = best4_pruned(a, b, pr);
+  const int nn = a.sc->n_new;
+  const int tiles_n = (t + 31) / 32;
+  const int it = blockIdx.x % tiles_n, jt = blockIdx.x / tiles_n;
+  if (32 * it >= nn || 32 * jt >= npr) return;
+  const int64_t r0 = (int64_t)blockIdx.y * a.gslab_rows;
+  const int64_t r1 = min(a.m, r0 + a.gslab_rows);
+  const int K = (int)max((int64_t)0, r1 - r0);
+  const T* pool = reinterpret_cast<const T*>(a.cpool);
+  double out[2][2][4];
+  gemm32_f64(32 * it, 32 * jt, K,
+             [&](int i, int k) {
+               if (i >= nn || k >= K) return 0.0;
+               const T* col = reinterpret_cast<const T*>(a.colptr[a.J[a.sc->new_slot[i]]]);
+               return (double)col[r0 + k];
+             },
+             [&](int k, int j) {
+               return (j < npr && k < K) ? (double)pool[(int64_t)pr[j] * a.ldc + r0 + k] : 0.0;
+             },
+             out, red);
+  if ((threadIdx.x >> 6) == 0) {
+    const int lane = threadIdx.x & 63, i16 = lane & 15, k4 = lane >> 4;
+    double* part = a.gpart + (int64_t)blockIdx.y * t * t;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 32 * it + 16 * x + k4 + 4 * v, j = 32 * jt + 16 * y + i16;
+          if (i < nn && j < npr) part[(int64_t)j * t + i] = out[x][y][v];
+        }
+  }
+}
+
+// Xc(new slot, pruned slot) = sum over the slabs in slab order.
+__global__ __launch_bounds__(256) void best4_cross_reduce_kernel(UpdArgs a, B4Args b) {
+  __shared__ int pr[kMaxT];
+  const int t = a.t;
+  const int npr = best4_pruned(a, b, pr);
+  const int nn = a.sc->n_new;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nn * npr) return;
+  const int i = (int)(idx % nn), j = (int)(idx / nn);
+  double s = 0.0;
+  for (int sl = 0; sl < a.gslabs; ++sl) s += a.gpart[(int64_t)sl * t * t + (int64_t)j * t + i];
+  b.Xc[(int64_t)pr[j] * t + a.sc->new_slot[i]] = s;
+}
+
+hipError_t launch_best4_cross(const UpdArgs& a, const B4Args& b, hipStream_t s) {
+  const int tiles_n = (a.t + 31) / 32;
+  if (a.data_f64)
+    hipLaunchKernelGGL(best4_cross_kernel<double>, dim3(tiles_n * tiles_n, a.gslabs), dim3(256), 0, s, a, b);
+  else
+    hipLaunchKernelGGL(best4_cross_kernel<float>, dim3(tiles_n * tiles_n, a.gslabs), dim3(256), 0, s, a, b);
+  hipLaunchKernelGGL(best4_cross_reduce_kernel, dim3((a.t * a.t + 255) / 256), dim3(256), 0, s, a, b);
+  return hipGetLastError();
+}
+
+// Keeps the update's record (the estimate of the candidate just evaluated).
+__global__ void best4_keep_kernel(UpdArgs a, B4Args b, int q) {
+  if (threadIdx.x == 0) b.recq[q] = a.recs[a.u];
+}
+
+// Cholesky factor of G over the occupied slots (compact order), one
+// workgroup: right-looking, column by column.  A pivot that is not positive
+// (a numerically dependent basis column) leaves a zero column: the solves
+// below then give that unknown 0.
+__global__ __launch_bounds__(1024) void best4_chol_kernel(UpdArgs a, B4Args b) {
+  const int t = a.t, no = min(a.sc->n_occ, a.ell);
+  const int* occ = a.sc->occ_slot;
+  double* L = b.L;
+  for (int idx = threadIdx.x; idx < no * no; idx += blockDim.x) {
+    const int i = idx % no, j = idx / no;
+    L[(int64_t)j * t + i] = (i >= j) ? a.G[(int64_t)occ[j] * t + occ[i]] : 0.0;
+  }
+  __syncthreads();
+  __shared__ double piv;
+  double gmax = 0.0;
+  for (int i = 0; i < no; ++i) gmax = fmax(gmax, a.G[(int64_t)occ[i] * t + occ[i]]);
+  const double tiny = (double)no * 2.220446049250313e-16 * gmax;
+  for (int j = 0; j < no; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = L[(int64_t)j * t + j];
+      piv = d > tiny ? sqrt(d) : 0.0;
+      L[(int64_t)j * t + j] = piv;
+    }
+    __syncthreads();
+    const double p = piv;
+    for (int i = j + 1 + threadIdx.x; i < no; i += blockDim.x)
+      L[(int64_t)j * t + i] = p > 0.0 ? L[(int64_t)j * t + i] / p : 0.0;
+    __syncthreads();
+    // trailing update of the lower triangle, column by column
+    const int rem = no - j - 1;
+    for (int idx = threadIdx.x; idx < rem * rem; idx += blockDim.x) {
+      const int i = j + 1 + idx % rem, c = j + 1 + idx / rem;
+      if (i >= c) L[(int64_t)c * t + i] -= L[(int64_t)j * t + i] * L[(int64_t)j * t + c];
+    }
+    __syncthreads();
+  }
+}
+
+// Right-hand sides, compact rows: which 0 -> M5 (no x l, Mm layout) holds
+// S_J^T / l; which 1 -> T (no x no_prev) holds A_J^T A_{J_prev} assembled from
+// the current Gram (unchanged previous columns), the previous Gram (kept x
+// pruned) and the new-by-pruned products.
+__global__ __launch_bounds__(256) void best4_rhs_kernel(UpdArgs a, B4Args b, int which) {
+  __shared__ int occp[kMaxT];
+  __shared__ int nop;
+  const int t = a.t, n = a.ell, no = min(a.sc->n_occ, n);
+  const int* occ = a.sc->occ_slot;
+  if (which == 0) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)no * n) return;
+    const int i = (int)(idx % no), r = (int)(idx / no);
+    b.M5[(int64_t)r * t + i] = a.S[a.J[occ[i]] * n + r] / (double)n;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int j = 0; j < t; ++j)
+      if (b.J_prev[j] >= 0) occp[c++] = j;
+    nop = c;
+  }
+  __syncthreads();
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)no * nop) return;
+  const int i = (int)(idx % no), c = (int)(idx / no);
+  const int si = occ[i], sj = occp[c];
+  const bool j_kept = a.J[sj] == b.J_prev[sj];
+  const bool i_kept = a.J[si] == b.J_prev[si];
+  double v;
+  if (j_kept) v = a.G[(int64_t)sj * t + si];
+  else if (i_kept) v = b.G_prev[(int64_t)sj * t + si];
+  else v = b.Xc[(int64_t)sj * t + si];
+  b.T[(int64_t)c * t + i] = v;
+}
+
+// X = L^{-T} L^{-1} X in place, one thread per right-hand side (column c of
+// no entries at c * t).  which 0: the l columns of M5; 1: the no_prev columns
+// of T.
+__global__ __launch_bounds__(64) void best4_solve_kernel(UpdArgs a, B4Args b, int which) {
+  const int t = a.t, no = min(a.sc->n_occ, a.ell);
+  int ncols;
+  if (which == 0) {
+    ncols = a.ell;
+  } else {
+    ncols = 0;
+    for (int j = 0; j < t; ++j) ncols += b.J_prev[j] >= 0;
+  }
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  double* x = (which == 0 ? b.M5 : b.T) + (int64_t)c * t;
+  const double* L = b.L;
+  for (int i = 0; i < no; ++i) {
+    double v = x[i];
+    for (int k = 0; k < i; ++k) v -= L[(int64_t)k * t + i] * x[k];
+    const double d = L[(int64_t)i * t + i];
+    x[i] = d > 0.0 ? v / d : 0.0;
+  }
+  for (int i = no - 1; i >= 0; --i) {
+    double v = x[i];
+    for (int k = i + 1; k < no; ++k) v -= L[(int64_t)i * t + k] * x[k];
+    const double d = L[(int64_t)i * t + i];
+    x[i] = d > 0.0 ? v / d : 0.0;
+  }
+}
+
+// The selection state restricted to the new slots (the Alg. 4 factorisation
+// of S over them gives their part of the residual fit of Alg. 6).
+__global__ void best4_sc6_kernel(UpdArgs a, B4Args b) {
+  constexpr int nw = (int)(sizeof(DevScalars) / sizeof(int32_t));
+  for (int k = threadIdx.x; k < nw; k += blockDim.x)
+    reinterpret_cast<int32_t*>(b.sc6)[k] = reinterpret_cast<const int32_t*>(a.sc)[k];
+  __syncthreads();
+  if (threadIdx.x == 0) b.sc6->n_occ = a.sc->n_new;
+  for (int i = threadIdx.x; i < a.sc->n_new; i += blockDim.x) b.sc6->occ_slot[i] = a.sc->new_slot[i];
+}
+
+// r_A = S - S_J Pz over the columns the previous P covers (Pz: the rows of
+// the slots that kept their column).
+__global__ __launch_bounds__(256) void best4_ra_kernel(UpdArgs a, B4Args b) {
+  __shared__ double red[4 * 16 * 64];
+  const int n = a.ell, t = a.t;
+  const int64_t np = b.n_prev;
+  const int nmt = (n + 31) / 32;
+  const int m0 = 32 * (blockIdx.x % nmt), n0 = 32 * (blockIdx.x / nmt);
+  if (n0 >= np) return;
+  double out[2][2][4];
+  gemm32_f64(m0, n0, t,
+             [&](int r, int k) {
+               return (r < n && k < t && a.J[k] >= 0 && a.J[k] == b.J_prev[k]) ? a.S[a.J[k] * n + r] : 0.0;
+             },
+             [&](int k, int c) { return (k < t && c < np) ? b.Pprev[(int64_t)c * t + k] : 0.0; }, out, red);
+  if ((threadIdx.x >> 6) == 0) {
+    const int lane = threadIdx.x & 63, i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = m0 + 16 * x + k4 + 4 * v, c = n0 + 16 * y + i16;
+          if (r < n && c < np) b.rA[(int64_t)c * n + r] = a.S[(int64_t)c * n + r] - out[x][y][v];
+        }
+  }
+}
+
+// P6 = Pz + D6 over the columns the previous P covers, P4 after them.
+__global__ __launch_bounds__(256) void best4_p6_kernel(UpdArgs a, B4Args b) {
+  const int t = a.t;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)t * a.n_obs) return;
+  const int i = (int)(idx % t);
+  const int64_t c = idx / t;
+  const double* P4 = b.Pc;
+  double* P6 = b.Pc + 2 * (int64_t)t * b.n_max;
+  if (c < b.n_prev) {
+    const bool kept = a.J[i] >= 0 && a.J[i] == b.J_prev[i];
+    P6[idx] = (kept ? b.Pprev[idx] : 0.0) + b.D6[idx];
+  } else {
+    P6[idx] = P4[idx];
+  }
+}
+
+// P7 = T P_prev over the columns the previous P covers (rows of the occupied
+// slots; zero rows for empty slots), P4 after them.
+__global__ __launch_bounds__(256) void best4_p7_kernel(UpdArgs a, B4Args b) {
+  __shared__ double red[4 * 16 * 64];
+  __shared__ int occp[kMaxT];
+  __shared__ int nop;
+  const int t = a.t, no = min(a.sc->n_occ, a.ell);
+  const int64_t np = b.n_prev, nobs = a.n_obs;
+  const double* P4 = b.Pc;
+  double* P7 = b.Pc + 3 * (int64_t)t * b.n_max;
+  const int nmt = (t + 31) / 32;
+  const int m0 = 32 * (blockIdx.x % nmt), n0 = 32 * (blockIdx.x / nmt);
+  if (n0 >= nobs) return;
+  // columns after the previous P: P4's (slots m0 .. m0 + 31 of this tile)
+  for (int idx = threadIdx.x; idx < 32 * 32; idx += blockDim.x) {
+    const int i = m0 + idx % 32;
+    const int64_t c = n0 + idx / 32;
+    if (i < t && c >= np && c < nobs) P7[c * t + i] = P4[c * t + i];
+  }
+  if (n0 >= np) return;
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int j = 0; j < t; ++j)
+      if (b.J_prev[j] >= 0) occp[c++] = j;
+    nop = c;
+  }
+  __syncthreads();
+  const int kp = nop;
+  // rows of empty slots are zero (this block's columns before np)
+  if (m0 == 0) {
+    for (int idx = threadIdx.x; idx < 32 * t; idx += blockDim.x) {
+      const int i = idx % t;
+      const int64_t c = n0 + idx / t;
+      if (a.J[i] < 0 && c < np) P7[c * t + i] = 0.0;
+    }
+  }
+  if (m0 >= no) return;
+  double out[2][2][4];
+  gemm32_f64(m0, n0, kp, [&](int i, int k) { return (i < no && k < kp) ? b.T[(int64_t)k * t + i] : 0.0; },
+             [&](int k, int c) { return (k < kp && c < np) ? b.Pprev[(int64_t)c * t + occp[k]] : 0.0; }, out, red);
+  if ((threadIdx.x >> 6) == 0) {
+    const int lane = threadIdx.x & 63, i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = m0 + 16 * x + k4 + 4 * v;
+          const int64_t c = n0 + 16 * y + i16;
+          if (i < no && c < np) P7[c * t + a.sc->occ_slot[i]] = out[x][y][v];
+        }
+  }
+}
+
+// The smallest estimate wins (ties: the lowest q): its record becomes the
+// update's, and the choice is kept.
+__global__ void best4_choose_kernel(UpdArgs a, B4Args b) {
+  if (threadIdx.x != 0) return;
+  int best = 0;
+  for (int q = 1; q < 4; ++q)
+    if (b.recq[q].E2 < b.recq[best].E2) best = q;
+  a.recs[a.u] = b.recq[best];
+  *b.qstar = 4 + best;
+}
+
+// P = P_{q*} into the stream's P and the next update's P_prev.
+__global__ __launch_bounds__(256) void best4_copy_kernel(UpdArgs a, B4Args b) {
+  const int64_t n = (int64_t)a.t * a.n_obs;
+  const double* src = b.Pc + (int64_t)(*b.qstar - 4) * a.t * b.n_max;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = src[i];
+    b.Pout[i] = v;
+    b.Pprev[i] = v;
+  }
+}
+
+namespace {
+
+// The Alg. 4 factorisation (Householder QR of S over the slots in a.sc, the
+// thin Q, M = R'^{-1} Q^T), for t <= kAlg4Gemm.
+void best4_factor(const UpdArgs& a, hipStream_t s) {
+  const int E = (a.ell + 63) / 64;
+  if (E <= 1 && a.t <= 16)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<1, 2, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (E <= 2 && a.t <= 64)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<2, 8, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (E <= 4 && a.t <= 112)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<4, 14, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (E <= 5 && a.t <= 152)
+    hipLaunchKernelGGL((alg4_qr_reg_kernel<5, 19, 8>), dim3(1), dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL(alg4_qr_kernel, dim3(1), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(alg4_q_kernel, dim3(a.t), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(alg4_m_kernel, dim3((a.ell + 3) / 4), dim3(256), alg4_m_lds(a.t), s, a);
+}
+
+// NA-Hutch++ (Alg. 8) of the coefficients in a.P, into a.recs[a.u].
+void best4_hutch(const UpdArgs& a, hipStream_t s) {
+  const int tiles = ((a.ell + 31) / 32) * ((a.t + 31) / 32) + ((a.t + 31) / 32) * ((a.t + 31) / 32);
+  hipLaunchKernelGGL(hutch_gemm_kernel, dim3(tiles), dim3(256), 0, s, a);
+  const int n3 = a.ell - a.n1 - a.n2;
+  const int64_t s0 = (int64_t)a.ell * a.t;
+  const int64_t s1 = (int64_t)a.n1 * a.n2 + (int64_t)a.n1 * a.t + (int64_t)a.n1 * n3 + (int64_t)n3 * a.n2;
+  const int64_t s2 = (int64_t)a.n1 * a.n2;
+  hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s0 + 255) / 256)), dim3(256), 0, s, a, 0);
+  hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s1 + 255) / 256)), dim3(256), 0, s, a, 1);
+  hipLaunchKernelGGL(hutch_mid_kernel, dim3((unsigned)((s2 + 255) / 256)), dim3(256), 0, s, a, 2);
+  const int E = (a.n2 + 63) / 64, nv = 3 * a.n1;
+  if (a.n1 > 0 && E <= 1 && nv <= 8 * 4)
+    hipLaunchKernelGGL((hutch_small_reg_kernel<1, 4, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (a.n1 > 0 && E <= 2 && nv <= 8 * 19)
+    hipLaunchKernelGGL((hutch_small_reg_kernel<2, 19, 8>), dim3(1), dim3(512), 0, s, a);
+  else if (a.n1 > 0 && E <= 3 && nv <= 8 * 29)
+    hipLaunchKernelGGL((hutch_small_reg_kernel<3, 29, 8>), dim3(1), dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL(hutch_small_kernel, dim3(1), dim3(1024), 0, s, a);
+}
+
+}  // namespace
+
+hipError_t launch_best4(const UpdArgs& a, const B4Args& b, hipStream_t s) {
+  alg4_m_attributes();
+  const int t = a.t, n = a.ell;
+  const int64_t tn = (int64_t)t * b.n_max;
+  const unsigned pcols = (unsigned)(((t + 31) / 32) * ((a.n_obs + 31) / 32));
+  hipLaunchKernelGGL(best4_keep_kernel, dim3(1), dim3(64), 0, s, a, b, 0);
+  // Alg. 5
+  hipLaunchKernelGGL(best4_chol_kernel, dim3(1), dim3(1024), 0, s, a, b);
+  hipLaunchKernelGGL(best4_rhs_kernel, dim3((unsigned)(((int64_t)t * n + 255) / 256)), dim3(256), 0, s, a, b, 0);
+  hipLaunchKernelGGL(best4_solve_kernel, dim3((n + 63) / 64), dim3(64), 0, s, a, b, 0);
+  UpdArgs a5 = a;
+  a5.Mm = b.M5;
+  a5.P = b.Pc + tn;
+  hipLaunchKernelGGL(alg4_pgemm_kernel, dim3(pcols), dim3(256), 0, s, a5);
+  // Alg. 6 (over the previous columns; the rest are P4's)
+  if (b.n_prev > 0) {
+    hipLaunchKernelGGL(best4_sc6_kernel, dim3(1), dim3(256), 0, s, a, b);
+    UpdArgs a6 = a;
+    a6.sc = b.sc6;
+    a6.QR = b.QR6;
+    a6.qr_tau = b.tau6;
+    a6.Qm = b.Qm6;
+    a6.Mm = b.Mm6;
+    a6.recs = b.scratch_rec;
+    a6.u = 0;
+    best4_factor(a6, s);
+    hipLaunchKernelGGL(best4_ra_kernel, dim3((unsigned)(((n + 31) / 32) * ((b.n_prev + 31) / 32))), dim3(256), 0,
+                       s, a, b);
+    a6.S = b.rA;
+    a6.n_obs = b.n_prev;
+    a6.P = b.D6;
+    hipLaunchKernelGGL(alg4_pgemm_kernel, dim3((unsigned)(((t + 31) / 32) * ((b.n_prev + 31) / 32))), dim3(256),
+                       0, s, a6);
+  }
+  hipLaunchKernelGGL(best4_p6_kernel, dim3((unsigned)(((int64_t)t * a.n_obs + 255) / 256)), dim3(256), 0, s, a,
+                     b);
+  // Alg. 7
+  if (b.n_prev > 0) {
+    hipLaunchKernelGGL(best4_rhs_kernel, dim3((unsigned)(((int64_t)t * t + 255) / 256)), dim3(256), 0, s, a, b, 1);
+    hipLaunchKernelGGL(best4_solve_kernel, dim3((t + 63) / 64), dim3(64), 0, s, a, b, 1);
+  }
+  hipLaunchKernelGGL(best4_p7_kernel, dim3(pcols), dim3(256), 0, s, a, b);
+  // estimates of Algs. 5, 6, 7 and the choice
+  for (int q = 1; q < 4; ++q) {
+    UpdArgs aq = a;
+    aq.P = b.Pc + q * tn;
+    best4_hutch(aq, s);
+    hipLaunchKernelGGL(best4_keep_kernel, dim3(1), dim3(64), 0, s, a, b, q);
+  }
+  hipLaunchKernelGGL(best4_choose_kernel, dim3(1), dim3(64), 0, s, a, b);
+  const int64_t nel = (int64_t)t * a.n_obs;
+  hipLaunchKernelGGL(best4_copy_kernel, dim3((unsigned)std::min<int64_t>(1024, (nel + 255) / 256)), dim3(256), 0,
+                     s, a, b);
+  return hipGetLastError();
+}
+
 size_t hutch_work_doubles(int ell, int t) {
   return (size_t)hutch_work_quarter(ell) * 5 + (size_t)ell * t * 2;
 }

@@ -37,6 +37,7 @@ class StreamConfig:
     hutch_n2: int = 0
     lookahead: int = 0
     tile: str = "auto"   # bf16 sketch work split: auto, narrow or wide
+    coeff: str = "alg4"  # "alg4" or "best4" (the best of Algs. 4-7 at every update)
 
     def to_c(self):
         c = L.rid_config()
@@ -48,6 +49,7 @@ class StreamConfig:
         c.delta, c.eps, c.c_sample, c.ridge_floor = self.delta, self.eps, self.c_sample, self.ridge_floor
         c.hutch_n1, c.hutch_n2, c.lookahead = self.hutch_n1, self.hutch_n2, self.lookahead
         c.sketch_tile = {"auto": L.RID_TILE_AUTO, "narrow": L.RID_TILE_NARROW, "wide": L.RID_TILE_WIDE}[self.tile]
+        c.coeff_mode = {"alg4": L.RID_COEFF_ALG4, "best4": L.RID_COEFF_BEST4}[self.coeff]
         return c
 
 
@@ -148,6 +150,13 @@ class OnlineRID:
         i = L.rid_info()
         self._check(L.lib().rid_get_info(self._h, C.byref(i)))
         return i
+
+    def coeff_choice(self, u):
+        """(E^2 of Algs. 4, 5, 6, 7, the kept algorithm) of update u (best4 mode)."""
+        e2 = np.zeros(4, dtype=np.float64)
+        q = C.c_int32()
+        self._check(L.lib().rid_get_coeff_choice(self._h, u, e2.ctypes.data_as(C.c_void_p), C.byref(q)))
+        return e2, q.value
 
     def update(self, u):
         rec = L.rid_update()

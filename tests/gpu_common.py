@@ -18,14 +18,15 @@ def log(*a):
 
 
 def run_gpu(A_cols, ell, k, t, sketch, omega_seed, select_seed, batch=None, borrow=True, lookahead=0,
-            finalize=True, n1=0, n2=0, tile="auto", n_max=None):
+            finalize=True, n1=0, n2=0, tile="auto", n_max=None, coeff="alg4"):
     """A_cols: numpy (n, m) (row j = snapshot j).  Returns the stream after
     pushing every snapshot (and finalizing)."""
     from paper_2405_16076_amd import OnlineRID, StreamConfig
     n, m = A_cols.shape
     dt = torch.float64 if A_cols.dtype == np.float64 else torch.float32
     cfg = StreamConfig(m=m, ell=ell, k=k, t=t, n_max=n_max or n, dtype=dt, sketch=sketch, omega_seed=omega_seed,
-                       select_seed=select_seed, lookahead=lookahead, hutch_n1=n1, hutch_n2=n2, tile=tile)
+                       select_seed=select_seed, lookahead=lookahead, hutch_n1=n1, hutch_n2=n2, tile=tile,
+                       coeff=coeff)
     s = OnlineRID(cfg)
     # padded device copy: every column starts on a 64-byte boundary
     ld = (m + 15) // 16 * 16
@@ -42,11 +43,12 @@ def run_gpu(A_cols, ell, k, t, sketch, omega_seed, select_seed, batch=None, borr
     return s
 
 
-def run_oracle(A_cols, ell, k, t, sketch, omega_seed, select_seed, finalize=True, n1=None, n2=None, workers=1):
+def run_oracle(A_cols, ell, k, t, sketch, omega_seed, select_seed, finalize=True, n1=None, n2=None, workers=1,
+               coeff="alg4"):
     n, m = A_cols.shape
     operand = {"f64": "f64", "f32": "f32", "bf16": "bf16", "fp8": "fp8"}[sketch]
     cfg = Config(m=m, ell=ell, k=k, t=t, omega_seed=omega_seed, select_seed=select_seed, operand=operand,
-                 hutch_n1=n1, hutch_n2=n2, workers=workers)
+                 hutch_n1=n1, hutch_n2=n2, workers=workers, coeff=coeff)
     o = OracleRID(cfg, n_max=n)
     o.push(A_cols.T)
     if finalize:
@@ -97,10 +99,11 @@ def compare_updates(s, o, tol, log_prefix=""):
 
 # Relative accuracy of the sketch S of each form against the oracle's S of the
 # same operands (the test matrices are equal bit for bit): binary64 sums in
-# another order (~sqrt(m) 2^-53); binary32 accumulation within a slab, for the
-# binary32 and bfloat16 forms (~1e-6); e4m3 operands: the scaled MFMA rounds
-# inside each 64-term product (a few 1e-5 of the sum of magnitudes, ~1e-4 of S).
-SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 1e-6, "fp8": 3e-4}
+# another order (~sqrt(m) 2^-53); binary32 accumulation within a slab (~1e-6;
+# the bfloat16 form's slabs of up to 64k rows are modelled at 5e-6); e4m3
+# operands: the scaled MFMA rounds inside each 64-term product (a few 1e-5 of
+# the sum of magnitudes, ~1e-4 of S).
+SKETCH_ACCURACY = {"f64": 1e-14, "f32": 1e-6, "bf16": 5e-6, "fp8": 3e-4}
 
 # Fixed bounds on the coefficients P and the reconstruction A_J P, declared
 # before any GPU value is seen: relative Frobenius norm of the difference from

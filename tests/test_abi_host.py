@@ -78,6 +78,7 @@ def test_status_strings_and_defaults(L):
     ("m", 0, "m must be"), ("ell", 3, "ell must"), ("ell", 513, "ell must"), ("k", 41, "k must"),
     ("t", 41, "t must"), ("n_max", 0, "n_max"), ("sketch_prec", 0, "f64 sketch"), ("delta", 1.5, "delta"),
     ("hutch_n1", 25, "n1"), ("sketch_tile", 3, "sketch_tile"), ("sketch_tile", 2, "wide sketch tile"),
+    ("coeff_mode", 2, "coeff_mode"),
 ])
 def test_invalid_configs_rejected_before_device(L, field, value, msg):
     expect = L.RID_ENOTSUP if msg == "wide sketch tile" else L.RID_EINVAL
@@ -93,6 +94,17 @@ def test_invalid_configs_rejected_before_device(L, field, value, msg):
     lib.rid_last_error(None, buf, 256)
     assert msg in buf.value.decode()
     assert not h.value
+
+
+def test_best4_needs_t_at_most_154(L):
+    lib = L.lib()
+    cfg = L.rid_config()
+    lib.rid_config_default(C.byref(cfg))
+    cfg.m, cfg.ell, cfg.k, cfg.t, cfg.n_max = 1000, 400, 200, 200, 1000
+    cfg.coeff_mode = L.RID_COEFF_BEST4
+    h = C.c_void_p()
+    assert lib.rid_init_stream(C.byref(cfg), None, C.byref(h)) == L.RID_ENOTSUP
+    assert lib.rid_get_coeff_choice(None, 0, None, None) == L.RID_EINVAL
 
 
 def test_null_handles_are_rejected(L):
