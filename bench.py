@@ -232,7 +232,7 @@ def channel_bench(args):
     }
 
     # lookahead variants of the same form
-    if not args.small:
+    if not args.small and not args.no_lookahead:
         rows = []
         for la in (300, 600):
             s2 = open_stream(m, n, ell, t, args.sketch, seeds, la)
@@ -498,6 +498,7 @@ def main():
     ap.add_argument("--push", type=int, default=100, help="snapshots per push call")
     ap.add_argument("--small", action="store_true", help="a small stream (quick check)")
     ap.add_argument("--no-compare", action="store_true", help="skip the other sketch forms")
+    ap.add_argument("--no-lookahead", action="store_true", help="skip the lookahead 300 and 600 passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched image streams")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank binary32 stream")

@@ -8,7 +8,7 @@ one dispatch, grid 2^26 work-items of four elements).  Under `rocprofv3 --pmc FE
 known byte count gives the scale factor applied to the counters of the
 streaming kernels.
 
-Usage: python -m paper_2405_16076_amd.traffic_calib [--gib 1] [--reps 3]
+Usage: python traffic_calib.py [--gib 1] [--reps 3]   (from the repository root)
 """
 import argparse
 import sys
