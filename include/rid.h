@@ -90,6 +90,19 @@ typedef enum rid_sketch_tile { RID_TILE_AUTO = 0, RID_TILE_NARROW = 1, RID_TILE_
  * G^{-1} A_J^T A_{J_prev} from exact Grams. */
 typedef enum rid_coeff_mode { RID_COEFF_ALG4 = 0, RID_COEFF_BEST4 = 1 } rid_coeff_mode;
 
+/* Arithmetic of the basis Gram G = A_J^T A_J (Alg. 8's ||A_J P||_F^2 term and
+ * the Grams of Algs. 5 and 7) for binary32 data.  EXACT: binary32 products are
+ * exact in binary64 and summed in binary64 (binary64 matrix cores).  SPLIT:
+ * each value is split exactly into three bfloat16 pieces, the six piece
+ * products of order <= 2 are summed on the bfloat16 matrix cores in binary32
+ * over 32 rows, then in binary64; elementwise
+ * |G_ij - A_i^T A_j| <= (37 * 2^-24 + (m / 32 + 1024) * 2^-53) sum_r |a_ri| |a_rj|
+ * for data of magnitude in [2^-100, 2^60] (or zero), so the NA-Hutch++
+ * estimate moves by at most that factor times || |A_J| |P| ||_F^2.  AUTO: SPLIT
+ * in RID_COEFF_ALG4 mode, EXACT in RID_COEFF_BEST4 mode (Algs. 5 and 7 solve
+ * with G).  binary64 data always uses binary64 products (AUTO or EXACT). */
+typedef enum rid_gram_mode { RID_GRAM_AUTO = 0, RID_GRAM_EXACT = 1, RID_GRAM_SPLIT = 2 } rid_gram_mode;
+
 /* Push flags. */
 #define RID_COPY   0u  /* copy the columns into the library's ring; the buffer
                           may be reused once prior work on the stream is done */
@@ -125,7 +138,7 @@ typedef struct rid_config {
   int64_t n_max;          /* capacity: maximum number of pushed columns */
   int32_t coeff_mode;     /* rid_coeff_mode (default RID_COEFF_ALG4); RID_COEFF_BEST4 needs
                              t <= 154 and a stream of its own (not a batch member) */
-  int32_t reserved1;      /* 0 */
+  int32_t gram_mode;      /* rid_gram_mode (default RID_GRAM_AUTO); SPLIT needs RID_F32 data */
 } rid_config;
 
 /* Error estimate of the last completed update (Alg. 8). */

@@ -17,6 +17,7 @@ RID_SKETCH_F64, RID_SKETCH_F32, RID_SKETCH_BF16, RID_SKETCH_FP8 = 0, 1, 2, 3
 RID_COPY, RID_BORROW = 0, 1
 RID_TILE_AUTO, RID_TILE_NARROW, RID_TILE_WIDE = 0, 1, 2
 RID_COEFF_ALG4, RID_COEFF_BEST4 = 0, 1
+RID_GRAM_AUTO, RID_GRAM_EXACT, RID_GRAM_SPLIT = 0, 1, 2
 RID_HOST, RID_DEVICE = 0, 1
 RID_UPD_SKIPPED, RID_UPD_RANK_DEFICIENT, RID_UPD_PINV_TRUNCATED = 1, 2, 4
 
@@ -28,7 +29,7 @@ class rid_config(C.Structure):
         ("omega_seed", C.c_uint64), ("select_seed", C.c_uint64),
         ("delta", C.c_double), ("eps", C.c_double), ("c_sample", C.c_double), ("ridge_floor", C.c_double),
         ("hutch_n1", C.c_int32), ("hutch_n2", C.c_int32), ("lookahead", C.c_int32), ("sketch_tile", C.c_int32),
-        ("n_max", C.c_int64), ("coeff_mode", C.c_int32), ("reserved1", C.c_int32),
+        ("n_max", C.c_int64), ("coeff_mode", C.c_int32), ("gram_mode", C.c_int32),
     ]
 
 

@@ -161,6 +161,7 @@ struct rid_stream {
   // the work space of Algs. 5-7 (B4Args); Xc has one t x t slot per update of
   // a flush, recq four records and qstar one choice per update
   bool best4 = false;
+  bool gram_split = false;  // binary32 Gram on the bfloat16 matrix cores
   double *b4_Pc = nullptr, *b4_Pprev = nullptr, *b4_M5 = nullptr, *b4_L = nullptr, *b4_T = nullptr;
   double *b4_rA = nullptr, *b4_D6 = nullptr, *b4_QR6 = nullptr, *b4_tau6 = nullptr, *b4_Qm6 = nullptr;
   double *b4_Mm6 = nullptr, *b4_Xc = nullptr;
@@ -364,6 +365,10 @@ static rid_status validate(const rid_config* c) {
     return fail(nullptr, RID_EINVAL, "unknown coeff_mode");
   if (c->coeff_mode == RID_COEFF_BEST4 && c->t > kAlg4Gemm)
     return fail(nullptr, RID_ENOTSUP, "RID_COEFF_BEST4 needs t <= 154");
+  if (c->gram_mode < RID_GRAM_AUTO || c->gram_mode > RID_GRAM_SPLIT)
+    return fail(nullptr, RID_EINVAL, "unknown gram_mode");
+  if (c->gram_mode == RID_GRAM_SPLIT && c->data_dtype != RID_F32)
+    return fail(nullptr, RID_EINVAL, "RID_GRAM_SPLIT needs RID_F32 data");
   return RID_OK;
 }
 
@@ -444,6 +449,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     }
   }
   h->best4 = cfg->coeff_mode == RID_COEFF_BEST4;
+  h->gram_split = !h->data_f64 && (cfg->gram_mode == RID_GRAM_SPLIT ||
+                                   (cfg->gram_mode == RID_GRAM_AUTO && !h->best4));
   if (h->best4) h->cgroup = 1;   // each update's choice feeds the next one's Algs. 6 and 7
   const size_t ell = h->ell, t = h->t, cg = h->cgroup;
   const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
@@ -695,6 +702,7 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
     a.m = h->m;
     a.ldc = h->ldc;
     a.data_f64 = h->data_f64;
+    a.gram_split = h->gram_split ? 1 : 0;
     a.S = h->S;
     a.SSTu = h->SSTk + (size_t)z * h->ell * h->ell;
     a.colsq = h->colsq;

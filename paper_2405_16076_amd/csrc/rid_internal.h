@@ -291,6 +291,7 @@ struct UpdArgs {
   uint64_t select_seed;
   int64_t m, ldc;      // rows and column-pool stride
   int data_f64;
+  int gram_split;      // binary32 data: Gram on the bfloat16 matrix cores (split form)
   // state
   const double* SSTu;  // SS^T of this update (l x l)
   double* S;           // l x n_max

@@ -1259,6 +1259,344 @@ __global__ void gram_reduce_kernel_b(Batched<UpdArgs> L) {
 }
 
 // ---------------------------------------------------------------------------
+// Gram entries of binary32 basis columns on the bfloat16 matrix cores (the
+// split form, the default for binary32 data).
+//
+// Every binary32 value a is split exactly into three bfloat16 pieces:
+// a0 = RN(a), a1 = RN(a - a0), a2 = a - a0 - a1.  Both residuals are exact in
+// binary32, and a2 has at most 8 significant bits, so a = a0 + a1 + a2 for
+// every a of magnitude in [2^-100, 2^60] (and zero).  The product a b is the
+// sum of the nine piece products, each exact in binary32 (8-bit significands);
+// the three of order >= 3 (a1 b2, a2 b1, a2 b2, together below
+// 2^-23 (1 + 2^-7) |a b|) are dropped.  v_mfma_f32_32x32x16_bf16 sums the six
+// others over 16 rows.  Per 32-row group the products of order 2, then 1,
+// then 0 enter a binary32 accumulator that starts at zero; the two groups of a
+// 64-row chunk are added in binary32 and the sum is added to a binary64 sum.
+// Counting every binary32 addition as rounded (the worst case of the
+// instruction's summation), with u = 2^-24, a group's order-2 and order-1
+// products (160 terms of total size below 2^-7 (1 + 2^-6) sum|a b|) add at
+// most 1.27 u sum|a b|, its order-0 products (32 additions on partial sums
+// below 1.02 sum|a b|) at most 32.7 u sum|a b|, and the addition of the two
+// groups at most 1.02 u sum|a b|; so per pair of columns
+//   |G_ij - A_i^T A_j| <= (37 u + (m / 64 + slabs) 2^-53) sum_r |a_ri| |a_rj|.
+//
+// A workgroup of 8 waves owns a row slab (the same slabs as the binary64
+// form) and a group of up to 16 of the 32 x 32 tiles (new columns x list
+// columns, the tiles wholly below the diagonal of the new-by-new part
+// skipped).  Waves 0-3 (one per SIMD) only multiply: each takes the same
+// number of tiles (round robin, the last ones repeating tile 0 with their
+// results dropped), so no SIMD waits on a larger share.  Waves 4-7 only stage:
+// per 64-row chunk each of their threads holds 16 bytes of up to sixteen
+// columns (16 lanes per column, so one column's 256 bytes are one coalesced
+// run), loaded two chunks ahead into registers; it splits them and writes the
+// three bfloat16 planes to LDS (double buffered when they fit), and copies
+// the new columns to the pool.  The two roles meet at one barrier per chunk,
+// so the splitting of chunk c + 1 runs on the vector ALUs while the matrix
+// cores multiply chunk c.  Plane layout: the 64 rows of one column in one
+// plane are 128 bytes, eight 16-byte slots of 8 rows, slot s stored at
+// s ^ col_swz(c), so the 16-byte operand reads of eight consecutive columns
+// hit eight distinct bank groups.  MFMA operand lane l reads rows
+// 16 s + 8 (l / 32) .. + 8 of column 32 x + l % 32 (the same rows for A and
+// B); D lane l holds column l % 32, rows (v % 4) + 4 (l / 32) + 8 (v / 4).
+// ---------------------------------------------------------------------------
+constexpr int kGsKC = 64;                      // rows per chunk
+constexpr int kGsWaves = 8;                    // 4 multiplying + 4 staging
+constexpr int kGsMfmaWaves = 4;
+constexpr int kGsMaxTPW = 4;                   // 32 x 32 tiles per multiplying wave
+constexpr int kGsGroup = kGsMfmaWaves * kGsMaxTPW;  // tiles per workgroup
+constexpr int kGsPlaneColBytes = kGsKC * 2;    // one column of one plane
+
+typedef __bf16 bf16x8_g __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_g __attribute__((ext_vector_type(2)));
+typedef float f32x2_g __attribute__((ext_vector_type(2)));
+typedef uint16_t u16x8_g __attribute__((ext_vector_type(8)));
+typedef float f32x16_g __attribute__((ext_vector_type(16)));
+
+// Staged columns: 160 (t <= 160, two plane buffers), 192 (two) or 256 (one).
+__host__ __device__ inline int gsplit_cols(int t) { return t <= 160 ? 160 : t <= 192 ? 192 : 256; }
+__host__ __device__ inline int gsplit_bufs(int t) { return t <= 192 ? 2 : 1; }
+__host__ __device__ inline int gsplit_skip(int r, int nq) { return min(r, nq / 32); }
+
+// Tiles of a list of nj columns whose first nq are new.
+__host__ __device__ inline int gsplit_tiles(int nq, int nj) {
+  const int TQ = (nq + 31) / 32, TJ = (nj + 31) / 32;
+  int n = 0;
+  for (int r = 0; r < TQ; ++r) n += TJ - gsplit_skip(r, nq);
+  return n;
+}
+
+size_t gram_split_lds(int t) { return (size_t)gsplit_bufs(t) * 3 * gsplit_cols(t) * kGsPlaneColBytes; }
+
+// Tile groups that cover every call with at most t list columns.
+int gram_split_groups(int t) {
+  int mx = 0;
+  for (int nq = 1; nq <= t; ++nq) mx = std::max(mx, gsplit_tiles(nq, t));
+  return (mx + kGsGroup - 1) / kGsGroup;
+}
+
+// Two binary32 values -> packed bfloat16 pair (RN) and the two residuals.
+__device__ __forceinline__ uint32_t gsplit_pair(float& x, float& y) {
+  const bf16x2_g h = __builtin_convertvector(f32x2_g{x, y}, bf16x2_g);
+  const uint32_t b = __builtin_bit_cast(uint32_t, h);
+  x -= __uint_as_float(b << 16);         // exact
+  y -= __uint_as_float(b & 0xFFFF0000u);  // exact
+  return b;
+}
+
+// The multiplying role: TPW tiles per wave, one barrier per chunk (two when
+// the planes are single buffered: the staging waves write between them).
+template <int NBUF, int NCOL, int TPW>
+__device__ __forceinline__ void gram_split_mfma(const UpdArgs& a, const int slab, const int g0, const int NT,
+                                                const int nq, const int nj, const int nch, char* const lds) {
+  constexpr int plane_bytes = NCOL * kGsPlaneColBytes;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l32 = lane & 31, hf = lane >> 5;
+  const int TJ = (nj + 31) / 32;
+  int tq[TPW], tj[TPW];
+  bool real[TPW];
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti) {
+    const int tile = g0 + wave + kGsMfmaWaves * ti;
+    real[ti] = tile < NT;
+    int r = 0, rem = real[ti] ? tile : 0;
+    while (rem >= TJ - gsplit_skip(r, nq)) {
+      rem -= TJ - gsplit_skip(r, nq);
+      ++r;
+    }
+    tq[ti] = r;
+    tj[ti] = gsplit_skip(r, nq) + rem;
+  }
+  // LDS byte offsets of this lane's operand columns, slot key applied per step
+  int offa[TPW], offb[TPW], keya[TPW], keyb[TPW];
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti) {
+    const int ca = 32 * tq[ti] + l32, cb = 32 * tj[ti] + l32;
+    offa[ti] = ca * kGsPlaneColBytes;
+    offb[ti] = cb * kGsPlaneColBytes;
+    keya[ti] = col_swz(ca);
+    keyb[ti] = col_swz(cb);
+  }
+  double gacc[TPW][16];
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) gacc[ti][v] = 0.0;
+
+  // the staging waves' barriers: one after chunk 0 is in buffer 0, then one
+  // per chunk (two when single buffered); this role passes the same number
+  lds_barrier();
+  for (int c = 0; c < nch; ++c) {
+    const char* base = lds + (NBUF == 2 ? (c & 1) : 0) * 3 * plane_bytes;
+#pragma unroll
+    for (int ti = 0; ti < TPW; ++ti) {
+      f32x16_g acc[2];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        bf16x8_g fa[2][3], fb[2][3];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int slot = 2 * (2 * g + s) + hf;
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            fa[s][p] = __builtin_bit_cast(bf16x8_g, *reinterpret_cast<const u16x8_g*>(
+                                                       base + p * plane_bytes + offa[ti] + ((slot ^ keya[ti]) << 4)));
+            fb[s][p] = __builtin_bit_cast(bf16x8_g, *reinterpret_cast<const u16x8_g*>(
+                                                       base + p * plane_bytes + offb[ti] + ((slot ^ keyb[ti]) << 4)));
+          }
+        }
+        f32x16_g x = {};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          x = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s][0], fb[s][2], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s][1], fb[s][1], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s][2], fb[s][0], x, 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          x = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s][0], fb[s][1], x, 0, 0, 0);
+          x = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s][1], fb[s][0], x, 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) x = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s][0], fb[s][0], x, 0, 0, 0);
+        acc[g] = x;
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) gacc[ti][v] += (double)(acc[0][v] + acc[1][v]);
+    }
+    if (NBUF == 1) lds_barrier();
+    lds_barrier();
+  }
+
+  double* out = a.gpart + (int64_t)slab * a.t * a.t;
+#pragma unroll
+  for (int ti = 0; ti < TPW; ++ti) {
+    const int j = 32 * tj[ti] + l32;
+    if (!real[ti] || j >= nj) continue;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int q = 32 * tq[ti] + (v & 3) + 4 * hf + 8 * (v >> 2);
+      if (q < nq) out[(int64_t)q * a.t + j] = gacc[ti][v];
+    }
+  }
+}
+
+// The staging role: NCOL / 16 loads per thread per chunk, two chunks ahead
+// (one for 256 columns, whose two register sets would not fit).
+template <int NBUF, int NCOL>
+__device__ __forceinline__ void gram_split_stage(const UpdArgs& a, const int64_t r0, const int64_t r1, const int nq,
+                                                 const int nj, const int nch, const bool copy_pool, char* const lds) {
+  constexpr int NLD = NCOL / 16;
+  constexpr int plane_bytes = NCOL * kGsPlaneColBytes;
+  const DevScalars* sc = a.sc;
+  const int st = threadIdx.x - 64 * kGsMfmaWaves;  // 0 .. 255
+  const int part = st & 15;
+  // this thread's columns st / 16 + 16 i.  Staged columns past the list read
+  // the pool's first column (valid rows, values ignored: a column of the
+  // planes only enters the products of its own tile row or column, which
+  // are dropped), so that every load is unconditional.
+  const float* cpool = reinterpret_cast<const float*>(a.cpool);
+  float* pool = reinterpret_cast<float*>(a.cpool);
+  const float* src[NLD];
+  int dsl[NLD], off[NLD];
+#pragma unroll
+  for (int i = 0; i < NLD; ++i) {
+    const int c = (st >> 4) + 16 * i;
+    src[i] = cpool;
+    dsl[i] = -1;
+    if (c < nj) {
+      const int slot = gram_slot(sc, c);
+      const int s = sc->slot_src[slot];  // >= 0 exactly for the new slots
+      src[i] = (s >= 0) ? reinterpret_cast<const float*>(a.colptr[a.c0 + s]) : cpool + (int64_t)slot * a.ldc;
+      if (c < nq) dsl[i] = sc->new_slot[c];
+    }
+    off[i] = c * kGsPlaneColBytes + (((part >> 1) ^ col_swz(c)) << 4) + ((part & 1) << 3);
+  }
+  float4 rawA[NLD], rawB[NLD];
+  auto load = [&](int c, float4 (&raw)[NLD]) {
+    int64_t row = r0 + (int64_t)c * kGsKC + 4 * part;
+    if (row >= r1) row = r0;  // past the slab end: a valid row, zeroed at the split
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) raw[i] = gload_f4(gload_ptr(src[i] + row));
+  };
+  // zero the rows past the slab end, copy new columns to the pool, split
+  // into the planes of buffer buf
+  auto store = [&](int c, int buf, const float4 (&raw)[NLD]) {
+    const int64_t row = r0 + (int64_t)c * kGsKC + 4 * part;
+    const bool full = r0 + (int64_t)(c + 1) * kGsKC <= r1;  // the same for the workgroup
+    char* bp = lds + buf * 3 * plane_bytes;
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      float x[4] = {raw[i].x, raw[i].y, raw[i].z, raw[i].w};
+      if (full) {
+        if (copy_pool && dsl[i] >= 0)
+          gstore_f4(gstore_ptr(pool + (int64_t)dsl[i] * a.ldc + row), make_float4(x[0], x[1], x[2], x[3]));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (row + e >= r1) x[e] = 0.0f;
+        if (copy_pool && dsl[i] >= 0)
+          for (int e = 0; e < 4; ++e)
+            if (row + e < r1) gstore_ptr(pool + (int64_t)dsl[i] * a.ldc + row)[e] = x[e];
+      }
+      uint2 p0, p1, p2;
+      p0.x = gsplit_pair(x[0], x[1]);
+      p0.y = gsplit_pair(x[2], x[3]);
+      p1.x = gsplit_pair(x[0], x[1]);
+      p1.y = gsplit_pair(x[2], x[3]);
+      p2.x = gsplit_pair(x[0], x[1]);
+      p2.y = gsplit_pair(x[2], x[3]);
+      *reinterpret_cast<uint2*>(bp + off[i]) = p0;
+      *reinterpret_cast<uint2*>(bp + plane_bytes + off[i]) = p1;
+      *reinterpret_cast<uint2*>(bp + 2 * plane_bytes + off[i]) = p2;
+    }
+  };
+  // lds_barrier, not __syncthreads: the barrier must not wait for the loads
+  // of the next chunks, which stay in flight.  Step c (while the multiplying
+  // waves take chunk c): split chunk c + 1, whose register set then takes
+  // chunk c + 1 + DEPTH.  Every step issues its loads (past the last chunk
+  // they read the last chunk again, unused), so that the compiler's wait
+  // before a register set's first use counts the other set's loads as issued
+  // after it and leaves them in flight.
+  constexpr int DEPTH = NCOL <= 192 ? 2 : 1;
+  auto step = [&](int c, float4 (&raw)[NLD]) {
+    if (NBUF == 1) lds_barrier();
+    if (c + 1 < nch) store(c + 1, NBUF == 2 ? ((c + 1) & 1) : 0, raw);
+    load(min(c + 1 + DEPTH, nch - 1), raw);
+    lds_barrier();
+  };
+  if (DEPTH == 2) {
+    load(0, rawB);
+    store(0, 0, rawB);
+    load(min(1, nch - 1), rawA);
+    load(min(2, nch - 1), rawB);
+    lds_barrier();
+    int c = 0;
+    for (; c + 1 < nch; c += 2) {
+      step(c, rawA);
+      step(c + 1, rawB);
+    }
+    if (c < nch) step(c, rawA);
+  } else {
+    load(0, rawA);
+    store(0, 0, rawA);
+    load(min(1, nch - 1), rawA);
+    lds_barrier();
+    for (int c = 0; c < nch; ++c) step(c, rawA);
+  }
+}
+
+template <int NBUF, int NCOL>
+__device__ __forceinline__ void gram_split_tiles(const UpdArgs& a, const Blk bk) {
+  extern __shared__ __attribute__((aligned(1024))) float gsm[];
+  const int nq = a.sc->n_new, nj = a.sc->n_occ;
+  if (nq == 0) return;
+  const int NT = gsplit_tiles(nq, nj);
+  const int g0 = bk.y * kGsGroup;
+  if (g0 >= NT) return;
+  const int slab = bk.x;
+  const int64_t r0 = (int64_t)slab * a.gslab_rows;
+  const int64_t r1 = min(a.m, r0 + a.gslab_rows);
+  const int nch = (int)((r1 - r0 + kGsKC - 1) / kGsKC);
+  char* const lds = reinterpret_cast<char*>(gsm);
+  if (threadIdx.x < 64 * kGsMfmaWaves) {
+    const int tpw = (min(kGsGroup, NT - g0) + kGsMfmaWaves - 1) / kGsMfmaWaves;
+    switch (tpw) {
+      case 1: gram_split_mfma<NBUF, NCOL, 1>(a, slab, g0, NT, nq, nj, nch, lds); break;
+      case 2: gram_split_mfma<NBUF, NCOL, 2>(a, slab, g0, NT, nq, nj, nch, lds); break;
+      case 3: gram_split_mfma<NBUF, NCOL, 3>(a, slab, g0, NT, nq, nj, nch, lds); break;
+      default: gram_split_mfma<NBUF, NCOL, 4>(a, slab, g0, NT, nq, nj, nch, lds); break;
+    }
+  } else {
+    gram_split_stage<NBUF, NCOL>(a, r0, r1, nq, nj, nch, bk.y == 0, lds);
+  }
+}
+
+// One kernel per staging shape (t <= 160, t <= 192, larger), so that each
+// gets its own register allocation.
+template <int NBUF, int NCOL>
+__global__ __launch_bounds__(64 * kGsWaves, 1) void gram_split_kernel(UpdArgs a) {
+  gram_split_tiles<NBUF, NCOL>(a, own_block());
+}
+
+template <int NBUF, int NCOL>
+__global__ __launch_bounds__(64 * kGsWaves, 1) void gram_split_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) gram_split_tiles<NBUF, NCOL>(*p, bk);
+}
+
+static const void* gram_split_fn(int t, bool batched) {
+  if (t <= 160)
+    return batched ? reinterpret_cast<const void*>(gram_split_kernel_b<2, 160>)
+                   : reinterpret_cast<const void*>(gram_split_kernel<2, 160>);
+  if (t <= 192)
+    return batched ? reinterpret_cast<const void*>(gram_split_kernel_b<2, 192>)
+                   : reinterpret_cast<const void*>(gram_split_kernel<2, 192>);
+  return batched ? reinterpret_cast<const void*>(gram_split_kernel_b<1, 256>)
+                 : reinterpret_cast<const void*>(gram_split_kernel<1, 256>);
+}
+
+// ---------------------------------------------------------------------------
 // Alg. 4: Householder QR of Omega A_J (occupied slots in slot order), then
 // P = R^{-1} Q^T S column by column.  Columns whose pivot |R_ii| falls to
 // max(l, n) eps max|R| are dropped from the solve (flag RID_UPD_RANK_DEFICIENT).
@@ -2449,6 +2787,12 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
   if (a.data_f64) {
     const int tt = (a.t + kGramTile - 1) / kGramTile;
     hipLaunchKernelGGL(gram_kernel<double>, dim3(a.gslabs, tt, tt), dim3(1024), 0, s, a);
+  } else if (a.gram_split) {
+    const size_t lds = gram_split_lds(a.t);
+    const void* f = gram_split_fn(a.t, false);
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    void* args[] = {const_cast<UpdArgs*>(&a)};
+    (void)hipLaunchKernel(f, dim3(a.gslabs, gram_split_groups(a.t)), dim3(64 * kGsWaves), args, lds, s);
   } else {
     const int tq = (a.t + 31) / 32;
     const int groups = (tq * tq + kGramGroup - 1) / kGramGroup;
@@ -2646,13 +2990,15 @@ void plan_update_select_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaun
 }
 
 void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
-  Planner<UpdArgs> P64, P32;
-  P64.kind = P32.kind = 3;
+  Planner<UpdArgs> P64, P32, PS;
+  P64.kind = P32.kind = PS.kind = 3;
   for (int i = 0; i < ns; ++i) {
     const UpdArgs& a = h[i];
     if (a.data_f64) {
       const int tt = (a.t + kGramTile - 1) / kGramTile;
       P64.add(fn(gram_kernel_b<double>), a, make_int4(a.gslabs, tt, tt, 0));
+    } else if (a.gram_split) {
+      PS.add(gram_split_fn(a.t, true), a, make_int4(a.gslabs, gram_split_groups(a.t), 1, 0), gram_split_lds(a.t));
     } else {
       const int tq = (a.t + 31) / 32;
       const int groups = (tq * tq + kGramGroup - 1) / kGramGroup;
@@ -2669,6 +3015,9 @@ void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch
       attr_lds = g.lds;
     }
   P32.emit(dim3(64 * kGramWaves), -1, st, out);
+  for (auto& g : PS.groups)
+    (void)hipFuncSetAttribute(g.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds);
+  PS.emit(dim3(64 * kGsWaves), -1, st, out);
   Planner<UpdArgs> P;
   for (int i = 0; i < ns; ++i) P.add(fn(gram_zero_kernel_b), h[i], make_int4(h[i].t, 1, 1, 0));
   P.emit(dim3(kMaxT), -1, st, out);

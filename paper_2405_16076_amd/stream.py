@@ -38,6 +38,7 @@ class StreamConfig:
     lookahead: int = 0
     tile: str = "auto"   # bf16 sketch work split: auto, narrow or wide
     coeff: str = "alg4"  # "alg4" or "best4" (the best of Algs. 4-7 at every update)
+    gram: str = "auto"   # basis Gram of binary32 data: "auto", "exact" (binary64 products) or "split"
 
     def to_c(self):
         c = L.rid_config()
@@ -50,6 +51,7 @@ class StreamConfig:
         c.hutch_n1, c.hutch_n2, c.lookahead = self.hutch_n1, self.hutch_n2, self.lookahead
         c.sketch_tile = {"auto": L.RID_TILE_AUTO, "narrow": L.RID_TILE_NARROW, "wide": L.RID_TILE_WIDE}[self.tile]
         c.coeff_mode = {"alg4": L.RID_COEFF_ALG4, "best4": L.RID_COEFF_BEST4}[self.coeff]
+        c.gram_mode = {"auto": L.RID_GRAM_AUTO, "exact": L.RID_GRAM_EXACT, "split": L.RID_GRAM_SPLIT}[self.gram]
         return c
 
 

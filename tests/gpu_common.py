@@ -18,7 +18,7 @@ def log(*a):
 
 
 def run_gpu(A_cols, ell, k, t, sketch, omega_seed, select_seed, batch=None, borrow=True, lookahead=0,
-            finalize=True, n1=0, n2=0, tile="auto", n_max=None, coeff="alg4"):
+            finalize=True, n1=0, n2=0, tile="auto", n_max=None, coeff="alg4", gram="auto"):
     """A_cols: numpy (n, m) (row j = snapshot j).  Returns the stream after
     pushing every snapshot (and finalizing)."""
     from paper_2405_16076_amd import OnlineRID, StreamConfig
@@ -26,7 +26,7 @@ def run_gpu(A_cols, ell, k, t, sketch, omega_seed, select_seed, batch=None, borr
     dt = torch.float64 if A_cols.dtype == np.float64 else torch.float32
     cfg = StreamConfig(m=m, ell=ell, k=k, t=t, n_max=n_max or n, dtype=dt, sketch=sketch, omega_seed=omega_seed,
                        select_seed=select_seed, lookahead=lookahead, hutch_n1=n1, hutch_n2=n2, tile=tile,
-                       coeff=coeff)
+                       coeff=coeff, gram=gram)
     s = OnlineRID(cfg)
     # padded device copy: every column starts on a 64-byte boundary
     ld = (m + 15) // 16 * 16
@@ -163,6 +163,40 @@ def check_fixed_bounds(sketch, S, So, P, Po, R, Ro, cond_SJ, tol=None, prefix=" 
 GRAM_ACCURACY = {"f64": 1e-15, "f32": 1e-15, "bf16": 1e-15, "fp8": 1e-15}
 
 
+def gram_split_eps(m):
+    """The library's elementwise bound of the split-form Gram, relative to
+    sum_r |a_ri| |a_rj| (three-piece bfloat16 split, order <= 2 products,
+    binary32 sums over 32 rows counted as rounded at every addition, then
+    binary64 over at most m / 32 + 1024 additions)."""
+    return 37 * 2.0 ** -24 + (m / 32 + 1024) * 2.0 ** -53
+
+
+def uses_gram_split(sketch, coeff="alg4", gram="auto"):
+    """Whether a stream of this form and modes forms G in the split form."""
+    return sketch != "f64" and (gram == "split" or (gram == "auto" and coeff == "alg4"))
+
+
+def split_gram_bounds(S, SJ, P, G, n1, n2, m, occ):
+    """Bounds on how far the split form's G moves the two NA-Hutch++ terms
+    that use it (Alg. 8): term1 = tr(K^+ Y1 G Y2^T) = sum_ij G_ij B_ji with
+    B = Y2^T K^+ Y1, and gpp = sum_ij G_ij (P P^T)_ij.  With
+    |dG_ij| <= eps sqrt(G_ii G_jj) (Cauchy-Schwarz on sum_r |a_ri||a_rj|),
+    |d term| <= eps sum_ij sqrt(G_ii G_jj) |C_ij|.  Returns (term1, gpp)."""
+    if not occ.size:
+        return 0.0, 0.0
+    eps = gram_split_eps(m)
+    dg = np.sqrt(np.abs(np.diag(G)))[occ]
+    Pk = P[occ]
+    b_gpp = eps * float(dg @ np.abs(Pk @ Pk.T) @ dg)
+    b_t1 = 0.0
+    if n1 and n2:
+        W = SJ @ P
+        K = S[:n1] @ W[n1:n1 + n2].T
+        B = (S[n1:n1 + n2] @ Pk.T).T @ np.linalg.pinv(K) @ (S[:n1] @ Pk.T)
+        b_t1 = eps * float(dg @ np.abs(B.T) @ dg)
+    return b_t1, b_gpp
+
+
 def hutch_regrouped(S, SJ, P, G, F, n1, n2):
     """The NA-Hutch++ terms of the oracle's formula with the same products
     grouped another way (through Y = S P^T and P P^T).  Mathematically equal;
@@ -197,7 +231,7 @@ def exact_gram(A_cols, idx, chunk=1 << 20):
     return G
 
 
-def perturbation_tolerances(o, A_cols, sketch, draws=3, factor=10.0, seed=0, recon=True):
+def perturbation_tolerances(o, A_cols, sketch, draws=3, factor=10.0, seed=0, recon=True, gram="auto"):
     """Forward-error tolerances derived from the conditioning of each step.
 
     The oracle's own S is perturbed column by column at the sketch accuracy of
@@ -205,12 +239,15 @@ def perturbation_tolerances(o, A_cols, sketch, draws=3, factor=10.0, seed=0, rec
     recomputed with the oracle's functions; for the NA-Hutch++ terms the spread
     between two groupings of the same products is included as well.  The
     tolerance is `factor` times the largest change seen (plus a floor at the
-    binary64 rounding level).  No GPU value enters."""
+    binary64 rounding level).  Where the stream forms G in the split form, the
+    tr_est, gpp and E2 tolerances also take that form's bounds on the two
+    terms that use G (split_gram_bounds).  No GPU value enters."""
     from oracle.rid import coeff_alg4, nahutchpp, ridge_lambda, ridge_scores
     rng = np.random.default_rng(seed)
     cfg = o.cfg
     u_S = SKETCH_ACCURACY[sketch]
-    tol = {"tau": [], "tr_est": [], "gpp": [], "E2": []}
+    tol = {"tau": [], "tr_est": [], "gpp": [], "E2": [], "b_term1": []}
+    split = uses_gram_split(sketch, getattr(cfg, "coeff", "alg4"), gram)
     S_full = o.S[:, :o.n_obs]
     norms = np.linalg.norm(S_full, axis=0) / np.sqrt(cfg.ell)
     perturbed = [S_full + u_S * norms * rng.standard_normal(S_full.shape) for _ in range(draws)]
@@ -249,10 +286,14 @@ def perturbation_tolerances(o, A_cols, sketch, draws=3, factor=10.0, seed=0, rec
             dgpp = max(dgpp, abs(hp["gpp"] - h0["gpp"]))
             dE2 = max(dE2, abs(hp["E2"] - h0["E2"]))
         floor = 1e-11 * max(rec.F, 1e-300)
+        b_t1 = b_gpp = 0.0
+        if split:
+            b_t1, b_gpp = split_gram_bounds(S, SJ0, P0, G, cfg.n1, cfg.n2, A_cols.shape[1], occ)
+        tol["b_term1"].append(b_t1)
         tol["tau"].append(factor * dtau + 1e-12)
-        tol["tr_est"].append(factor * dtr + floor)
-        tol["gpp"].append(factor * dgpp + floor)
-        tol["E2"].append(factor * dE2 + 2 * floor)
+        tol["tr_est"].append(factor * dtr + floor + b_t1)
+        tol["gpp"].append(factor * dgpp + floor + b_gpp)
+        tol["E2"].append(factor * dE2 + 2 * floor + 2 * b_t1 + b_gpp)
     # final coefficients and reconstruction
     Pn = o.P
     dP = dR = 0.0

@@ -78,7 +78,7 @@ def test_status_strings_and_defaults(L):
     ("m", 0, "m must be"), ("ell", 3, "ell must"), ("ell", 513, "ell must"), ("k", 41, "k must"),
     ("t", 41, "t must"), ("n_max", 0, "n_max"), ("sketch_prec", 0, "f64 sketch"), ("delta", 1.5, "delta"),
     ("hutch_n1", 25, "n1"), ("sketch_tile", 3, "sketch_tile"), ("sketch_tile", 2, "wide sketch tile"),
-    ("coeff_mode", 2, "coeff_mode"),
+    ("coeff_mode", 2, "coeff_mode"), ("gram_mode", 3, "gram_mode"), ("gram_mode", -1, "gram_mode"),
 ])
 def test_invalid_configs_rejected_before_device(L, field, value, msg):
     expect = L.RID_ENOTSUP if msg == "wide sketch tile" else L.RID_EINVAL
@@ -105,6 +105,20 @@ def test_best4_needs_t_at_most_154(L):
     h = C.c_void_p()
     assert lib.rid_init_stream(C.byref(cfg), None, C.byref(h)) == L.RID_ENOTSUP
     assert lib.rid_get_coeff_choice(None, 0, None, None) == L.RID_EINVAL
+
+
+def test_split_gram_needs_binary32_data(L):
+    lib = L.lib()
+    cfg = L.rid_config()
+    lib.rid_config_default(C.byref(cfg))
+    assert cfg.gram_mode == L.RID_GRAM_AUTO
+    cfg.m, cfg.ell, cfg.k, cfg.t, cfg.n_max = 1000, 40, 20, 20, 100
+    cfg.data_dtype, cfg.sketch_prec, cfg.gram_mode = L.RID_F64, L.RID_SKETCH_F64, L.RID_GRAM_SPLIT
+    h = C.c_void_p()
+    assert lib.rid_init_stream(C.byref(cfg), None, C.byref(h)) == L.RID_EINVAL
+    buf = C.create_string_buffer(256)
+    lib.rid_last_error(None, buf, 256)
+    assert b"RID_GRAM_SPLIT" in buf.value
 
 
 def test_null_handles_are_rejected(L):

@@ -29,7 +29,8 @@ import torch
 
 import oracle
 import synth
-from gpu_common import check_fixed_bounds, compare_updates, log, perturbation_tolerances, rel_fro, run_gpu, run_oracle
+from gpu_common import (check_fixed_bounds, compare_updates, gram_split_eps, log, perturbation_tolerances, rel_fro,
+                        run_gpu, run_oracle, split_gram_bounds, uses_gram_split)
 
 pytestmark = pytest.mark.gpu
 
@@ -170,7 +171,12 @@ def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True, n_max
     Sg, _, G = s.debug_state()
     eg = rel_fro(G, o.G)
     log(f"  Gram rel fro {eg:.2e}")
-    assert eg <= 1e-12
+    if uses_gram_split(sketch):
+        # the split form's bound, through sum_r |a_ri||a_rj| <= sqrt(G_ii G_jj)
+        dgo = np.sqrt(np.abs(np.diag(o.G)))
+        assert np.all(np.abs(G - o.G) <= gram_split_eps(A.shape[1]) * np.outer(dgo, dgo))
+    else:
+        assert eg <= 1e-12
     # S, P and the reconstruction of a column range against fixed bounds
     n = A.shape[0]
     c0, c = max(0, n // 2 - 5), min(17, n)
@@ -310,69 +316,100 @@ def test_back_to_back_passes_without_host_sync():
     assert np.array_equal(s.coefficients(), PB)
 
 
-@pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_gram_and_estimate_terms_after_first_update(dtype):
-    # G = A_J^T A_J is formed from exact products in binary64; each NA-Hutch++
-    # term is checked against the oracle separately (well-conditioned data)
+def _gram_check(G, A_cols, J, gram, m, label=""):
+    """G against A_J^T A_J from the host bytes: binary64 products within 1e-13
+    of sqrt(G_ii G_jj); the split form within its stated bound
+    eps(m) sum_r |a_ri| |a_rj| elementwise.  Returns the worst ratio to the bound."""
+    t = J.size
+    occ = np.flatnonzero(J >= 0)
+    X = A_cols[J[occ]].astype(np.float64)
+    Gx = np.zeros((t, t))
+    Gx[np.ix_(occ, occ)] = X @ X.T
+    if gram == "split":
+        Ga = np.zeros((t, t))
+        Ga[np.ix_(occ, occ)] = np.abs(X) @ np.abs(X).T
+        bound = gram_split_eps(m) * Ga
+    else:
+        bound = 1e-13 * np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)))
+    err = np.abs(G - Gx)
+    ratio = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0), np.where(err > 0, np.inf, 0.0))
+    scaled = err / np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)) + 1e-300)
+    log(f"  {label}Gram ({gram}) max scaled err {scaled.max():.2e}, worst err/bound {ratio.max():.2e}")
+    assert ratio.max() <= 1.0, (gram, float(ratio.max()))
+    return float(ratio.max())
+
+
+@pytest.mark.parametrize("dtype,gram", [(np.float64, "auto"), (np.float32, "exact"), (np.float32, "split")])
+def test_gram_and_estimate_terms_after_first_update(dtype, gram):
+    # G = A_J^T A_J: binary64 products (exact for binary32 data), or the split
+    # form within its bound; each NA-Hutch++ term is checked against the oracle
+    # separately (well-conditioned data); gpp also takes the split form's bound
     rng = np.random.default_rng(21)
     m, t, ell = 4099, 40, 80
     A = (rng.standard_normal((t, 12)) @ rng.standard_normal((12, m)) + 0.1 * rng.standard_normal((t, m))).astype(dtype)
     sk = "f64" if dtype == np.float64 else "f32"
-    s = run_gpu(A, ell, t, t, sk, 31, 32)
+    s = run_gpu(A, ell, t, t, sk, 31, 32, gram=gram)
     o = run_oracle(A, ell, t, t, sk, 31, 32)
     _, _, G = s.debug_state()
     J = s.select()
     occ = np.flatnonzero(J >= 0)
-    A64 = A.T.astype(np.float64)
-    Gx = np.zeros((t, t))
-    Gx[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
-    err = np.abs(G - Gx) / np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)) + 1e-300)
-    log(f"  Gram max scaled err {err.max():.2e} at {np.unravel_index(np.argmax(err), err.shape)}")
+    _gram_check(G, A, J, "split" if gram == "split" else "exact", m)
     g = s.update(0)
     h = o.records[0].hutch
     log("  terms gpu " + " ".join(f"{k}={g[k]:.6e}" for k in ("term1", "h", "corr", "gpp", "E2")))
     log("  terms orc " + " ".join(f"{k}={h[k]:.6e}" for k in ("term1", "h", "corr", "gpp", "E2")))
-    assert err.max() <= 1e-13
+    extra = {}
+    if gram == "split":  # n = t: one update, o.P is its P
+        SJ = np.zeros((ell, t))
+        SJ[:, occ] = o.S[:, J[occ]]
+        extra["term1"], extra["gpp"] = split_gram_bounds(o.S[:, :A.shape[0]], SJ, o.P, G, o.cfg.n1, o.cfg.n2, m, occ)
     for k in ("term1", "h", "corr", "gpp"):
-        assert abs(g[k] - h[k]) <= 1e-7 * max(abs(h[k]), o.F), k
+        assert abs(g[k] - h[k]) <= 1e-7 * max(abs(h[k]), o.F) + extra.get(k, 0.0), k
 
 
-@pytest.mark.parametrize("dtype,m,t,growth", [(np.float32, 20_011, 150, 1.02), (np.float32, 9_001, 100, 1.0),
-                                              (np.float64, 8_011, 100, 1.0)])
-def test_gram_after_every_update(dtype, m, t, growth):
-    # after each update G must equal A_J^T A_J of that update's J; partial
-    # refills of varied size exercise the new-by-new blocks taken from their
-    # mirrors and the blocks past the ends of the lists
+@pytest.mark.parametrize("dtype,m,t,growth,gram", [(np.float32, 20_011, 150, 1.02, "split"),
+                                                   (np.float32, 20_011, 150, 1.02, "exact"),
+                                                   (np.float32, 9_001, 100, 1.0, "split"),
+                                                   (np.float32, 9_001, 100, 1.0, "exact"),
+                                                   (np.float32, 12_007, 200, 1.0, "split"),
+                                                   (np.float32, 10_007, 60, "dyn", "split"),
+                                                   (np.float64, 8_011, 100, 1.0, "auto")])
+def test_gram_after_every_update(dtype, m, t, growth, gram):
+    # after each update G must equal A_J^T A_J of that update's J (binary64
+    # products: to 1e-13; split form: within its stated bound); partial refills
+    # of varied size exercise the new-by-new blocks taken from their mirrors
+    # and the blocks past the ends of the lists; t = 200 (224 staged columns)
+    # takes the single-buffered split planes; "dyn" draws magnitudes over 2^-40 .. 2^40
+    # inside every column (the split is exact at any exponent)
     from paper_2405_16076_amd import OnlineRID, StreamConfig
     rng = np.random.default_rng(29)
     n, ell = 5 * t, 2 * t
-    A = (rng.standard_normal((n, m)) * (growth ** np.arange(n))[:, None]).astype(dtype)
+    if growth == "dyn":
+        A = (rng.standard_normal((n, m)) * 2.0 ** rng.uniform(-40, 40, (n, m))).astype(dtype)
+    else:
+        A = (rng.standard_normal((n, m)) * (growth ** np.arange(n))[:, None]).astype(dtype)
     dt = torch.float64 if dtype == np.float64 else torch.float32
     sk = "f64" if dtype == np.float64 else "f32"
-    cfg = StreamConfig(m=m, ell=ell, k=t, t=t, n_max=n, dtype=dt, sketch=sk, omega_seed=51, select_seed=52)
+    cfg = StreamConfig(m=m, ell=ell, k=t, t=t, n_max=n, dtype=dt, sketch=sk, omega_seed=51, select_seed=52,
+                       gram=gram)
     s = OnlineRID(cfg)
     ld = (m + 15) // 16 * 16  # borrowed columns start on 64-byte boundaries
     Xp = torch.zeros((n, ld), dtype=dt, device="cuda:0")
     Xp[:, :m] = torch.from_numpy(A).to("cuda:0")
     X = Xp[:, :m]
-    A64 = A.T.astype(np.float64)
     fills = []
     for u, j0 in enumerate(range(0, n, t)):
         s.push(X[j0:j0 + t], borrow=True)
         J = s.select()
         fills.append(s.update(u)["n_filled"])
         _, _, G = s.debug_state()
-        occ = np.flatnonzero(J >= 0)
-        Gx = np.zeros((t, t))
-        Gx[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
-        err = np.abs(G - Gx) / np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)) + 1e-300)
-        assert err.max() <= 1e-13, (u, fills, float(err.max()))
+        _gram_check(G, A, J, "split" if gram == "split" else "exact", m, label=f"update {u}: ")
     log(f"  filled per update {fills}")
     assert any(0 < f < t for f in fills[1:]), fills
 
 
-@pytest.mark.parametrize("growth", [1.0, 1.03])
-def test_gram_incremental_matches_exact_products(growth):
+@pytest.mark.parametrize("growth,gram", [(1.0, "split"), (1.03, "split"), (1.03, "exact")])
+def test_gram_incremental_matches_exact_products(growth, gram):
     # G is built incrementally over several updates (all-new first update, then
     # new x occupied blocks, possibly two tile groups when many slots refill);
     # after the last update it must equal A_J^T A_J of the final J.  Columns
@@ -380,16 +417,9 @@ def test_gram_incremental_matches_exact_products(growth):
     rng = np.random.default_rng(23)
     m, n, ell, t = 20_011, 600, 300, 150
     A = (rng.standard_normal((n, m)) * (growth ** np.arange(n))[:, None]).astype(np.float32)
-    s = run_gpu(A, ell, t, t, "f32", 41, 42, batch=100)
+    s = run_gpu(A, ell, t, t, "f32", 41, 42, batch=100, gram=gram)
     info = s.info()
     fills = [s.update(u)["n_filled"] for u in range(int(info.n_updates))]
     log(f"  growth {growth}: filled per update {fills}")
     _, _, G = s.debug_state()
-    J = s.select()
-    occ = np.flatnonzero(J >= 0)
-    A64 = A.T.astype(np.float64)
-    Gx = np.zeros((t, t))
-    Gx[np.ix_(occ, occ)] = A64[:, J[occ]].T @ A64[:, J[occ]]
-    err = np.abs(G - Gx) / np.sqrt(np.outer(np.diag(Gx), np.diag(Gx)) + 1e-300)
-    log(f"  Gram max scaled err {err.max():.2e}")
-    assert err.max() <= 1e-13
+    _gram_check(G, A, s.select(), gram, m)
