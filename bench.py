@@ -145,6 +145,22 @@ def sketch_roofline(prof, kernel, traffic=None):
             "bytes_per_launch": per_launch, "ms_per_launch": round(per_ms, 4)}
 
 
+def gram_roofline(prof, kernel, traffic=None):
+    """The basis Gram's launches: the algorithmic bytes are the occupied
+    columns each launch reads (the method's B_basis; the pool copy of new
+    columns is listed apart, as it is not the method's own traffic), over the
+    average duration of the update's Gram phase (the Gram kernel and its small
+    slab reduction)."""
+    n = max(prof.get("gram_launches", 0), 1)
+    per_launch = prof["gram_bytes"] / n
+    per_ms = prof["gram_ms"] / n
+    achieved = per_launch / (per_ms / 1000.0) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "bytes_per_launch": per_launch, "pool_copy_bytes_per_launch": prof["pool_copy_bytes"] / n,
+            "ms_per_launch": round(per_ms, 4), "launches_per_pass": None}
+
+
 SAMPLE_BLOCKS, SAMPLE_WIDTH = 8, 16
 
 
@@ -227,9 +243,17 @@ def channel_bench(args):
             "ms_per_pass": round(ms_b2b, 3), "value": round(B_snap / (ms_b2b / 1000.0) / 1e9, 2),
             "note": "passes enqueued back to back: each pass's coefficient phases run beside the next "
                     "pass's sketch"},
-        "roofline": sketch_roofline(prof, f"sketch_{args.sketch}_kernel", traffic),
         "device_bytes": dev_bytes,
     }
+    # the roofline of the kernel that takes the larger share of the pass; the
+    # other one beside it
+    rf_sketch = sketch_roofline(prof, f"sketch_{args.sketch}_kernel", traffic)
+    rf_gram = gram_roofline(prof, "gram_split_kernel")
+    rf_gram["launches_per_pass"] = round(prof.get("gram_launches", 0) / steps, 2)
+    if prof["gram_ms"] > prof["sketch_ms"]:
+        line["roofline"], line["roofline_other"] = rf_gram, rf_sketch
+    else:
+        line["roofline"], line["roofline_other"] = rf_sketch, rf_gram
 
     # lookahead variants of the same form
     if not args.small and not args.no_lookahead:

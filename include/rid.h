@@ -287,6 +287,8 @@ typedef struct rid_profile {
                                so their span is not additive with the other phases */
   double pool_copy_bytes;   /* new basis columns written into the pool (columns x m x size);
                                not part of the method's own traffic (single streams only) */
+  int64_t gram_launches;    /* updates that brought new columns, each one Gram launch
+                               (single streams only) */
 } rid_profile;
 
 /* on != 0 starts recording (and clears earlier records); on == 0 stops.

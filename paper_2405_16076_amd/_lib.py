@@ -57,7 +57,7 @@ class rid_profile(C.Structure):
     _fields_ = [("sketch_ms", C.c_double), ("sketch_launches", C.c_int64), ("sketch_bytes", C.c_double),
                 ("reduce_ms", C.c_double), ("update_ms", C.c_double), ("updates", C.c_int64),
                 ("gram_ms", C.c_double), ("gram_bytes", C.c_double), ("coeff_ms", C.c_double),
-                ("pool_copy_bytes", C.c_double)]
+                ("pool_copy_bytes", C.c_double), ("gram_launches", C.c_int64)]
 
 
 RID_BATCH_NO_GRAPH, RID_BATCH_NO_TUNE = 1, 2

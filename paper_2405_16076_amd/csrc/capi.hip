@@ -1229,6 +1229,7 @@ rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
         if (r.n_filled > 0) {
           p->gram_bytes += (double)r.n_occupied * (double)h->m * h->esize;
           p->pool_copy_bytes += (double)r.n_filled * (double)h->m * h->esize;
+          p->gram_launches += 1;
         }
         break;
       }
