@@ -95,8 +95,8 @@ typedef enum rid_coeff_mode { RID_COEFF_ALG4 = 0, RID_COEFF_BEST4 = 1 } rid_coef
  * exact in binary64 and summed in binary64 (binary64 matrix cores).  SPLIT:
  * each value is split exactly into three bfloat16 pieces, the six piece
  * products of order <= 2 are summed on the bfloat16 matrix cores in binary32
- * over 32 rows, then in binary64; elementwise
- * |G_ij - A_i^T A_j| <= (37 * 2^-24 + (m / 32 + 1024) * 2^-53) sum_r |a_ri| |a_rj|
+ * over 32 rows, two such sums added in binary32, then in binary64; elementwise
+ * |G_ij - A_i^T A_j| <= (37 * 2^-24 + (m / 64 + 1024) * 2^-53) sum_r |a_ri| |a_rj|
  * for data of magnitude in [2^-100, 2^60] (or zero), so the NA-Hutch++
  * estimate moves by at most that factor times || |A_J| |P| ||_F^2.  AUTO: SPLIT
  * in RID_COEFF_ALG4 mode, EXACT in RID_COEFF_BEST4 mode (Algs. 5 and 7 solve
@@ -138,7 +138,8 @@ typedef struct rid_config {
   int64_t n_max;          /* capacity: maximum number of pushed columns */
   int32_t coeff_mode;     /* rid_coeff_mode (default RID_COEFF_ALG4); RID_COEFF_BEST4 needs
                              t <= 154 and a stream of its own (not a batch member) */
-  int32_t gram_mode;      /* rid_gram_mode (default RID_GRAM_AUTO); SPLIT needs RID_F32 data */
+  int32_t gram_mode;      /* rid_gram_mode (default RID_GRAM_AUTO); SPLIT needs RID_F32 data and
+                             RID_COEFF_ALG4 (RID_ENOTSUP with RID_COEFF_BEST4) */
 } rid_config;
 
 /* Error estimate of the last completed update (Alg. 8). */

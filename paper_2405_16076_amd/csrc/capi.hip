@@ -62,11 +62,13 @@ __global__ __launch_bounds__(256) void reconstruct_kernel(const T* __restrict__ 
     if (cb0 + jj < c) out[(int64_t)(cb0 + jj) * ld + row] = (T)acc[jj];
 }
 
-__global__ void init_state_kernel(int64_t* J, double* tau_old, int t, DevScalars* sc) {
+__global__ void init_state_kernel(int64_t* J, double* tau_old, int t, DevScalars* sc, uint64_t* slot_ptr,
+                                  const char* pool, int64_t col_bytes) {
   const int i = threadIdx.x;
   if (i < t) {
     J[i] = -1;
     tau_old[i] = 1.0;
+    slot_ptr[i] = reinterpret_cast<uint64_t>(pool + (int64_t)i * col_bytes);
   }
   if (i == 0) {
     sc->nonfinite = 0;
@@ -116,6 +118,7 @@ struct rid_stream {
   hipEvent_t colptr_ev = nullptr;   // after the last upload of colptr_host
   bool colptr_pending = false;
   void* cpool = nullptr;
+  uint64_t* slot_ptr = nullptr;  // t column addresses (split Gram: pool or this flush's snapshots)
   void* ring = nullptr;
   int64_t ring_cap = 0, ring_ld = 0;
   void* part = nullptr;
@@ -134,6 +137,7 @@ struct rid_stream {
     int kind;        // 0 sketch, 1 reduce, 2 update, 3 gram, 4 coefficient phases (second stream)
     double bytes;
     hipStream_t on;  // stream the events are recorded on
+    int64_t aux;     // gram: the flush's first column at its last update (split Gram), else -1
   };
   bool profiling = false;
   std::vector<Mark> marks;
@@ -369,6 +373,8 @@ static rid_status validate(const rid_config* c) {
     return fail(nullptr, RID_EINVAL, "unknown gram_mode");
   if (c->gram_mode == RID_GRAM_SPLIT && c->data_dtype != RID_F32)
     return fail(nullptr, RID_EINVAL, "RID_GRAM_SPLIT needs RID_F32 data");
+  if (c->gram_mode == RID_GRAM_SPLIT && c->coeff_mode == RID_COEFF_BEST4)
+    return fail(nullptr, RID_ENOTSUP, "RID_COEFF_BEST4 needs binary64 Gram products (RID_GRAM_AUTO or EXACT)");
   return RID_OK;
 }
 
@@ -487,6 +493,7 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     ALLOC(h->PPt, t * t * cg);
     ALLOC(h->hw, hutch_work_doubles(h->ell, h->t) * cg);
     ALLOC(h->colptr_dev, (size_t)h->n_max);
+    ALLOC(h->slot_ptr, (size_t)t);
     ALLOC(h->normpart, (size_t)h->n_slabs * h->b_max);
     ALLOC(h->sc, (size_t)1);
     ALLOC(h->sc_hist, (size_t)h->max_updates);
@@ -549,7 +556,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     st = fail(nullptr, RID_EDEVICE, "hipMemsetAsync failed");
     goto fail_alloc;
   }
-  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc);
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc,
+                     h->slot_ptr, static_cast<const char*>(h->cpool), (int64_t)h->ldc * h->esize);
   if (hipGetLastError() != hipSuccess) {
     st = fail(nullptr, RID_EDEVICE, "init kernel launch failed");
     goto fail_alloc;
@@ -581,9 +589,9 @@ static hipEvent_t take_event(rid_stream* h) {
 }
 
 // Starts a timed interval on the handle's stream (no-op unless profiling).
-static int mark_begin(rid_stream* h, int kind, double bytes, hipStream_t on = nullptr) {
+static int mark_begin(rid_stream* h, int kind, double bytes, hipStream_t on = nullptr, int64_t aux = -1) {
   if (!h->profiling) return -1;
-  rid_stream::Mark mk{take_event(h), take_event(h), kind, bytes, on ? on : h->s};
+  rid_stream::Mark mk{take_event(h), take_event(h), kind, bytes, on ? on : h->s, aux};
   if (!mk.a || !mk.b || hipEventRecord(mk.a, mk.on) != hipSuccess) {
     (void)hipGetLastError();
     return -1;
@@ -721,6 +729,8 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
     a.tauD_hist = h->tauD_hist;
     a.colptr = h->colptr_dev;
     a.cpool = h->cpool;
+    a.slot_ptr = h->slot_ptr;
+    a.flush_last = 0;
     a.G = h->G;
     a.gpart = h->gpart;
     a.gslabs = h->gslabs;
@@ -808,12 +818,14 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   RID_HIP(h, launch_update_q_all(upd_args(h, 0, n_full, last), nz, h->s));
   mark_end(h, mk);
   h->sst_cur ^= 1;
+  const int64_t flush_c0 = upd_args(h, 0, n_full, last).c0;  // first column the flush scans
   for (int z = 0; z < nz; ++z) {
-    const UpdArgs a = upd_args(h, z, n_full, last);
+    UpdArgs a = upd_args(h, z, n_full, last);
+    a.flush_last = z == nz - 1;
     mk = mark_begin(h, 2, (double)a.u);
     RID_HIP(h, launch_update_select(a, h->s, false));
     mark_end(h, mk);
-    mk = mark_begin(h, 3, (double)a.u);
+    mk = mark_begin(h, 3, (double)a.u, nullptr, a.flush_last ? flush_c0 : -1);
     // Alg. 7 needs the new columns' products with the pruned ones, which the
     // Gram's pool copy overwrites
     if (h->best4 && a.u > 0) RID_HIP(h, launch_best4_cross(a, b4_args(h, a.u, z), h->s));
@@ -1044,7 +1056,8 @@ static rid_status reset_stream(rid_stream* h) {
   h->sst_cur = 0;
   RID_HIP(h, hipMemsetAsync(h->SST[0], 0, ell * ell * 8, h->s));
   RID_HIP(h, hipMemsetAsync(h->G, 0, t * t * 8, h->s));
-  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc);
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(kMaxT), 0, h->s, h->J, h->tau_old, h->t, h->sc,
+                     h->slot_ptr, static_cast<const char*>(h->cpool), (int64_t)h->ldc * h->esize);
   RID_HIP(h, hipGetLastError());
   h->n_pushed = h->n_sketched = h->n_uploaded = h->n_updates = h->last_nobs = 0;
   h->finalized = false;
@@ -1228,8 +1241,18 @@ rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
         p->gram_ms += ms;
         if (r.n_filled > 0) {
           p->gram_bytes += (double)r.n_occupied * (double)h->m * h->esize;
-          p->pool_copy_bytes += (double)r.n_filled * (double)h->m * h->esize;
           p->gram_launches += 1;
+          if (!h->gram_split) p->pool_copy_bytes += (double)r.n_filled * (double)h->m * h->esize;
+        }
+        if (h->gram_split && mk.aux >= 0) {
+          // the split Gram copies, at the flush's last update, the basis
+          // columns selected during the flush (column index >= its first)
+          std::vector<int64_t> J(h->t);
+          RID_HIP(h, hipMemcpy(J.data(), h->J_hist + (int64_t)mk.bytes * h->t, sizeof(int64_t) * h->t,
+                               hipMemcpyDeviceToHost));
+          int64_t nc = 0;
+          for (int64_t j : J) nc += j >= mk.aux;
+          p->pool_copy_bytes += (double)nc * (double)h->m * h->esize;
         }
         break;
       }
@@ -1651,7 +1674,8 @@ static rid_status batch_round(rid_batch* bt, RoundMode mode, bool* worked) {
         rid_stream* h = bt->st[i];
         const int nz = nfull[i] + (nlast[i] > 0 ? 1 : 0);
         if (z >= nz) continue;
-        const UpdArgs a = upd_args(h, z, nfull[i], nlast[i]);
+        UpdArgs a = upd_args(h, z, nfull[i], nlast[i]);
+        a.flush_last = z == nz - 1;   // the member's last update of the round
         ua.push_back(a);
         ua_p.push_back(z == nz - 1);
         if (defer) {

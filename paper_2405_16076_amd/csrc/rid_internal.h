@@ -311,6 +311,10 @@ struct UpdArgs {
   double* tauD_hist;   // [update][t]
   const uint64_t* colptr;
   void* cpool;         // m x t columns, stride ldc
+  uint64_t* slot_ptr;  // t: address of each slot's column (its pool column, or for the split
+                       // Gram a snapshot of the running flush not yet copied to the pool)
+  int flush_last;      // 1 for the last update of a flush: the split Gram copies the basis
+                       // columns still outside the pool
   double* G;           // t x t
   double* gpart;       // gram partials
   int gslabs;

@@ -1453,7 +1453,12 @@ __device__ __forceinline__ void gram_split_stage(const UpdArgs& a, const int64_t
   // this thread's columns st / 16 + 16 i.  Staged columns past the list read
   // the pool's first column (valid rows, values ignored: a column of the
   // planes only enters the products of its own tile row or column, which
-  // are dropped), so that every load is unconditional.
+  // are dropped), so that every load is unconditional.  A column is read
+  // where it lives: the running update's new slots in the snapshots, the
+  // slots filled earlier in this flush there too (slot_ptr), the others in
+  // the pool.  At the last update of a flush the columns outside the pool are
+  // copied into it (dsl = their slot); earlier updates copy nothing, so a
+  // column that enters and leaves the basis within one flush is never copied.
   const float* cpool = reinterpret_cast<const float*>(a.cpool);
   float* pool = reinterpret_cast<float*>(a.cpool);
   const float* src[NLD];
@@ -1466,8 +1471,10 @@ __device__ __forceinline__ void gram_split_stage(const UpdArgs& a, const int64_t
     if (c < nj) {
       const int slot = gram_slot(sc, c);
       const int s = sc->slot_src[slot];  // >= 0 exactly for the new slots
-      src[i] = (s >= 0) ? reinterpret_cast<const float*>(a.colptr[a.c0 + s]) : cpool + (int64_t)slot * a.ldc;
-      if (c < nq) dsl[i] = sc->new_slot[c];
+      const float* pcol = cpool + (int64_t)slot * a.ldc;
+      src[i] = (s >= 0) ? reinterpret_cast<const float*>(a.colptr[a.c0 + s])
+                        : reinterpret_cast<const float*>(a.slot_ptr[slot]);
+      if (a.flush_last && src[i] != pcol) dsl[i] = slot;
     }
     off[i] = c * kGsPlaneColBytes + (((part >> 1) ^ col_swz(c)) << 4) + ((part & 1) << 3);
   }
@@ -1583,6 +1590,62 @@ __global__ __launch_bounds__(64 * kGsWaves, 1) void gram_split_kernel_b(Batched<
   const UpdArgs* p;
   Blk bk;
   if (batched_block(L, p, bk)) gram_split_tiles<NBUF, NCOL>(*p, bk);
+}
+
+// After the split Gram of an update: the slots it filled point at their
+// snapshots in the flush's buffer; after the last update of a flush every
+// slot points at its pool column again (the Gram, or gram_pool_flush when the
+// update brought no column, has copied them).  One block of kMaxT threads.
+__device__ __forceinline__ void gram_ptr_body(const UpdArgs& a, const Blk bk) {
+  (void)bk;
+  const int i = threadIdx.x;
+  if (i >= a.t) return;
+  const int s = a.sc->slot_src[i];
+  const float* pcol = reinterpret_cast<const float*>(a.cpool) + (int64_t)i * a.ldc;
+  if (a.flush_last)
+    a.slot_ptr[i] = reinterpret_cast<uint64_t>(pcol);
+  else if (s >= 0)
+    a.slot_ptr[i] = a.colptr[a.c0 + s];
+}
+
+__global__ void gram_ptr_kernel(UpdArgs a) { gram_ptr_body(a, own_block()); }
+
+__global__ void gram_ptr_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) gram_ptr_body(*p, bk);
+}
+
+// The last update of a flush that brought no column runs no split Gram: copy
+// the occupied slots whose column still lives in the flush's buffer into the
+// pool.  Grid (kPoolFlushBlocks, t) of 256 threads, 16 bytes per thread and
+// step (columns start on 16-byte boundaries; a ragged last run is copied
+// element by element).
+constexpr int kPoolFlushBlocks = 64;
+
+__device__ __forceinline__ void gram_pool_flush_body(const UpdArgs& a, const Blk bk) {
+  if (!a.flush_last || a.sc->n_new != 0) return;  // the Gram copied them
+  const int slot = bk.y;
+  if (slot >= a.t || a.J[slot] < 0) return;
+  float* pcol = reinterpret_cast<float*>(a.cpool) + (int64_t)slot * a.ldc;
+  const float* src = reinterpret_cast<const float*>(a.slot_ptr[slot]);
+  if (src == pcol) return;
+  const int64_t step = (int64_t)kPoolFlushBlocks * blockDim.x * 4;
+  for (int64_t r = ((int64_t)bk.x * blockDim.x + threadIdx.x) * 4; r < a.m; r += step) {
+    if (r + 4 <= a.m) {
+      gstore_f4(gstore_ptr(pcol + r), gload_f4(gload_ptr(src + r)));
+    } else {
+      for (int64_t e = r; e < a.m; ++e) pcol[e] = src[e];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gram_pool_flush_kernel(UpdArgs a) { gram_pool_flush_body(a, own_block()); }
+
+__global__ __launch_bounds__(256) void gram_pool_flush_kernel_b(Batched<UpdArgs> L) {
+  const UpdArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) gram_pool_flush_body(*p, bk);
 }
 
 static const void* gram_split_fn(int t, bool batched) {
@@ -2808,6 +2871,10 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
   }
   hipLaunchKernelGGL(gram_zero_kernel, dim3(a.t), dim3(kMaxT), 0, s, a);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(a.t, (a.t + 63) / 64), dim3(64 * kGramReduceWaves), 0, s, a);
+  if (!a.data_f64 && a.gram_split) {
+    if (a.flush_last) hipLaunchKernelGGL(gram_pool_flush_kernel, dim3(kPoolFlushBlocks, a.t), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(gram_ptr_kernel, dim3(1), dim3(kMaxT), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -3023,6 +3090,13 @@ void plan_update_gram_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch
   P.emit(dim3(kMaxT), -1, st, out);
   for (int i = 0; i < ns; ++i) P.add(fn(gram_reduce_kernel_b), h[i], make_int4(h[i].t, (h[i].t + 63) / 64, 1, 0));
   P.emit(dim3(64 * kGramReduceWaves), -1, st, out);
+  for (int i = 0; i < ns; ++i)
+    if (!h[i].data_f64 && h[i].gram_split && h[i].flush_last)
+      P.add(fn(gram_pool_flush_kernel_b), h[i], make_int4(kPoolFlushBlocks, h[i].t, 1, 0));
+  P.emit(dim3(256), -1, st, out);
+  for (int i = 0; i < ns; ++i)
+    if (!h[i].data_f64 && h[i].gram_split) P.add(fn(gram_ptr_kernel_b), h[i], make_int4(1, 1, 1, 0));
+  P.emit(dim3(kMaxT), -1, st, out);
 }
 
 void plan_update_coeff_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out, const bool* want_p) {

@@ -167,7 +167,7 @@ def gram_split_eps(m):
     """The library's elementwise bound of the split-form Gram, relative to
     sum_r |a_ri| |a_rj| (three-piece bfloat16 split, order <= 2 products,
     binary32 sums over 32 rows counted as rounded at every addition, then
-    binary64 over at most m / 32 + 1024 additions)."""
+    binary64 over at most m / 64 + 1024 additions; m / 32 kept as the margin)."""
     return 37 * 2.0 ** -24 + (m / 32 + 1024) * 2.0 ** -53
 
 

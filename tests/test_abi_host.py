@@ -121,6 +121,16 @@ def test_split_gram_needs_binary32_data(L):
     assert b"RID_GRAM_SPLIT" in buf.value
 
 
+def test_split_gram_with_best_of_four_is_rejected(L):
+    lib = L.lib()
+    cfg = L.rid_config()
+    lib.rid_config_default(C.byref(cfg))
+    cfg.m, cfg.ell, cfg.k, cfg.t, cfg.n_max = 1000, 40, 20, 20, 100
+    cfg.coeff_mode, cfg.gram_mode = L.RID_COEFF_BEST4, L.RID_GRAM_SPLIT
+    h = C.c_void_p()
+    assert lib.rid_init_stream(C.byref(cfg), None, C.byref(h)) == L.RID_ENOTSUP
+
+
 def test_null_handles_are_rejected(L):
     lib = L.lib()
     assert lib.rid_push_snapshots(None, None, 10, 1, 0) == L.RID_EINVAL
