@@ -450,8 +450,9 @@ rid_status rid_batch_stream(rid_batch* bt, int32_t i, rid_stream** out);
 rid_status rid_batch_get_info(rid_batch* bt, rid_batch_info* info);
 
 /* Candidate i (0-based, in the order timed) of the slab tuner: its slab
- * rows, work split (1 = RID_TILE_WIDE) and median time of the round's
- * persistent sketch in ms.  RID_EINVAL past the last candidate (none when
+ * rows, work split (1 = RID_TILE_WIDE) and the faster of two timed runs of
+ * the round's persistent sketch over one column tile per member, in ms (the
+ * scan of a split stops at the first slab 15% slower than its best).  RID_EINVAL past the last candidate (none when
  * the shape was tuned earlier in the process or RID_BATCH_NO_TUNE is set). */
 rid_status rid_batch_tune_result(rid_batch* bt, int32_t i, int64_t* slab_rows, int32_t* wide, double* ms);
 

@@ -1535,7 +1535,13 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
   auto apply_tile = [](rid_stream* h, int wide) {
     set_tile(h, h->cfg.sketch_tile == RID_TILE_WIDE || (h->cfg.sketch_tile == RID_TILE_AUTO && wide));
   };
-  for (int wide = 0; wide <= (any_wide ? 1 : 0); ++wide)
+  // Each candidate times the round's persistent sketch and reduction on one
+  // column tile per member (the slab decides the per-item work, not how many
+  // tiles there are): one untimed run, then the faster of two timed ones.
+  // Candidates go by increasing slab; the times are U-shaped in the slab, so
+  // the scan stops once a candidate runs 15% behind the best.
+  for (int wide = 0; wide <= (any_wide ? 1 : 0); ++wide) {
+  double best_here = 1e300;
   for (int64_t rows : slab_candidates(prec)) {
     if (rows < bt->min_slab_rows) continue;
     for (rid_stream* h : bt->st) {
@@ -1545,12 +1551,12 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
     std::vector<SketchArgs> args;
     std::vector<int> precs;
     for (size_t i = 0; i < who.size(); ++i) {
-      args.push_back(sketch_args(bt->st[who[i]], c0[i], b[i]));
-      precs.push_back(bt->st[who[i]]->prec);
+      rid_stream* h = bt->st[who[i]];
+      args.push_back(sketch_args(h, c0[i], std::min(b[i], h->cols_per_wg)));
+      precs.push_back(h->prec);
     }
-    // one untimed run, then the median of three timed ones
-    float ms_rep[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (int rep = 0; rep < 4; ++rep) {
+    float ms_rep[3] = {0.0f, 0.0f, 0.0f};
+    for (int rep = 0; rep < 3; ++rep) {
       Stage stg;
       rid_status sts = take_slot(bt, stg);
       if (sts != RID_OK) return sts;
@@ -1563,15 +1569,17 @@ static rid_status batch_tune(rid_batch* bt, const std::vector<int>& who, const s
       BT_HIP(bt, hipEventSynchronize(e1));
       BT_HIP(bt, hipEventElapsedTime(&ms_rep[rep], e0, e1));
     }
-    std::sort(ms_rep + 1, ms_rep + 4);
-    const float ms_last = ms_rep[2];
+    const float ms_last = std::min(ms_rep[1], ms_rep[2]);
     bt->tune_table.push_back(rid_batch::Cand{rows, wide, ms_last});
-    bt->tune_ms += ms_last;
+    bt->tune_ms += ms_rep[0] + ms_rep[1] + ms_rep[2];
     if (ms_last < best) {
       best = ms_last;
       best_rows = rows;
       best_wide = wide;
     }
+    best_here = std::min(best_here, (double)ms_last);
+    if (ms_last > 1.15 * best_here) break;
+  }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
