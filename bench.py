@@ -88,12 +88,67 @@ def channel_workload(small):
     return dict(nx=192, ny=129, nz=192, fields=4, n=1000, ell=300, t=150, n_modes=300)
 
 
-def open_stream(m, n_max, ell, t, sketch, seeds, lookahead):
+def open_stream(m, n_max, ell, t, sketch, seeds, lookahead, k=None):
     import torch
     from paper_2405_16076_amd import OnlineRID, StreamConfig
-    cfg = StreamConfig(m=m, ell=ell, k=t, t=t, n_max=n_max, dtype=torch.float32, sketch=sketch,
+    cfg = StreamConfig(m=m, ell=ell, k=k or t, t=t, n_max=n_max, dtype=torch.float32, sketch=sketch,
                        omega_seed=seeds[0], select_seed=seeds[1], lookahead=lookahead)
     return OnlineRID(cfg)
+
+
+# --------------------------------------------------------------------------
+# method quality from the stream's Gram matrix A^T A (binary64)
+# --------------------------------------------------------------------------
+
+def stream_gram(X, rows_per_chunk=1 << 20):
+    """A^T A of the n snapshots X (n x m, binary32 on the GPU), accumulated in
+    binary64 over row chunks."""
+    import torch
+    n, m = X.shape
+    G = torch.zeros((n, n), dtype=torch.float64, device=X.device)
+    for r0 in range(0, m, rows_per_chunk):
+        Y = X[:, r0:r0 + rows_per_chunk].double()
+        G += Y @ Y.T
+        del Y
+    return G
+
+
+def subset_rel_error(G, S):
+    """min over C of ||A - A_S C||_F / ||A||_F from A^T A (G: numpy, binary64;
+    the least-squares coefficients on the columns S)."""
+    import numpy as np
+    S = np.asarray(S, dtype=np.int64)
+    GS = G[:, S]
+    proj = float(np.sum(GS * np.linalg.lstsq(G[np.ix_(S, S)], GS.T, rcond=None)[0].T))
+    tot = float(np.trace(G))
+    return math.sqrt(max((tot - proj) / tot, 0.0))
+
+
+def coeff_rel_error(G, J, P):
+    """||A - A_J P||_F / ||A||_F from A^T A for the stream's own J and P."""
+    import numpy as np
+    J = np.asarray(J)
+    occ = np.flatnonzero(J >= 0)
+    Jo, Po = J[occ], np.asarray(P, dtype=np.float64)[occ]
+    tot = float(np.trace(G))
+    cross = float(np.sum(Po * G[Jo]))
+    quad = float(np.sum(Po * (G[np.ix_(Jo, Jo)] @ Po)))
+    return math.sqrt(max((tot - 2.0 * cross + quad) / tot, 0.0))
+
+
+def method_quality(G, k, t, J, P, draws=5, seed=7):
+    """The stream's ID against the rank-k SVD and random t-column subsets
+    (G = A^T A as a numpy binary64 array)."""
+    import numpy as np
+    ev = np.clip(np.linalg.eigvalsh(G)[::-1], 0.0, None)
+    tot = float(ev.sum())
+    svd = lambda r: math.sqrt(max(float(ev[r:].sum()) / tot, 0.0))
+    rng = np.random.default_rng(seed)
+    n = G.shape[0]
+    rnd = [subset_rel_error(G, rng.permutation(n)[:t]) for _ in range(draws)]
+    J = np.asarray(J)
+    return {"svd_rank_k": svd(k), "svd_rank_t": svd(t), "random_t_subset_mean": sum(rnd) / len(rnd),
+            "id_basis_best_coefficients": subset_rel_error(G, J[J >= 0]), "id_exact_all_columns": coeff_rel_error(G, J, P)}
 
 
 def one_pass(s, X, n, push):
@@ -210,6 +265,7 @@ def channel_bench(args):
     A_smp = [X[j0:j0 + SAMPLE_WIDTH] for j0 in sample_starts(n)]
     exact = rel_error(R_main, A_smp)
     J_main = s.select()
+    P_main = s.coefficients()
     dev_bytes = int(s.info().device_bytes)
     s.close()
     log(f"  [{args.sketch}] {ms:.2f} ms per pass, back to back {ms_b2b:.2f}; estimate rel {est['rel']:.4e}, "
@@ -269,6 +325,23 @@ def channel_bench(args):
         rows.append({"lookahead": 1024, "ms_per_pass": round(ms, 3), "value": line["value"],
                      "device_bytes": dev_bytes, "borrowed_window_bytes": float(min(n, 1024 + push)) * m * 4})
         line["lookahead"] = rows
+
+    # what the selection is worth: the rank-k SVD and random t-column subsets
+    # on the same stream, and a run with k < t (the basis size of Sec. 2.2.2's
+    # bound against a smaller target rank)
+    if not args.small and not args.no_quality:
+        G = stream_gram(X).cpu().numpy()
+        q = method_quality(G, t, t, J_main, P_main)
+        k2 = t // 3
+        s2 = open_stream(m, n, ell, t, args.sketch, seeds, 1024, k=k2)
+        one_pass(s2, X, n, push)
+        q2 = method_quality(G, k2, t, s2.select(), s2.coefficients())
+        s2.close()
+        del G
+        line["method_quality"] = {"k_eq_t": {"k": t, "t": t, **{a: round(b, 4) for a, b in q.items()}},
+                                  "k_lt_t": {"k": k2, "t": t, **{a: round(b, 4) for a, b in q2.items()}},
+                                  "note": "relative Frobenius errors over all n columns from A^T A in binary64"}
+        log(f"  method quality {line['method_quality']}")
 
     # the other sketch forms; reconstructions compared with the binary32 form's
     if not args.no_compare:
@@ -523,6 +596,7 @@ def main():
     ap.add_argument("--small", action="store_true", help="a small stream (quick check)")
     ap.add_argument("--no-compare", action="store_true", help="skip the other sketch forms")
     ap.add_argument("--no-lookahead", action="store_true", help="skip the lookahead 300 and 600 passes")
+    ap.add_argument("--no-quality", action="store_true", help="skip the SVD / random-subset comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched image streams")
     ap.add_argument("--no-lowrank", action="store_true", help="skip the low-rank binary32 stream")
