@@ -46,16 +46,20 @@ METRIC = "snapshot GB/s ingested (and % HBM roofline) at stated rel. Frobenius e
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "sketch_bf16_channel_traffic.json")
+GRAM_TRAFFIC_FILE = os.path.join(HERE, "profiles", "gram_split_channel_traffic.json")
+SKETCH_SOURCES = ("sketch.hip", "rid_internal.h", "omega_table.h")
+GRAM_SOURCES = ("update.hip", "capi.hip", "rid_internal.h")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash():
+def source_hash(files=SKETCH_SOURCES):
+    """Hash of the kernel sources a stored traffic figure was measured on."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_2405_16076_amd", "csrc")
-    for f in ("sketch.hip", "rid_internal.h", "omega_table.h"):
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -200,6 +204,20 @@ def sketch_roofline(prof, kernel, traffic=None):
             "bytes_per_launch": per_launch, "ms_per_launch": round(per_ms, 4)}
 
 
+def stored_traffic(path, sources, small, sketch):
+    """Per-launch HBM bytes from a committed counter summary, while the
+    kernel sources it was measured on are unchanged (else None)."""
+    if small or not os.path.exists(path):
+        return None
+    try:
+        tr = json.load(open(path))
+        if tr.get("source_hash") == source_hash(sources) and tr.get("sketch") == sketch:
+            return tr.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
 def gram_roofline(prof, kernel, traffic=None):
     """The basis Gram's launches: the algorithmic bytes are the occupied
     columns each launch reads (the method's B_basis; the pool copy of new
@@ -271,13 +289,8 @@ def channel_bench(args):
     log(f"  [{args.sketch}] {ms:.2f} ms per pass, back to back {ms_b2b:.2f}; estimate rel {est['rel']:.4e}, "
         f"exact (sampled) {exact:.4e}")
     traffic = None
-    if os.path.exists(TRAFFIC_FILE) and not args.small:
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("source_hash") == source_hash() and tr.get("sketch") == args.sketch:
-                traffic = tr.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = stored_traffic(TRAFFIC_FILE, SKETCH_SOURCES, args.small, sketch=args.sketch)
+    gram_traffic = stored_traffic(GRAM_TRAFFIC_FILE, GRAM_SOURCES, args.small, sketch=args.sketch)
     steps = args.steps
     basis = prof["gram_bytes"] / steps
     line = {
@@ -304,7 +317,7 @@ def channel_bench(args):
     # the roofline of the kernel that takes the larger share of the pass; the
     # other one beside it
     rf_sketch = sketch_roofline(prof, f"sketch_{args.sketch}_kernel", traffic)
-    rf_gram = gram_roofline(prof, "gram_split_kernel")
+    rf_gram = gram_roofline(prof, "gram_split_kernel", gram_traffic)
     rf_gram["launches_per_pass"] = round(prof.get("gram_launches", 0) / steps, 2)
     if prof["gram_ms"] > prof["sketch_ms"]:
         line["roofline"], line["roofline_other"] = rf_gram, rf_sketch
