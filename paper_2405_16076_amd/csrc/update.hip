@@ -211,17 +211,33 @@ __global__ __launch_bounds__(256) void sst_batch_kernel_b(Batched<BatchArgs> L) 
 // hv layout: [0,l) reflector tau, [l,2l) d, [2l,3l) e, [3l,4l) Dinv, [4l,5l) L,
 // [5l,6l) top eigenvalues (descending).
 // ---------------------------------------------------------------------------
-__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += (q < 0.0);
+// Sturm counts at two shifts, the recurrences interleaved: the number of
+// negative pivots of the LDL^T factorisation of T - x I for x = x0 and x1.
+// The division by the previous pivot is a reciprocal refined by two Newton
+// steps (a few units in the last place, which the count's backward stability
+// absorbs; pivots are kept at least pivmin in magnitude, so it stays finite).
+__device__ __forceinline__ void sturm_count2(const double* d, const double* e2, int n, double x0, double x1,
+                                             double pivmin, int& c0, int& c1) {
+  double q0 = d[0] - x0, q1 = d[0] - x1;
+  if (fabs(q0) < pivmin) q0 = -pivmin;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  int k0 = q0 < 0.0, k1 = q1 < 0.0;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += (q < 0.0);
+    const double di = d[i], ei = e2[i - 1];
+    double r0 = __builtin_amdgcn_rcp(q0), r1 = __builtin_amdgcn_rcp(q1);
+    r0 = fma(r0, fma(-q0, r0, 1.0), r0);
+    r1 = fma(r1, fma(-q1, r1, 1.0), r1);
+    r0 = fma(r0, fma(-q0, r0, 1.0), r0);
+    r1 = fma(r1, fma(-q1, r1, 1.0), r1);
+    q0 = di - x0 - ei * r0;
+    q1 = di - x1 - ei * r1;
+    if (fabs(q0) < pivmin) q0 = -pivmin;
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    k0 += q0 < 0.0;
+    k1 += q1 < 0.0;
   }
-  return cnt;
+  c0 = k0;
+  c1 = k1;
 }
 
 template <int EMT, int NW>
@@ -463,23 +479,26 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   lo -= 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   hi += 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-  // Multisection: a group of G lanes per eigenvalue, on at most 8 waves (two
-  // per SIMD: the Sturm recurrence is a chain of binary64 divisions, so more
-  // waves would only queue on the same units); lane r = 1..G-1 of the group
-  // counts the eigenvalues below the r-th of the G - 1 equispaced interior
-  // points of the group's interval, and the group keeps the subinterval
-  // holding its target (Sturm counts are monotone in the shift, so the points
-  // with count <= target are a prefix).  Stops at a width of one ulp of the
-  // eigenvalue or 2 eps ||T||, the accuracy of the reduction itself.
+  // Multisection: a group of GL lanes per eigenvalue, on at most 8 waves (two
+  // per SIMD: the Sturm recurrences keep the binary64 units busy, so more
+  // waves would only queue on them); lane r of the group counts the
+  // eigenvalues below points 2r + 1 and 2r + 2 of the 2 GL equispaced interior
+  // points that cut the group's interval into G = 2 GL + 1 parts, and the
+  // group keeps the part holding its target (Sturm counts are monotone in the
+  // shift, so the points with count <= target are a prefix).  Stops at a
+  // width of one ulp of the eigenvalue or 2 eps ||T||, the accuracy of the
+  // reduction itself.
   const int kk = min(b.k, n);
   const int nwe = min(nw, 8);
-  int G = 2;
-  for (int g = 16; g > 2; --g)
+  int GL = 1;
+  for (int g = 8; g > 1; --g)
     if ((64 / g) * nwe >= kk) {
-      G = g;
+      GL = g;
       break;
     }
-  const int gpw = 64 / G, gi = lane / G, r = lane % G;
+  const int G = 2 * GL + 1;
+  const int gpw = 64 / GL, gi = lane / GL, r = lane % GL;
+  const uint64_t gmask = ((1ull << GL) - 1) << (gi * GL);
   const double atol = 2.0 * 2.220446049250313e-16 * bnd;
   for (int idx = (gi < gpw && wv < nwe) ? wv * gpw + gi : kk; idx < kk; idx += nwe * gpw) {
     const int target = n - 1 - idx;  // ascending index of the idx-th largest
@@ -488,9 +507,10 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
       if (bb - aa <= fmax(2.220446049250313e-16 * fmax(fabs(aa), fabs(bb)), atol)) break;
       const double hs = (bb - aa) / G;
       if (!(aa + hs > aa) || !(aa + (G - 1) * hs < bb)) break;
-      const bool below = r > 0 && sturm_count(ds, e2s, n, aa + r * hs, pivmin) <= target;
-      const uint64_t bal = __ballot(below);
-      const int cnt = __popcll((bal >> (gi * G)) & ((1ull << G) - 1));
+      int c0, c1;
+      sturm_count2(ds, e2s, n, aa + (2 * r + 1) * hs, aa + (2 * r + 2) * hs, pivmin, c0, c1);
+      const uint64_t bal0 = __ballot(c0 <= target), bal1 = __ballot(c1 <= target);
+      const int cnt = __popcll(bal0 & gmask) + __popcll(bal1 & gmask);
       const double na = cnt == 0 ? aa : aa + cnt * hs;
       const double nb = cnt == G - 1 ? bb : aa + (cnt + 1) * hs;
       aa = na;
