@@ -284,21 +284,16 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   // diagonal; the partials meet in LDS in wave order.  Vectors in LDS are
   // indexed by absolute row; in registers element q of a lane is row
   // j + 1 + lane + 64 q.  EMT = ceil(l / 64); the columns of a wave go CB at a
-  // time, their loads issued together (the step is bound by L2 latency).
+  // time, their loads issued together.  The pass is bound by the SIMDs' issue
+  // rate, so per column it keeps to the pending update, the store and two
+  // FMAs per row: v_c is a broadcast read of the wave's own copy of v in
+  // LDS, and the dots of a batch are summed together (16 lanes per column).
   constexpr int CB = EMT <= 3 ? 4 : (EMT <= 5 ? 3 : (EMT <= 6 ? 2 : 1));
   __shared__ double ppart[NW][kMaxEll];
+  __shared__ double dred[NW][4][64];   // a batch's per-lane column dots
   __shared__ double pd[kMaxEll];
   __shared__ double vs[2][kMaxEll];   // reflector of step j at [j & 1]
   __shared__ double ps[2][kMaxEll];   // p of step j at [j & 1]
-  // value of element q of a wave-uniform row slot `k` of a register vector
-  auto pick = [&](const double (&x)[EMT], int k) {
-    k = __builtin_amdgcn_readfirstlane(k);
-    double r = 0.0;
-#pragma unroll
-    for (int q = 0; q < EMT; ++q)
-      if ((k >> 6) == q) r = readlane_f64(x[q], k & 63);
-    return r;
-  };
   double Kp = 0.0;   // K of the pending step
   for (int j = 0; j + 2 < n; ++j) {
     const int m = n - j - 1;            // order of the trailing block, rows j+1..n-1
@@ -365,10 +360,20 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     }
     // trailing block: pending update, store, p partials with the new v
     double* A22 = W + (int64_t)base * n + base;  // A22(k, c) = A22[c n + k], k >= c
+    // this wave's row of partials holds its copy of v until the pass ends, so
+    // v_c is one broadcast read
+    double* vloc = ppart[wv];
+#pragma unroll
+    for (int q = 0; q < EMT; ++q) {
+      const int k = lane + 64 * q;
+      if (k < m) vloc[k] = cv[q];
+    }
     double pp[EMT];
 #pragma unroll
     for (int q = 0; q < EMT; ++q) pp[q] = 0.0;
-    for (int c0 = wv; c0 < m; c0 += CB * nw) {
+    // the wave index as a scalar, so that column addresses stay in SGPRs
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    for (int c0 = wvu; c0 < m; c0 += CB * nw) {
       double a[CB][EMT];
 #pragma unroll
       for (int u = 0; u < CB; ++u) {
@@ -389,7 +394,7 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
         double* col = A22 + (int64_t)c * n;
         const double vc_p = pend ? Vp[base + c] : 0.0;
         const double wc_p = pend ? Pp[base + c] - Kp * vc_p : 0.0;
-        const double vc = pick(cv, c);
+        const double vc = vloc[c];
 #pragma unroll
         for (int q = 0; q < EMT; ++q) {
           const int k = lane + 64 * q;
@@ -401,11 +406,20 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
           }
         }
       }
+      // the batch's dots: 16 lanes per column add four partials each, then
+      // the 16 lanes of a row add by DPP
 #pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        const double sv = wave_sum(dot[u]);
-        const int c = c0 + u * nw;
-        if (lane == 0 && c < m) pd[c] = sv;
+      for (int u = 0; u < CB; ++u) dred[wv][u][lane] = dot[u];
+      {
+        const int uu = lane >> 4, j = lane & 15;
+        double s4 = 0.0;
+        if (uu < CB) s4 = (dred[wv][uu][j] + dred[wv][uu][j + 16]) + (dred[wv][uu][j + 32] + dred[wv][uu][j + 48]);
+        s4 += dpp_mov_f64<0xB1>(s4);   // quad_perm(1,0,3,2)
+        s4 += dpp_mov_f64<0x4E>(s4);   // quad_perm(2,3,0,1)
+        s4 += dpp_mov_f64<0x141>(s4);  // row_half_mirror
+        s4 += dpp_mov_f64<0x140>(s4);  // row_mirror
+        const int cu = c0 + uu * nw;
+        if (j == 0 && uu < CB && cu < m) pd[cu] = s4;
       }
     }
 #pragma unroll
