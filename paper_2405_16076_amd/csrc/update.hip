@@ -1768,13 +1768,8 @@ __global__ __launch_bounds__(1024) void alg4_qr_kernel_b(Batched<UpdArgs> L) {
 // wave c % NW (slot c / NW), row r in lane r % 64 (element r / 64).  Step jj:
 // the owner wave of column jj forms the reflector and publishes it in LDS
 // (double-buffered by step parity), one barrier, then every wave applies it to
-// its own columns, with the wave sums of a batch of columns interleaved.
-// E = ceil(l / 64), NS = ceil(t / NW).
-template <int N>
-__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
-}
+// its own columns still to be reduced (c > jj), over the row chunks that
+// reach row jj.  E = ceil(l / 64), NS = ceil(t / NW).
 
 template <int E, int NS, int NW>
 __device__ __forceinline__ void alg4_qr_reg_body(const UpdArgs& a, const Blk bk) {
@@ -1848,26 +1843,32 @@ __device__ __forceinline__ void alg4_qr_reg_body(const UpdArgs& a, const Blk bk)
         const int r = lane + 64 * e;
         v[e] = (r >= jj && r < n) ? vb[buf][r] : 0.0;
       }
+      // Only columns c > jj take the reflector, and v is zero above row jj:
+      // batches whose columns are all done and row chunks wholly above jj are
+      // skipped by scalar branches (their terms are exact zeros).
       constexpr int B = (E >= 5) ? 4 : 8;
+      const int e0 = jj >> 6;
 #pragma unroll
       for (int s0 = 0; s0 < NS; s0 += B) {
+        if (wave + NW * min(s0 + B - 1, NS - 1) <= jj) continue;
         double d[B];
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           d[i] = 0.0;
           if (s0 + i < NS)
 #pragma unroll
-            for (int e = 0; e < E; ++e) d[i] = fma(v[e], col[s0 + i][e], d[i]);
+            for (int e = 0; e < E; ++e)
+              if (e >= e0) d[i] = fma(v[e], col[s0 + i][e], d[i]);
         }
-        wave_sum_n(d);
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           if (s0 + i < NS) {
             const int c = wave + NW * (s0 + i);
             if (c > jj && c < no) {
-              const double g = tau * d[i];
+              const double g = tau * wave_sum(d[i]);
 #pragma unroll
-              for (int e = 0; e < E; ++e) col[s0 + i][e] = fma(-g, v[e], col[s0 + i][e]);
+              for (int e = 0; e < E; ++e)
+                if (e >= e0) col[s0 + i][e] = fma(-g, v[e], col[s0 + i][e]);
             }
           }
         }
@@ -2695,27 +2696,33 @@ __device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk
         const int r = lane + 64 * e;
         v[e] = (r >= jj && r < n2) ? vb[buf][r] : 0.0;
       }
+      // Chosen pivots and empty slots take no reflector, and v is zero above
+      // row jj: their dots, sums and row chunks wholly above jj are skipped
+      // by scalar branches (the skipped terms are exact zeros).
       constexpr int B = 8;
+      const int e0 = jj >> 6;
 #pragma unroll
       for (int s0 = 0; s0 < NS; s0 += B) {
+        if (wave + NW * s0 >= nv) continue;
         double d[B];
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           d[i] = 0.0;
           if (s0 + i < NS)
 #pragma unroll
-            for (int e = 0; e < E; ++e) d[i] = fma(v[e], vec[s0 + i][e], d[i]);
+            for (int e = 0; e < E; ++e)
+              if (e >= e0) d[i] = fma(v[e], vec[s0 + i][e], d[i]);
         }
-        wave_sum_n(d);
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           if (s0 + i >= NS) continue;
           const int q = wave + NW * (s0 + i);
           const bool apply = (q < n1) ? (ipos[q] < 0) : (q < nv);
           if (apply) {
-            const double g = tau * d[i];
+            const double g = tau * wave_sum(d[i]);
 #pragma unroll
-            for (int e = 0; e < E; ++e) vec[s0 + i][e] = fma(-g, v[e], vec[s0 + i][e]);
+            for (int e = 0; e < E; ++e)
+              if (e >= e0) vec[s0 + i][e] = fma(-g, v[e], vec[s0 + i][e]);
           }
         }
       }
