@@ -137,7 +137,9 @@ struct rid_stream {
     int kind;        // 0 sketch, 1 reduce, 2 update, 3 gram, 4 coefficient phases (second stream)
     double bytes;
     hipStream_t on;  // stream the events are recorded on
-    int64_t aux;     // gram: the flush's first column at its last update (split Gram), else -1
+    int64_t aux;     // gram: the flush's first column at its last update (split Gram), -2 for a
+                     // run of updates' Grams in one pass (bytes: its reads), else -1
+    int nu = 1;      // updates of a run
   };
   bool profiling = false;
   std::vector<Mark> marks;
@@ -166,6 +168,12 @@ struct rid_stream {
   // a flush, recq four records and qstar one choice per update
   bool best4 = false;
   bool gram_split = false;  // binary32 Gram on the bfloat16 matrix cores
+  // Split Grams of runs of consecutive updates of a flush in one pass
+  // (stand-alone streams in ALG4 mode): partials with leading dimension
+  // gld = max(t, 256) and the running list
+  bool gram_merge = false;
+  int gld = 0;
+  GramRun* grun = nullptr;
   double *b4_Pc = nullptr, *b4_Pprev = nullptr, *b4_M5 = nullptr, *b4_L = nullptr, *b4_T = nullptr;
   double *b4_rA = nullptr, *b4_D6 = nullptr, *b4_QR6 = nullptr, *b4_tau6 = nullptr, *b4_Qm6 = nullptr;
   double *b4_Mm6 = nullptr, *b4_Xc = nullptr;
@@ -458,6 +466,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
   h->gram_split = !h->data_f64 && (cfg->gram_mode == RID_GRAM_SPLIT ||
                                    (cfg->gram_mode == RID_GRAM_AUTO && !h->best4));
   if (h->best4) h->cgroup = 1;   // each update's choice feeds the next one's Algs. 6 and 7
+  h->gram_merge = h->gram_split && !h->best4 && !member;
+  h->gld = h->gram_merge ? std::max(h->t, kGramRunCols) : h->t;
   const size_t ell = h->ell, t = h->t, cg = h->cgroup;
   const size_t psize = (h->prec == RID_SKETCH_F64) ? 8 : 4;
 #define ALLOC(ptr, n) \
@@ -481,7 +491,8 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     ALLOC(h->J, (size_t)kMaxT);
     ALLOC(h->J_hist, t * h->max_updates);
     ALLOC(h->G, t * t);
-    ALLOC(h->gpart, (size_t)h->gslabs * t * t);
+    ALLOC(h->gpart, (size_t)h->gslabs * h->gld * h->gld);
+    if (h->gram_merge) ALLOC(h->grun, (size_t)1);
     ALLOC(h->QR, ell * t * cg);
     ALLOC(h->qr_tau, (size_t)kMaxT * cg);
     ALLOC(h->P, t * h->n_max);
@@ -691,6 +702,15 @@ static BatchArgs batch_args(rid_stream* h, int n_full, int last) {
   return b;
 }
 
+// 32 x 32 tiles of the split Gram of a list of nj columns whose first nq are
+// new (the new-against-new tiles below the diagonal are not formed).
+static int gram_tiles(int nq, int nj) {
+  const int TQ = (nq + 31) / 32, TJ = (nj + 31) / 32;
+  int n = 0;
+  for (int r = 0; r < TQ; ++r) n += TJ - std::min(r, nq / 32);
+  return n;
+}
+
 // Arguments of update n_updates + z of a batch of n_full full updates.
 static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
   UpdArgs a;
@@ -733,6 +753,9 @@ static UpdArgs upd_args(rid_stream* h, int z, int n_full, int last) {
     a.flush_last = 0;
     a.G = h->G;
     a.gpart = h->gpart;
+    a.gld = h->gld;
+    a.grun = nullptr;
+    a.grun_u = 0;
     a.gslabs = h->gslabs;
     a.gslab_rows = h->gslab_rows;
     a.QR = h->QR;
@@ -819,7 +842,77 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
   mark_end(h, mk);
   h->sst_cur ^= 1;
   const int64_t flush_c0 = upd_args(h, 0, n_full, last).c0;  // first column the flush scans
-  for (int z = 0; z < nz; ++z) {
+  // Alg. 4 and Alg. 8 of each update read snapshots of the selection state
+  // (the next update's selection rewrites J, G and the slot lists)
+  auto hist = [&](const UpdArgs& x, int zz) {
+    UpdArgs ac = x;
+    ac.sc = h->sc_hist + x.u;
+    ac.G = h->Ghist + (size_t)x.u * h->t * h->t;
+    ac.J = h->J_hist + (size_t)x.u * h->t;
+    coeff_slice(h, ac, zz, nz);
+    if (h->best4) ac.P = h->b4_Pc;   // Alg. 4's candidate
+    return ac;
+  };
+  int z = 0;
+  if (h->gram_merge && nz > 1) {
+    // Every selection of the flush first (none reads a Gram entry), each
+    // state kept; then the split Grams of runs of consecutive updates (the
+    // last excepted: its Gram copies the basis into the pool), a run growing
+    // while its list [new at each update, the others occupied at its first]
+    // fits one workgroup's tiles, so that the run reads each column once.
+    std::vector<UpdArgs> A(nz);
+    for (int zz = 0; zz < nz; ++zz) {
+      A[zz] = upd_args(h, zz, n_full, last);
+      A[zz].flush_last = zz == nz - 1;
+      mk = mark_begin(h, 2, (double)A[zz].u);
+      RID_HIP(h, launch_update_select(A[zz], h->s, false));
+      mark_end(h, mk);
+      if (zz < nz - 1) {
+        const UpdArgs ac = hist(A[zz], zz);
+        RID_HIP(h, launch_update_snapshot(A[zz], ac.sc, ac.G, h->s));  // its state; G follows its Gram
+      }
+    }
+    std::vector<rid_update> R(nz);
+    RID_HIP(h, hipMemcpyAsync(R.data(), h->recs + A[0].u, sizeof(rid_update) * nz, hipMemcpyDeviceToHost, h->s));
+    RID_HIP(h, hipStreamSynchronize(h->s));
+    while (z < nz - 1) {
+      int zb = z, nq = R[z].n_filled, nj = R[z].n_occupied;
+      while (zb + 1 < nz - 1 && zb + 2 - z <= kGramRunMax) {
+        const int nq2 = nq + R[zb + 1].n_filled, nj2 = nj + R[zb + 1].n_filled;
+        if (nj2 > kGramRunCols || gram_tiles(nq2, nj2) > kGramRunTiles) break;
+        nq = nq2;
+        nj = nj2;
+        ++zb;
+      }
+      const int nu = zb - z + 1;
+      mk = mark_begin(h, 3, nq > 0 ? (double)nj * (double)h->m * h->esize : 0.0, nullptr, -2);
+      if (mk >= 0) h->marks[mk].nu = nu;
+      RID_HIP(h, launch_update_gram_run(A[zb], nu, nq, nj, h->sc_hist, h->J_hist, h->grun, h->s));
+      for (int w = 0; w < nu; ++w) {
+        const UpdArgs ac = hist(A[z + w], z + w);
+        UpdArgs aw = A[z + w];
+        aw.sc = ac.sc;
+        aw.J = ac.J;
+        RID_HIP(h, launch_update_gram_run_entries(aw, w, h->grun, h->s));
+        RID_HIP(h, launch_update_snapshot(aw, ac.sc, ac.G, h->s));
+        co[z + w] = ac;
+      }
+      mark_end(h, mk);
+      h->last_nobs = A[zb].n_obs;
+      z = zb + 1;
+    }
+    // the last update: its Gram on the running state, as below
+    UpdArgs a = A[z];
+    mk = mark_begin(h, 3, (double)a.u, nullptr, flush_c0);
+    RID_HIP(h, launch_update_gram(a, h->s));
+    mark_end(h, mk);
+    const UpdArgs ac = hist(a, z);
+    co[z] = ac;
+    RID_HIP(h, launch_update_snapshot(a, ac.sc, ac.G, h->s));
+    h->last_nobs = a.n_obs;
+    z = nz;
+  }
+  for (; z < nz;) {
     UpdArgs a = upd_args(h, z, n_full, last);
     a.flush_last = z == nz - 1;
     mk = mark_begin(h, 2, (double)a.u);
@@ -831,17 +924,11 @@ static rid_status run_updates(rid_stream* h, int n_full, int last) {
     if (h->best4 && a.u > 0) RID_HIP(h, launch_best4_cross(a, b4_args(h, a.u, z), h->s));
     RID_HIP(h, launch_update_gram(a, h->s));
     mark_end(h, mk);
-    // Alg. 4 and Alg. 8 of this update read snapshots of the selection state
-    // (the next update's selection rewrites J, G and the slot lists)
-    UpdArgs ac = a;
-    ac.sc = h->sc_hist + a.u;
-    ac.G = h->Ghist + (size_t)a.u * h->t * h->t;
-    ac.J = h->J_hist + (size_t)a.u * h->t;
-    coeff_slice(h, ac, z, nz);
-    if (h->best4) ac.P = h->b4_Pc;   // Alg. 4's candidate
+    const UpdArgs ac = hist(a, z);
     co[z] = ac;
     RID_HIP(h, launch_update_snapshot(a, ac.sc, ac.G, h->s));
     h->last_nobs = a.n_obs;
+    ++z;
   }
   // The coefficient phases of the flush, on the side stream once the last
   // snapshot is taken: each is a chain of small latency-bound kernels (one
@@ -1234,6 +1321,17 @@ rid_status rid_profile_read(rid_stream* h, rid_profile* p) {
         // an update that brings new columns reads every occupied basis column
         // once (the new ones from the snapshots, the others from the pool)
         // and writes the new ones into the pool
+        if (mk.aux == -2) {
+          // a run of updates' Grams in one pass: its list's columns, read once
+          p->update_ms += ms;
+          p->updates += mk.nu;
+          p->gram_ms += ms;
+          if (mk.bytes > 0) {
+            p->gram_bytes += mk.bytes;
+            p->gram_launches += 1;
+          }
+          break;
+        }
         rid_update r;
         RID_HIP(h, hipMemcpy(&r, h->recs + (int64_t)mk.bytes, sizeof(r), hipMemcpyDeviceToHost));
         p->update_ms += ms;

@@ -280,6 +280,21 @@ struct BatchArgs {
   rid_update* recs;
 };
 
+// The split Grams of a run of consecutive updates of a flush in one pass:
+// the list holds the columns new at each update of the run, the latest
+// update's first, then the others occupied at the run's first update.  Per
+// update of the run, the list rows new at it and each list column's slot at
+// it (-1 outside its basis).
+constexpr int kGramRunMax = 8;      // updates per run
+constexpr int kGramRunCols = 256;   // longest list (the 256-column staging)
+constexpr int kGramRunTiles = 16;   // 32 x 32 tiles of one split-Gram workgroup
+struct GramRun {
+  int32_t nq, nj, nu, pad;          // list rows (new columns), list length, updates
+  int32_t q0[kGramRunMax], q1[kGramRunMax];
+  uint64_t ptr[kGramRunCols];
+  int32_t slot[kGramRunMax][kGramRunCols];
+};
+
 struct UpdArgs {
   int ell, k, t, n1, n2;
   int64_t u;           // update index
@@ -316,7 +331,10 @@ struct UpdArgs {
   int flush_last;      // 1 for the last update of a flush: the split Gram copies the basis
                        // columns still outside the pool
   double* G;           // t x t
-  double* gpart;       // gram partials
+  double* gpart;       // gram partials: [slab][gld][gld]
+  int gld;             // their leading dimension: t, or 256 when runs of updates share a Gram
+  const GramRun* grun; // explicit column list of the split Gram (null: the selection state's)
+  int grun_u;          // with grun: the update of the run whose entries the reduction writes
   int gslabs;
   int64_t gslab_rows;
   double* QR;          // l x t
@@ -476,6 +494,16 @@ hipError_t launch_update_select(const UpdArgs& a, hipStream_t s, bool with_q = t
 // the orthogonal factor Q of the tridiagonalisation of updates a0.u .. a0.u + nz - 1
 hipError_t launch_update_q_all(const UpdArgs& a0, int nz, hipStream_t s);
 hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s);
+// The split Gram of the run of updates a.u - nu + 1 .. a.u (all selected;
+// their states in sc_hist / J_hist, a the last one's arguments), a list of
+// nq new columns and nj in all (one workgroup's tiles when nu > 1): builds the
+// list in run and runs the Gram kernel.  launch_update_gram_run_entries then
+// writes update w's entries (w = index in the run; aw its arguments with sc
+// and J from the history) and moves its slots' addresses.  Not for the last
+// update of a flush.
+hipError_t launch_update_gram_run(const UpdArgs& a, int nu, int nq, int nj, const DevScalars* sc_hist,
+                                  const int64_t* J_hist, GramRun* run, hipStream_t s);
+hipError_t launch_update_gram_run_entries(const UpdArgs& aw, int w, const GramRun* run, hipStream_t s);
 // want_p: form P (the last update of a flush; Alg. 8 needs only Y and P P^T)
 hipError_t launch_update_coeff(const UpdArgs& a, hipStream_t s, bool want_p = true);
 hipError_t launch_update_snapshot(const UpdArgs& a, DevScalars* sc_out, double* g_out, hipStream_t s);

@@ -1271,7 +1271,7 @@ __device__ __forceinline__ void gram_reduce_body(const UpdArgs& a, const Blk bk)
   if (act) {
     const int per = (a.gslabs + kGramReduceWaves - 1) / kGramReduceWaves;
     const int s1 = min(a.gslabs, (w + 1) * per);
-    for (int sl = w * per; sl < s1; ++sl) s += a.gpart[((int64_t)sl * a.t + q) * a.t + jj];
+    for (int sl = w * per; sl < s1; ++sl) s += a.gpart[((int64_t)sl * a.gld + q) * a.gld + jj];
   }
   part[w][lane] = s;
   __syncthreads();
@@ -1338,6 +1338,7 @@ constexpr int kGsWaves = 8;                    // 4 multiplying + 4 staging
 constexpr int kGsMfmaWaves = 4;
 constexpr int kGsMaxTPW = 4;                   // 32 x 32 tiles per multiplying wave
 constexpr int kGsGroup = kGsMfmaWaves * kGsMaxTPW;  // tiles per workgroup
+static_assert(kGsGroup == kGramRunTiles, "a run's list must fit one workgroup's tiles");
 constexpr int kGsPlaneColBytes = kGsKC * 2;    // one column of one plane
 
 typedef __bf16 bf16x8_g __attribute__((ext_vector_type(8)));
@@ -1461,7 +1462,7 @@ __device__ __forceinline__ void gram_split_mfma(const UpdArgs& a, const int slab
     lds_barrier();
   }
 
-  double* out = a.gpart + (int64_t)slab * a.t * a.t;
+  double* out = a.gpart + (int64_t)slab * a.gld * a.gld;
 #pragma unroll
   for (int ti = 0; ti < TPW; ++ti) {
     const int j = 32 * tj[ti] + l32;
@@ -1469,7 +1470,7 @@ __device__ __forceinline__ void gram_split_mfma(const UpdArgs& a, const int slab
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int q = 32 * tq[ti] + (v & 3) + 4 * hf + 8 * (v >> 2);
-      if (q < nq) out[(int64_t)q * a.t + j] = gacc[ti][v];
+      if (q < nq) out[(int64_t)q * a.gld + j] = gacc[ti][v];
     }
   }
 }
@@ -1497,12 +1498,16 @@ __device__ __forceinline__ void gram_split_stage(const UpdArgs& a, const int64_t
   float* pool = reinterpret_cast<float*>(a.cpool);
   const float* src[NLD];
   int dsl[NLD], off[NLD];
+  const GramRun* gl = a.grun;
 #pragma unroll
   for (int i = 0; i < NLD; ++i) {
     const int c = (st >> 4) + 16 * i;
     src[i] = cpool;
     dsl[i] = -1;
-    if (c < nj) {
+    if (gl) {
+      // an explicit list (a run of updates' Grams in one pass): never a flush's last
+      if (c < nj) src[i] = reinterpret_cast<const float*>(gl->ptr[c]);
+    } else if (c < nj) {
       const int slot = gram_slot(sc, c);
       const int s = sc->slot_src[slot];  // >= 0 exactly for the new slots
       const float* pcol = cpool + (int64_t)slot * a.ldc;
@@ -1589,7 +1594,11 @@ __device__ __forceinline__ void gram_split_stage(const UpdArgs& a, const int64_t
 template <int NBUF, int NCOL>
 __device__ __forceinline__ void gram_split_tiles(const UpdArgs& a, const Blk bk) {
   extern __shared__ __attribute__((aligned(1024))) float gsm[];
-  const int nq = a.sc->n_new, nj = a.sc->n_occ;
+  int nq = a.sc->n_new, nj = a.sc->n_occ;
+  if (const GramRun* gl = a.grun) {
+    nq = gl->nq;
+    nj = gl->nj;
+  }
   if (nq == 0) return;
   const int NT = gsplit_tiles(nq, nj);
   const int g0 = bk.y * kGsGroup;
@@ -1681,6 +1690,96 @@ __global__ __launch_bounds__(256) void gram_pool_flush_kernel_b(Batched<UpdArgs>
   Blk bk;
   if (batched_block(L, p, bk)) gram_pool_flush_body(*p, bk);
 }
+
+// ---------------------------------------------------------------------------
+// The split Grams of a run of consecutive updates ua .. ub of a flush.  Update
+// v's Gram needs the columns new at v against its basis; every such column is
+// in [new at ub, ..., new at ua, the others occupied at ua], so when that list
+// fits one workgroup's tiles one pass reads it once for the whole run.  In
+// that order each entry has the operands it has in the updates' own calls
+// (the column that entered later as the tile row; the columns new at one
+// update in their order), so its sum is bitwise the same in or out of a run.
+// Runs after the selections of the run (no selection reads G).
+// ---------------------------------------------------------------------------
+// The list of the run of nu updates ending at a.u, from their selection
+// states: a column new at v is read from its snapshot (colptr), the others
+// where slot_ptr points before the run.  A list column keeps its slot at a
+// later update while the slot holds the same column.  One block.
+__global__ void gram_run_list_kernel(UpdArgs a, int nu, const DevScalars* sc_hist, const int64_t* J_hist,
+                                     GramRun* R) {
+  const int64_t ua = a.u - nu + 1;
+  __shared__ int q0s[kGramRunMax], q1s[kGramRunMax], nqs;  // list rows new at update ua + w
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int w = nu - 1; w >= 0; --w) {
+      q0s[w] = o;
+      o += sc_hist[ua + w].n_new;
+      q1s[w] = o;
+      R->q0[w] = q0s[w];
+      R->q1[w] = o;
+    }
+    nqs = o;
+    R->nq = o;
+    R->nj = o + sc_hist[ua].n_occ - sc_hist[ua].n_new;
+    R->nu = nu;
+  }
+  __syncthreads();
+  const int nq = nqs, nj = nq + sc_hist[ua].n_occ - sc_hist[ua].n_new;
+  for (int c = threadIdx.x; c < nj; c += blockDim.x) {
+    int v = -1, sl;
+    uint64_t p;
+    if (c < nq) {
+      v = 0;
+      while (!(c >= q0s[v] && c < q1s[v])) ++v;
+      const DevScalars* sv = sc_hist + ua + v;
+      const int i = c - R->q0[v];
+      sl = sv->new_slot[i];
+      p = a.colptr[(ua + v) * a.t + sv->new_src[i]];
+    } else {
+      v = 0;
+      sl = sc_hist[ua].old_slot[c - nq];
+      p = a.slot_ptr[sl];
+    }
+    R->ptr[c] = p;
+    const int64_t col = J_hist[(ua + v) * a.t + sl];
+    for (int w = 0; w < nu; ++w)
+      R->slot[w][c] = (w >= v && J_hist[(ua + w) * a.t + sl] == col) ? sl : -1;
+  }
+}
+
+// Update entries of G from a run's partials: the list rows new at update w of
+// the run against the list columns in its basis.  An entry between two list
+// rows lies in the tile of the smaller row; two new columns of this update
+// are written once, from the smaller.  Grid (t, list chunks of 64) of 4
+// waves, the slab sums as in gram_reduce.
+__device__ __forceinline__ void gram_reduce_run_body(const UpdArgs& a, const Blk bk) {
+  __shared__ double part[kGramReduceWaves][64];
+  const GramRun* R = a.grun;
+  const int w = a.grun_u, q0 = R->q0[w], q1 = R->q1[w];
+  const int q = q0 + bk.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (q >= q1) return;  // the same for the whole workgroup
+  const int jj = bk.y * 64 + lane;
+  const bool act = jj < R->nj && R->slot[w][jj] >= 0 && !(jj >= q0 && jj < q1 && jj < q);
+  const bool low = jj < R->nq && jj < q;
+  const int r = low ? jj : q, c = low ? q : jj;
+  double s = 0.0;
+  if (act) {
+    const int per = (a.gslabs + kGramReduceWaves - 1) / kGramReduceWaves;
+    const int s1 = min(a.gslabs, (wv + 1) * per);
+    for (int sl = wv * per; sl < s1; ++sl) s += a.gpart[((int64_t)sl * a.gld + r) * a.gld + c];
+  }
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv != 0 || !act) return;
+  double tot = part[0][lane];
+#pragma unroll
+  for (int i = 1; i < kGramReduceWaves; ++i) tot += part[i][lane];
+  const int si = R->slot[w][q], sj = R->slot[w][jj];
+  a.G[(int64_t)sj * a.t + si] = tot;
+  a.G[(int64_t)si * a.t + sj] = tot;
+}
+
+__global__ void gram_reduce_run_kernel(UpdArgs a) { gram_reduce_run_body(a, own_block()); }
 
 static const void* gram_split_fn(int t, bool batched) {
   if (t <= 160)
@@ -2916,6 +3015,32 @@ hipError_t launch_update_gram(const UpdArgs& a, hipStream_t s) {
     if (a.flush_last) hipLaunchKernelGGL(gram_pool_flush_kernel, dim3(kPoolFlushBlocks, a.t), dim3(256), 0, s, a);
     hipLaunchKernelGGL(gram_ptr_kernel, dim3(1), dim3(kMaxT), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_update_gram_run(const UpdArgs& a, int nu, int nq, int nj, const DevScalars* sc_hist,
+                                  const int64_t* J_hist, GramRun* run, hipStream_t s) {
+  hipLaunchKernelGGL(gram_run_list_kernel, dim3(1), dim3(256), 0, s, a, nu, sc_hist, J_hist, run);
+  if (nq == 0) return hipGetLastError();
+  UpdArgs g = a;
+  g.grun = run;
+  const int cols = std::max(nj, 1);
+  const void* f = gram_split_fn(cols, false);
+  const size_t lds = gram_split_lds(cols);
+  (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  void* args[] = {&g};
+  const int groups = (gsplit_tiles(nq, nj) + kGsGroup - 1) / kGsGroup;
+  (void)hipLaunchKernel(f, dim3(a.gslabs, groups), dim3(64 * kGsWaves), args, lds, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_gram_run_entries(const UpdArgs& aw, int w, const GramRun* run, hipStream_t s) {
+  UpdArgs g = aw;
+  g.grun = run;
+  g.grun_u = w;
+  hipLaunchKernelGGL(gram_zero_kernel, dim3(aw.t), dim3(kMaxT), 0, s, aw);
+  hipLaunchKernelGGL(gram_reduce_run_kernel, dim3(aw.t, kGramRunCols / 64), dim3(64 * kGramReduceWaves), 0, s, g);
+  hipLaunchKernelGGL(gram_ptr_kernel, dim3(1), dim3(kMaxT), 0, s, aw);
   return hipGetLastError();
 }
 
