@@ -408,6 +408,51 @@ def test_gram_after_every_update(dtype, m, t, growth, gram):
     assert any(0 < f < t for f in fills[1:]), fills
 
 
+def test_gram_runs_equal_one_launch_per_update():
+    # With the whole stream in one flush the split Grams of runs of updates
+    # share a pass (the list of a run: the columns new at each update, latest
+    # first, then the others occupied at its first); every entry keeps the
+    # operands of its own update's launch, so G after every update, and with
+    # it each NA-Hutch++ term, is bitwise that of one flush per update
+    # (lookahead t).  The profile must show fewer Gram passes than updates
+    # bringing columns, i.e. that runs formed.
+    from paper_2405_16076_amd import OnlineRID, StreamConfig
+    rng = np.random.default_rng(37)
+    m, n, ell, t = 12_007, 640, 128, 64
+    A = (rng.standard_normal((n, m)) * (1.02 ** np.arange(n))[:, None]).astype(np.float32)
+    ld = (m + 15) // 16 * 16
+    Xp = torch.zeros((n, ld), dtype=torch.float32, device="cuda:0")
+    Xp[:, :m] = torch.from_numpy(A).to("cuda:0")
+    X = Xp[:, :m]
+    out = {}
+    for la in (t, n):
+        cfg = StreamConfig(m=m, ell=ell, k=t, t=t, n_max=n, dtype=torch.float32, sketch="f32", omega_seed=61,
+                           select_seed=62, lookahead=la, gram="split")
+        s = OnlineRID(cfg)
+        s.profile_enable(True)
+        for j0 in range(0, n, t):
+            s.push(X[j0:j0 + t], borrow=True)
+        s.finalize()
+        prof = s.profile_read()
+        nu = int(s.info().n_updates)
+        recs = [s.update(u) for u in range(nu)]
+        _, _, G = s.debug_state()
+        out[la] = (s.select(), s.coefficients(), recs, G, prof)
+        s.close()
+    J0, P0, R0, G0, p0 = out[t]
+    J1, P1, R1, G1, p1 = out[n]
+    fills = [r["n_filled"] for r in R0]
+    log(f"  filled per update {fills}; Gram passes {int(p0['gram_launches'])} one flush per update, "
+        f"{int(p1['gram_launches'])} in one flush")
+    assert np.array_equal(J0, J1) and np.array_equal(P0, P1) and np.array_equal(G0, G1)
+    for a, b in zip(R0, R1):
+        for key in ("F", "sk2", "lam", "E2", "tr_est", "gpp", "term1", "h", "corr"):
+            assert a[key] == b[key], (a["update"], key, a[key], b[key])
+    assert sum(f > 0 for f in fills) == int(p0["gram_launches"])
+    assert int(p1["gram_launches"]) < int(p0["gram_launches"]), (fills, p0["gram_launches"], p1["gram_launches"])
+    _gram_check(G1, A, J1, "split", m)
+
+
 @pytest.mark.parametrize("growth,gram", [(1.0, "split"), (1.03, "split"), (1.03, "exact")])
 def test_gram_incremental_matches_exact_products(growth, gram):
     # G is built incrementally over several updates (all-new first update, then
