@@ -45,6 +45,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// Sums over the 64 lanes of N <= 4 per-lane values at once, each returned to
+// every lane: the values go to this wave's LDS area red (4 x 64 doubles), 16
+// lanes per value add four partials, the 16 lanes of a row add by DPP, and
+// lane 16u's total is read back as a scalar.  Cheaper than N wave_sum calls;
+// the wave reads only what it wrote, in order, so no barrier is needed.
+template <int N>
+__device__ __forceinline__ void wave_sum4(double (&v)[N], double* red) {
+  static_assert(N >= 1 && N <= 4, "four values per call");
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < N; ++u) red[u * 64 + lane] = v[u];
+  const int uu = lane >> 4, j = lane & 15;
+  double s = 0.0;
+  if (uu < N) s = (red[uu * 64 + j] + red[uu * 64 + j + 16]) + (red[uu * 64 + j + 32] + red[uu * 64 + j + 48]);
+  s += dpp_mov_f64<0xB1>(s);   // quad_perm(1,0,3,2)
+  s += dpp_mov_f64<0x4E>(s);   // quad_perm(2,3,0,1)
+  s += dpp_mov_f64<0x141>(s);  // row_half_mirror
+  s += dpp_mov_f64<0x140>(s);  // row_mirror
+#pragma unroll
+  for (int u = 0; u < N; ++u) v[u] = readlane_f64(s, 16 * u);
+}
+
 // Block-wide sum; every thread gets the total.  red must hold blockDim/64 doubles.
 __device__ double block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1874,6 +1896,7 @@ template <int E, int NS, int NW>
 __device__ __forceinline__ void alg4_qr_reg_body(const UpdArgs& a, const Blk bk) {
   __shared__ double vb[2][64 * E];
   __shared__ double tb[2];
+  __shared__ double qred[NW][4 * 64];   // each wave's dot sums (wave_sum4)
   const int n = a.ell, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   DevScalars* sc = a.sc;
   const int no = sc->n_occ;
@@ -1960,11 +1983,18 @@ __device__ __forceinline__ void alg4_qr_reg_body(const UpdArgs& a, const Blk bk)
               if (e >= e0) d[i] = fma(v[e], col[s0 + i][e], d[i]);
         }
 #pragma unroll
+        for (int h = 0; h < B; h += 4) {
+          double d4[4] = {d[h], d[h + 1], d[h + 2], d[h + 3]};
+          wave_sum4<4>(d4, qred[wave]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) d[h + u] = d4[u];
+        }
+#pragma unroll
         for (int i = 0; i < B; ++i) {
           if (s0 + i < NS) {
             const int c = wave + NW * (s0 + i);
             if (c > jj && c < no) {
-              const double g = tau * wave_sum(d[i]);
+              const double g = tau * d[i];
 #pragma unroll
               for (int e = 0; e < E; ++e)
                 if (e >= e0) col[s0 + i][e] = fma(-g, v[e], col[s0 + i][e]);
@@ -2654,6 +2684,7 @@ __device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk
   __shared__ int pos[kMaxN1];
   __shared__ int ipos[kMaxN1];
   __shared__ double rinv[kMaxN1 * kMaxN1];
+  __shared__ double qred[NW][4 * 64];   // each wave's dot sums (wave_sum4)
   const int n = a.ell, t = a.t, n1 = a.n1, n2 = a.n2, n3 = a.ell - a.n1 - a.n2;
   const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6;
   rid_update* rec = a.recs + a.u;
@@ -2813,12 +2844,19 @@ __device__ __forceinline__ void hutch_small_reg_body(const UpdArgs& a, const Blk
               if (e >= e0) d[i] = fma(v[e], vec[s0 + i][e], d[i]);
         }
 #pragma unroll
+        for (int h = 0; h < B; h += 4) {
+          double d4[4] = {d[h], d[h + 1], d[h + 2], d[h + 3]};
+          wave_sum4<4>(d4, qred[wave]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) d[h + u] = d4[u];
+        }
+#pragma unroll
         for (int i = 0; i < B; ++i) {
           if (s0 + i >= NS) continue;
           const int q = wave + NW * (s0 + i);
           const bool apply = (q < n1) ? (ipos[q] < 0) : (q < nv);
           if (apply) {
-            const double g = tau * wave_sum(d[i]);
+            const double g = tau * d[i];
 #pragma unroll
             for (int e = 0; e < E; ++e)
               if (e >= e0) vec[s0 + i][e] = fma(-g, v[e], vec[s0 + i][e]);
