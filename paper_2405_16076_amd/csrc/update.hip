@@ -789,6 +789,7 @@ __device__ __forceinline__ void select_body(const UpdArgs& a, const Blk bk) {
   __shared__ int used[kMaxT];
   __shared__ int64_t sJ[kMaxT];
   __shared__ double stold[kMaxT], stauD[kMaxT];
+  __shared__ int lnew_slot[kMaxT], lnew_src[kMaxT], lslot_src[kMaxT];  // the slot lists, built here
   const int lane = threadIdx.x;
   DevScalars* sc = a.sc;
   const int t = a.t;
@@ -838,8 +839,8 @@ __device__ __forceinline__ void select_body(const UpdArgs& a, const Blk bk) {
             sJ[i] = a.c0 + rs;
             stold[i] = stauD[rs];
             used[rs] = 1;
-            sc->new_slot[n_new] = i;
-            sc->new_src[n_new] = rs;
+            lnew_slot[n_new] = i;
+            lnew_src[n_new] = rs;
           }
           __syncthreads();
           ++n_new;
@@ -854,16 +855,30 @@ __device__ __forceinline__ void select_body(const UpdArgs& a, const Blk bk) {
     a.tau_old[i] = stold[i];
     a.J_hist[a.u * t + i] = sJ[i];
   }
+  // the slot lists in LDS by all lanes (occupied and old slots compacted in
+  // slot order through ballots), then written out once
+  for (int i = lane; i < t; i += 64) lslot_src[i] = -1;
+  __syncthreads();
+  for (int q = lane; q < n_new; q += 64) lslot_src[lnew_slot[q]] = lnew_src[q];
+  __syncthreads();
+  int n_occ = 0, n_old = 0;
+  const uint64_t below = (1ull << lane) - 1;
+  for (int base = 0; base < t; base += 64) {
+    const int i = base + lane;
+    const bool occ = i < t && sJ[i] >= 0;
+    const bool old = occ && lslot_src[i] < 0;
+    const uint64_t bo = __ballot(occ), bd = __ballot(old);
+    if (occ) sc->occ_slot[n_occ + __popcll(bo & below)] = i;
+    if (old) sc->old_slot[n_old + __popcll(bd & below)] = i;
+    n_occ += __popcll(bo);
+    n_old += __popcll(bd);
+  }
+  for (int i = lane; i < t; i += 64) sc->slot_src[i] = lslot_src[i];
+  for (int q = lane; q < n_new; q += 64) {
+    sc->new_slot[q] = lnew_slot[q];
+    sc->new_src[q] = lnew_src[q];
+  }
   if (lane == 0) {
-    int n_occ = 0, n_old = 0;
-    for (int i = 0; i < t; ++i) sc->slot_src[i] = -1;
-    for (int q = 0; q < n_new; ++q) sc->slot_src[sc->new_slot[q]] = sc->new_src[q];
-    for (int i = 0; i < t; ++i) {
-      if (sJ[i] >= 0) {
-        sc->occ_slot[n_occ++] = i;
-        if (sc->slot_src[i] < 0) sc->old_slot[n_old++] = i;
-      }
-    }
     sc->n_new = n_new;
     sc->n_occ = n_occ;
     rid_update* rec = a.recs + a.u;
