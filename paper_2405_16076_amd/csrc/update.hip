@@ -1274,7 +1274,7 @@ __global__ __launch_bounds__(256, 2) void gram_f32_kernel_b(Batched<UpdArgs> L) 
   if (batched_block(L, p, bk)) gram_f32_body(*p, bk);
 }
 
-constexpr int kGramReduceWaves = 4;
+constexpr int kGramReduceWaves = 16;   // slab ranges summed in parallel, then in wave order
 
 // Zero the Gram rows/columns of empty slots, then write the new entries
 // (fixed-order sum over slabs), symmetrically.
@@ -1292,8 +1292,9 @@ __global__ void gram_zero_kernel_b(Batched<UpdArgs> L) {
   if (batched_block(L, p, bk)) gram_zero_body(*p, bk);
 }
 
-// One workgroup of 4 waves per (new slot q, 64 list entries): wave w sums the
-// w-th quarter of the row slabs in order, then the quarters are added in order.
+// One workgroup of 16 waves per (new slot q, 64 list entries): wave w sums the
+// w-th sixteenth of the row slabs in order, then the sixteen sums are added in
+// order.
 __device__ __forceinline__ void gram_reduce_body(const UpdArgs& a, const Blk bk) {
   __shared__ double part[kGramReduceWaves][64];
   const DevScalars* sc = a.sc;
@@ -1308,6 +1309,7 @@ __device__ __forceinline__ void gram_reduce_body(const UpdArgs& a, const Blk bk)
   if (act) {
     const int per = (a.gslabs + kGramReduceWaves - 1) / kGramReduceWaves;
     const int s1 = min(a.gslabs, (w + 1) * per);
+#pragma unroll 8
     for (int sl = w * per; sl < s1; ++sl) s += a.gpart[((int64_t)sl * a.gld + q) * a.gld + jj];
   }
   part[w][lane] = s;
@@ -1787,7 +1789,7 @@ __global__ void gram_run_list_kernel(UpdArgs a, int nu, const DevScalars* sc_his
 // Update entries of G from a run's partials: the list rows new at update w of
 // the run against the list columns in its basis.  An entry between two list
 // rows lies in the tile of the smaller row; two new columns of this update
-// are written once, from the smaller.  Grid (t, list chunks of 64) of 4
+// are written once, from the smaller.  Grid (t, list chunks of 64) of 16
 // waves, the slab sums as in gram_reduce.
 __device__ __forceinline__ void gram_reduce_run_body(const UpdArgs& a, const Blk bk) {
   __shared__ double part[kGramReduceWaves][64];
@@ -1803,6 +1805,7 @@ __device__ __forceinline__ void gram_reduce_run_body(const UpdArgs& a, const Blk
   if (act) {
     const int per = (a.gslabs + kGramReduceWaves - 1) / kGramReduceWaves;
     const int s1 = min(a.gslabs, (wv + 1) * per);
+#pragma unroll 8
     for (int sl = wv * per; sl < s1; ++sl) s += a.gpart[((int64_t)sl * a.gld + r) * a.gld + c];
   }
   part[wv][lane] = s;
