@@ -106,6 +106,7 @@ struct rid_stream {
   int sst_cur = 0;
   int nzmax = 0;                        // updates per batch (slots of W and hv)
   double* Fu = nullptr;
+  double* Tu = nullptr;   // tr(SS^T) per update
   int32_t* skipu = nullptr;
   double *tauC = nullptr, *tauD = nullptr, *tau_old = nullptr, *tauC_hist = nullptr,
          *tauD_hist = nullptr;
@@ -482,6 +483,7 @@ static rid_status init_stream(const rid_config* cfg, void* stream, rid_stream** 
     ALLOC(h->Qs, ell * ell * h->nzmax);
     ALLOC(h->Ys, ell * 2 * t * h->nzmax);
     ALLOC(h->Fu, (size_t)h->max_updates);
+    ALLOC(h->Tu, (size_t)h->max_updates);
     ALLOC(h->skipu, (size_t)h->max_updates);
     ALLOC(h->tauC, (size_t)kMaxT);
     ALLOC(h->tauD, (size_t)kMaxT);
@@ -697,6 +699,7 @@ static BatchArgs batch_args(rid_stream* h, int n_full, int last) {
   b.W = h->W;
   b.hv = h->hv;
   b.Fu = h->Fu;
+  b.tru = h->Tu;
   b.skipu = h->skipu;
   b.recs = h->recs;
   return b;

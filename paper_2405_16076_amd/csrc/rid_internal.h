@@ -276,6 +276,7 @@ struct BatchArgs {
   double* W;              // nz slots of l x l
   double* hv;             // nz slots of 6 l
   double* Fu;             // ||A_obs||^2 per update
+  double* tru;            // tr(SS^T) per update
   int32_t* skipu;         // 1 when the update skips selection (F == 0)
   rid_update* recs;
 };

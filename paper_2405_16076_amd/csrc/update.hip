@@ -229,7 +229,9 @@ __global__ __launch_bounds__(256) void sst_batch_kernel_b(Batched<BatchArgs> L) 
 }
 
 // ---------------------------------------------------------------------------
-// Tridiagonalisation + bisection + LDL^T.  One workgroup of 1024 threads.
+// Tridiagonalisation (one workgroup of 1024 threads per update), then the
+// top eigenvalues by multisection (one wave per eigenvalue, all updates at
+// once), then the ridge parameter and LDL^T (one thread per update).
 // hv layout: [0,l) reflector tau, [l,2l) d, [2l,3l) e, [3l,4l) Dinv, [4l,5l) L,
 // [5l,6l) top eigenvalues (descending).
 // ---------------------------------------------------------------------------
@@ -264,8 +266,6 @@ __device__ __forceinline__ void sturm_count2(const double* d, const double* e2, 
 
 template <int EMT, int NW>
 __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
-  __shared__ double e2s[kMaxEll];
-  __shared__ double ds[kMaxEll];
   const int z = bk.x;
   const int64_t u = b.u0 + z;
   const int n = b.ell, tid = threadIdx.x, nth = blockDim.x;
@@ -275,9 +275,6 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   double* htau = hv;
   double* d = hv + n;
   double* e = hv + 2 * n;
-  double* Dinv = hv + 3 * n;
-  double* L = hv + 4 * n;
-  double* mu = hv + 5 * n;
   if (b.skipu[u]) {
     if (tid == 0) {
       b.recs[u].sk2 = 0.0;
@@ -286,12 +283,11 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     return;
   }
   // tr(SS^T), the sketch's total energy, before the reduction overwrites W
-  __shared__ double trace_s;
   if (wv == 0) {
     double part = 0.0;
     for (int k = lane; k < n; k += 64) part += W[(int64_t)k * n + k];
     part = wave_sum(part);
-    if (lane == 0) trace_s = part;
+    if (lane == 0) b.tru[u] = part;
   }
   __syncthreads();
   // Householder tridiagonalisation on the lower triangle, one pass over the
@@ -497,89 +493,134 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
     e[n - 1] = 0.0;
     htau[n - 1] = 0.0;
   }
-  __syncthreads();
-  for (int i = tid; i < n; i += nth) {
+}
+
+// Top eigenvalues of T, the tridiagonal form of SS^T: wave w of workgroup
+// (update, y) finds eigenvalue idx = 4 y + w in descending order (idx < k) by
+// multisection.  Lane r counts the eigenvalues below points 2r + 1 and 2r + 2
+// of the 128 equispaced interior points that cut the wave's interval into 129
+// parts, and the wave keeps the part holding its target (Sturm counts are
+// monotone in the shift, so the points with count <= target are a prefix).
+// Stops at a width of one ulp of the eigenvalue or 2 eps ||T||, the accuracy
+// of the reduction itself.
+constexpr int kEigWaves = 4;
+__device__ __forceinline__ void tridiag_eig_body(const BatchArgs& b, const Blk bk) {
+  __shared__ double e2s[kMaxEll];
+  __shared__ double ds[kMaxEll];
+  const int z = bk.x;
+  const int64_t u = b.u0 + z;
+  const int n = b.ell, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int kk = min(b.k, n);
+  if (b.skipu[u] || bk.y * kEigWaves >= kk) return;  // uniform over the workgroup
+  double* hv = b.hv + (int64_t)z * 6 * n;
+  const double* d = hv + n;
+  const double* e = hv + 2 * n;
+  for (int i = tid; i < n; i += blockDim.x) {
     ds[i] = d[i];
     e2s[i] = (i + 1 < n) ? e[i] * e[i] : 0.0;
   }
   __syncthreads();
-  // Gershgorin interval and pivot threshold
-  double lo = 0.0, hi = 0.0, emax2 = 0.0;
-  for (int i = 0; i < n; ++i) {
+  const int idx = bk.y * kEigWaves + wv;
+  if (idx >= kk) return;
+  // Gershgorin interval and pivot threshold (minima and maxima are exact in
+  // any order)
+  double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
+  for (int i = lane; i < n; i += 64) {
     const double r = ((i > 0) ? fabs(e[i - 1]) : 0.0) + ((i + 1 < n) ? fabs(e[i]) : 0.0);
-    lo = (i == 0) ? ds[i] - r : fmin(lo, ds[i] - r);
-    hi = (i == 0) ? ds[i] + r : fmax(hi, ds[i] + r);
+    lo = fmin(lo, ds[i] - r);
+    hi = fmax(hi, ds[i] + r);
     emax2 = fmax(emax2, e2s[i]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o));
   }
   const double bnd = fmax(fabs(lo), fabs(hi));
   lo -= 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   hi += 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-  // Multisection: a group of GL lanes per eigenvalue, on at most 8 waves (two
-  // per SIMD: the Sturm recurrences keep the binary64 units busy, so more
-  // waves would only queue on them); lane r of the group counts the
-  // eigenvalues below points 2r + 1 and 2r + 2 of the 2 GL equispaced interior
-  // points that cut the group's interval into G = 2 GL + 1 parts, and the
-  // group keeps the part holding its target (Sturm counts are monotone in the
-  // shift, so the points with count <= target are a prefix).  Stops at a
-  // width of one ulp of the eigenvalue or 2 eps ||T||, the accuracy of the
-  // reduction itself.
-  const int kk = min(b.k, n);
-  const int nwe = min(nw, 8);
-  int GL = 1;
-  for (int g = 8; g > 1; --g)
-    if ((64 / g) * nwe >= kk) {
-      GL = g;
-      break;
-    }
-  const int G = 2 * GL + 1;
-  const int gpw = 64 / GL, gi = lane / GL, r = lane % GL;
-  const uint64_t gmask = ((1ull << GL) - 1) << (gi * GL);
   const double atol = 2.0 * 2.220446049250313e-16 * bnd;
-  for (int idx = (gi < gpw && wv < nwe) ? wv * gpw + gi : kk; idx < kk; idx += nwe * gpw) {
-    const int target = n - 1 - idx;  // ascending index of the idx-th largest
-    double aa = lo, bb = hi;
-    for (int it = 0; it < 200; ++it) {
-      if (bb - aa <= fmax(2.220446049250313e-16 * fmax(fabs(aa), fabs(bb)), atol)) break;
-      const double hs = (bb - aa) / G;
-      if (!(aa + hs > aa) || !(aa + (G - 1) * hs < bb)) break;
-      int c0, c1;
-      sturm_count2(ds, e2s, n, aa + (2 * r + 1) * hs, aa + (2 * r + 2) * hs, pivmin, c0, c1);
-      const uint64_t bal0 = __ballot(c0 <= target), bal1 = __ballot(c1 <= target);
-      const int cnt = __popcll(bal0 & gmask) + __popcll(bal1 & gmask);
-      const double na = cnt == 0 ? aa : aa + cnt * hs;
-      const double nb = cnt == G - 1 ? bb : aa + (cnt + 1) * hs;
-      aa = na;
-      bb = nb;
-    }
-    if (r == 0) mu[idx] = 0.5 * (aa + bb);
+  constexpr int G = 129;
+  const int target = n - 1 - idx;  // ascending index of the idx-th largest
+  double aa = lo, bb = hi;
+  for (int it = 0; it < 200; ++it) {
+    if (bb - aa <= fmax(2.220446049250313e-16 * fmax(fabs(aa), fabs(bb)), atol)) break;
+    const double hs = (bb - aa) / G;
+    if (!(aa + hs > aa) || !(aa + (G - 1) * hs < bb)) break;
+    int c0, c1;
+    sturm_count2(ds, e2s, n, aa + (2 * lane + 1) * hs, aa + (2 * lane + 2) * hs, pivmin, c0, c1);
+    const int cnt = __popcll(__ballot(c0 <= target)) + __popcll(__ballot(c1 <= target));
+    const double na = cnt == 0 ? aa : aa + cnt * hs;
+    const double nb = cnt == G - 1 ? bb : aa + (cnt + 1) * hs;
+    aa = na;
+    bb = nb;
+  }
+  if (lane == 0) hv[5 * n + idx] = 0.5 * (aa + bb);
+}
+
+__global__ __launch_bounds__(64 * kEigWaves) void tridiag_eig_kernel(BatchArgs b) {
+  tridiag_eig_body(b, own_block());
+}
+
+__global__ __launch_bounds__(64 * kEigWaves) void tridiag_eig_kernel_b(Batched<BatchArgs> L) {
+  const BatchArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) tridiag_eig_body(*p, bk);
+}
+
+// ||S_k||^2 (the top-k eigenvalues summed in index order), the ridge
+// parameter, and T + l lambda' I = L D L^T of each update: one wave stages
+// d, e and the eigenvalues in LDS, one thread runs the recurrences.
+__device__ __forceinline__ void tridiag_ridge_body(const BatchArgs& b, const Blk bk) {
+  __shared__ double sd[kMaxEll], se[kMaxEll], smu[kMaxEll];
+  const int z = bk.x;
+  const int64_t u = b.u0 + z;
+  if (b.skipu[u]) return;
+  const int n = b.ell, tid = threadIdx.x;
+  const int kk = min(b.k, n);
+  double* hv = b.hv + (int64_t)z * 6 * n;
+  for (int i = tid; i < n; i += blockDim.x) {
+    sd[i] = hv[n + i];
+    se[i] = hv[2 * n + i];
+    smu[i] = i < kk ? hv[5 * n + i] : 0.0;
   }
   __syncthreads();
-  if (tid == 0) {
-    double sk2 = 0.0;
-    for (int i = 0; i < kk; ++i) sk2 += mu[i];
-    const double F = b.Fu[u];
-    // the ridge parameter: the rank-k tail energy over k, the tail taken as
-    // the sketch's own tail fraction (tr(SS^T) - ||S_k||^2) / tr(SS^T) of F
-    // (eqs. ridge-leverage-score, sketch_ridge_leverage_score,
-    // g_ridge_leverage_score), floored at rho F / k
-    const double tr = trace_s;
-    const double tail = tr > 0.0 ? F * (tr - sk2) / tr : 0.0;
-    const double lam = fmax(tail / b.k, b.ridge_floor * F / b.k);
-    const double shift = n * lam;
-    b.recs[u].sk2 = sk2;
-    b.recs[u].lam = lam;
-    // T + shift I = L D L^T (T symmetric positive definite for shift > 0)
-    double Di = ds[0] + shift;
-    Dinv[0] = 1.0 / Di;
-    for (int i = 0; i + 1 < n; ++i) {
-      const double li = e[i] / Di;
-      L[i] = li;
-      Di = ds[i + 1] + shift - li * e[i];
-      Dinv[i + 1] = 1.0 / Di;
-    }
-    L[n - 1] = 0.0;
+  if (tid != 0) return;
+  double* Dinv = hv + 3 * n;
+  double* L = hv + 4 * n;
+  double sk2 = 0.0;
+  for (int i = 0; i < kk; ++i) sk2 += smu[i];
+  const double F = b.Fu[u];
+  // the ridge parameter: the rank-k tail energy over k, the tail taken as
+  // the sketch's own tail fraction (tr(SS^T) - ||S_k||^2) / tr(SS^T) of F
+  // (eqs. ridge-leverage-score, sketch_ridge_leverage_score,
+  // g_ridge_leverage_score), floored at rho F / k
+  const double tr = b.tru[u];
+  const double tail = tr > 0.0 ? F * (tr - sk2) / tr : 0.0;
+  const double lam = fmax(tail / b.k, b.ridge_floor * F / b.k);
+  const double shift = n * lam;
+  b.recs[u].sk2 = sk2;
+  b.recs[u].lam = lam;
+  // T + shift I = L D L^T (T symmetric positive definite for shift > 0)
+  double Di = sd[0] + shift;
+  Dinv[0] = 1.0 / Di;
+  for (int i = 0; i + 1 < n; ++i) {
+    const double li = se[i] / Di;
+    L[i] = li;
+    Di = sd[i + 1] + shift - li * se[i];
+    Dinv[i + 1] = 1.0 / Di;
   }
+  L[n - 1] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void tridiag_ridge_kernel(BatchArgs b) { tridiag_ridge_body(b, own_block()); }
+
+__global__ __launch_bounds__(64) void tridiag_ridge_kernel_b(Batched<BatchArgs> L) {
+  const BatchArgs* p;
+  Blk bk;
+  if (batched_block(L, p, bk)) tridiag_ridge_body(*p, bk);
 }
 
 template <int EMT>
@@ -3018,6 +3059,9 @@ hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
     case 7: hipLaunchKernelGGL(tridiag_kernel<7>, dim3(b.nz), dim3(1024), 0, s, b); break;
     default: hipLaunchKernelGGL(tridiag_kernel<8>, dim3(b.nz), dim3(1024), 0, s, b); break;
   }
+  const int kk = std::min(b.k, b.ell);
+  hipLaunchKernelGGL(tridiag_eig_kernel, dim3(b.nz, (kk + kEigWaves - 1) / kEigWaves), dim3(64 * kEigWaves), 0, s, b);
+  hipLaunchKernelGGL(tridiag_ridge_kernel, dim3(b.nz), dim3(64), 0, s, b);
   return hipGetLastError();
 }
 
@@ -3253,6 +3297,13 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
     P.add(f, h[i], make_int4(h[i].nz, 1, 1, 0));
   }
   P.emit(dim3(half ? 512 : 1024), -1, st, out);
+  for (int i = 0; i < ns; ++i) {
+    const int kk = std::min(h[i].k, h[i].ell);
+    P.add(fn(tridiag_eig_kernel_b), h[i], make_int4(h[i].nz, (kk + kEigWaves - 1) / kEigWaves, 1, 0));
+  }
+  P.emit(dim3(64 * kEigWaves), -1, st, out);
+  for (int i = 0; i < ns; ++i) P.add(fn(tridiag_ridge_kernel_b), h[i], make_int4(h[i].nz, 1, 1, 0));
+  P.emit(dim3(64), -1, st, out);
 }
 
 void plan_update_q_b(const UpdArgs* h, int ns, Stage& st, std::vector<BLaunch>& out) {
