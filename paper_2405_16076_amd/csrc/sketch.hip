@@ -961,7 +961,7 @@ __global__ __launch_bounds__(256) void sketch_f64_multi(MultiSketch ms) {
 // sums the w-th share of the slabs in slab order, then the shares are added in
 // wave order.  The column's norm: lane i of wave 1 sums slabs i, i + 64, ...,
 // then a fixed butterfly over the lanes, lane 0's result kept.
-constexpr int kReduceWaves = 4;
+constexpr int kReduceWaves = 16;
 
 template <typename T>
 __device__ __forceinline__ void sketch_reduce_body(const SketchArgs& a, const Blk bk) {
@@ -974,8 +974,10 @@ __device__ __forceinline__ void sketch_reduce_body(const SketchArgs& a, const Bl
   const int per = (a.n_slabs + kReduceWaves - 1) / kReduceWaves;
   const int s1 = min(a.n_slabs, (w + 1) * per);
   double s = 0.0;
-  if (r < a.ell)
+  if (r < a.ell) {
+#pragma unroll 8
     for (int sl = w * per; sl < s1; ++sl) s += (double)part[((int64_t)sl * a.b_max + c) * a.ell_pad + r];
+  }
   share[w][lane] = s;
   __syncthreads();
   if (w == 0 && r < a.ell) {

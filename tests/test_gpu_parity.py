@@ -169,6 +169,16 @@ def _pipeline(A, ell, k, t, sketch, oseed, sseed, batch=None, borrow=True, n_max
             assert d <= tol[key][u], (u, key, g[key], h[key], tol[key][u])
     log("  NA-Hutch++ diff/tol " + " ".join(f"{k} {v:.2e}" for k, v in worst.items()))
     Sg, _, G = s.debug_state()
+    # the last update's ||S_k||^2 and lambda' (tridiagonalisation, multisection
+    # and ridge kernels) against LAPACK's eigenvalues of the device's own S S^T
+    last = s.update(len(o.records) - 1)
+    Sd = Sg[:, :o.n_obs].astype(np.float64)
+    SST = Sd @ Sd.T
+    tr = float(np.trace(SST))
+    sk2 = float(np.sum(np.linalg.eigvalsh(SST)[::-1][:min(k, ell)]))
+    assert abs(last["sk2"] - sk2) <= 1e-10 * tr, (last["sk2"], sk2, tr)
+    lam = max(last["F"] * (tr - last["sk2"]) / tr / k, 1e-8 * last["F"] / k)
+    assert abs(last["lam"] - lam) <= 1e-8 * lam + 1e-12 * last["F"] / k, (last["lam"], lam)
     eg = rel_fro(G, o.G)
     log(f"  Gram rel fro {eg:.2e}")
     if uses_gram_split(sketch):
