@@ -49,33 +49,42 @@ __device__ __forceinline__ bool sketch_item(const SketchArgs& a, int bid, int& s
 // so every snapshot element is read from HBM by exactly one workgroup.  Wave w
 // owns row group w/4 (RBW blocks of 32 rows) and the column pair w%4 (two
 // blocks of 32 columns): 2*RBW accumulator tiles; each SIMD (waves s, s+4)
-// holds one wave of each row group.  Per 32-row chunk:
-//   * the binary32 snapshot chunk (32 rows x 256 columns, 128-byte runs) is
-//     copied HBM -> LDS by the LDS-DMA path (global_load_lds_dwordx4) into a
-//     three-stage ring, so two chunks are in flight while one is consumed,
-//     without holding them in registers (the accumulators fill the register
-//     file); the consumer rounds its operands to bfloat16 and accumulates the
-//     binary64 column norms;
-//   * the matching 64*RBW x 32 tile of Omega is generated into LDS (double
-//     buffered) one chunk ahead.  Row-group-0 waves multiply first and
-//     generate second, row-group-1 waves the other way round, so each SIMD
-//     overlaps the matrix cores of one wave with the VALU work of the other.
-// LDS layout of a data stage: column c at 128*c bytes, its 16-byte slot j
-// holding rows 4(j ^ swz(c)).. (swizzled against bank conflicts of the
-// operand reads).
+// holds one wave of each row group.  Per 64-row chunk:
+//   * the binary32 chunk is copied HBM -> LDS by the LDS-DMA path
+//     (global_load_lds_dwordx4) in two halves of 128 columns (32 KB each);
+//     every instruction reads whole 256-byte column runs (16 lanes per column,
+//     4 columns), and both halves of the next chunk are in flight while one
+//     chunk is multiplied;
+//   * once a half has landed every thread rounds its part of it to bfloat16
+//     into the chunk's bfloat16 stage (32 KB), adding the binary64 column
+//     norms, and the half's buffer is refilled with the following chunk at
+//     once;
+//   * the 64*RBW x 32 tiles of Omega are generated into LDS (double buffered)
+//     one half-chunk ahead.  Row-group-0 waves multiply first and generate
+//     second, row-group-1 waves the other way round, so each SIMD overlaps the
+//     matrix cores of one wave with the VALU work of the other.
+// The products take the k-steps in row order with the same operands for any
+// chunking, so every sketch element is the same sum of the same products.
+// LDS layouts: a DMA half holds column c at 256*c bytes, lane q of the
+// column's 16 fetching lanes at 16*q bytes holding rows 4(q ^ (c % 4))..+4
+// (so that the converting reads fall on distinct banks); the bfloat16 stage
+// holds column c at 128*c bytes, its 16-byte slot j (rows 8j..8j+7) at
+// position j ^ ((c >> 1) & 7).
 // ---------------------------------------------------------------------------
 constexpr int kBf16Cols = 256;
-constexpr int kBf16KC = 32;
-constexpr int kBf16Stages = 3;
+constexpr int kBf16KC = 64;              // data rows per chunk (256-byte runs)
+constexpr int kBf16HC = 32;              // data rows per Omega tile
+
+__device__ __forceinline__ int bf16_slot(int c, int j) { return j ^ ((c >> 1) & 7); }
 
 template <int RBW>
 __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, int mt, int nt) {
-  constexpr int KC = kBf16KC;            // rows per chunk
+  constexpr int KC = kBf16KC, HC = kBf16HC;
   constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
-  constexpr int LDA = KC + 8;            // bf16 per Omega LDS row (80 bytes)
+  constexpr int LDA = HC + 8;            // bf16 per Omega LDS row (80 bytes)
   __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
-  __shared__ __attribute__((aligned(1024))) float dt[kBf16Stages][kBf16Cols * KC];
-  __shared__ double nsh[kBf16Cols];
+  __shared__ __attribute__((aligned(1024))) float stg[2][(kBf16Cols / 2) * KC];
+  __shared__ __attribute__((aligned(16))) uint16_t db[kBf16Cols * KC];
   __shared__ __attribute__((aligned(16))) uint16_t otab[kOmegaTabSize];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
@@ -88,55 +97,99 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
   const bool ragged = (r1 - r0) % KC != 0;
   const int row_base = mt * MROWS;       // first test-matrix row of this workgroup
 
-  // LDS-DMA geometry: instruction i of wave w copies columns 8(4w+i)..+8 of the
-  // tile, 8 lanes per column.  Columns beyond the batch copy the tile's first
-  // column instead: their results are never stored.
-  const gmem_t<float>* dsrc[4];
-  int drow[4];
+  // LDS-DMA geometry: instruction i of wave w for half h copies local columns
+  // 128 h + 16 w + 4 i + lane / 16; lane q = lane % 16 of a column fetches the
+  // column's rows 4 dq .. 4 dq + 3, dq = q ^ (column % 4).  Columns beyond the
+  // batch copy the tile's first column instead: their results are never
+  // stored.
+  const int dq = (lane & 15) ^ ((lane >> 4) & 3);
+  const gmem_t<float>* dsrc[2][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int cl = 8 * (4 * wave + i) + (lane >> 3);
-    const int cg = nt * kBf16Cols + cl;
-    const int cs = cg < a.b ? cg : nt * kBf16Cols;
-    dsrc[i] = gload_ptr(reinterpret_cast<const float*>(a.colptr[a.c0 + cs]));
-    drow[i] = 4 * ((lane & 7) ^ col_swz(cl));
-  }
-  // Rows wholly past the slab end are fetched from row r0 (in bounds) and the
-  // fix-up below zeroes them; a 16-byte run that straddles the end of the
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cl = 128 * h + 16 * wave + 4 * i + (lane >> 4);
+      const int cg = nt * kBf16Cols + cl;
+      const int cs = cg < a.b ? cg : nt * kBf16Cols;
+      dsrc[h][i] = gload_ptr(reinterpret_cast<const float*>(a.colptr[a.c0 + cs]));
+    }
+  // Rows wholly past the slab end are fetched from row r0 (in bounds) and
+  // zeroed when converted; a 16-byte run that straddles the end of the
   // snapshot stays inside the 16-byte-aligned block holding its last row.
-  auto issue = [&](int c, int stage) {
-    const int64_t k0 = r0 + (int64_t)c * KC;
-    const uint32_t sb = lds_addr(&dt[stage][0]);
+  auto issue = [&](int c, int h) {
+    int64_t row = r0 + (int64_t)c * KC + 4 * dq;
+    if (row >= r1) row = r0;
+    const uint32_t sb = lds_addr(&stg[h][0]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int64_t row = k0 + drow[i];
-      if (row >= r1) row = r0;
-      lds_dma16(dsrc[i] + row, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(4 * wave + i) * 1024u));
-    }
-  };
-  // After this wave's copies of chunk c have landed: zero the rows past r1.
-  auto fixup = [&](int c, int stage) {
-    const int64_t k0 = r0 + (int64_t)c * KC;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t row = k0 + drow[i];
-      float* slot = &dt[stage][(8 * (4 * wave + i) + (lane >> 3)) * KC + 4 * (lane & 7)];
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (row + e >= r1) slot[e] = 0.0f;
-    }
+    for (int i = 0; i < 4; ++i)
+      lds_dma16(dsrc[h][i] + row, __builtin_amdgcn_readfirstlane(sb + (uint32_t)(4 * wave + i) * 1024u));
   };
 
-  // Gaussian tile: item = (row group g of 8 rows, data row k of the chunk).
-  // Row groups at or beyond ell stay zero (written once below).
+  // Conversion of half h of chunk c: thread t takes rows 16 g .. 16 g + 15
+  // (g = t % 4) of the half's column t / 4, adds their squares to the column's
+  // norm (binary64, row order) and writes them as two bfloat16 slots.
+  double nrm[2] = {0.0, 0.0};
+  const int ccl = tid >> 2, g4 = tid & 3;
+  auto convert = [&](int c, int h, bool fix) {
+    const float* col = &stg[h][ccl * KC];
+    const int key = ccl & 3;
+    float4 x[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[i] = *reinterpret_cast<const float4*>(col + 4 * ((4 * g4 + i) ^ key));
+    if (fix) {
+      const int64_t k0 = r0 + (int64_t)c * KC + 16 * g4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (k0 + 4 * i >= r1) x[i].x = 0.0f;
+        if (k0 + 4 * i + 1 >= r1) x[i].y = 0.0f;
+        if (k0 + 4 * i + 2 >= r1) x[i].z = 0.0f;
+        if (k0 + 4 * i + 3 >= r1) x[i].w = 0.0f;
+      }
+    }
+    if (mt == 0) {
+      double t = nrm[h];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        t = fma((double)x[i].x, (double)x[i].x, t);
+        t = fma((double)x[i].y, (double)x[i].y, t);
+        t = fma((double)x[i].z, (double)x[i].z, t);
+        t = fma((double)x[i].w, (double)x[i].w, t);
+      }
+      nrm[h] = t;
+    }
+    const int gc = 128 * h + ccl;
+    const bf16x8 lo = bf16x8{(__bf16)x[0].x, (__bf16)x[0].y, (__bf16)x[0].z, (__bf16)x[0].w,
+                             (__bf16)x[1].x, (__bf16)x[1].y, (__bf16)x[1].z, (__bf16)x[1].w};
+    const bf16x8 hi = bf16x8{(__bf16)x[2].x, (__bf16)x[2].y, (__bf16)x[2].z, (__bf16)x[2].w,
+                             (__bf16)x[3].x, (__bf16)x[3].y, (__bf16)x[3].z, (__bf16)x[3].w};
+    *reinterpret_cast<u16x8*>(db + gc * KC + 8 * bf16_slot(gc, 2 * g4)) = __builtin_bit_cast(u16x8, lo);
+    *reinterpret_cast<u16x8*>(db + gc * KC + 8 * bf16_slot(gc, 2 * g4 + 1)) = __builtin_bit_cast(u16x8, hi);
+  };
+  // Chunk c into the bfloat16 stage: both its halves are in flight on entry
+  // (four copies each per wave, half 0 issued first); each half is refilled
+  // with chunk c + 1 as soon as every thread has read it.
+  auto convert_chunk = [&](int c) {
+    const bool fix = ragged && c == nch - 1;
+    wait_dma_keep4();                    // this wave's half-0 copies have landed
+    lds_barrier();                       // everyone's; the stage is no longer read
+    convert(c, 0, fix);
+    wait_dma_all();                      // this wave's half-1 copies have landed
+    lds_barrier();                       // everyone's; half 0 has been read
+    if (c + 1 < nch) issue(c + 1, 0);
+    convert(c, 1, fix);
+    lds_barrier();                       // half 1 has been read; the stage is complete
+    if (c + 1 < nch) issue(c + 1, 1);
+  };
+
+  // Gaussian tile: item = (row group g of 8 rows, data row k of the tile).
+  // Row groups at or beyond ell stay zero (written once below).  With 38 row
+  // groups the 1216 single Philox calls of a tile fall on the four SIMDs as
+  // 5, 5, 5, 4 wave-calls.
   const int n_groups = min(MROWS / 8, max(0, (a.ell - row_base + 7) / 8));
-  // Items are single Philox calls (8 rows x 1 data row): with 38 row groups
-  // the 1216 calls of a chunk fall on the four SIMDs as 5, 5, 5, 4 wave-calls
-  // (pairs of calls per item gave 6, 6, 4, 4).
-  const int n_items = n_groups * KC;
+  const int n_items = n_groups * HC;
   auto gen = [&](int64_t k0, uint16_t* d) {
     for (int it = tid; it < n_items; it += 512) {
-      const int g = it / KC, k = it % KC;
+      const int g = it / HC, k = it % HC;
       uint16_t* dst = d + (8 * g) * LDA + k;
       uint16_t z[8];
       omega8_bf16(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), otab, z);
@@ -152,41 +205,25 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[r][c][v] = 0.0f;
-  double nrm[2] = {0.0, 0.0};
 
-  // One chunk on the matrix cores.  Lane (l32, half) reads rows
-  // 16 s + 8 half .. +8 of column (2 cp + cc) 32 + l32; row group rg squares
-  // the rows of k-step s == rg, so each element enters the norm once.
-  auto mfma_chunk = [&](const uint16_t* O, const float* D) {
+  // Half hh of the chunk on the matrix cores: k-steps s = 2 hh, 2 hh + 1
+  // (rows 16 s .. 16 s + 15) against the Omega tile O of those 32 rows; lane
+  // (l32, half) reads rows 16 s + 8 half .. +8 of column (2 cp + cc) 32 + l32.
+  auto mfma_half = [&](const uint16_t* O, int hh) {
 #pragma unroll
-    for (int s = 0; s < KC / 16; ++s) {
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int s = 2 * hh + s2;
       bf16x8 bop[2];
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc) {
         const int cl = (2 * cp + cc) * 32 + l32;
-        const int key = col_swz(cl);
-        const float* colb = D + cl * KC;
-        const float4 x0 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half) ^ key));
-        const float4 x1 = *reinterpret_cast<const float4*>(colb + 4 * ((4 * s + 2 * half + 1) ^ key));
-        if (s == rg) {
-          double t = nrm[cc];
-          t = fma((double)x0.x, (double)x0.x, t);
-          t = fma((double)x0.y, (double)x0.y, t);
-          t = fma((double)x0.z, (double)x0.z, t);
-          t = fma((double)x0.w, (double)x0.w, t);
-          t = fma((double)x1.x, (double)x1.x, t);
-          t = fma((double)x1.y, (double)x1.y, t);
-          t = fma((double)x1.z, (double)x1.z, t);
-          t = fma((double)x1.w, (double)x1.w, t);
-          nrm[cc] = t;
-        }
-        bop[cc] = bf16x8{(__bf16)x0.x, (__bf16)x0.y, (__bf16)x0.z, (__bf16)x0.w,
-                         (__bf16)x1.x, (__bf16)x1.y, (__bf16)x1.z, (__bf16)x1.w};
+        bop[cc] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const u16x8*>(db + cl * KC + 8 * bf16_slot(cl, 2 * s + half)));
       }
 #pragma unroll
       for (int r = 0; r < RBW; ++r) {
         const bf16x8 av = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const u16x8*>(&O[((rg * RBW + r) * 32 + l32) * LDA + 16 * s + 8 * half]));
+            bf16x8, *reinterpret_cast<const u16x8*>(&O[((rg * RBW + r) * 32 + l32) * LDA + 16 * s2 + 8 * half]));
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc)
           acc[r][cc] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bop[cc], acc[r][cc], 0, 0, 0);
@@ -194,37 +231,38 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
     }
   };
 
-  // prologue: chunks 0 and 1 in flight, Omega of chunk 0, zero rows of Omega
+  // prologue: both halves of chunk 0 in flight, zero rows of Omega, the Omega
+  // tile of rows 0..31, chunk 0 converted (chunk 1 then in flight)
   issue(0, 0);
-  if (nch > 1) issue(1, 1);
+  issue(0, 1);
   for (int i = tid + n_groups * 8 * (LDA / 2); i < MROWS * (LDA / 2); i += 512) {
     reinterpret_cast<uint32_t*>(om[0])[i] = 0u;
     reinterpret_cast<uint32_t*>(om[1])[i] = 0u;
   }
   gen(r0, om[0]);
-  if (nch > 1) wait_dma_keep4(); else wait_dma_all();
-  if (nch == 1 && ragged) fixup(0, 0);
-  lds_barrier();
+  convert_chunk(0);
 
-  int st_cur = 0;
   for (int c = 0; c < nch; ++c) {
-    const int st_next = st_cur == kBf16Stages - 1 ? 0 : st_cur + 1;
-    const int st_issue = st_next == kBf16Stages - 1 ? 0 : st_next + 1;
-    if (c + 2 < nch) issue(c + 2, st_issue);
-    const int64_t k1 = r0 + (int64_t)(c + 1) * KC;
-    const uint16_t* O = om[c & 1];
-    uint16_t* On = om[(c + 1) & 1];
+    const int64_t kb = r0 + (int64_t)c * KC;
+    const bool more = c + 1 < nch;
+    // rows 0..31 against om[0]; the tile of rows 32..63 into om[1]
     if (rg == 0) {
-      mfma_chunk(O, dt[st_cur]);
-      if (c + 1 < nch) gen(k1, On);
+      mfma_half(om[0], 0);
+      gen(kb + HC, om[1]);
     } else {
-      if (c + 1 < nch) gen(k1, On);
-      mfma_chunk(O, dt[st_cur]);
+      gen(kb + HC, om[1]);
+      mfma_half(om[0], 0);
     }
-    if (c + 2 < nch) wait_dma_keep4(); else wait_dma_all();
-    if (ragged && c + 1 == nch - 1) fixup(c + 1, st_next);
     lds_barrier();
-    st_cur = st_next;
+    // rows 32..63 against om[1]; the next chunk's rows 0..31 into om[0]
+    if (rg == 0) {
+      mfma_half(om[1], 1);
+      if (more) gen(kb + KC, om[0]);
+    } else {
+      if (more) gen(kb + KC, om[0]);
+      mfma_half(om[1], 1);
+    }
+    if (more) convert_chunk(c + 1);
   }
 
   float* part = reinterpret_cast<float*>(a.part);
@@ -243,22 +281,14 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
       }
   }
   if (mt == 0) {
-    // lanes l and l + 32 hold the two row halves of one column
-    double t[2];
+    // the four threads of a column add their sums with a fixed butterfly
 #pragma unroll
-    for (int cc = 0; cc < 2; ++cc) t[cc] = nrm[cc] + __shfl_xor(nrm[cc], 32);
-    if (rg == 0 && half == 0) {
-      nsh[(2 * cp) * 32 + l32] = t[0];
-      nsh[(2 * cp + 1) * 32 + l32] = t[1];
-    }
-    __syncthreads();
-    if (rg == 1 && half == 0) {
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        const int cl = (2 * cp + cc) * 32 + l32;
-        const int col = nt * kBf16Cols + cl;
-        if (col < a.b) a.normpart[(int64_t)slab * a.b_max + col] = nsh[cl] + t[cc];
-      }
+    for (int h = 0; h < 2; ++h) {
+      double t = nrm[h];
+      t += __shfl_xor(t, 1);
+      t += __shfl_xor(t, 2);
+      const int col = nt * kBf16Cols + 128 * h + ccl;
+      if (g4 == 0 && col < a.b) a.normpart[(int64_t)slab * a.b_max + col] = t;
     }
   }
 }
