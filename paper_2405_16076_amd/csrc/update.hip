@@ -495,23 +495,28 @@ __device__ __forceinline__ void tridiag_body(const BatchArgs& b, const Blk bk) {
   }
 }
 
-// Top eigenvalues of T, the tridiagonal form of SS^T: wave w of workgroup
-// (update, y) finds eigenvalue idx = 4 y + w in descending order (idx < k) by
-// multisection.  Lane r counts the eigenvalues below points 2r + 1 and 2r + 2
-// of the 128 equispaced interior points that cut the wave's interval into 129
-// parts, and the wave keeps the part holding its target (Sturm counts are
-// monotone in the shift, so the points with count <= target are a prefix).
-// Stops at a width of one ulp of the eigenvalue or 2 eps ||T||, the accuracy
-// of the reduction itself.
+// Top eigenvalues of T, the tridiagonal form of SS^T, by multisection: a
+// group of GL lanes per eigenvalue (64 / GL groups per wave, 4 waves per
+// workgroup (update, y), eigenvalue idx = (4 y + w) 64 / GL + group in
+// descending order, idx < k).  Lane r of a group counts the eigenvalues below
+// points 2r + 1 and 2r + 2 of the 2 GL equispaced interior points that cut
+// the group's interval into 2 GL + 1 parts, and the group keeps the part
+// holding its target (Sturm counts are monotone in the shift, so the points
+// with count <= target are a prefix).  Stops at a width of one ulp of the
+// eigenvalue or 2 eps ||T||, the accuracy of the reduction itself.  A single
+// stream's few updates take GL = 64 (fewest rounds on otherwise idle compute
+// units); a batch's many take GL = 4 (least work on a full device).
 constexpr int kEigWaves = 4;
+template <int GL>
 __device__ __forceinline__ void tridiag_eig_body(const BatchArgs& b, const Blk bk) {
+  constexpr int EPW = 64 / GL;           // eigenvalues per wave
   __shared__ double e2s[kMaxEll];
   __shared__ double ds[kMaxEll];
   const int z = bk.x;
   const int64_t u = b.u0 + z;
   const int n = b.ell, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int kk = min(b.k, n);
-  if (b.skipu[u] || bk.y * kEigWaves >= kk) return;  // uniform over the workgroup
+  if (b.skipu[u] || bk.y * kEigWaves * EPW >= kk) return;  // uniform over the workgroup
   double* hv = b.hv + (int64_t)z * 6 * n;
   const double* d = hv + n;
   const double* e = hv + 2 * n;
@@ -520,8 +525,9 @@ __device__ __forceinline__ void tridiag_eig_body(const BatchArgs& b, const Blk b
     e2s[i] = (i + 1 < n) ? e[i] * e[i] : 0.0;
   }
   __syncthreads();
-  const int idx = bk.y * kEigWaves + wv;
-  if (idx >= kk) return;
+  const int gi = lane / GL, r = lane % GL;
+  const int idx = (bk.y * kEigWaves + wv) * EPW + gi;
+  if ((bk.y * kEigWaves + wv) * EPW >= kk) return;  // uniform over the wave
   // Gershgorin interval and pivot threshold (minima and maxima are exact in
   // any order)
   double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
@@ -542,32 +548,37 @@ __device__ __forceinline__ void tridiag_eig_body(const BatchArgs& b, const Blk b
   hi += 4.0 * 2.220446049250313e-16 * bnd + 1e-300;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   const double atol = 2.0 * 2.220446049250313e-16 * bnd;
-  constexpr int G = 129;
-  const int target = n - 1 - idx;  // ascending index of the idx-th largest
+  constexpr int G = 2 * GL + 1;
+  const uint64_t gmask = GL == 64 ? ~0ull : ((1ull << (GL & 63)) - 1) << (gi * GL);
+  const int target = n - 1 - min(idx, kk - 1);  // ascending index of the idx-th largest
   double aa = lo, bb = hi;
   for (int it = 0; it < 200; ++it) {
     if (bb - aa <= fmax(2.220446049250313e-16 * fmax(fabs(aa), fabs(bb)), atol)) break;
     const double hs = (bb - aa) / G;
     if (!(aa + hs > aa) || !(aa + (G - 1) * hs < bb)) break;
     int c0, c1;
-    sturm_count2(ds, e2s, n, aa + (2 * lane + 1) * hs, aa + (2 * lane + 2) * hs, pivmin, c0, c1);
-    const int cnt = __popcll(__ballot(c0 <= target)) + __popcll(__ballot(c1 <= target));
+    sturm_count2(ds, e2s, n, aa + (2 * r + 1) * hs, aa + (2 * r + 2) * hs, pivmin, c0, c1);
+    const uint64_t bal0 = __ballot(c0 <= target), bal1 = __ballot(c1 <= target);
+    const int cnt = __popcll(bal0 & gmask) + __popcll(bal1 & gmask);
     const double na = cnt == 0 ? aa : aa + cnt * hs;
     const double nb = cnt == G - 1 ? bb : aa + (cnt + 1) * hs;
     aa = na;
     bb = nb;
   }
-  if (lane == 0) hv[5 * n + idx] = 0.5 * (aa + bb);
+  if (r == 0 && idx < kk) hv[5 * n + idx] = 0.5 * (aa + bb);
 }
 
+constexpr int kEigLanesStream = 64;
+constexpr int kEigLanesBatch = 4;
+
 __global__ __launch_bounds__(64 * kEigWaves) void tridiag_eig_kernel(BatchArgs b) {
-  tridiag_eig_body(b, own_block());
+  tridiag_eig_body<kEigLanesStream>(b, own_block());
 }
 
 __global__ __launch_bounds__(64 * kEigWaves) void tridiag_eig_kernel_b(Batched<BatchArgs> L) {
   const BatchArgs* p;
   Blk bk;
-  if (batched_block(L, p, bk)) tridiag_eig_body(*p, bk);
+  if (batched_block(L, p, bk)) tridiag_eig_body<kEigLanesBatch>(*p, bk);
 }
 
 // ||S_k||^2 (the top-k eigenvalues summed in index order), the ridge
@@ -3060,7 +3071,8 @@ hipError_t launch_update_batch(const BatchArgs& b, hipStream_t s) {
     default: hipLaunchKernelGGL(tridiag_kernel<8>, dim3(b.nz), dim3(1024), 0, s, b); break;
   }
   const int kk = std::min(b.k, b.ell);
-  hipLaunchKernelGGL(tridiag_eig_kernel, dim3(b.nz, (kk + kEigWaves - 1) / kEigWaves), dim3(64 * kEigWaves), 0, s, b);
+  constexpr int per_wg = kEigWaves * 64 / kEigLanesStream;
+  hipLaunchKernelGGL(tridiag_eig_kernel, dim3(b.nz, (kk + per_wg - 1) / per_wg), dim3(64 * kEigWaves), 0, s, b);
   hipLaunchKernelGGL(tridiag_ridge_kernel, dim3(b.nz), dim3(64), 0, s, b);
   return hipGetLastError();
 }
@@ -3299,7 +3311,8 @@ void plan_update_batch_b(const BatchArgs* h, int ns, Stage& st, std::vector<BLau
   P.emit(dim3(half ? 512 : 1024), -1, st, out);
   for (int i = 0; i < ns; ++i) {
     const int kk = std::min(h[i].k, h[i].ell);
-    P.add(fn(tridiag_eig_kernel_b), h[i], make_int4(h[i].nz, (kk + kEigWaves - 1) / kEigWaves, 1, 0));
+    constexpr int per_wg = kEigWaves * 64 / kEigLanesBatch;
+    P.add(fn(tridiag_eig_kernel_b), h[i], make_int4(h[i].nz, (kk + per_wg - 1) / per_wg, 1, 0));
   }
   P.emit(dim3(64 * kEigWaves), -1, st, out);
   for (int i = 0; i < ns; ++i) P.add(fn(tridiag_ridge_kernel_b), h[i], make_int4(h[i].nz, 1, 1, 0));
