@@ -36,6 +36,9 @@ def _device_block(A, ld=None):
     ("f64", 4096, 37, 40), ("f64", 20_001, 64, 71),
     ("f32", 100_003, 33, 40), ("f32", 65_536, 300, 200),
     ("bf16", 100_003, 45, 40), ("bf16", 1_000_000, 16, 300), ("bf16", 70_000, 257, 300),
+    # one ragged 64-row chunk (a 16-byte piece straddles the last row), and two
+    # chunks plus one row over two column tiles; l not a multiple of 8
+    ("bf16", 37, 5, 13), ("bf16", 129, 260, 70),
     ("fp8", 100_003, 45, 40), ("fp8", 65_536, 300, 300),
 ])
 def test_sketch_columns_matches_oracle(sketch, m, b, ell):
