@@ -117,6 +117,21 @@ __device__ __forceinline__ void omega8_bf16(uint64_t seed, uint64_t i, uint32_t 
   }
 }
 
+// The same rows from a signed copy of the bfloat16 table in LDS: entry j of
+// its 2048 is T[j mod 1024] with the sign bit set for j >= 1024, so bits
+// 15..5 of a half index the signed value directly.
+__device__ __forceinline__ void load_omega_table_bf16_signed(uint16_t* lds) {
+  for (int i = threadIdx.x; i < 2 * kOmegaTabSize; i += blockDim.x)
+    lds[i] = (uint16_t)(kOmegaTabBf16[i & (kOmegaTabSize - 1)] | ((i & kOmegaTabSize) ? 0x8000u : 0u));
+}
+
+__device__ __forceinline__ void omega8_bf16_signed(uint64_t seed, uint64_t i, uint32_t g, const uint16_t* tab2,
+                                                   uint16_t z[8]) {
+  const Words4 w = omega_words(seed, i, g);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) z[q] = tab2[(omega_half(w, q) >> 5) & (2 * kOmegaTabSize - 1)];
+}
+
 // Rows 8g..8g+7 at data row i as e4m3 codes of 64 Omega, from an LDS copy.
 __device__ __forceinline__ void omega8_e4m3(uint64_t seed, uint64_t i, uint32_t g, const uint8_t* tab,
                                             uint32_t z[8]) {

@@ -82,14 +82,16 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
   constexpr int KC = kBf16KC, HC = kBf16HC;
   constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
   constexpr int LDA = HC + 8;            // bf16 per Omega LDS row (80 bytes)
+  // the signed table first, so that its address fits the LDS instructions'
+  // immediate offset
+  __shared__ __attribute__((aligned(4096))) uint16_t otab[2 * kOmegaTabSize];
   __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
   __shared__ __attribute__((aligned(1024))) float stg[2][(kBf16Cols / 2) * KC];
   __shared__ __attribute__((aligned(16))) uint16_t db[kBf16Cols * KC];
-  __shared__ __attribute__((aligned(16))) uint16_t otab[kOmegaTabSize];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
   const int rg = wave >> 2, cp = wave & 3;
-  load_omega_table(otab, kOmegaTabBf16);
+  load_omega_table_bf16_signed(otab);
   __syncthreads();
   const int64_t r0 = (int64_t)slab * a.slab_rows;
   const int64_t r1 = min(a.m, r0 + a.slab_rows);
@@ -191,10 +193,9 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
     for (int it = tid; it < n_items; it += 512) {
       const int g = it / HC, k = it % HC;
       uint16_t* dst = d + (8 * g) * LDA + k;
-      uint16_t z[8];
-      omega8_bf16(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g), otab, z);
+      const Words4 w = omega_words(a.seed, (uint64_t)(k0 + k), (uint32_t)(row_base / 8 + g));
 #pragma unroll
-      for (int j = 0; j < 8; ++j) dst[j * LDA] = z[j];
+      for (int j = 0; j < 8; ++j) dst[j * LDA] = otab[(omega_half(w, j) >> 5) & (2 * kOmegaTabSize - 1)];
     }
   };
 
