@@ -132,6 +132,13 @@ __device__ __forceinline__ void omega8_bf16_signed(uint64_t seed, uint64_t i, ui
   for (int q = 0; q < 8; ++q) z[q] = tab2[(omega_half(w, q) >> 5) & (2 * kOmegaTabSize - 1)];
 }
 
+// A signed copy of the e4m3 table (entry j: code j mod 1024 with the sign
+// bit set for j >= 1024), indexed by bits 15..5 of a half.
+__device__ __forceinline__ void load_omega_table_e4m3_signed(uint8_t* lds) {
+  for (int i = threadIdx.x; i < 2 * kOmegaTabSize; i += blockDim.x)
+    lds[i] = (uint8_t)(kOmegaTabE4M3[i & (kOmegaTabSize - 1)] | ((i & kOmegaTabSize) ? 0x80u : 0u));
+}
+
 // Rows 8g..8g+7 at data row i as e4m3 codes of 64 Omega, from an LDS copy.
 __device__ __forceinline__ void omega8_e4m3(uint64_t seed, uint64_t i, uint32_t g, const uint8_t* tab,
                                             uint32_t z[8]) {

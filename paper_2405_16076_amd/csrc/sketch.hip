@@ -562,12 +562,14 @@ __device__ __forceinline__ void sketch_fp8_body(const SketchArgs& a, int slab, i
   constexpr int NST = 4;                 // DMA stages
   constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
   constexpr int LDO = 80;                // bytes per Omega tile row (64 + pad)
+  // the signed e4m3 table at LDS address 0 (the largest alignment is placed
+  // first), so that a half's bits 15..5 address it with no base add
+  __shared__ __attribute__((aligned(2048))) uint8_t otab[2 * kOmegaTabSize];
   __shared__ __attribute__((aligned(16))) uint8_t om[MROWS * LDO];
   __shared__ __attribute__((aligned(1024))) float dt[NST][kBf16Cols * KC];
   __shared__ uint64_t csrc[kBf16Cols];
   __shared__ int scl[2][kBf16Cols];      // E8M0 code of (chunk of the step, column)
-  __shared__ __attribute__((aligned(16))) uint8_t otab[kOmegaTabSize];
-  load_omega_table(otab, kOmegaTabE4M3);
+  load_omega_table_e4m3_signed(otab);
   __syncthreads();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, l32 = lane & 31;
@@ -614,12 +616,14 @@ __device__ __forceinline__ void sketch_fp8_body(const SketchArgs& a, int slab, i
     const int64_t k0 = r0 + (int64_t)q * 64;
     for (int it = tid; it < n_items; it += 512) {
       const int g = it >> 5, kp = it & 31;
-      uint32_t z0[8], z1[8];
-      omega8_e4m3(a.seed, (uint64_t)(k0 + 2 * kp), (uint32_t)(row_base / 8 + g), otab, z0);
-      omega8_e4m3(a.seed, (uint64_t)(k0 + 2 * kp + 1), (uint32_t)(row_base / 8 + g), otab, z1);
+      const Words4 w0 = omega_words(a.seed, (uint64_t)(k0 + 2 * kp), (uint32_t)(row_base / 8 + g));
+      const Words4 w1 = omega_words(a.seed, (uint64_t)(k0 + 2 * kp + 1), (uint32_t)(row_base / 8 + g));
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        *reinterpret_cast<uint16_t*>(&om[(8 * g + j) * LDO + 2 * kp]) = (uint16_t)(z0[j] | (z1[j] << 8));
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t z0 = otab[(omega_half(w0, j) >> 5) & (2 * kOmegaTabSize - 1)];
+        const uint32_t z1 = otab[(omega_half(w1, j) >> 5) & (2 * kOmegaTabSize - 1)];
+        *reinterpret_cast<uint16_t*>(&om[(8 * g + j) * LDO + 2 * kp]) = (uint16_t)(z0 | (z1 << 8));
+      }
     }
   };
 
