@@ -60,9 +60,11 @@ __device__ __forceinline__ bool sketch_item(const SketchArgs& a, int bid, int& s
 //     norms, and the half's buffer is refilled with the following chunk at
 //     once;
 //   * the 64*RBW x 32 tiles of Omega are generated into LDS (double buffered)
-//     one half-chunk ahead.  Row-group-0 waves multiply first and generate
-//     second, row-group-1 waves the other way round, so each SIMD overlaps the
-//     matrix cores of one wave with the VALU work of the other.
+//     one half-chunk ahead, each entry one lookup of its Philox half's bits
+//     15..5 in a signed copy of the table (entry j: T[j mod 1024] with the
+//     sign bit set for j >= 1024).  Row-group-0 waves multiply first and
+//     generate second, row-group-1 waves the other way round, so each SIMD
+//     overlaps the matrix cores of one wave with the VALU work of the other.
 // The products take the k-steps in row order with the same operands for any
 // chunking, so every sketch element is the same sum of the same products.
 // LDS layouts: a DMA half holds column c at 256*c bytes, lane q of the
@@ -82,8 +84,8 @@ __device__ __forceinline__ void sketch_bf16_body(const SketchArgs& a, int slab, 
   constexpr int KC = kBf16KC, HC = kBf16HC;
   constexpr int MROWS = 64 * RBW;        // test-matrix rows per workgroup
   constexpr int LDA = HC + 8;            // bf16 per Omega LDS row (80 bytes)
-  // the signed table first, so that its address fits the LDS instructions'
-  // immediate offset
+  // the largest alignment places the signed table at LDS address 0, so a
+  // lookup's address is the index doubled, with no base to add
   __shared__ __attribute__((aligned(4096))) uint16_t otab[2 * kOmegaTabSize];
   __shared__ __attribute__((aligned(16))) uint16_t om[2][MROWS * LDA];
   __shared__ __attribute__((aligned(1024))) float stg[2][(kBf16Cols / 2) * KC];
