@@ -994,21 +994,24 @@ __global__ __launch_bounds__(256) void sketch_f64_multi(MultiSketch ms) {
 // Fixed-order binary64 sum of the slab partials into S(:, c0:c0+b) and
 // ||a_j||^2; a non-finite norm (a non-finite snapshot value) sets the flag.
 // Block (x, y): rows 64 x.., column y of the batch.
-// One workgroup of kReduceWaves waves per (64 sketch rows, column): wave w
-// sums the w-th share of the slabs in slab order, then the shares are added in
-// wave order.  The column's norm: lane i of wave 1 sums slabs i, i + 64, ...,
-// then a fixed butterfly over the lanes, lane 0's result kept.
+// One workgroup of NWR waves per (64 sketch rows, column): wave w sums the
+// w-th share of the slabs in slab order, then the shares are added in wave
+// order.  The column's norm: lane i of wave 1 sums slabs i, i + 64, ..., then a
+// fixed butterfly over the lanes, lane 0's result kept.  A single stream's
+// hundreds of slabs take 16 waves; a batch's members, most with few slabs,
+// take 4.
 constexpr int kReduceWaves = 16;
+constexpr int kReduceWavesBatch = 4;
 
-template <typename T>
+template <typename T, int NWR>
 __device__ __forceinline__ void sketch_reduce_body(const SketchArgs& a, const Blk bk) {
-  __shared__ double share[kReduceWaves][64];
+  __shared__ double share[NWR][64];
   const T* __restrict__ part = reinterpret_cast<const T*>(a.part);
   const int c = bk.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r = bk.x * 64 + lane;
   if (c >= a.b) return;  // the same for the whole workgroup
-  const int per = (a.n_slabs + kReduceWaves - 1) / kReduceWaves;
+  const int per = (a.n_slabs + NWR - 1) / NWR;
   const int s1 = min(a.n_slabs, (w + 1) * per);
   double s = 0.0;
   if (r < a.ell) {
@@ -1020,7 +1023,7 @@ __device__ __forceinline__ void sketch_reduce_body(const SketchArgs& a, const Bl
   if (w == 0 && r < a.ell) {
     double tot = share[0][lane];
 #pragma unroll
-    for (int i = 1; i < kReduceWaves; ++i) tot += share[i][lane];
+    for (int i = 1; i < NWR; ++i) tot += share[i][lane];
     a.S[(a.c0 + c) * a.ell + r] = tot;
   }
   if (bk.x == 0 && w == 1) {
@@ -1037,14 +1040,14 @@ __device__ __forceinline__ void sketch_reduce_body(const SketchArgs& a, const Bl
 
 template <typename T>
 __global__ __launch_bounds__(64 * kReduceWaves) void sketch_reduce_kernel(SketchArgs a) {
-  sketch_reduce_body<T>(a, own_block());
+  sketch_reduce_body<T, kReduceWaves>(a, own_block());
 }
 
 template <typename T>
-__global__ __launch_bounds__(64 * kReduceWaves) void sketch_reduce_kernel_b(Batched<SketchArgs> L) {
+__global__ __launch_bounds__(64 * kReduceWavesBatch) void sketch_reduce_kernel_b(Batched<SketchArgs> L) {
   const SketchArgs* a;
   Blk bk;
-  if (batched_block(L, a, bk)) sketch_reduce_body<T>(*a, bk);
+  if (batched_block(L, a, bk)) sketch_reduce_body<T, kReduceWavesBatch>(*a, bk);
 }
 
 __global__ void omega_block_kernel(int prec, uint64_t seed, int ell, int64_t i0, int64_t count,
@@ -1240,7 +1243,7 @@ void plan_sketch_reduce_b(int prec, const SketchArgs* h, int ns, Stage& st, std:
   L.func = prec == RID_SKETCH_F64 ? reinterpret_cast<const void*>(sketch_reduce_kernel_b<double>)
                                   : reinterpret_cast<const void*>(sketch_reduce_kernel_b<float>);
   L.grid = dim3((unsigned)maxb, (unsigned)ns);
-  L.block = dim3(64 * kReduceWaves);
+  L.block = dim3(64 * kReduceWavesBatch);
   L.extra = -1;
   L.args = st.put(g.data(), g.size());
   L.aux = st.put(dims.data(), dims.size());
