@@ -48,3 +48,19 @@ def test_every_format_rounds_the_oracle_quantiles():
 
     e8 = np.array([e4m3(int(v, 16)) for v in _array(text, "kOmegaTabE4M3")]) / 64.0
     assert np.array_equal(e8, quantize_fp8_omega(T))
+
+
+def test_signed_tables_index_the_same_entries():
+    """The bfloat16 and e4m3 sketch kernels look Omega entries up in a signed
+    2048-entry copy of their table (entry j: entry j mod 1024 with the sign bit
+    set for j >= 1024), indexed by bits 15..5 of the Philox half.  Over every
+    16-bit half this is the definition's sign-and-magnitude entry:
+    (-1)^(bit 15) T[bits 14..5]."""
+    text = open(HEADER).read()
+    h = np.arange(1 << 16, dtype=np.uint32)
+    j = np.arange(2048, dtype=np.uint32)
+    for name, sign in (("kOmegaTabBf16", 0x8000), ("kOmegaTabE4M3", 0x80)):
+        tab = np.array([int(v, 16) for v in _array(text, name)], dtype=np.uint32)
+        signed = tab[j & 1023] | np.where(j & 1024, sign, 0).astype(np.uint32)
+        direct = tab[(h >> 5) & 1023] | np.where(h & 0x8000, sign, 0).astype(np.uint32)
+        assert np.array_equal(signed[(h >> 5) & 2047], direct)
